@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""Throughput of the binary Hough hot path on one MI355X.
+
+One step = one pass of the whole hot path over one band of synthetic data already resident
+in HBM: peakgram, stage-1 weighted count over every template, stage-1 top-k, decoding of the
+winners, stage-2 power (and the winners' counts) on the exact track, stage-2 top-k.
+
+Default workload: 4000 segments (2 detectors x 2000, gapped), one sky pixel, band
+200.0-200.1 Hz (90 f0 bins), a_p 64 x P 32 x t_asc 64 -> 11 796 480 templates; stage-1
+top-10^4 then stage-2 top-100.  Work unit: template x segment of stage 1.
+
+Prints one JSON line.  The CPU oracle is timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Hough templates·segments/s on 1 GPU, batched vs plain, at oracle-exact top-k"
+# 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: 32-bit VALU lane-operations per second
+VALU_PEAK_OPS = 256 * 64 * 2.4e9
+# algorithmic VALU lane-ops per template x segment of the weighted count: extract the peak
+# bit, select the weight, add
+OPS_PER_TS = 3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-ap", type=int, default=8,
+                    help="a_p values (of 64) in the oracle's timed sample")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU sharding is "
+                                   "described in DESIGN.md but not part of it", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import bsh_synth as S
+    from paper_1904_04873_amd import bsh
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    w = S.config2()
+    seg, spec = w.segments[0], w.grids[0]
+    k1, k2 = w.topk_stage1, w.topk_stage2
+    print(f"[bench] workload cfg2: {seg.n_seg} segments, building device tables", file=sys.stderr, flush=True)
+    ds = bsh.DeviceSegments.from_host(seg)
+    g = bsh.DeviceGrid.build(spec, seg.t_span_mid(), w.sky)
+    n_t = g.n_templates
+    ts_per_step = n_t * seg.n_seg
+    st = bsh.Status(dev)
+    ws_map = torch.empty(n_t, dtype=torch.float32, device=dev)
+    top1 = bsh.TopK(n_t, k1, dev)
+    top2 = bsh.TopK(k1, k2, dev)
+    s1_score = torch.empty(k1, dtype=torch.float32, device=dev)
+    s1_index = torch.empty(k1, dtype=torch.int64, device=dev)
+    s2_score = torch.empty(k2, dtype=torch.float32, device=dev)
+    s2_pos = torch.empty(k2, dtype=torch.int64, device=dev)
+    P = torch.empty(k1, dtype=torch.float32, device=dev)
+    ev_count = []
+
+    def step(record):
+        bsh.bsh_peakgram(ds.power, 1.6, out=ds.peak_bits)
+        if record:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+        bsh.bsh_hough_count(ds, g, status=st, wsum_out=ws_map)
+        if record:
+            e1.record()
+            ev_count.append((e0, e1))
+        top1(ws_map, out_score=s1_score, out_index=s1_index)
+        cs, cp = bsh.bsh_decode_templates(g, s1_index)
+        bsh.bsh_power_stat(ds, g.sky, cs, cp, mode=0, with_counts=True, status=st, out=P)
+        top2(P, out_score=s2_score, out_index=s2_pos)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    st.raise_if_set("warmup")
+    print(f"[bench] warmup done, timing {args.steps} steps", file=sys.stderr, flush=True)
+
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record()
+    for _ in range(args.steps):
+        step(True)
+    t_end.record()
+    torch.cuda.synchronize()
+    st.raise_if_set("timed steps")
+    ms_total = t_start.elapsed_time(t_end)
+    ms_step = ms_total / max(args.steps, 1)
+    count_ms = float(np.mean([a.elapsed_time(b) for a, b in ev_count]))
+    value = ts_per_step / (ms_step / 1e3)
+    achieved = OPS_PER_TS * ts_per_step / (count_ms / 1e3)
+    print(f"[bench] {ms_step:.3f} ms/step, count kernel {count_ms:.3f} ms", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        a_p, per, off, t_asc = O.grid_tables(spec, seg.t_span_mid())
+        n_ap = max(1, min(args.cpu_sample_ap, spec.n_ap))
+        cells = n_ap * spec.n_per
+        sub_off = off[:cells + 1]
+        t0 = time.perf_counter()
+        O.hough_count(seg, w.sky, spec.k0, spec.n_f0, a_p[:n_ap], per, sub_off, t_asc[:sub_off[-1]])
+        dt = time.perf_counter() - t0
+        ts_cpu = int(sub_off[-1]) * spec.n_f0 * seg.n_seg
+        cpu = {"value": ts_cpu / dt, "unit": "template*segments/s", "cores": O.num_threads(),
+               "kind": "oracle",
+               "sample": f"stage-1 count of the first {n_ap} of {spec.n_ap} a_p values (all P, t_asc, f0 "
+                         f"and {seg.n_seg} segments): {ts_cpu:.3e} template*segments in {dt:.1f} s"}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "template*segments/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64/f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "band 200.0-200.1 Hz: 4000 segments (2 detectors x 2000, gapped), 1 sky "
+                        "pixel, 90 f0 x 64 a_p x 32 P x 64 t_asc = 11796480 templates; stage-1 "
+                        "weighted count -> top-10^4 -> stage-2 power -> top-100",
+            "templates": n_t,
+            "segments": seg.n_seg,
+            "template_segments_per_step": ts_per_step,
+            "topk_stage1": k1,
+            "topk_stage2": k2,
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "hough_count_kernel",
+            "achieved": achieved / 1e12,
+            "peak": VALU_PEAK_OPS / 1e12,
+            "unit": "TOP/s",
+            "frac": achieved / VALU_PEAK_OPS,
+            "traffic": None,
+            "count_kernel_ms": count_ms,
+            "ops_per_template_segment": OPS_PER_TS,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -273,7 +273,8 @@ CFG3_MARGINS = (12, 19, 26, 33)
 
 def config3(n_patches: int = 256, bands: Sequence[float] = CFG3_BANDS,
             build_items: Optional[Sequence[int]] = None) -> Workload:
-    """256 one-pixel patches x 4 bands; per-item gapped segment sets of 1500-3000 per detector.
+    """256 one-pixel patches x 4 bands; per-item gapped segment sets of 1500-3000 per detector
+    (each detector fills 70 % of ceil(max count / 0.7) contiguous Tc slots).
 
     Items are ordered band-major (item = band * n_patches + patch).  With
     ``build_items`` only those items get segment data (the others are left
@@ -299,7 +300,9 @@ def config3(n_patches: int = 256, bands: Sequence[float] = CFG3_BANDS,
             segs.append(None)
             continue
         r = np.random.default_rng(seeds[it])
-        t0, det = two_detector_starts(r, tuple(int(c) for c in counts[it]), 2858)
+        # the 70 % duty factor of config 2, with enough Tc slots for the larger detector
+        n_slots = int(math.ceil(max(int(c) for c in counts[it]) / 0.7))
+        t0, det = two_detector_starts(r, tuple(int(c) for c in counts[it]), n_slots)
         w = lognormal_weights(r, t0.size)
         k_lo, n_bins = band_window(grids[bi].k0, 90, CFG3_MARGINS[bi])
         segs.append(_segments(t0, det, w, r, k_lo, n_bins))

@@ -1,0 +1,208 @@
+/*
+ * bsh.h -- C ABI of libbsh.so, the MI355X (gfx950) semi-coherent Hough search for
+ * continuous gravitational waves from neutron stars in circular binary orbits
+ * (Covas & Sintes, "BinarySkyHough", arXiv:1904.04873).
+ *
+ * The search evaluates, for every template theta = (sky n, f0, a_p, P, t_asc) and every
+ * short-FFT segment J, the frequency track of eq:frequencyevoFinal (Sec. II) in the
+ * product form used by eq:hough1 (Sec. IV.B):
+ *
+ *     x_J = f(t_J) Tc = F (1 + v_J.n) (1 - a_p W cos(W (t_J - t_asc))),   F = f0 Tc, W = 2 pi / P
+ *
+ * rounds it to the nearest DFT bin k_J = floor(x_J + 1/2) (bin k <-> frequency k/Tc, Sec. IV.A),
+ * and sums a per-segment quantity along the track: the weighted peak (stage 1, number count
+ * of eq:hough2) or the weighted normalized power (stage 2, eq:hough3).
+ *
+ * Conventions shared by every call
+ *   - Pointers are device pointers unless a field name ends in _host.  The caller allocates
+ *     every buffer and keeps it alive until the stream has finished the call.
+ *   - Every call that launches work is asynchronous on `stream` (a hipStream_t, NULL = the
+ *     null stream) and returns once the work is queued.
+ *   - Return value: BSH_OK or a negative code.  BSH_EINVAL (bad pointer, shape or
+ *     non-finite parameter) and BSH_ERANGE found on the host are reported before anything
+ *     is launched.  BSH_EHIP reports a HIP runtime error; bsh_last_error() gives the text
+ *     (thread-local, valid until the next call on the same thread).
+ *   - `status` (where present) is a device int32 that the caller zeroes and later reads:
+ *     kernels OR in BSH_STATUS_RANGE when a track leaves the staged row [k_lo, k_lo+n_bins)
+ *     (the segment is then skipped, never clamped, and the outputs of that call are not
+ *     meaningful) and BSH_STATUS_MODEL when a track's drift across the f0 band exceeds one
+ *     bin (parameters outside the model's validity), and BSH_STATUS_INPUT when a candidate
+ *     names a sky pixel outside [0, n_sky) (that candidate's outputs are then 0).
+ *   - Template index of the stage-1 grid (f0 fastest):
+ *         idx = ((s * n_bin) + b) * n_f0 + i,   b = tasc_off[ia * n_per + ip] + j
+ *     with s the sky pixel, i the f0 bin (F = k0 + i), ia/ip the a_p/P indices and j the
+ *     t_asc point of that (a_p, P) cell.
+ *   - Candidates (stage 2) are rows of cand_params[n][4] = (F = f0 Tc, a_p in light-seconds,
+ *     P in s, t_asc in s) with a sky pixel cand_sky[n]; they need not lie on the grid.
+ *     Taking F rather than f0 keeps grid templates bit-identical between the two stages.
+ *
+ * No exception crosses this ABI; the library allocates no device memory in any call.
+ */
+#ifndef BSH_H_
+#define BSH_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BSH_OK 0
+#define BSH_EINVAL (-1)
+#define BSH_ERANGE (-2)
+#define BSH_EHIP (-3)
+#define BSH_ENOMEM (-4)
+
+#define BSH_STATUS_RANGE 1
+#define BSH_STATUS_MODEL 2
+#define BSH_STATUS_INPUT 4
+
+#define BSH_MAX_PER 256     /* largest number of orbital periods in one grid */
+#define BSH_MAX_F0 90       /* stage-1 f0 bins per band (a 0.1 Hz band at Tc = 900 s) */
+#define BSH_MAX_WORDS 16    /* longest staged peakgram row: 512 bins */
+
+typedef void* bsh_stream;
+
+/* Per-segment inputs of one work item (Sec. IV.A).  n_seg segments of length t_coh. */
+typedef struct bsh_segments {
+    int64_t n_seg;
+    double t_coh;               /* coherent time Tc (s), > 0 */
+    const double* t_mid;        /* [n_seg] segment mid-times (s), same origin as t_asc */
+    const double* v_over_c;     /* [n_seg][3] detector velocity / c, same frame as the sky vectors */
+    const float* weight;        /* [n_seg] or [n_sky][n_seg] segment weights (eq:weigths) */
+    int32_t weight_per_sky;     /* 1: weight is [n_sky][n_seg] */
+    int32_t n_bins;             /* staged row width, 1 .. 32*BSH_MAX_WORDS */
+    int64_t k_lo;               /* absolute bin of column 0 */
+    const uint32_t* peak_bits;  /* [n_seg][(n_bins+31)/32] peakgram, bit b of word w = column 32w+b;
+                                   NULL for calls that read only power */
+    const float* power;         /* [n_seg][n_bins] normalized power (eq:HoughPower); NULL for
+                                   calls that read only peak_bits */
+    double v_max_host;          /* max |v/c| over the segments, or 0 if unknown (host value;
+                                   enables the host-side window check) */
+} bsh_segments;
+
+/* Stage-1 template grid of one band (Sec. IV.C, resolution and ranges). */
+typedef struct bsh_grid {
+    int32_t n_sky;
+    const double* sky;            /* [n_sky][3] unit vectors */
+    int64_t k0;                   /* first f0 bin: f0_i = (k0 + i) / Tc */
+    int32_t n_f0;                 /* 1 .. BSH_MAX_F0 */
+    int32_t n_ap;
+    int32_t n_per;                /* 1 .. BSH_MAX_PER */
+    const double* a_p;            /* [n_ap] projected semi-major axes (light-seconds) */
+    const double* period;         /* [n_per] orbital periods (s) */
+    const int64_t* tasc_off;      /* [n_ap*n_per+1] prefix offsets of each cell's t_asc points */
+    const double* t_asc;          /* [n_bin] times of ascending node (s) */
+    const double* a_p_host;       /* host copies of the three small tables above */
+    const double* period_host;
+    const int64_t* tasc_off_host;
+} bsh_grid;
+
+/* Numeric ranges from which bsh_grid_build enumerates one band's grid. */
+typedef struct bsh_grid_spec {
+    int64_t k0;
+    int32_t n_f0;
+    double t_coh;
+    double ap_lo, ap_hi;          /* a_p values: lo + i*((hi-lo)/(n-1)), last = hi */
+    int32_t n_ap;
+    double per_lo, per_hi;        /* P values (s), same rule */
+    int32_t n_per;
+    int32_t tasc_fixed;           /* > 0: that many t_asc points in every cell */
+    double tasc_rule_m;           /* else N = clamp(ceil(m * Tc * f_hi * a_p * W), min, max) */
+    int32_t tasc_min, tasc_max;
+} bsh_grid_spec;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int bsh_version(void);
+
+/* Text of the last error on this thread ("" if none). */
+const char* bsh_last_error(void);
+
+/*
+ * Template-bank enumeration for one band (host only; Sec. IV.C):
+ *   f0 on bin centres (delta f = 1/Tc); a_p and P on inclusive uniform lists;
+ *   t_asc_j = t_mid - P/2 + j (P/N) so that t_mid - P/2 <= t_asc < t_mid + P/2;
+ *   N per cell fixed, or from the spacing of eq:binaryres as N = m Tc f_hi a_p W, evaluated
+ *   left to right and clamped (f_hi = (k0 + n_f0)/Tc).
+ * Writes host arrays a_p[n_ap], period[n_per], tasc_off[n_ap*n_per+1] and, if t_asc is not
+ * NULL, t_asc[*n_bin_out] (BSH_ENOMEM if t_asc_cap is too small).  Cells are a_p-major.
+ */
+int bsh_grid_build(const bsh_grid_spec* spec, double t_mid, double* a_p, double* period,
+                   int64_t* tasc_off, double* t_asc, int64_t t_asc_cap, int64_t* n_bin_out);
+
+/*
+ * Peakgram (Sec. IV.A): bits[J][w] bit b = [power[J][32w+b] > rho_th], compared in double
+ * precision; unused high bits of the last word are zero.
+ * power [n_seg][n_bins] float32, bits [n_seg][(n_bins+31)/32] uint32.
+ */
+int bsh_peakgram(const float* power, int64_t n_seg, int32_t n_bins, double rho_th,
+                 uint32_t* bits, bsh_stream stream);
+
+/*
+ * Stage-1 weighted number count over every template of `grid` (Sec. IV.C eq:hough2; the
+ * GPU loop K1 of Sec. IV.B), reading seg->peak_bits.
+ *   wsum_out [n_sky*n_bin*n_f0]: sum_J w_J p_J  (FP32, at least 64 partial sums per template)
+ *   count_out (may be NULL): sum_J p_J (uint32)
+ * Either output may be NULL but not both.  Requires n_per <= BSH_MAX_PER, n_f0 <= BSH_MAX_F0.
+ */
+int bsh_hough_count(const bsh_segments* seg, const bsh_grid* grid, uint32_t* count_out,
+                    float* wsum_out, int32_t* status, bsh_stream stream);
+
+/*
+ * Exact top-k under the total order (score descending, index ascending) (Sec. IV.C
+ * top-lists).  score [n]; index [n] int64 or NULL for 0..n-1 (indices must be distinct).
+ * Writes out_score[k], out_index[k] sorted; if n < k the tail is -inf / -1.
+ * ws / ws_bytes: device workspace of at least bsh_topk_workspace(n, k) bytes.
+ * Scores must not be NaN.  Merging per-item lists is a call with their concatenation.
+ */
+size_t bsh_topk_workspace(int64_t n, int32_t k);
+int bsh_topk(const float* score, const int64_t* index, int64_t n, int32_t k,
+             float* out_score, int64_t* out_index, void* ws, size_t ws_bytes, bsh_stream stream);
+
+/*
+ * Stage-1 template index -> candidate row (sky pixel, F = k0+i, a_p, P, t_asc).
+ * index [n] int64 (entries < 0 give sky -1 and zero parameters); cand_sky [n]; cand_params [n][4].
+ */
+int bsh_decode_templates(const bsh_grid* grid, const int64_t* index, int64_t n,
+                         int32_t* cand_sky, double* cand_params, bsh_stream stream);
+
+/*
+ * Stage-2 statistic on the exact track for n candidates (Sec. IV.C eq:hough3; the GPU
+ * loop K2 of Sec. IV.B).  sky [n_sky][3]; candidates as above; with weight_per_sky the
+ * weight row of the candidate's pixel is used.
+ *   mode 0: P_out[c] = sum_J w_J rho_{J,k_J} (nearest bin, needs seg->power); when
+ *           seg->peak_bits is set, count_out / wsum_out (each may be NULL) get the
+ *           stage-1 count and weighted count of the same track;
+ *   mode 1: P_out[c] = sum_J w_J ((1-a) rho_{J,k'} + a rho_{J,k'+1}), k' = floor(x_J),
+ *           a = x_J - k' (bin-interpolated extension, piecewise linear in the parameters).
+ * P_out may be NULL in mode 0 when only counts are wanted.
+ */
+int bsh_power_stat(const bsh_segments* seg, const double* sky, int32_t n_sky, const int32_t* cand_sky,
+                   const double* cand_params, int64_t n, int32_t mode, float* P_out,
+                   uint32_t* count_out, float* wsum_out, int32_t* status, bsh_stream stream);
+
+/*
+ * Vector-Jacobian product of the mode-1 statistic:
+ *   grad_params[c][q] = grad_P[c] * dP_lin/dtheta_q,  theta = (F, a_p, P, t_asc), FP64.
+ * At an exact integer x the right-hand interval is used.  grad_P may be NULL (all ones).
+ */
+int bsh_power_stat_grad(const bsh_segments* seg, const double* sky, int32_t n_sky,
+                        const int32_t* cand_sky,
+                        const double* cand_params, int64_t n, const double* grad_P,
+                        double* grad_params, int32_t* status, bsh_stream stream);
+
+/*
+ * Absolute bins k_J of each candidate's track: bins_out [n][n_seg] int32.  The same
+ * evaluation as bsh_power_stat; for inspection and for placing injected signals.  No row
+ * is read, so no window applies; a bad sky index gives bins of -1 and BSH_STATUS_INPUT.
+ */
+int bsh_track_bins(const bsh_segments* seg, const double* sky, int32_t n_sky, const int32_t* cand_sky,
+                   const double* cand_params, int64_t n, int32_t* bins_out, int32_t* status,
+                   bsh_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSH_H_ */

@@ -74,7 +74,7 @@ def lib():
         L.orc_power_stat.argtypes = [i64, P, P, P, i32, i64, i32, P, f64, P, i64, P, P, i32,
                                      P, P, P, P]
         L.orc_power_stat.restype = ctypes.c_int
-        L.orc_power_grad.argtypes = [i64, P, P, P, i32, i64, i32, P, P, i64, P, P, P, P]
+        L.orc_power_grad.argtypes = [i64, P, P, P, i32, i64, i32, P, P, i64, P, P, P, P, P]
         L.orc_power_grad.restype = ctypes.c_int
         L.orc_peakgram.argtypes = [i64, i32, P, f64, i32, P]
         L.orc_peakgram.restype = None
@@ -229,8 +229,12 @@ def power_stat(seg, sky, cand_sky, cand, mode: int = 0, rho_th: float = P_PEAK_D
     return P, cnt, nw, nt
 
 
-def power_grad(seg, sky, cand_sky, cand, grad_p=None, weight_per_sky: bool = False):
-    """d P_lin / d(F, a_p, P, t_asc) per candidate, [n, 4] float64 (times grad_p if given)."""
+def power_grad(seg, sky, cand_sky, cand, grad_p=None, weight_per_sky: bool = False,
+               with_abs: bool = False):
+    """d P_lin / d(F, a_p, P, t_asc) per candidate, [n, 4] float64 (times grad_p if given).
+
+    With ``with_abs`` also returns the sums of the absolute per-segment terms, the scale
+    against which a differently ordered summation is compared."""
     t = _c(seg.t_mid, np.float64)
     v = _c(seg.v_over_c, np.float64)
     w = _c(seg.weight, np.float32)
@@ -240,12 +244,13 @@ def power_grad(seg, sky, cand_sky, cand, grad_p=None, weight_per_sky: bool = Fal
     cs = _c(cand_sky, np.int32).reshape(-1)
     n = cand.shape[0]
     g = np.zeros((n, 4), np.float64)
+    a = np.zeros((n, 4), np.float64) if with_abs else None
     gp = None if grad_p is None else _c(grad_p, np.float64)
     rc = lib().orc_power_grad(t.size, _p(t), _p(v), _p(w), int(weight_per_sky), seg.k_lo,
-                              seg.n_bins, _p(pw), _p(sky), n, _p(cs), _p(cand), _p(gp), _p(g))
+                              seg.n_bins, _p(pw), _p(sky), n, _p(cs), _p(cand), _p(gp), _p(g), _p(a))
     if rc != 0:
         raise OracleRangeError("a track left the staged bins")
-    return g
+    return (g, a) if with_abs else g
 
 
 def peakgram(power: np.ndarray, rho_th: float = P_PEAK_DEFAULT_TH) -> np.ndarray:

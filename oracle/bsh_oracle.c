@@ -215,7 +215,7 @@ int orc_power_grad(int64_t n_seg, const double* t_mid, const double* v_over_c,
                    const float* weight, int32_t weight_per_sky,
                    int64_t k_lo, int32_t n_bins, const float* power,
                    const double* sky, int64_t n_cand, const int32_t* cand_sky,
-                   const double* cand, const double* grad_p, double* grad_out)
+                   const double* cand, const double* grad_p, double* grad_out, double* abs_out)
 {
     int err = ORC_OK;
     #pragma omp parallel for schedule(static) reduction(min:err)
@@ -224,6 +224,7 @@ int orc_power_grad(int64_t n_seg, const double* t_mid, const double* v_over_c,
         const double F = th[0], ap = th[1], per = th[2], ta = th[3];
         const float* w = weight + (weight_per_sky ? (int64_t)cand_sky[c] * n_seg : 0);
         double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;   /* sums of |term|, for tolerances */
         for (int64_t J = 0; J < n_seg; ++J) {
             double D = doppler_factor(v_over_c + 3 * J, sky + 3 * cand_sky[c]);
             double W = TWO_PI / per;
@@ -237,16 +238,24 @@ int orc_power_grad(int64_t n_seg, const double* t_mid, const double* v_over_c,
             if (col < 0 || col + 1 >= n_bins) { err = ORC_ERANGE; continue; }
             const float* row = power + J * n_bins;
             double S = (double)w[J] * ((double)row[col + 1] - (double)row[col]);
-            g0 += S * (D * B);
-            g1 += S * (-F * D * W * cp);
-            g2 += S * (F * D * ap * (W / per) * (cp - W * dt * sp));
-            g3 += S * (-F * D * ap * W * W * sp);
+            double t0 = S * (D * B);
+            double t1 = S * (-F * D * W * cp);
+            double t2 = S * (F * D * ap * (W / per) * (cp - W * dt * sp));
+            double t3 = S * (-F * D * ap * W * W * sp);
+            g0 += t0; g1 += t1; g2 += t2; g3 += t3;
+            a0 += fabs(t0); a1 += fabs(t1); a2 += fabs(t2); a3 += fabs(t3);
         }
         const double s = grad_p ? grad_p[c] : 1.0;
         grad_out[4 * c + 0] = s * g0;
         grad_out[4 * c + 1] = s * g1;
         grad_out[4 * c + 2] = s * g2;
         grad_out[4 * c + 3] = s * g3;
+        if (abs_out) {
+            abs_out[4 * c + 0] = fabs(s) * a0;
+            abs_out[4 * c + 1] = fabs(s) * a1;
+            abs_out[4 * c + 2] = fabs(s) * a2;
+            abs_out[4 * c + 3] = fabs(s) * a3;
+        }
     }
     return err;
 }

@@ -1,0 +1,302 @@
+"""Torch-facing binding of libbsh (same names as include/bsh.h).
+
+PyTorch only provides device memory and the current HIP stream; every step of
+the search runs in the library's HIP kernels.  All calls are asynchronous on
+``torch.cuda.current_stream()``; outputs are returned as new tensors unless an
+``out=`` tensor is given.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import _native as N
+from ._native import BshError, check
+
+__all__ = [
+    "BshError", "DeviceSegments", "DeviceGrid", "Status", "bsh_version", "bsh_grid_build",
+    "bsh_peakgram", "bsh_hough_count", "bsh_topk", "bsh_decode_templates", "bsh_power_stat",
+    "bsh_power_stat_grad", "bsh_track_bins",
+]
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _dev(a, dtype, device) -> torch.Tensor:
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=dtype).contiguous()
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dtype)
+
+
+class Status:
+    """A device int32 the kernels OR error bits into; read it after a synchronisation."""
+
+    def __init__(self, device):
+        self.t = torch.zeros(1, dtype=torch.int32, device=device)
+
+    def ptr(self) -> int:
+        return self.t.data_ptr()
+
+    def reset(self) -> None:
+        self.t.zero_()
+
+    def value(self) -> int:
+        return int(self.t.item())
+
+    def raise_if_set(self, where: str = "kernel") -> None:
+        v = self.value()
+        if v:
+            what = []
+            if v & N.STATUS_RANGE:
+                what.append("a track left the staged row")
+            if v & N.STATUS_MODEL:
+                what.append("a track drifted more than one bin across the f0 band")
+            if v & N.STATUS_INPUT:
+                what.append("a candidate names a sky pixel out of range")
+            raise BshError(N.BSH_ERANGE, where, "; ".join(what))
+
+
+@dataclasses.dataclass
+class DeviceSegments:
+    """One work item's per-segment tables on the device plus the C struct that points at them."""
+    t_mid: torch.Tensor
+    v_over_c: torch.Tensor
+    weight: torch.Tensor
+    k_lo: int
+    n_bins: int
+    t_coh: float
+    peak_bits: Optional[torch.Tensor] = None
+    power: Optional[torch.Tensor] = None
+    weight_per_sky: bool = False
+    v_max: float = 0.0
+
+    @classmethod
+    def from_host(cls, seg, device="cuda", with_power: bool = True, rho_th: float = 1.6,
+                  weight=None) -> "DeviceSegments":
+        """Upload a host segment set (fields t_mid, v_over_c, weight, power, k_lo, n_bins, t_coh)
+        and build its peakgram on the device with bsh_peakgram."""
+        w = seg.weight if weight is None else weight
+        power = _dev(seg.power, torch.float32, device)
+        ds = cls(t_mid=_dev(seg.t_mid, torch.float64, device),
+                 v_over_c=_dev(seg.v_over_c, torch.float64, device),
+                 weight=_dev(w, torch.float32, device), k_lo=int(seg.k_lo), n_bins=int(seg.n_bins),
+                 t_coh=float(seg.t_coh), power=power if with_power else None,
+                 weight_per_sky=bool(np.ndim(w) == 2),
+                 v_max=float(np.linalg.norm(np.asarray(seg.v_over_c), axis=1).max()) if seg.n_seg else 0.0)
+        ds.peak_bits = bsh_peakgram(power, rho_th)
+        return ds
+
+    @property
+    def n_seg(self) -> int:
+        return int(self.t_mid.numel())
+
+    def struct(self) -> N.Segments:
+        return N.Segments(n_seg=self.n_seg, t_coh=self.t_coh, t_mid=_ptr(self.t_mid),
+                          v_over_c=_ptr(self.v_over_c), weight=_ptr(self.weight),
+                          weight_per_sky=int(self.weight_per_sky), n_bins=self.n_bins, k_lo=self.k_lo,
+                          peak_bits=_ptr(self.peak_bits), power=_ptr(self.power),
+                          v_max_host=float(self.v_max))
+
+
+@dataclasses.dataclass
+class DeviceGrid:
+    """One band's template grid: device tables, host copies of the small ones, and the C struct."""
+    sky: torch.Tensor
+    k0: int
+    n_f0: int
+    a_p: np.ndarray
+    period: np.ndarray
+    tasc_off: np.ndarray
+    t_asc_dev: torch.Tensor
+    a_p_dev: torch.Tensor
+    period_dev: torch.Tensor
+    tasc_off_dev: torch.Tensor
+
+    @classmethod
+    def build(cls, spec, t_mid: float, sky, device="cuda") -> "DeviceGrid":
+        """Enumerate the grid with bsh_grid_build (host) and upload its tables."""
+        a_p, per, off, t_asc = bsh_grid_build(spec, t_mid)
+        return cls.from_tables(sky, spec.k0, spec.n_f0, a_p, per, off, t_asc, device)
+
+    @classmethod
+    def from_tables(cls, sky, k0, n_f0, a_p, per, off, t_asc, device="cuda") -> "DeviceGrid":
+        a_p = np.ascontiguousarray(a_p, np.float64)
+        per = np.ascontiguousarray(per, np.float64)
+        off = np.ascontiguousarray(off, np.int64)
+        return cls(sky=_dev(sky, torch.float64, device), k0=int(k0), n_f0=int(n_f0), a_p=a_p, period=per,
+                   tasc_off=off, t_asc_dev=_dev(t_asc, torch.float64, device),
+                   a_p_dev=_dev(a_p, torch.float64, device), period_dev=_dev(per, torch.float64, device),
+                   tasc_off_dev=_dev(off, torch.int64, device))
+
+    @property
+    def n_sky(self) -> int:
+        return int(self.sky.shape[0])
+
+    @property
+    def n_bin(self) -> int:
+        return int(self.tasc_off[-1])
+
+    @property
+    def n_templates(self) -> int:
+        return self.n_sky * self.n_bin * self.n_f0
+
+    def struct(self) -> N.Grid:
+        return N.Grid(n_sky=self.n_sky, sky=_ptr(self.sky), k0=self.k0, n_f0=self.n_f0,
+                      n_ap=int(self.a_p.size), n_per=int(self.period.size), a_p=_ptr(self.a_p_dev),
+                      period=_ptr(self.period_dev), tasc_off=_ptr(self.tasc_off_dev),
+                      t_asc=_ptr(self.t_asc_dev),
+                      a_p_host=self.a_p.ctypes.data, period_host=self.period.ctypes.data,
+                      tasc_off_host=self.tasc_off.ctypes.data)
+
+
+# ---------------------------------------------------------------- entry points
+
+def bsh_version() -> int:
+    return int(N.load().bsh_version())
+
+
+def bsh_grid_build(spec, t_mid: float):
+    """Template bank of one band (host): (a_p, period, tasc_off, t_asc) NumPy arrays.
+
+    ``spec`` has the fields of bsh_grid_spec (e.g. a bsh_synth.GridSpec)."""
+    L = N.load()
+    cs = N.GridSpec(k0=int(spec.k0), n_f0=int(spec.n_f0), t_coh=float(spec.t_coh),
+                    ap_lo=float(spec.ap_lo), ap_hi=float(spec.ap_hi), n_ap=int(spec.n_ap),
+                    per_lo=float(spec.per_lo), per_hi=float(spec.per_hi), n_per=int(spec.n_per),
+                    tasc_fixed=int(spec.tasc_fixed), tasc_rule_m=float(spec.tasc_rule_m),
+                    tasc_min=int(spec.tasc_min), tasc_max=int(spec.tasc_max))
+    a_p = np.zeros(spec.n_ap, np.float64)
+    per = np.zeros(spec.n_per, np.float64)
+    off = np.zeros(spec.n_ap * spec.n_per + 1, np.int64)
+    n_bin = ctypes.c_int64(0)
+    check(L.bsh_grid_build(ctypes.byref(cs), float(t_mid), a_p.ctypes.data, per.ctypes.data,
+                           off.ctypes.data, None, 0, ctypes.byref(n_bin)), "bsh_grid_build")
+    t_asc = np.zeros(max(1, n_bin.value), np.float64)
+    check(L.bsh_grid_build(ctypes.byref(cs), float(t_mid), a_p.ctypes.data, per.ctypes.data,
+                           off.ctypes.data, t_asc.ctypes.data, t_asc.size, ctypes.byref(n_bin)),
+          "bsh_grid_build")
+    return a_p, per, off, t_asc[:n_bin.value]
+
+
+def bsh_peakgram(power: torch.Tensor, rho_th: float = 1.6, out: Optional[torch.Tensor] = None):
+    """Bit-packed peakgram [n_seg, ceil(n_bins/32)] int32 (bit patterns of uint32 words)."""
+    assert power.is_cuda and power.dtype == torch.float32 and power.dim() == 2
+    power = power.contiguous()
+    n_seg, n_bins = power.shape
+    nw = (n_bins + 31) // 32
+    if out is None:
+        out = torch.empty((n_seg, nw), dtype=torch.int32, device=power.device)
+    check(N.load().bsh_peakgram(_ptr(power), n_seg, n_bins, float(rho_th), _ptr(out), _stream()),
+          "bsh_peakgram")
+    return out
+
+
+def bsh_hough_count(seg: DeviceSegments, grid: DeviceGrid, with_count: bool = False,
+                    status: Optional[Status] = None, wsum_out=None, count_out=None):
+    """Stage-1 map: (wsum float32 [n_templates], count int32 [n_templates] or None)."""
+    dev = seg.t_mid.device
+    if wsum_out is None:
+        wsum_out = torch.empty(grid.n_templates, dtype=torch.float32, device=dev)
+    if with_count and count_out is None:
+        count_out = torch.empty(grid.n_templates, dtype=torch.int32, device=dev)
+    s_c, g_c = seg.struct(), grid.struct()
+    check(N.load().bsh_hough_count(ctypes.byref(s_c), ctypes.byref(g_c), _ptr(count_out),
+                                   _ptr(wsum_out), status.ptr() if status else None, _stream()),
+          "bsh_hough_count")
+    return wsum_out, (count_out if with_count else None)
+
+
+class TopK:
+    """Reusable workspace for bsh_topk."""
+
+    def __init__(self, n: int, k: int, device="cuda"):
+        self.n, self.k = int(n), int(k)
+        nbytes = int(N.load().bsh_topk_workspace(self.n, self.k))
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+    def __call__(self, score: torch.Tensor, index: Optional[torch.Tensor] = None,
+                 out_score=None, out_index=None):
+        n = int(score.numel())
+        if n > self.n:
+            raise ValueError("more entries than the workspace was sized for")
+        dev = score.device
+        if out_score is None:
+            out_score = torch.empty(self.k, dtype=torch.float32, device=dev)
+        if out_index is None:
+            out_index = torch.empty(self.k, dtype=torch.int64, device=dev)
+        check(N.load().bsh_topk(_ptr(score), _ptr(index), n, self.k, _ptr(out_score), _ptr(out_index),
+                                _ptr(self.ws), self.ws.numel(), _stream()), "bsh_topk")
+        return out_score, out_index
+
+
+def bsh_topk(score: torch.Tensor, k: int, index: Optional[torch.Tensor] = None):
+    """Exact top-k under (score desc, index asc): (scores float32 [k], indices int64 [k])."""
+    assert score.dtype == torch.float32 and score.is_contiguous()
+    if index is not None:
+        assert index.dtype == torch.int64 and index.numel() == score.numel()
+    return TopK(score.numel(), k, score.device)(score, index)
+
+
+def bsh_decode_templates(grid: DeviceGrid, index: torch.Tensor):
+    """Stage-1 template indices -> (cand_sky int32 [n], cand_params float64 [n, 4])."""
+    n = int(index.numel())
+    dev = index.device
+    cs = torch.empty(n, dtype=torch.int32, device=dev)
+    cp = torch.empty((n, 4), dtype=torch.float64, device=dev)
+    g_c = grid.struct()
+    check(N.load().bsh_decode_templates(ctypes.byref(g_c), _ptr(index.contiguous()), n, _ptr(cs),
+                                        _ptr(cp), _stream()), "bsh_decode_templates")
+    return cs, cp
+
+
+def bsh_power_stat(seg: DeviceSegments, sky: torch.Tensor, cand_sky: torch.Tensor,
+                   cand_params: torch.Tensor, mode: int = 0, with_power: bool = True,
+                   with_counts: bool = False, status: Optional[Status] = None, out=None):
+    """Stage-2 statistic: P float32 [n] (or None), and (count int32, wsum float32) if with_counts."""
+    n = int(cand_sky.numel())
+    dev = cand_sky.device
+    P = (out if out is not None else torch.empty(n, dtype=torch.float32, device=dev)) if with_power else None
+    cnt = torch.empty(n, dtype=torch.int32, device=dev) if with_counts else None
+    ws = torch.empty(n, dtype=torch.float32, device=dev) if with_counts else None
+    s_c = seg.struct()
+    check(N.load().bsh_power_stat(ctypes.byref(s_c), _ptr(sky), int(sky.shape[0]), _ptr(cand_sky),
+                                  _ptr(cand_params), n, int(mode), _ptr(P), _ptr(cnt), _ptr(ws),
+                                  status.ptr() if status else None, _stream()), "bsh_power_stat")
+    return (P, cnt, ws) if with_counts else P
+
+
+def bsh_power_stat_grad(seg: DeviceSegments, sky: torch.Tensor, cand_sky: torch.Tensor,
+                        cand_params: torch.Tensor, grad_P: Optional[torch.Tensor] = None,
+                        status: Optional[Status] = None):
+    """d P_lin / d(F, a_p, P, t_asc), scaled by grad_P: float64 [n, 4]."""
+    n = int(cand_sky.numel())
+    out = torch.empty((n, 4), dtype=torch.float64, device=cand_sky.device)
+    gp = None if grad_P is None else grad_P.to(torch.float64).contiguous()
+    s_c = seg.struct()
+    check(N.load().bsh_power_stat_grad(ctypes.byref(s_c), _ptr(sky), int(sky.shape[0]), _ptr(cand_sky),
+                                       _ptr(cand_params), n, _ptr(gp), _ptr(out),
+                                       status.ptr() if status else None, _stream()),
+          "bsh_power_stat_grad")
+    return out
+
+
+def bsh_track_bins(seg: DeviceSegments, sky: torch.Tensor, cand_sky: torch.Tensor,
+                   cand_params: torch.Tensor, status: Optional[Status] = None):
+    """Absolute bins of each candidate's track: int32 [n, n_seg]."""
+    n = int(cand_sky.numel())
+    out = torch.empty((n, seg.n_seg), dtype=torch.int32, device=cand_sky.device)
+    s_c = seg.struct()
+    check(N.load().bsh_track_bins(ctypes.byref(s_c), _ptr(sky), int(sky.shape[0]), _ptr(cand_sky),
+                                  _ptr(cand_params), n, _ptr(out), status.ptr() if status else None,
+                                  _stream()), "bsh_track_bins")
+    return out

@@ -1,0 +1,112 @@
+// Internal helpers of libbsh: error state, argument checks and the device-side
+// evaluation of the frequency track.  Not part of the public ABI (include/bsh.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/bsh.h"
+
+namespace bsh {
+
+// Nearest double to 2 pi; the orbital angular frequency is W = TWO_PI / P.
+constexpr double kTwoPi = 6.283185307179586;
+
+// ---------------------------------------------------------------- host error state
+
+void set_error(const char* fmt, ...);
+void clear_error();
+
+inline int fail_inval(const char* what)
+{
+    set_error("invalid argument: %s", what);
+    return BSH_EINVAL;
+}
+
+inline int check_launch(const char* where)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error("%s: %s", where, hipGetErrorString(e));
+        return BSH_EHIP;
+    }
+    return BSH_OK;
+}
+
+inline int words_for(int32_t n_bins) { return (n_bins + 31) / 32; }
+
+// Host-side validation of a segment table; `need_bits` / `need_power` select the rows.
+int check_segments(const bsh_segments* seg, bool need_bits, bool need_power);
+// Host-side validation of a grid (small host tables are read).
+int check_grid(const bsh_grid* g);
+// Conservative host check that every stage-1 track stays inside the staged row.
+int check_window(const bsh_segments* seg, const bsh_grid* g);
+
+// ---------------------------------------------------------------- device track
+
+// Doppler factor D = 1 + v.n, one fixed operation order (no contraction: the library is
+// built with -ffp-contract=off).
+__device__ __forceinline__ double doppler_factor(const double* v, double nx, double ny, double nz)
+{
+    double d = v[0] * nx + v[1] * ny;
+    d = d + v[2] * nz;
+    return 1.0 + d;
+}
+
+// A candidate template (F = f0 Tc, a_p, P, t_asc) with the quantities every segment reuses:
+// W = 2 pi / P, a_p W and cos / sin of W t_asc.
+struct Cand {
+    double F, ap, P, ta, W, apW, cb, sb;
+};
+
+__device__ __forceinline__ Cand load_cand(const double* cand)
+{
+    Cand c;
+    c.F = cand[0];
+    c.ap = cand[1];
+    c.P = cand[2];
+    c.ta = cand[3];
+    c.W = kTwoPi / c.P;
+    c.apW = c.ap * c.W;
+    sincos(c.W * c.ta, &c.sb, &c.cb);
+    return c;
+}
+
+// cos and sin of the orbital phase W (t - t_asc), from cos / sin of W t and W t_asc by the
+// angle-difference formulas.  Every kernel evaluates the phase this way (the stage-1 kernel
+// with cos / sin of W t staged once per block), so all of them select identical bins.
+__device__ __forceinline__ void orbit_phase(double ct, double st, const Cand& c, double& cphi,
+                                            double& sphi)
+{
+    cphi = fma(ct, c.cb, st * c.sb);
+    sphi = fma(st, c.cb, -(ct * c.sb));
+}
+
+// The track x = F D (1 - a_p W cos phi)  (eq:frequencyevoFinal, product form).
+__device__ __forceinline__ double track_x(double F, double D, double apW, double cphi)
+{
+    return F * (D * (1.0 - apW * cphi));
+}
+
+// Nearest-bin rounding of a track value: floor(x + 1/2).
+__device__ __forceinline__ double nearest_bin(double x) { return floor(x + 0.5); }
+
+__device__ __forceinline__ void raise_status(int32_t* status, int32_t bit)
+{
+    if (status) atomicOr(status, bit);
+}
+
+// Wave64 sum (all lanes end with the total).
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+}  // namespace bsh

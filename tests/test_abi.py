@@ -1,0 +1,145 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared symbol, enumerates
+the template bank exactly like the oracle, and rejects bad arguments before any launch."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import bsh_synth as S
+import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_1904_04873_amd import _native
+    try:
+        return _native.load()
+    except ImportError as e:
+        pytest.fail(f"libbsh.so must be built before the tests run: {e}")
+
+
+def _declared_functions():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names += re.findall(r"\b(bsh_\w+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    names = _declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    from paper_1904_04873_amd import _native
+    assert sorted(_native.SIGNATURES) == names
+
+
+def test_version():
+    assert _lib().bsh_version() == 10000
+
+
+@pytest.mark.parametrize("cfg", ["cfg1", "cfg2", "cfg3", "cfg5"])
+def test_grid_build_equals_oracle_bitwise(cfg):
+    from paper_1904_04873_amd import bsh
+    grids = {"cfg1": lambda: S.config1().grids, "cfg2": lambda: S.config2(n_per_det=5).grids,
+             "cfg3": lambda: S.config3(build_items=[]).grids,
+             "cfg5": lambda: S.config5(n_pixels=1, n_per_det=5).grids}[cfg]()
+    for g in grids:
+        t_mid = 1.0e6 + 0.37
+        a = bsh.bsh_grid_build(g, t_mid)
+        b = O.grid_tables(g, t_mid)
+        for x, y in zip(a, b):
+            assert x.dtype == y.dtype and np.array_equal(x, y)
+
+
+def test_grid_build_rejects_small_capacity():
+    from paper_1904_04873_amd import _native as N
+    L = _lib()
+    g = S.config1().grids[0]
+    cs = N.GridSpec(k0=g.k0, n_f0=g.n_f0, t_coh=900.0, ap_lo=g.ap_lo, ap_hi=g.ap_hi, n_ap=g.n_ap,
+                    per_lo=g.per_lo, per_hi=g.per_hi, n_per=g.n_per, tasc_fixed=8, tasc_rule_m=60.0,
+                    tasc_min=4, tasc_max=256)
+    a = np.zeros(8); p = np.zeros(8); off = np.zeros(65, np.int64); t = np.zeros(10)
+    nb = ctypes.c_int64(0)
+    rc = L.bsh_grid_build(ctypes.byref(cs), 0.0, a.ctypes.data, p.ctypes.data, off.ctypes.data,
+                          t.ctypes.data, 10, ctypes.byref(nb))
+    assert rc == N.BSH_ENOMEM
+    assert b"capacity" in L.bsh_last_error()
+
+
+def _structs(n_bins=114, k_lo=90000 - 12, v_max=0.0, n_f0=90, n_per=8):
+    from paper_1904_04873_amd import _native as N
+    g = S.config1().grids[0]
+    a_p, per, off, t_asc = O.grid_tables(g, 5e6)
+    fake = 0x1000   # never dereferenced: every case below fails on the host
+    seg = N.Segments(n_seg=64, t_coh=900.0, t_mid=fake, v_over_c=fake, weight=fake, weight_per_sky=0,
+                     n_bins=n_bins, k_lo=k_lo, peak_bits=fake, power=fake, v_max_host=v_max)
+    keep = (a_p, per, off)
+    grid = N.Grid(n_sky=1, sky=fake, k0=90000, n_f0=n_f0, n_ap=8, n_per=n_per, a_p=fake, period=fake,
+                  tasc_off=fake, t_asc=fake, a_p_host=a_p.ctypes.data, period_host=per.ctypes.data,
+                  tasc_off_host=off.ctypes.data)
+    return seg, grid, keep
+
+
+def test_hough_count_rejects_bad_arguments_on_host():
+    from paper_1904_04873_amd import _native as N
+    L = _lib()
+    seg, grid, keep = _structs()
+    fake = ctypes.c_void_p(0x2000)
+    assert L.bsh_hough_count(None, ctypes.byref(grid), fake, fake, None, None) == N.BSH_EINVAL
+    assert L.bsh_hough_count(ctypes.byref(seg), None, fake, fake, None, None) == N.BSH_EINVAL
+    assert L.bsh_hough_count(ctypes.byref(seg), ctypes.byref(grid), None, None, None, None) == N.BSH_EINVAL
+    seg2, grid2, keep2 = _structs(n_bins=0)
+    assert L.bsh_hough_count(ctypes.byref(seg2), ctypes.byref(grid2), fake, fake, None, None) == N.BSH_EINVAL
+    seg3, grid3, keep3 = _structs(n_f0=91)
+    assert L.bsh_hough_count(ctypes.byref(seg3), ctypes.byref(grid3), fake, fake, None, None) == N.BSH_EINVAL
+    seg4, grid4, keep4 = _structs(n_per=300)
+    assert L.bsh_hough_count(ctypes.byref(seg4), ctypes.byref(grid4), fake, fake, None, None) == N.BSH_EINVAL
+    seg.t_coh = float("nan")
+    assert L.bsh_hough_count(ctypes.byref(seg), ctypes.byref(grid), fake, fake, None, None) == N.BSH_EINVAL
+    assert b"t_coh" in L.bsh_last_error()
+
+
+def test_hough_count_host_window_check():
+    """With |v|max known the host refuses a staged row narrower than the tracks' bound."""
+    from paper_1904_04873_amd import _native as N
+    L = _lib()
+    fake = ctypes.c_void_p(0x2000)
+    seg, grid, keep = _structs(n_bins=100, k_lo=90000 - 5, v_max=1.015e-4)
+    assert L.bsh_hough_count(ctypes.byref(seg), ctypes.byref(grid), fake, fake, None, None) == N.BSH_ERANGE
+    assert b"does not cover" in L.bsh_last_error()
+
+
+def test_other_entry_points_reject_bad_arguments():
+    from paper_1904_04873_amd import _native as N
+    L = _lib()
+    seg, grid, keep = _structs()
+    fake = ctypes.c_void_p(0x2000)
+    assert L.bsh_power_stat(ctypes.byref(seg), fake, 1, fake, fake, 10, 2, fake, None, None, None, None) == N.BSH_EINVAL
+    assert L.bsh_power_stat(ctypes.byref(seg), fake, 1, fake, fake, 10, 1, fake, fake, None, None, None) == N.BSH_EINVAL
+    assert L.bsh_power_stat(ctypes.byref(seg), fake, 0, fake, fake, 10, 0, fake, None, None, None, None) == N.BSH_EINVAL
+    assert L.bsh_power_stat_grad(ctypes.byref(seg), fake, 1, fake, fake, -1, None, fake, None, None) == N.BSH_EINVAL
+    assert L.bsh_track_bins(ctypes.byref(seg), None, 1, fake, fake, 3, fake, None, None) == N.BSH_EINVAL
+    assert L.bsh_peakgram(fake, 10, 0, 1.6, fake, None) == N.BSH_EINVAL
+    assert L.bsh_peakgram(fake, 10, 5, float("nan"), fake, None) == N.BSH_EINVAL
+    assert L.bsh_topk(fake, None, 100, 10, fake, fake, fake, 16, None) == N.BSH_ENOMEM
+    assert L.bsh_topk(fake, None, -1, 10, fake, fake, fake, 1 << 20, None) == N.BSH_EINVAL
+    assert L.bsh_decode_templates(None, fake, 3, fake, fake, None) == N.BSH_EINVAL
+    # empty work is a successful no-op without touching any pointer
+    assert L.bsh_topk(None, None, 0, 0, None, None, None, 0, None) == N.BSH_OK
+    assert L.bsh_power_stat(ctypes.byref(seg), fake, 1, fake, fake, 0, 0, fake, None, None, None, None) == N.BSH_OK
+
+
+def test_topk_workspace_grows_with_n_and_k():
+    L = _lib()
+    a = L.bsh_topk_workspace(1000, 10)
+    b = L.bsh_topk_workspace(100000, 10)
+    c = L.bsh_topk_workspace(1000, 5000)
+    assert b > a and c > a and a >= 8 * 1000

@@ -1,0 +1,433 @@
+"""GPU parity of every entry point against the CPU oracle, through the C ABI.
+
+Acceptance (floating point decides the integers only at near-ties):
+* bins, unweighted counts and peakgram bits: identical, except that a template may differ by
+  at most its number of oracle-flagged near-tie segments (|x - half-integer| < 1e-9 bins);
+* weighted counts and powers: within 1e-5 relative of the FP64 oracle (plus the near-tie
+  segments' weight);
+* gradients: |g_gpu - g_cpu| <= 1e-5 * sum_J |term_J|;
+* top-k: identical for exactly representable scores; otherwise every entry of the symmetric
+  difference has an oracle score within 1e-5 relative of the oracle's k-th score.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import bsh_synth as S
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch  # noqa: F401
+    from paper_1904_04873_amd import bsh
+    return bsh
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _grid_pair(B, spec, seg_host, sky):
+    """GPU grid (bsh_grid_build) and oracle grid (its own enumeration); asserted identical."""
+    t_mid = seg_host.t_span_mid()
+    g = B.DeviceGrid.build(spec, t_mid, sky)
+    o = O.grid_tables(spec, t_mid)
+    assert np.array_equal(g.tasc_off, o[2]) and np.array_equal(_np(g.t_asc_dev), o[3])
+    return g, o
+
+
+def _check_counts(cnt_g, ws_g, cnt_o, nw_o, nt_o, ntw_o):
+    cnt_g = cnt_g.astype(np.int64)
+    diff = np.abs(cnt_g - cnt_o.astype(np.int64))
+    assert np.all(diff <= nt_o), f"count mismatch outside near-ties at {np.nonzero(diff > nt_o)[0][:10]}"
+    err = np.abs(ws_g.astype(np.float64) - nw_o)
+    assert np.all(err <= REL * np.abs(nw_o) + ntw_o + 1e-30), f"max rel err {np.max(err / np.maximum(nw_o, 1e-30))}"
+
+
+def _status(B):
+    import torch
+    return B.Status(torch.device("cuda"))
+
+
+# ---------------------------------------------------------------- peakgram
+
+@pytest.mark.parametrize("n_bins", [1, 31, 32, 33, 134, 512])
+def test_peakgram_bit_exact(B, n_bins):
+    import torch
+    _say(f"peakgram n_bins={n_bins}")
+    rng = np.random.default_rng(n_bins)
+    pw = rng.exponential(1.0, (257, n_bins)).astype(np.float32)
+    pw.flat[::7] = np.float32(1.6)
+    pw.flat[3::11] = np.nextafter(np.float32(1.6), np.float32(0))
+    bits = _np(B.bsh_peakgram(torch.from_numpy(pw).cuda(), 1.6)).view(np.uint32)
+    assert np.array_equal(bits, O.peakgram(pw, 1.6))
+
+
+# ---------------------------------------------------------------- stage-1 count
+
+def _run_count(B, seg_host, spec, sky, with_count=True, weight=None):
+    import torch
+    ds = B.DeviceSegments.from_host(seg_host, weight=weight)
+    g, o = _grid_pair(B, spec, seg_host, sky)
+    st = _status(B)
+    ws, cnt = B.bsh_hough_count(ds, g, with_count=with_count, status=st)
+    torch.cuda.synchronize()
+    st.raise_if_set("bsh_hough_count")
+    return ds, g, o, _np(ws), (_np(cnt).view(np.uint32) if cnt is not None else None)
+
+
+def test_count_config1_full_map(B):
+    _say("count cfg1 full map")
+    w = S.config1()
+    seg, spec = w.segments[0], w.grids[0]
+    ds, g, o, ws, cnt = _run_count(B, seg, spec, w.sky)
+    cnt_o, nw_o, nt_o, ntw_o = O.hough_count(seg, w.sky, spec.k0, spec.n_f0, *o)
+    _check_counts(cnt, ws, cnt_o, nw_o, nt_o, ntw_o)
+    if nt_o.sum() == 0:
+        assert np.array_equal(cnt, cnt_o)
+    assert np.array_equal(ws, cnt.astype(np.float32))      # unit weights: n_w == count exactly
+
+
+def test_count_weighted_several_tiles(B):
+    """4 x 100 gapped segments, 8 a_p x 4 P x 64 t_asc: 8 tiles per pixel, full map vs oracle."""
+    _say("count weighted 400 seg")
+    w = S.config2(n_per_det=200)
+    seg = w.segments[0]
+    spec = S.GridSpec(k0=180000, n_f0=90, ap_lo=0.01, ap_hi=3.0, n_ap=8, per_lo=15 * S.DAY,
+                      per_hi=45 * S.DAY, n_per=4, tasc_fixed=64)
+    ds, g, o, ws, cnt = _run_count(B, seg, spec, w.sky)
+    cnt_o, nw_o, nt_o, ntw_o = O.hough_count(seg, w.sky, spec.k0, spec.n_f0, *o)
+    _check_counts(cnt, ws, cnt_o, nw_o, nt_o, ntw_o)
+    # the count-free kernel gives the same weighted sums
+    import torch
+    ws2, _ = B.bsh_hough_count(ds, g, with_count=False)
+    torch.cuda.synchronize()
+    assert np.array_equal(_np(ws2), ws)
+
+
+def test_count_ragged_rule_grid_multisky_per_sky_weights(B):
+    """Uneven t_asc counts (partial tiles), 3 pixels with their own weights, n_f0 = 37, 300 segments."""
+    _say("count ragged multisky")
+    rng = np.random.default_rng(4)
+    base = S.tiny_segments(n_seg=300, k0=150000, n_f0=37, margin=19, seed=21, span_days=200)
+    spec = S.GridSpec(k0=150000, n_f0=37, ap_lo=0.05, ap_hi=3.25, n_ap=5, per_lo=15 * S.DAY,
+                      per_hi=45 * S.DAY, n_per=3)
+    sky = S.fibonacci_sphere(3)
+    wps = np.exp(0.3 * rng.standard_normal((3, 300))).astype(np.float32)
+    ds, g, o, ws, cnt = _run_count(B, base, spec, sky, weight=wps)
+    assert ds.weight_per_sky
+    assert (np.diff(g.tasc_off) != np.diff(g.tasc_off)[0]).any()
+    seg_o = S.Segments(t_mid=base.t_mid, v_over_c=base.v_over_c, weight=wps, power=base.power,
+                       k_lo=base.k_lo, n_bins=base.n_bins)
+    cnt_o, nw_o, nt_o, ntw_o = O.hough_count(seg_o, sky, spec.k0, spec.n_f0, *o, weight_per_sky=True)
+    _check_counts(cnt, ws, cnt_o, nw_o, nt_o, ntw_o)
+
+
+def test_count_config2_full_size_sampled(B):
+    """The full 11.8M-template map at 4000 segments; 3000 sampled templates plus the top 500
+    recomputed one by one by the oracle."""
+    import torch
+    _say("count cfg2 full size")
+    w = S.config2()
+    seg, spec = w.segments[0], w.grids[0]
+    ds, g, o, ws, cnt = _run_count(B, seg, spec, w.sky)
+    assert ws.size == 11796480
+    rng = np.random.default_rng(7)
+    top = np.argsort(-ws, kind="stable")[:500]
+    idx = np.concatenate([rng.integers(0, ws.size, 3000), top])
+    s, b, i, ia, ip = O.decode_index(idx, g.n_bin, 90, o[2], spec.n_per)
+    cand = np.stack([(spec.k0 + i).astype(np.float64), o[0][ia], o[1][ip], o[3][b]], axis=1)
+    _, c_o, nw_o, nt_o = O.power_stat(seg, w.sky, s.astype(np.int32), cand, mode=0)
+    ntw_o = nt_o * float(seg.weight.max())
+    _check_counts(cnt[idx], ws[idx], c_o, nw_o, nt_o, ntw_o)
+    # mean count under noise ~ N exp(-1.6) (statistical sanity at full size)
+    assert abs(cnt.mean() / 4000 - math.exp(-1.6)) < 0.01
+
+
+def test_count_edge_cases(B):
+    import torch
+    _say("count edge cases")
+    # one segment
+    seg1 = S.tiny_segments(n_seg=1, k0=90000, n_f0=90, margin=12, seed=3)
+    spec = S.GridSpec(k0=90000, n_f0=90, ap_lo=0.01, ap_hi=3.0, n_ap=3, per_lo=15 * S.DAY,
+                      per_hi=45 * S.DAY, n_per=2, tasc_fixed=5)
+    _, g, o, ws, cnt = _run_count(B, seg1, spec, S.fixed_pixel())
+    c_o, nw_o, nt_o, ntw_o = O.hough_count(seg1, S.fixed_pixel(), 90000, 90, *o)
+    _check_counts(cnt, ws, c_o, nw_o, nt_o, ntw_o)
+    # no motion, no orbit: column popcounts
+    seg0 = S.tiny_segments(n_seg=77, k0=90000, n_f0=90, margin=12, seed=4)
+    seg0.v_over_c[:] = 0.0
+    spec0 = S.GridSpec(k0=90000, n_f0=90, ap_lo=0.0, ap_hi=0.0, n_ap=1, per_lo=20 * S.DAY,
+                       per_hi=30 * S.DAY, n_per=2, tasc_fixed=3)
+    _, g, o, ws, cnt = _run_count(B, seg0, spec0, S.fixed_pixel())
+    col = (seg0.power.astype(np.float64) > 1.6).sum(axis=0)[12:102]
+    assert np.array_equal(cnt.reshape(-1, 90), np.tile(col, (6, 1)))
+    # zero segments: all zeros
+    seg_e = S.Segments(t_mid=np.zeros(0), v_over_c=np.zeros((0, 3)), weight=np.zeros(0, np.float32),
+                       power=np.zeros((0, 114), np.float32), k_lo=90000 - 12, n_bins=114)
+    ds = B.DeviceSegments(t_mid=torch.zeros(0, dtype=torch.float64, device="cuda"),
+                          v_over_c=torch.zeros((0, 3), dtype=torch.float64, device="cuda"),
+                          weight=torch.zeros(0, dtype=torch.float32, device="cuda"), k_lo=seg_e.k_lo,
+                          n_bins=114, t_coh=900.0,
+                          peak_bits=torch.zeros((0, 4), dtype=torch.int32, device="cuda"))
+    g0, _ = _grid_pair(B, spec, seg1, S.fixed_pixel())
+    ws, cnt = B.bsh_hough_count(ds, g0, with_count=True)
+    torch.cuda.synchronize()
+    assert float(ws.abs().sum()) == 0.0 and int(cnt.sum()) == 0
+
+
+def test_count_noiseless_injection_full_weight(B):
+    import torch
+    _say("count noiseless injection")
+    w = S.config2(n_per_det=150)
+    seg = w.segments[0]
+    spec = S.GridSpec(k0=180000, n_f0=90, ap_lo=0.01, ap_hi=3.0, n_ap=4, per_lo=15 * S.DAY,
+                      per_hi=45 * S.DAY, n_per=4, tasc_fixed=16)
+    o = O.grid_tables(spec, seg.t_span_mid())
+    b_true, i_true = 100, 33
+    cell = np.searchsorted(o[2], b_true, side="right") - 1
+    cand = np.array([[180000 + i_true, o[0][cell // 4], o[1][cell % 4], o[3][b_true]]])
+    _, k = O.track(seg, w.sky, [0], cand)
+    seg.power[:] = 0.0
+    seg.power[np.arange(seg.n_seg), k[0] - seg.k_lo] = 2.0
+    _, g, o2, ws, cnt = _run_count(B, seg, spec, w.sky)
+    idx = b_true * 90 + i_true
+    assert cnt[idx] == seg.n_seg
+    assert ws[idx] == pytest.approx(float(seg.weight.astype(np.float64).sum()), rel=REL)
+    assert int(np.argmax(ws)) == idx
+
+
+def test_count_window_violation_sets_status(B):
+    """A row too narrow for the tracks (host bound unknown): the kernel skips, flags RANGE, no fault."""
+    import torch
+    _say("count window status")
+    seg = S.tiny_segments(n_seg=40, k0=90000, n_f0=90, margin=2, seed=5)
+    spec = S.GridSpec(k0=90000, n_f0=90, ap_lo=2.0, ap_hi=3.0, n_ap=2, per_lo=15 * S.DAY,
+                      per_hi=20 * S.DAY, n_per=2, tasc_fixed=4)
+    ds = B.DeviceSegments.from_host(seg)
+    ds.v_max = 0.0      # skip the host check so the device flag is exercised
+    g, _ = _grid_pair(B, spec, seg, S.fixed_pixel())
+    st = _status(B)
+    B.bsh_hough_count(ds, g, status=st)
+    torch.cuda.synchronize()
+    assert st.value() & 1
+    with pytest.raises(B.BshError):
+        st.raise_if_set()
+    # with |v|max given the host refuses before launching
+    ds.v_max = 1.015e-4
+    with pytest.raises(B.BshError):
+        B.bsh_hough_count(ds, g)
+
+
+def test_count_deterministic(B):
+    import torch
+    _say("count determinism")
+    w = S.config2(n_per_det=300)
+    seg = w.segments[0]
+    spec = S.GridSpec(k0=180000, n_f0=90, ap_lo=0.01, ap_hi=3.0, n_ap=16, per_lo=15 * S.DAY,
+                      per_hi=45 * S.DAY, n_per=4, tasc_fixed=64)
+    ds = B.DeviceSegments.from_host(seg)
+    g, _ = _grid_pair(B, spec, seg, w.sky)
+    a, ca = B.bsh_hough_count(ds, g, with_count=True)
+    b, cb = B.bsh_hough_count(ds, g, with_count=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(ca, cb)
+
+
+# ---------------------------------------------------------------- top-k
+
+def _topk_ref(score, k, index=None):
+    return O.topk(score, k, index)
+
+
+@pytest.mark.parametrize("n,k,kind", [(1, 1, "float"), (5, 10, "float"), (1000, 1, "int"),
+                                      (46080, 100, "int"), (200000, 10000, "int"),
+                                      (300001, 777, "float"), (100000, 5000, "const")])
+def test_topk_exact(B, n, k, kind):
+    import torch
+    _say(f"topk n={n} k={k} {kind}")
+    rng = np.random.default_rng(n + k)
+    if kind == "int":
+        sc = rng.integers(0, 30, n).astype(np.float32)
+    elif kind == "const":
+        sc = np.full(n, 3.5, np.float32)
+    else:
+        sc = rng.standard_normal(n).astype(np.float32)
+        sc[::13] = 0.0
+        sc[1::17] = -0.0
+    vs, ix = B.bsh_topk(torch.from_numpy(sc).cuda(), k)
+    torch.cuda.synchronize()
+    rv, ri = _topk_ref(sc, k)
+    kk = min(n, k)
+    assert np.array_equal(_np(ix)[:kk], ri)
+    assert np.array_equal(_np(vs)[:kk], rv.astype(np.float32))
+    if k > n:
+        assert np.all(_np(ix)[n:] == -1) and np.all(np.isneginf(_np(vs)[n:]))
+
+
+def test_topk_with_index_array_merges_lists(B):
+    """Merging per-item lists: top-k of a concatenation with explicit (large) indices."""
+    import torch
+    _say("topk merge")
+    rng = np.random.default_rng(1)
+    parts = []
+    for item in range(6):
+        sc = rng.integers(0, 50, 3000).astype(np.float32)
+        idx = (np.int64(item) << 40) | rng.permutation(10**6)[:3000].astype(np.int64)
+        parts.append((sc, idx))
+    allsc = np.concatenate([p[0] for p in parts])
+    allix = np.concatenate([p[1] for p in parts])
+    vs, ix = B.bsh_topk(torch.from_numpy(allsc).cuda(), 1234, torch.from_numpy(allix).cuda())
+    # merge of per-part top-k equals top-k of the union
+    sub_s, sub_i = [], []
+    for sc, idx in parts:
+        a, b = B.bsh_topk(torch.from_numpy(sc).cuda(), 1234, torch.from_numpy(idx).cuda())
+        sub_s.append(a); sub_i.append(b)
+    vs2, ix2 = B.bsh_topk(torch.cat(sub_s), 1234, torch.cat(sub_i))
+    torch.cuda.synchronize()
+    rv, ri = _topk_ref(allsc, 1234, allix)
+    assert np.array_equal(_np(ix), ri) and np.array_equal(_np(vs), rv)
+    assert np.array_equal(_np(ix2), ri)
+
+
+# ---------------------------------------------------------------- stage 2
+
+def _cands(seg, n, k0, seed, n_sky=1, spread=89.0):
+    rng = np.random.default_rng(seed)
+    cand = np.stack([k0 + rng.uniform(0, spread, n), rng.uniform(0.01, 3, n),
+                     rng.uniform(15, 45, n) * S.DAY, rng.uniform(0, 3e6, n)], axis=1)
+    return cand, rng.integers(0, n_sky, n).astype(np.int32)
+
+
+def _dev_cands(cand, cs):
+    import torch
+    return (torch.from_numpy(cs).cuda(), torch.from_numpy(np.ascontiguousarray(cand)).cuda())
+
+
+def test_decode_templates_matches_oracle(B):
+    import torch
+    _say("decode")
+    w = S.config3(build_items=[0])
+    seg = w.segments[0]
+    spec = w.grids[0]
+    sky = S.fibonacci_sphere(4)
+    g, o = _grid_pair(B, spec, seg, sky)
+    rng = np.random.default_rng(2)
+    idx = rng.integers(0, g.n_templates, 5000)
+    idx[:3] = [0, g.n_templates - 1, -5]
+    cs, cp = B.bsh_decode_templates(g, torch.from_numpy(idx).cuda())
+    torch.cuda.synchronize()
+    s, b, i, ia, ip = O.decode_index(idx[3:], g.n_bin, spec.n_f0, o[2], spec.n_per)
+    assert np.array_equal(_np(cs)[3:], s)
+    ref = np.stack([(spec.k0 + i).astype(np.float64), o[0][ia], o[1][ip], o[3][b]], axis=1)
+    assert np.array_equal(_np(cp)[3:], ref)
+    assert _np(cs)[2] == -1
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_power_stat_matches_oracle(B, mode):
+    import torch
+    _say(f"power_stat mode={mode}")
+    w = S.config2()
+    seg = w.segments[0]
+    ds = B.DeviceSegments.from_host(seg)
+    sky = torch.from_numpy(w.sky).cuda()
+    cand, cs = _cands(seg, 3000, 180000, seed=mode)
+    st = _status(B)
+    out = B.bsh_power_stat(ds, sky, *_dev_cands(cand, cs), mode=mode, with_counts=(mode == 0), status=st)
+    torch.cuda.synchronize()
+    st.raise_if_set()
+    P_o, c_o, nw_o, nt_o = O.power_stat(seg, w.sky, cs, cand, mode=mode)
+    if mode == 0:
+        P, cnt, ws = (_np(x) for x in out)
+        ntw = nt_o * float(seg.weight.max())
+        _check_counts(cnt.view(np.uint32), ws, c_o, nw_o, nt_o, ntw)
+        # a flip at a near-tie moves P by at most w (rho_a - rho_b) for that segment
+        tol = REL * np.abs(P_o) + nt_o * float(seg.weight.max()) * float(seg.power.max())
+    else:
+        P = _np(out)
+        tol = REL * np.abs(P_o)
+    assert np.all(np.abs(P.astype(np.float64) - P_o) <= tol)
+
+
+def test_power_stat_unit_powers_and_ramp(B):
+    import torch
+    _say("power_stat special powers")
+    w = S.config2(n_per_det=300)
+    seg = w.segments[0]
+    cand, cs = _cands(seg, 200, 180000, seed=3)
+    sky = torch.from_numpy(w.sky).cuda()
+    seg.power[:] = 1.0
+    ds = B.DeviceSegments.from_host(seg)
+    sw = float(seg.weight.astype(np.float64).sum())
+    for mode in (0, 1):
+        P = _np(B.bsh_power_stat(ds, sky, *_dev_cands(cand, cs), mode=mode))
+        assert np.allclose(P, sw, rtol=REL, atol=0)
+    seg.power[:] = (np.arange(seg.n_bins, dtype=np.float64) + seg.k_lo)[None, :].astype(np.float32)
+    ds = B.DeviceSegments.from_host(seg)
+    x, _ = O.track(seg, w.sky, cs, cand)
+    P = _np(B.bsh_power_stat(ds, sky, *_dev_cands(cand, cs), mode=1))
+    assert np.allclose(P, x @ seg.weight.astype(np.float64), rtol=REL)
+
+
+def test_power_stat_grad_matches_oracle(B):
+    import torch
+    _say("power_stat_grad")
+    w = S.config2()
+    seg = w.segments[0]
+    ds = B.DeviceSegments.from_host(seg)
+    sky = torch.from_numpy(w.sky).cuda()
+    cand, cs = _cands(seg, 2000, 180000, seed=9)
+    gp = np.random.default_rng(1).standard_normal(2000)
+    st = _status(B)
+    g = _np(B.bsh_power_stat_grad(ds, sky, *_dev_cands(cand, cs), torch.from_numpy(gp).cuda(), status=st))
+    torch.cuda.synchronize()
+    st.raise_if_set()
+    g_o, a_o = O.power_grad(seg, w.sky, cs, cand, grad_p=gp, with_abs=True)
+    assert np.all(np.abs(g - g_o) <= REL * a_o + 1e-300)
+
+
+def test_track_bins_match_oracle(B):
+    import torch
+    _say("track bins")
+    w = S.config2()
+    seg = w.segments[0]
+    ds = B.DeviceSegments.from_host(seg)
+    sky = S.fibonacci_sphere(5)
+    cand, cs = _cands(seg, 500, 180000, seed=4, n_sky=5)
+    cs[0] = 7   # out of range: flagged, bins -1
+    st = _status(B)
+    k = _np(B.bsh_track_bins(ds, torch.from_numpy(sky).cuda(), *_dev_cands(cand, cs), status=st))
+    torch.cuda.synchronize()
+    assert st.value() == 4 and np.all(k[0] == -1)
+    x_o, k_o = O.track(seg, sky, np.where(cs < 5, cs, 0), cand)
+    near = np.abs((x_o + 0.5) - np.round(x_o + 0.5)) < O.NEAR_TIE
+    same = k[1:] == k_o[1:]
+    assert np.all(same | near[1:])
+
+
+def test_stage2_bins_agree_with_stage1_on_grid(B):
+    """Per-candidate counts at grid templates equal the stage-1 map exactly (same bins)."""
+    import torch
+    _say("stage1 vs stage2 bins")
+    w = S.config1()
+    seg, spec = w.segments[0], w.grids[0]
+    ds, g, o, ws, cnt = _run_count(B, seg, spec, w.sky)
+    idx = torch.arange(g.n_templates, device="cuda", dtype=torch.int64)
+    cs, cp = B.bsh_decode_templates(g, idx)
+    _, c2, w2 = B.bsh_power_stat(ds, g.sky, cs, cp, mode=0, with_power=False, with_counts=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(_np(c2).view(np.uint32), cnt)
+    assert np.array_equal(_np(w2), ws)
