@@ -36,6 +36,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-ap", type=int, default=8,
                     help="a_p values (of 64) in the oracle's timed sample")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="before timing, run one plain device copy of this many MiB (a known-size "
+                         "kernel for scaling HBM byte counters)")
     return ap.parse_args()
 
 
@@ -90,6 +93,14 @@ def main():
         cs, cp = bsh.bsh_decode_templates(g, s1_index)
         bsh.bsh_power_stat(ds, g.sky, cs, cp, mode=0, with_counts=True, status=st, out=P)
         top2(P, out_score=s2_score, out_index=s2_pos)
+
+    if args.calibrate_copy_mb > 0:
+        n_f = args.calibrate_copy_mb * (1 << 20) // 4
+        src = torch.ones(n_f, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         step(False)

@@ -150,8 +150,17 @@ int bsh_hough_count(const bsh_segments* seg, const bsh_grid* grid, uint32_t* cou
                     float* wsum_out, int32_t* status, bsh_stream stream);
 
 /*
+ * Same as bsh_hough_count with an explicit tile shape: `lanes` binary templates per block
+ * (64, 128 or 256) and `chunk` segments staged in LDS per pass (128, 256 or 512).  Results do
+ * not depend on the shape.
+ */
+int bsh_hough_count_ex(const bsh_segments* seg, const bsh_grid* grid, int32_t lanes, int32_t chunk,
+                       uint32_t* count_out, float* wsum_out, int32_t* status, bsh_stream stream);
+
+/*
  * Exact top-k under the total order (score descending, index ascending) (Sec. IV.C
- * top-lists).  score [n]; index [n] int64 or NULL for 0..n-1 (indices must be distinct).
+ * top-lists).  score [n]; index [n] int64 or NULL for 0..n-1 (indices must be distinct and
+ * non-negative).
  * Writes out_score[k], out_index[k] sorted; if n < k the tail is -inf / -1.
  * ws / ws_bytes: device workspace of at least bsh_topk_workspace(n, k) bytes.
  * Scores must not be NaN.  Merging per-item lists is a call with their concatenation.
@@ -159,6 +168,20 @@ int bsh_hough_count(const bsh_segments* seg, const bsh_grid* grid, uint32_t* cou
 size_t bsh_topk_workspace(int64_t n, int32_t k);
 int bsh_topk(const float* score, const int64_t* index, int64_t n, int32_t k,
              float* out_score, int64_t* out_index, void* ws, size_t ws_bytes, bsh_stream stream);
+
+/*
+ * Many independent top-k lists in the same launches: segment g is score[offsets[g] ..
+ * offsets[g+1]) and its list goes to out_score[g*k .. g*k+k), out_index likewise.
+ * offsets: device [n_segs+1] and a host copy (for launch sizing); each segment shorter than
+ * 2^32 - 1.  index NULL: entry e of segment g gets the implicit index
+ * (g << index_shift) | (e - offsets[g]) (just the position when index_shift is 0).
+ * Workspace: bsh_topk_segmented_workspace(n_segs, k) bytes.  n_segs <= 65535.
+ */
+size_t bsh_topk_segmented_workspace(int32_t n_segs, int32_t k);
+int bsh_topk_segmented(const float* score, const int64_t* index, const int64_t* offsets,
+                       const int64_t* offsets_host, int32_t n_segs, int32_t k, int32_t index_shift,
+                       float* out_score, int64_t* out_index, void* ws, size_t ws_bytes,
+                       bsh_stream stream);
 
 /*
  * Stage-1 template index -> candidate row (sky pixel, F = k0+i, a_p, P, t_asc).
@@ -200,6 +223,63 @@ int bsh_power_stat_grad(const bsh_segments* seg, const double* sky, int32_t n_sk
 int bsh_track_bins(const bsh_segments* seg, const double* sky, int32_t n_sky, const int32_t* cand_sky,
                    const double* cand_params, int64_t n, int32_t* bins_out, int32_t* status,
                    bsh_stream stream);
+
+/*
+ * Batched stage 1 over many work items of uneven size (independent band x sky-patch jobs,
+ * eq:cost of Sec. IV.F).  An item is one segment set, one band grid (index into grids[]) and
+ * the pixels [sky_lo, sky_lo + n_sky) of that grid's sky table; items must be ordered by band.
+ * Item i's stage-1 map (as bsh_hough_count would write it) goes to
+ * maps[off_i .. off_i + n_sky*n_bin*n_f0) with off_i the running sum over earlier items;
+ * bsh_items_map_floats gives the total.  Global template index of an item's entry at
+ * position q of its map: (i << 40) | q.
+ */
+typedef struct bsh_item {
+    bsh_segments seg;
+    int32_t grid;
+    int32_t sky_lo;
+    int32_t n_sky;
+    int32_t band;
+} bsh_item;
+
+typedef struct bsh_plan_opts {
+    int32_t lanes;        /* tile shape as in bsh_hough_count_ex (0: default 256) */
+    int32_t chunk;        /* (0: default 256) */
+    int32_t k_item;       /* top-k of every item's map (0: maps only) */
+    int32_t k_band;       /* top-k per band over its items' lists (0: none) */
+    int32_t use_graph;    /* 1: capture one run in a HIP graph at creation, replay it */
+    int32_t lpt;          /* 1: queue units longest-first */
+    int32_t blocks;       /* persistent blocks (0: CUs x resident blocks per CU) */
+} bsh_plan_opts;
+
+typedef struct bsh_plan bsh_plan;
+
+int64_t bsh_items_map_floats(const bsh_item* items, int32_t n_items, const bsh_grid* grids,
+                             int32_t n_grids);
+
+/*
+ * Build a plan: validates every item on the host, builds the unit queue (one unit per
+ * item x pixel x period x tile) and, with use_graph, captures one run.  The plan owns its
+ * device tables and top-k workspaces (allocated here, freed by bsh_plan_destroy); every
+ * pointer passed in (items' tables, grids, maps, item lists [n_items][k_item], band lists
+ * [n_bands][k_band], status) must stay valid for the plan's life.  Two runs of one plan, or
+ * other work on the same arrays, must not overlap in time.
+ */
+int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh_grid* grids, int32_t n_grids,
+                    int32_t n_bands, const bsh_plan_opts* opts, float* maps, int64_t maps_floats,
+                    float* item_score, int64_t* item_index, float* band_score, int64_t* band_index,
+                    int32_t* status, bsh_plan** plan);
+
+/* One batched run: persistent count kernel, per-item lists, per-band lists (one graph launch). */
+int bsh_plan_run(bsh_plan* plan, bsh_stream stream);
+
+/* The same results from one plain launch (plus its own top-k) per item, in item order. */
+int bsh_plan_run_plain(bsh_plan* plan, bsh_stream stream);
+
+/* Number of queued units and persistent blocks of a plan (-1 for NULL). */
+int64_t bsh_plan_units(const bsh_plan* plan);
+int32_t bsh_plan_blocks(const bsh_plan* plan);
+
+int bsh_plan_destroy(bsh_plan* plan);
 
 #ifdef __cplusplus
 }

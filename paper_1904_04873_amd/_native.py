@@ -77,6 +77,28 @@ class GridSpec(ctypes.Structure):
     ]
 
 
+class Item(ctypes.Structure):
+    _fields_ = [
+        ("seg", Segments),
+        ("grid", _c_i32),
+        ("sky_lo", _c_i32),
+        ("n_sky", _c_i32),
+        ("band", _c_i32),
+    ]
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [
+        ("lanes", _c_i32),
+        ("chunk", _c_i32),
+        ("k_item", _c_i32),
+        ("k_band", _c_i32),
+        ("use_graph", _c_i32),
+        ("lpt", _c_i32),
+        ("blocks", _c_i32),
+    ]
+
+
 # name -> (restype, argtypes); the complete exported surface of include/bsh.h
 SIGNATURES = {
     "bsh_version": (ctypes.c_int, []),
@@ -86,8 +108,22 @@ SIGNATURES = {
     "bsh_peakgram": (ctypes.c_int, [_vp, _c_i64, _c_i32, _c_f64, _vp, _vp]),
     "bsh_hough_count": (ctypes.c_int, [ctypes.POINTER(Segments), ctypes.POINTER(Grid), _vp, _vp, _vp,
                                        _vp]),
+    "bsh_hough_count_ex": (ctypes.c_int, [ctypes.POINTER(Segments), ctypes.POINTER(Grid), _c_i32, _c_i32,
+                                          _vp, _vp, _vp, _vp]),
+    "bsh_items_map_floats": (_c_i64, [ctypes.POINTER(Item), _c_i32, ctypes.POINTER(Grid), _c_i32]),
+    "bsh_plan_create": (ctypes.c_int, [ctypes.POINTER(Item), _c_i32, ctypes.POINTER(Grid), _c_i32, _c_i32,
+                                       ctypes.POINTER(PlanOpts), _vp, _c_i64, _vp, _vp, _vp, _vp, _vp,
+                                       ctypes.POINTER(_vp)]),
+    "bsh_plan_run": (ctypes.c_int, [_vp, _vp]),
+    "bsh_plan_run_plain": (ctypes.c_int, [_vp, _vp]),
+    "bsh_plan_units": (_c_i64, [_vp]),
+    "bsh_plan_blocks": (_c_i32, [_vp]),
+    "bsh_plan_destroy": (ctypes.c_int, [_vp]),
     "bsh_topk_workspace": (ctypes.c_size_t, [_c_i64, _c_i32]),
     "bsh_topk": (ctypes.c_int, [_vp, _vp, _c_i64, _c_i32, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "bsh_topk_segmented_workspace": (ctypes.c_size_t, [_c_i32, _c_i32]),
+    "bsh_topk_segmented": (ctypes.c_int, [_vp, _vp, _vp, _vp, _c_i32, _c_i32, _c_i32, _vp, _vp, _vp,
+                                          ctypes.c_size_t, _vp]),
     "bsh_decode_templates": (ctypes.c_int, [ctypes.POINTER(Grid), _vp, _c_i64, _vp, _vp, _vp]),
     "bsh_power_stat": (ctypes.c_int, [ctypes.POINTER(Segments), _vp, _c_i32, _vp, _vp, _c_i64, _c_i32,
                                       _vp, _vp, _vp, _vp, _vp]),

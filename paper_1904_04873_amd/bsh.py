@@ -202,17 +202,26 @@ def bsh_peakgram(power: torch.Tensor, rho_th: float = 1.6, out: Optional[torch.T
 
 
 def bsh_hough_count(seg: DeviceSegments, grid: DeviceGrid, with_count: bool = False,
-                    status: Optional[Status] = None, wsum_out=None, count_out=None):
-    """Stage-1 map: (wsum float32 [n_templates], count int32 [n_templates] or None)."""
+                    status: Optional[Status] = None, wsum_out=None, count_out=None,
+                    lanes: int = 0, chunk: int = 0):
+    """Stage-1 map: (wsum float32 [n_templates], count int32 [n_templates] or None).
+
+    lanes / chunk select the tile shape (bsh_hough_count_ex); 0 keeps the default."""
     dev = seg.t_mid.device
     if wsum_out is None:
         wsum_out = torch.empty(grid.n_templates, dtype=torch.float32, device=dev)
     if with_count and count_out is None:
         count_out = torch.empty(grid.n_templates, dtype=torch.int32, device=dev)
     s_c, g_c = seg.struct(), grid.struct()
-    check(N.load().bsh_hough_count(ctypes.byref(s_c), ctypes.byref(g_c), _ptr(count_out),
-                                   _ptr(wsum_out), status.ptr() if status else None, _stream()),
-          "bsh_hough_count")
+    if lanes or chunk:
+        check(N.load().bsh_hough_count_ex(ctypes.byref(s_c), ctypes.byref(g_c), int(lanes or 256),
+                                          int(chunk or 256), _ptr(count_out), _ptr(wsum_out),
+                                          status.ptr() if status else None, _stream()),
+              "bsh_hough_count_ex")
+    else:
+        check(N.load().bsh_hough_count(ctypes.byref(s_c), ctypes.byref(g_c), _ptr(count_out),
+                                       _ptr(wsum_out), status.ptr() if status else None, _stream()),
+              "bsh_hough_count")
     return wsum_out, (count_out if with_count else None)
 
 
@@ -300,3 +309,81 @@ def bsh_track_bins(seg: DeviceSegments, sky: torch.Tensor, cand_sky: torch.Tenso
                                   _ptr(cand_params), n, _ptr(out), status.ptr() if status else None,
                                   _stream()), "bsh_track_bins")
     return out
+
+
+# ---------------------------------------------------------------- batched plan
+
+ITEM_SHIFT = 40
+
+
+class Plan:
+    """A batched stage-1 run over many items (bsh_plan_create / _run / _run_plain).
+
+    items: sequence of (DeviceSegments, grid index, sky_lo, n_sky, band), ordered by band.
+    The plan keeps references to every tensor it points at."""
+
+    def __init__(self, items, grids: Sequence[DeviceGrid], n_bands: int, k_item: int = 0,
+                 k_band: int = 0, lanes: int = 0, chunk: int = 0, use_graph: bool = True,
+                 lpt: bool = True, blocks: int = 0, status: Optional[Status] = None, device="cuda"):
+        L = N.load()
+        self._keep = [items, grids]
+        self.n_items = len(items)
+        self.n_bands, self.k_item, self.k_band = int(n_bands), int(k_item), int(k_band)
+        self._segs = [it[0].struct() for it in items]
+        arr_i = (N.Item * self.n_items)()
+        for q, (ds, gi, lo, ns, band) in enumerate(items):
+            arr_i[q] = N.Item(seg=self._segs[q], grid=int(gi), sky_lo=int(lo), n_sky=int(ns), band=int(band))
+        arr_g = (N.Grid * len(grids))()
+        for q, g in enumerate(grids):
+            arr_g[q] = g.struct()
+        self._arr_i, self._arr_g = arr_i, arr_g
+        n_maps = int(L.bsh_items_map_floats(arr_i, self.n_items, arr_g, len(grids)))
+        if n_maps < 0:
+            raise BshError(N.BSH_EINVAL, "bsh_items_map_floats", "bad items")
+        self.maps = torch.empty(max(1, n_maps), dtype=torch.float32, device=device)
+        self.item_score = torch.empty((self.n_items, max(1, self.k_item)), dtype=torch.float32, device=device)
+        self.item_index = torch.empty((self.n_items, max(1, self.k_item)), dtype=torch.int64, device=device)
+        self.band_score = torch.empty((self.n_bands, max(1, self.k_band)), dtype=torch.float32, device=device)
+        self.band_index = torch.empty((self.n_bands, max(1, self.k_band)), dtype=torch.int64, device=device)
+        self.status = status if status is not None else Status(device)
+        opts = N.PlanOpts(lanes=int(lanes), chunk=int(chunk), k_item=self.k_item, k_band=self.k_band,
+                          use_graph=int(bool(use_graph)), lpt=int(bool(lpt)), blocks=int(blocks))
+        h = ctypes.c_void_p()
+        check(L.bsh_plan_create(arr_i, self.n_items, arr_g, len(grids), self.n_bands, ctypes.byref(opts),
+                                _ptr(self.maps), self.maps.numel(), _ptr(self.item_score),
+                                _ptr(self.item_index), _ptr(self.band_score), _ptr(self.band_index),
+                                self.status.ptr(), ctypes.byref(h)),
+              "bsh_plan_create")
+        self.h = h
+        self.offsets = np.zeros(self.n_items + 1, np.int64)
+        for q, (ds, gi, lo, ns, band) in enumerate(items):
+            self.offsets[q + 1] = self.offsets[q] + ns * grids[gi].n_bin * grids[gi].n_f0
+
+    def run(self) -> None:
+        check(N.load().bsh_plan_run(self.h, _stream()), "bsh_plan_run")
+
+    def run_plain(self) -> None:
+        check(N.load().bsh_plan_run_plain(self.h, _stream()), "bsh_plan_run_plain")
+
+    def item_map(self, q: int) -> torch.Tensor:
+        return self.maps[int(self.offsets[q]):int(self.offsets[q + 1])]
+
+    @property
+    def units(self) -> int:
+        return int(N.load().bsh_plan_units(self.h))
+
+    @property
+    def blocks(self) -> int:
+        return int(N.load().bsh_plan_blocks(self.h))
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            torch.cuda.synchronize()
+            N.load().bsh_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,79 @@
+// Shared declarations of the stage-1 count kernels (bsh_count.hip) and the batched plan
+// (bsh_batch.hip).  Internal to libbsh.
+#pragma once
+
+#include "bsh_internal.h"
+
+namespace bsh {
+
+constexpr int kMaxLanes = 256;       // largest tile (binary templates per block)
+constexpr int kDefaultLanes = 256;
+constexpr int kDefaultChunk = 256;   // segments staged per LDS pass
+constexpr int kFlush = 64;           // segments per FP32 partial sum
+constexpr int kRowPad = 3;           // zero words staged after each row
+constexpr int kNF = BSH_MAX_F0;
+
+// Everything a tile needs about its work item (one segment set, one band grid, a run of
+// sky pixels of that grid, and the item's output map).
+struct ItemDesc {
+    const double* t_mid;
+    const double* v;
+    const float* w;
+    const uint32_t* bits;
+    const double* sky;
+    const double* a_p;
+    const double* period;
+    const int64_t* tasc_off;
+    const double* t_asc;
+    uint32_t* count_out;
+    float* wsum_out;
+    int32_t* status;
+    int64_t n_seg;
+    int64_t n_bin;
+    int64_t k_lo;
+    int64_t k0;
+    int32_t w_per_sky;
+    int32_t n_words;
+    int32_t n_bins;
+    int32_t n_f0;
+    int32_t n_ap;
+    int32_t n_per;
+    int32_t sky_lo;     // first pixel of the item in the grid's sky table
+    int32_t n_sky;      // pixels of the item
+};
+
+struct PlainLaunch {
+    ItemDesc d;
+    int32_t tiles_per_sky;
+    int32_t tile_start[BSH_MAX_PER + 1];   // first tile of each period group
+};
+
+// One queue entry of the persistent kernel.
+struct WorkUnit {
+    int32_t item;
+    int32_t sky;        // pixel inside the item
+    int32_t ip;         // period index
+    int32_t tile;       // tile inside the period group
+};
+
+template <int kChunk>
+struct TileSmem {
+    double C[kChunk];
+    double S[kChunk];
+    double D[kChunk];
+    float W[kChunk];
+    uint32_t row[kChunk * (BSH_MAX_WORDS + kRowPad)];
+};
+
+int64_t plan_tiles(const bsh_grid* g, int lanes, int32_t* tile_start, int64_t* group_sizes);
+void fill_desc(ItemDesc& d, const bsh_segments* seg, const bsh_grid* grid, int32_t sky_lo,
+               int32_t n_sky, uint32_t* count_out, float* wsum_out, int32_t* status);
+int zero_words(void* p, int64_t n_words, hipStream_t stream);
+int launch_plain(const PlainLaunch& p, int64_t blocks, int lanes, int chunk, bool with_count,
+                 hipStream_t stream);
+int launch_batch(const ItemDesc* items, const WorkUnit* units, int64_t n_units, uint32_t* counter,
+                 int blocks, int lanes, int chunk, bool with_count, hipStream_t stream);
+int batch_blocks_per_cu(int lanes, int chunk, bool with_count);
+bool valid_tile_shape(int lanes, int chunk);
+
+}  // namespace bsh

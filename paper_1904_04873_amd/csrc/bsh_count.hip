@@ -1,14 +1,14 @@
 // Stage-1 weighted number count (Sec. IV.C eq:hough2; the GPU loop K1 of Sec. IV.B).
 //
-// Work decomposition.  A block owns one sky pixel, one orbital period P and a tile of
-// kBlock binary templates (a_p, t_asc) of that period; each lane owns one binary template
-// and all n_f0 (<= 90) frequency bins of the band.  Segments stream through LDS in chunks:
-// per segment the block stages cos(W t_J), sin(W t_J) (shared by every lane, since W is the
-// block's), the Doppler factor D_J of the pixel, the weight and the bit-packed peakgram row.
+// Work decomposition.  A tile is one sky pixel, one orbital period P and `lanes` binary
+// templates (a_p, t_asc) of that period; each lane owns one binary template and all n_f0
+// (<= 90) frequency bins of the band.  Segments stream through LDS in chunks: per segment the
+// block stages cos(W t_J), sin(W t_J) (shared by every lane, since W is the tile's), the
+// Doppler factor D_J of the pixel, the weight and the bit-packed peakgram row.
 //
 // Per (lane, segment) the orbit factor is B = 1 - a_p W (cos(W t_J) cos(W t_asc) +
-// sin(W t_J) sin(W t_asc)) and G = D B, in the operation order of track_x.  Bins of the band follow from G alone:
-//   k_i = floor(fl((k0 + i) G) + 1/2),  i = 0 .. n_f0-1.
+// sin(W t_J) sin(W t_asc)) and G = D B, in the operation order of track_x.  The band's bins
+// follow from G alone:  k_i = floor(fl((k0 + i) G) + 1/2),  i = 0 .. n_f0-1.
 // For |G - 1| < 1/(2 n_f0) the offsets r_i = k_i - (k0 + i) form a monotone step with at
 // most one step (the canonical rounding is monotone in i and the exact offsets drift by
 // (n_f0-1)|G-1| < 1 bin).  So two evaluations (i = 0 and the last) give r_0 and r_last;
@@ -22,46 +22,15 @@
 // totals every kFlush segments (bounded error for long observations), plus optional uint32
 // counts.  Each bit costs a sign-extending bit-field extract, an AND with the weight's bit
 // pattern and an add.
+//
+// Two launch forms share the tile body: the plain kernel (one block per tile of one work
+// item, bsh_hough_count) and the persistent kernel of the batched plan (bsh_batch.hip), whose
+// blocks pull (item, pixel, period, tile) units from a queue.
 #include <cstring>
 
-#include "bsh_internal.h"
+#include "bsh_count.h"
 
-namespace {
-
-using namespace bsh;
-
-constexpr int kBlock = 256;    // binary templates per block (lanes)
-constexpr int kChunk = 256;    // segments staged per LDS pass
-constexpr int kFlush = 64;     // segments per FP32 partial sum
-constexpr int kRowPad = 3;     // zero words staged after each row
-constexpr int kNF = BSH_MAX_F0;
-
-struct CountParams {
-    const double* t_mid;
-    const double* v;
-    const float* w;
-    const uint32_t* bits;
-    const double* sky;
-    const double* a_p;
-    const double* period;
-    const int64_t* tasc_off;
-    const double* t_asc;
-    uint32_t* count_out;
-    float* wsum_out;
-    int32_t* status;
-    int64_t n_seg;
-    int64_t n_bin;
-    int64_t k_lo;
-    int64_t k0;
-    int32_t w_per_sky;
-    int32_t n_words;
-    int32_t n_bins;
-    int32_t n_f0;
-    int32_t n_ap;
-    int32_t n_per;
-    int32_t tiles_per_sky;
-    int32_t tile_start[BSH_MAX_PER + 1];   // first tile of each period group
-};
+namespace bsh {
 
 __device__ __forceinline__ uint32_t upper_mask(int t)
 {
@@ -69,53 +38,38 @@ __device__ __forceinline__ uint32_t upper_mask(int t)
     return t <= 0 ? 0xffffffffu : (t >= 32 ? 0u : (0xffffffffu << t));
 }
 
-template <bool kCount>
-__global__ __launch_bounds__(kBlock) void hough_count_kernel(const CountParams p)
+template <bool kCount, int kChunk>
+__device__ __forceinline__ void count_tile(const ItemDesc& d, int s, int ip, int64_t tile,
+                                           TileSmem<kChunk>& sm)
 {
-    __shared__ double sC[kChunk];
-    __shared__ double sS[kChunk];
-    __shared__ double sD[kChunk];
-    __shared__ float sW[kChunk];
-    __shared__ uint32_t sRow[kChunk * (BSH_MAX_WORDS + kRowPad)];
-
     const int tid = threadIdx.x;
-    const int blk = blockIdx.x;
-    const int s = blk / p.tiles_per_sky;
-    const int t = blk - s * p.tiles_per_sky;
-    int ip = 0;
-    {
-        int lo = 0, hi = p.n_per;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (p.tile_start[mid] <= t) lo = mid; else hi = mid;
-        }
-        ip = lo;
-    }
-    const int64_t q = (int64_t)(t - p.tile_start[ip]) * kBlock + tid;
+    const int lanes = blockDim.x;
+    const int64_t q = tile * lanes + tid;
 
     // position q of the period group -> (a_p index, t_asc point)
     int ia = -1;
     int64_t j = 0, cum = 0;
-    for (int a = 0; a < p.n_ap; ++a) {
-        const int64_t c0 = p.tasc_off[(int64_t)a * p.n_per + ip];
-        const int64_t n = p.tasc_off[(int64_t)a * p.n_per + ip + 1] - c0;
+    for (int a = 0; a < d.n_ap; ++a) {
+        const int64_t c0 = d.tasc_off[(int64_t)a * d.n_per + ip];
+        const int64_t n = d.tasc_off[(int64_t)a * d.n_per + ip + 1] - c0;
         if (ia < 0 && q < cum + n) { ia = a; j = q - cum; }
         cum += n;
     }
     const bool active = ia >= 0;
-    const int64_t b = active ? p.tasc_off[(int64_t)ia * p.n_per + ip] + j : 0;
-    const double W = kTwoPi / p.period[ip];
-    const double apW = active ? p.a_p[ia] * W : 0.0;
+    const int64_t b = active ? d.tasc_off[(int64_t)ia * d.n_per + ip] + j : 0;
+    const double W = kTwoPi / d.period[ip];
+    const double apW = active ? d.a_p[ia] * W : 0.0;
     double sb = 0.0, cb = 1.0;
-    if (active) sincos(W * p.t_asc[b], &sb, &cb);
+    if (active) sincos(W * d.t_asc[b], &sb, &cb);
 
-    const double nx = p.sky[3 * s], ny = p.sky[3 * s + 1], nz = p.sky[3 * s + 2];
-    const float* wrow = p.w + (p.w_per_sky ? (int64_t)s * p.n_seg : 0);
-    const double F0 = (double)p.k0;
-    const int last = p.n_f0 - 1;
-    const double FL = (double)(p.k0 + last);
-    const double klo = (double)p.k_lo;
-    const int nwp = p.n_words + kRowPad;
+    const int sg = d.sky_lo + s;
+    const double nx = d.sky[3 * sg], ny = d.sky[3 * sg + 1], nz = d.sky[3 * sg + 2];
+    const float* wrow = d.w + (d.w_per_sky ? (int64_t)s * d.n_seg : 0);
+    const double F0 = (double)d.k0;
+    const int last = d.n_f0 - 1;
+    const double FL = (double)(d.k0 + last);
+    const double klo = (double)d.k_lo;
+    const int nwp = d.n_words + kRowPad;
 
     float acc[kNF], tot[kNF];
     uint32_t cnt[kCount ? kNF : 1];
@@ -126,40 +80,40 @@ __global__ __launch_bounds__(kBlock) void hough_count_kernel(const CountParams p
     int since_flush = 0;
     bool bad_range = false, bad_model = false;
 
-    for (int64_t j0 = 0; j0 < p.n_seg; j0 += kChunk) {
-        const int nj = (int)min((int64_t)kChunk, p.n_seg - j0);
+    for (int64_t j0 = 0; j0 < d.n_seg; j0 += kChunk) {
+        const int nj = (int)min((int64_t)kChunk, d.n_seg - j0);
         __syncthreads();
-        for (int jj = tid; jj < nj; jj += kBlock) {
+        for (int jj = tid; jj < nj; jj += lanes) {
             const int64_t J = j0 + jj;
             double sp, cp;
-            sincos(W * p.t_mid[J], &sp, &cp);
-            sC[jj] = cp;
-            sS[jj] = sp;
-            sD[jj] = doppler_factor(p.v + 3 * J, nx, ny, nz);
-            sW[jj] = wrow[J];
+            sincos(W * d.t_mid[J], &sp, &cp);
+            sm.C[jj] = cp;
+            sm.S[jj] = sp;
+            sm.D[jj] = doppler_factor(d.v + 3 * J, nx, ny, nz);
+            sm.W[jj] = wrow[J];
         }
-        for (int e = tid; e < nj * nwp; e += kBlock) {
+        for (int e = tid; e < nj * nwp; e += lanes) {
             const int jj = e / nwp;
             const int wd = e - jj * nwp;
-            sRow[e] = wd < p.n_words ? p.bits[(j0 + jj) * p.n_words + wd] : 0u;
+            sm.row[e] = wd < d.n_words ? d.bits[(j0 + jj) * d.n_words + wd] : 0u;
         }
         __syncthreads();
         if (!active) continue;
 
         for (int jj = 0; jj < nj; ++jj) {
             // same operation order as orbit_phase / track_x: G = D (1 - a_p W cos phi)
-            const double cphi = fma(sC[jj], cb, sS[jj] * sb);
-            const double G = sD[jj] * (1.0 - apW * cphi);
+            const double cphi = fma(sm.C[jj], cb, sm.S[jj] * sb);
+            const double G = sm.D[jj] * (1.0 - apW * cphi);
             const double kf = floor(F0 * G + 0.5);
             const double kl = floor(FL * G + 0.5);
             const int r0 = (int)(kf - F0);
             const int delta = (int)(kl - FL) - r0;
             const int base = (int)(kf - klo);
             const int top = (int)(kl - klo);
-            if (base < 0 || top >= p.n_bins) { bad_range = true; continue; }
+            if (base < 0 || top >= d.n_bins) { bad_range = true; continue; }
             if (delta < -1 || delta > 1) { bad_model = true; continue; }
 
-            const uint32_t* row = sRow + jj * nwp;
+            const uint32_t* row = sm.row + jj * nwp;
             const int qw = base >> 5;
             const int sh = base & 31;
             const uint32_t w0 = row[qw], w1 = row[qw + 1], w2 = row[qw + 2], w3 = row[qw + 3];
@@ -190,7 +144,7 @@ __global__ __launch_bounds__(kBlock) void hough_count_kernel(const CountParams p
                 m2 = (n2 & s2) | (m2 & ~s2);
             }
 
-            const uint32_t wb = __float_as_uint(sW[jj]);
+            const uint32_t wb = __float_as_uint(sm.W[jj]);
 #pragma unroll
             for (int i = 0; i < kNF; ++i) {
                 const uint32_t m = i < 32 ? m0 : (i < 64 ? m1 : m2);
@@ -205,24 +159,195 @@ __global__ __launch_bounds__(kBlock) void hough_count_kernel(const CountParams p
             }
         }
     }
-    if (bad_range) raise_status(p.status, BSH_STATUS_RANGE);
-    if (bad_model) raise_status(p.status, BSH_STATUS_MODEL);
+    if (bad_range) raise_status(d.status, BSH_STATUS_RANGE);
+    if (bad_model) raise_status(d.status, BSH_STATUS_MODEL);
     if (!active) return;
 
-    const int64_t base_idx = ((int64_t)s * p.n_bin + b) * p.n_f0;
+    const int64_t base_idx = ((int64_t)s * d.n_bin + b) * d.n_f0;
 #pragma unroll
     for (int i = 0; i < kNF; ++i) {
-        if (i < p.n_f0) {
-            if (p.wsum_out) p.wsum_out[base_idx + i] = tot[i] + acc[i];
-            if (kCount && p.count_out) p.count_out[base_idx + i] = cnt[kCount ? i : 0];
+        if (i < d.n_f0) {
+            if (d.wsum_out) d.wsum_out[base_idx + i] = tot[i] + acc[i];
+            if (kCount && d.count_out) d.count_out[base_idx + i] = cnt[kCount ? i : 0];
         }
     }
 }
 
-}  // namespace
+template <bool kCount, int kChunk>
+__global__ __launch_bounds__(kMaxLanes) void hough_count_kernel(const PlainLaunch p)
+{
+    __shared__ TileSmem<kChunk> sm;
+    const int blk = blockIdx.x;
+    const int s = blk / p.tiles_per_sky;
+    const int t = blk - s * p.tiles_per_sky;
+    int lo = 0, hi = p.d.n_per;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (p.tile_start[mid] <= t) lo = mid; else hi = mid;
+    }
+    count_tile<kCount, kChunk>(p.d, s, lo, t - p.tile_start[lo], sm);
+}
 
-extern "C" int bsh_hough_count(const bsh_segments* seg, const bsh_grid* grid, uint32_t* count_out,
-                               float* wsum_out, int32_t* status, bsh_stream stream)
+template <bool kCount, int kChunk>
+__global__ __launch_bounds__(kMaxLanes) void hough_batch_kernel(const ItemDesc* __restrict__ items,
+                                                               const WorkUnit* __restrict__ units,
+                                                               int64_t n_units, uint32_t* counter)
+{
+    __shared__ TileSmem<kChunk> sm;
+    __shared__ int64_t next;
+    for (;;) {
+        if (threadIdx.x == 0) next = (int64_t)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int64_t u = next;
+        __syncthreads();
+        if (u >= n_units) break;
+        const WorkUnit w = units[u];
+        const ItemDesc d = items[w.item];
+        count_tile<kCount, kChunk>(d, w.sky, w.ip, w.tile, sm);
+    }
+}
+
+// Tiles of each period group of one item, in tile_start form.
+int64_t plan_tiles(const bsh_grid* g, int lanes, int32_t* tile_start, int64_t* group_sizes)
+{
+    int64_t tiles = 0;
+    for (int32_t ip = 0; ip < g->n_per; ++ip) {
+        int64_t group = 0;
+        for (int32_t ia = 0; ia < g->n_ap; ++ia) {
+            const int64_t c = (int64_t)ia * g->n_per + ip;
+            group += g->tasc_off_host[c + 1] - g->tasc_off_host[c];
+        }
+        if (tile_start) tile_start[ip] = (int32_t)tiles;
+        if (group_sizes) group_sizes[ip] = group;
+        tiles += (group + lanes - 1) / lanes;
+    }
+    if (tile_start)
+        for (int32_t ip = g->n_per; ip <= BSH_MAX_PER; ++ip) tile_start[ip] = (int32_t)tiles;
+    return tiles;
+}
+
+void fill_desc(ItemDesc& d, const bsh_segments* seg, const bsh_grid* grid, int32_t sky_lo,
+               int32_t n_sky, uint32_t* count_out, float* wsum_out, int32_t* status)
+{
+    std::memset(&d, 0, sizeof(d));
+    d.t_mid = seg->t_mid;
+    d.v = seg->v_over_c;
+    d.w = seg->weight;
+    d.bits = seg->peak_bits;
+    d.sky = grid->sky;
+    d.a_p = grid->a_p;
+    d.period = grid->period;
+    d.tasc_off = grid->tasc_off;
+    d.t_asc = grid->t_asc;
+    d.count_out = count_out;
+    d.wsum_out = wsum_out;
+    d.status = status;
+    d.n_seg = seg->n_seg;
+    d.k_lo = seg->k_lo;
+    d.k0 = grid->k0;
+    d.w_per_sky = seg->weight_per_sky;
+    d.n_words = words_for(seg->n_bins);
+    d.n_bins = seg->n_bins;
+    d.n_f0 = grid->n_f0;
+    d.n_ap = grid->n_ap;
+    d.n_per = grid->n_per;
+    d.sky_lo = sky_lo;
+    d.n_sky = n_sky;
+    d.n_bin = grid->tasc_off_host[(int64_t)grid->n_ap * grid->n_per];
+}
+
+__global__ void fill_zero_kernel(uint32_t* p, int64_t n)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = 0u;
+}
+
+int zero_words(void* p, int64_t n_words, hipStream_t stream)
+{
+    if (n_words <= 0 || !p) return BSH_OK;
+    int64_t blocks = (n_words + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, (uint32_t*)p, n_words);
+    return check_launch("zero fill");
+}
+
+template <bool kCount, int kChunk>
+static int launch_plain_t(const PlainLaunch& p, int64_t blocks, int lanes, hipStream_t stream)
+{
+    hipLaunchKernelGGL((hough_count_kernel<kCount, kChunk>), dim3((unsigned)blocks), dim3(lanes), 0,
+                       stream, p);
+    return check_launch("bsh_hough_count");
+}
+
+int launch_plain(const PlainLaunch& p, int64_t blocks, int lanes, int chunk, bool with_count,
+                 hipStream_t stream)
+{
+    switch (chunk) {
+    case 128: return with_count ? launch_plain_t<true, 128>(p, blocks, lanes, stream)
+                                : launch_plain_t<false, 128>(p, blocks, lanes, stream);
+    case 512: return with_count ? launch_plain_t<true, 512>(p, blocks, lanes, stream)
+                                : launch_plain_t<false, 512>(p, blocks, lanes, stream);
+    default: return with_count ? launch_plain_t<true, 256>(p, blocks, lanes, stream)
+                               : launch_plain_t<false, 256>(p, blocks, lanes, stream);
+    }
+}
+
+template <bool kCount, int kChunk>
+static int launch_batch_t(const ItemDesc* items, const WorkUnit* units, int64_t n_units,
+                          uint32_t* counter, int blocks, int lanes, hipStream_t stream)
+{
+    hipLaunchKernelGGL((hough_batch_kernel<kCount, kChunk>), dim3(blocks), dim3(lanes), 0, stream, items,
+                       units, n_units, counter);
+    return check_launch("batched count");
+}
+
+int launch_batch(const ItemDesc* items, const WorkUnit* units, int64_t n_units, uint32_t* counter,
+                 int blocks, int lanes, int chunk, bool with_count, hipStream_t stream)
+{
+    switch (chunk) {
+    case 128: return with_count ? launch_batch_t<true, 128>(items, units, n_units, counter, blocks, lanes, stream)
+                                : launch_batch_t<false, 128>(items, units, n_units, counter, blocks, lanes, stream);
+    case 512: return with_count ? launch_batch_t<true, 512>(items, units, n_units, counter, blocks, lanes, stream)
+                                : launch_batch_t<false, 512>(items, units, n_units, counter, blocks, lanes, stream);
+    default: return with_count ? launch_batch_t<true, 256>(items, units, n_units, counter, blocks, lanes, stream)
+                               : launch_batch_t<false, 256>(items, units, n_units, counter, blocks, lanes, stream);
+    }
+}
+
+int batch_blocks_per_cu(int lanes, int chunk, bool with_count)
+{
+    int n = 0;
+    hipError_t e = hipSuccess;
+    switch (chunk) {
+    case 128:
+        e = with_count ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, hough_batch_kernel<true, 128>, lanes, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, hough_batch_kernel<false, 128>, lanes, 0);
+        break;
+    case 512:
+        e = with_count ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, hough_batch_kernel<true, 512>, lanes, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, hough_batch_kernel<false, 512>, lanes, 0);
+        break;
+    default:
+        e = with_count ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, hough_batch_kernel<true, 256>, lanes, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, hough_batch_kernel<false, 256>, lanes, 0);
+    }
+    if (e != hipSuccess || n < 1) n = 1;
+    return n;
+}
+
+bool valid_tile_shape(int lanes, int chunk)
+{
+    return (lanes == 64 || lanes == 128 || lanes == 256) && (chunk == 128 || chunk == 256 || chunk == 512);
+}
+
+}  // namespace bsh
+
+using namespace bsh;
+
+extern "C" int bsh_hough_count_ex(const bsh_segments* seg, const bsh_grid* grid, int32_t lanes,
+                                  int32_t chunk, uint32_t* count_out, float* wsum_out,
+                                  int32_t* status, bsh_stream stream)
 {
     clear_error();
     int rc = check_segments(seg, true, false);
@@ -230,67 +355,31 @@ extern "C" int bsh_hough_count(const bsh_segments* seg, const bsh_grid* grid, ui
     rc = check_grid(grid);
     if (rc) return rc;
     if (!count_out && !wsum_out) return fail_inval("both outputs are NULL");
+    if (!valid_tile_shape(lanes, chunk)) return fail_inval("tile shape: lanes 64/128/256, chunk 128/256/512");
     rc = check_window(seg, grid);
     if (rc) return rc;
 
-    CountParams p;
+    PlainLaunch p;
     std::memset(&p, 0, sizeof(p));
-    p.t_mid = seg->t_mid;
-    p.v = seg->v_over_c;
-    p.w = seg->weight;
-    p.bits = seg->peak_bits;
-    p.sky = grid->sky;
-    p.a_p = grid->a_p;
-    p.period = grid->period;
-    p.tasc_off = grid->tasc_off;
-    p.t_asc = grid->t_asc;
-    p.count_out = count_out;
-    p.wsum_out = wsum_out;
-    p.status = status;
-    p.n_seg = seg->n_seg;
-    p.k_lo = seg->k_lo;
-    p.k0 = grid->k0;
-    p.w_per_sky = seg->weight_per_sky;
-    p.n_words = words_for(seg->n_bins);
-    p.n_bins = seg->n_bins;
-    p.n_f0 = grid->n_f0;
-    p.n_ap = grid->n_ap;
-    p.n_per = grid->n_per;
-    const int64_t n_cells = (int64_t)grid->n_ap * grid->n_per;
-    p.n_bin = grid->tasc_off_host[n_cells];
-
-    // tiles of each period group
-    int64_t tiles = 0;
-    for (int32_t ip = 0; ip < grid->n_per; ++ip) {
-        int64_t group = 0;
-        for (int32_t ia = 0; ia < grid->n_ap; ++ia) {
-            const int64_t c = (int64_t)ia * grid->n_per + ip;
-            group += grid->tasc_off_host[c + 1] - grid->tasc_off_host[c];
-        }
-        p.tile_start[ip] = (int32_t)tiles;
-        tiles += (group + kBlock - 1) / kBlock;
-    }
-    p.tile_start[grid->n_per] = (int32_t)tiles;
-    for (int32_t ip = grid->n_per + 1; ip <= BSH_MAX_PER; ++ip) p.tile_start[ip] = (int32_t)tiles;
+    fill_desc(p.d, seg, grid, 0, grid->n_sky, count_out, wsum_out, status);
+    const int64_t tiles = plan_tiles(grid, lanes, p.tile_start, nullptr);
     p.tiles_per_sky = (int32_t)tiles;
     const int64_t blocks = tiles * grid->n_sky;
-    if (tiles == 0 || p.n_bin == 0) return BSH_OK;
+    if (tiles == 0 || p.d.n_bin == 0) return BSH_OK;
     if (blocks > 0x7fffffff) return fail_inval("grid too large for one launch");
+    hipStream_t s = (hipStream_t)stream;
     if (seg->n_seg == 0) {
         // no segments: every count is zero
-        const int64_t n_t = (int64_t)grid->n_sky * p.n_bin * grid->n_f0;
-        if (wsum_out && hipMemsetAsync(wsum_out, 0, n_t * sizeof(float), (hipStream_t)stream) != hipSuccess)
-            return check_launch("bsh_hough_count memset");
-        if (count_out && hipMemsetAsync(count_out, 0, n_t * sizeof(uint32_t), (hipStream_t)stream) != hipSuccess)
-            return check_launch("bsh_hough_count memset");
-        return BSH_OK;
+        const int64_t n_t = (int64_t)grid->n_sky * p.d.n_bin * grid->n_f0;
+        rc = zero_words(wsum_out, wsum_out ? n_t : 0, s);
+        if (rc) return rc;
+        return zero_words(count_out, count_out ? n_t : 0, s);
     }
+    return launch_plain(p, blocks, lanes, chunk, count_out != nullptr, s);
+}
 
-    if (count_out)
-        hipLaunchKernelGGL(hough_count_kernel<true>, dim3((unsigned)blocks), dim3(kBlock), 0,
-                           (hipStream_t)stream, p);
-    else
-        hipLaunchKernelGGL(hough_count_kernel<false>, dim3((unsigned)blocks), dim3(kBlock), 0,
-                           (hipStream_t)stream, p);
-    return check_launch("bsh_hough_count");
+extern "C" int bsh_hough_count(const bsh_segments* seg, const bsh_grid* grid, uint32_t* count_out,
+                               float* wsum_out, int32_t* status, bsh_stream stream)
+{
+    return bsh_hough_count_ex(seg, grid, kDefaultLanes, kDefaultChunk, count_out, wsum_out, status, stream);
 }

@@ -46,6 +46,12 @@ int check_grid(const bsh_grid* g);
 // Conservative host check that every stage-1 track stays inside the staged row.
 int check_window(const bsh_segments* seg, const bsh_grid* g);
 
+// Segmented exact top-k (bsh_topk.hip): offsets on the device, longest segment from the host.
+size_t topk_workspace_bytes(int32_t n_segs, int32_t k);
+int topk_segmented(const float* score, const int64_t* index, const int64_t* offsets, int32_t n_segs,
+                   int64_t max_len, int32_t shift, int32_t k, float* out_score, int64_t* out_index,
+                   void* ws, size_t ws_bytes, hipStream_t stream);
+
 // ---------------------------------------------------------------- device track
 
 // Doppler factor D = 1 + v.n, one fixed operation order (no contraction: the library is

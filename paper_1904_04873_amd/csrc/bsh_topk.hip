@@ -1,18 +1,21 @@
 // Exact top-k under the total order (score descending, index ascending): the per-band
-// top-lists of Sec. IV.C (N_C candidates out of stage 1, N_CF out of stage 2).
+// top-lists of Sec. IV.C (N_C candidates out of stage 1, N_CF out of stage 2), for one list
+// or for many independent lists ("segments") in the same launches.
 //
+// Per segment:
 // 1. Radix select on the 32-bit order-preserving key of the score: four 8-bit digit passes
-//    (block histograms in LDS, one global histogram, a one-block digit pick) find the key T
-//    of the k-th best score, the number of scores strictly better, and how many ties at T
-//    are still needed.
-// 2. One compaction pass writes every entry with key > T to the output pool and the
-//    indices of entries with key == T to a tie buffer.
-// 3. Ties are resolved by index: a radix select over the 64-bit indices of the tie buffer
-//    finds the largest index that still makes the cut, and a second compaction appends the
-//    chosen ties.
+//    (block histograms in LDS, one global histogram per segment, a one-block digit pick) find
+//    the key T of the k-th best score, the number of scores strictly better, and how many
+//    ties at T are still needed.
+// 2. One compaction pass writes every entry with key > T to the segment's output pool.
+// 3. Ties at T are resolved by index with a second radix select over the index bits of the
+//    entries whose key equals T (re-reading the scores instead of buffering the ties, so the
+//    workspace stays O(k) per segment), then a pass appends the chosen ties.
 // 4. The k chosen entries are ordered by rank counting (each entry counts the entries that
 //    precede it), which is exact, deterministic and independent of the arrival order.
 // Everything stays on the stream: no host synchronisation, counts live in the workspace.
+#include <cstring>
+
 #include "bsh_internal.h"
 
 namespace {
@@ -21,50 +24,52 @@ using namespace bsh;
 
 constexpr int kThreads = 256;
 constexpr int kBins = 256;
+constexpr int kMaxBlocksPerSeg = 1024;
 
 struct State {
-    uint32_t prefix;         // key digits fixed so far
+    uint32_t prefix;         // key digits fixed so far (the full key T after four passes)
     uint32_t remaining;      // entries still to take at the current prefix
-    uint32_t n_gt;           // entries with key > T (after the key passes)
-    uint32_t n_tie;          // tie-buffer fill
     uint32_t n_sel;          // output-pool fill
-    uint32_t pad;
+    uint32_t k_eff;          // min(k, segment length)
     unsigned long long iprefix;    // index digits fixed so far (tie resolution)
     uint32_t iremaining;
-    uint32_t n_lt;
+    uint32_t pad;
 };
 
-struct Work {
-    State* st;
-    uint32_t* hist;          // [kBins]
-    int64_t* tie;            // [n]
-    float* sel_score;        // [k]
-    int64_t* sel_index;      // [k]
+struct Seg {
+    const float* score;
+    const int64_t* index;    // NULL: implicit index (g << shift) | position
+    const int64_t* off;      // [n_segs + 1] device offsets
+    int32_t n_segs;
+    int32_t shift;           // implicit-index segment shift (0: position only)
+    int32_t k;
+    int32_t idx_bits;        // index bits that can differ inside a segment
+    State* st;               // [n_segs]
+    uint32_t* hist;          // [n_segs][kBins]
+    float* sel_score;        // [n_segs][k]
+    int64_t* sel_index;      // [n_segs][k]
 };
 
 __host__ __device__ inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-Work carve(void* ws, int64_t n, int32_t k)
+size_t workspace_bytes(int32_t n_segs, int32_t k)
 {
-    char* p = (char*)ws;
-    Work w;
-    w.st = (State*)p;
-    p += align_up(sizeof(State));
-    w.hist = (uint32_t*)p;
-    p += align_up(sizeof(uint32_t) * kBins);
-    w.tie = (int64_t*)p;
-    p += align_up(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
-    w.sel_score = (float*)p;
-    p += align_up(sizeof(float) * (size_t)k);
-    w.sel_index = (int64_t*)p;
-    return w;
+    const size_t ns = (size_t)(n_segs > 0 ? n_segs : 1);
+    return align_up(sizeof(State) * ns) + align_up(sizeof(uint32_t) * kBins * ns) +
+           align_up(sizeof(float) * (size_t)k * ns) + align_up(sizeof(int64_t) * (size_t)k * ns);
 }
 
-size_t workspace_bytes(int64_t n, int32_t k)
+void carve(void* ws, Seg& s)
 {
-    return align_up(sizeof(State)) + align_up(sizeof(uint32_t) * kBins) +
-           align_up(sizeof(int64_t) * (size_t)(n > 0 ? n : 1)) + align_up(sizeof(float) * (size_t)k) +
-           align_up(sizeof(int64_t) * (size_t)k);
+    const size_t ns = (size_t)s.n_segs;
+    char* p = (char*)ws;
+    s.st = (State*)p;
+    p += align_up(sizeof(State) * ns);
+    s.hist = (uint32_t*)p;
+    p += align_up(sizeof(uint32_t) * kBins * ns);
+    s.sel_score = (float*)p;
+    p += align_up(sizeof(float) * (size_t)s.k * ns);
+    s.sel_index = (int64_t*)p;
 }
 
 // Order-preserving map float -> uint32 (larger float -> larger key); -0 is folded onto +0.
@@ -81,158 +86,171 @@ __device__ __forceinline__ float key_score(uint32_t k)
     return __uint_as_float(u);
 }
 
-__device__ __forceinline__ int64_t entry_index(const int64_t* index, int64_t e)
+__device__ __forceinline__ int64_t entry_index(const Seg& s, int g, int64_t e, int64_t lo)
 {
-    return index ? index[e] : e;
+    if (s.index) return s.index[e];
+    const int64_t pos = e - lo;
+    return s.shift > 0 ? (((int64_t)g << s.shift) | pos) : pos;
 }
 
-__global__ void init_kernel(Work w, uint32_t k_eff)
+__global__ void init_kernel(Seg s)
 {
-    const int t = threadIdx.x;
-    if (t == 0) {
-        w.st->prefix = 0u;
-        w.st->remaining = k_eff;
-        w.st->n_gt = 0u;
-        w.st->n_tie = 0u;
-        w.st->n_sel = 0u;
-        w.st->iprefix = 0ull;
-        w.st->iremaining = 0u;
-        w.st->n_lt = 0u;
+    const int g = blockIdx.x;
+    const int64_t len = s.off[g + 1] - s.off[g];
+    if (threadIdx.x == 0) {
+        const uint32_t k_eff = (uint32_t)(len < (int64_t)s.k ? len : (int64_t)s.k);
+        s.st[g].prefix = 0u;
+        s.st[g].remaining = k_eff;
+        s.st[g].n_sel = 0u;
+        s.st[g].k_eff = k_eff;
+        s.st[g].iprefix = 0ull;
+        s.st[g].iremaining = 0u;
     }
-    for (int b = t; b < kBins; b += blockDim.x) w.hist[b] = 0u;
+    for (int b = threadIdx.x; b < kBins; b += blockDim.x) s.hist[(size_t)g * kBins + b] = 0u;
 }
 
 // Histogram of key digit `pass` (0 = most significant byte) over entries matching the prefix.
-__global__ __launch_bounds__(kThreads) void key_hist_kernel(const float* __restrict__ score,
-                                                            int64_t n, Work w, int pass)
+__global__ __launch_bounds__(kThreads) void key_hist_kernel(Seg s, int pass)
 {
     __shared__ uint32_t h[kBins];
+    const int g = blockIdx.y;
+    if (s.st[g].remaining == 0u) return;
     for (int b = threadIdx.x; b < kBins; b += kThreads) h[b] = 0u;
     __syncthreads();
-    const uint32_t prefix = w.st->prefix;
+    const int64_t lo = s.off[g], hi = s.off[g + 1];
+    const uint32_t prefix = s.st[g].prefix;
     const int shift = 24 - 8 * pass;
-    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n;
+    for (int64_t e = lo + (int64_t)blockIdx.x * kThreads + threadIdx.x; e < hi;
          e += (int64_t)gridDim.x * kThreads) {
-        const uint32_t key = score_key(score[e]);
+        const uint32_t key = score_key(s.score[e]);
         if (pass == 0 || (key >> (shift + 8)) == prefix) atomicAdd(&h[(key >> shift) & 0xffu], 1u);
     }
     __syncthreads();
     for (int b = threadIdx.x; b < kBins; b += kThreads)
-        if (h[b]) atomicAdd(&w.hist[b], h[b]);
+        if (h[b]) atomicAdd(&s.hist[(size_t)g * kBins + b], h[b]);
 }
 
 // Pick the digit holding the remaining-th best entry; entries with larger digits are taken.
-__global__ void key_pick_kernel(Work w)
+__global__ void key_pick_kernel(Seg s)
 {
     __shared__ uint32_t h[kBins];
+    const int g = blockIdx.x;
     const int t = threadIdx.x;   // kBins threads
-    h[t] = w.hist[t];
+    h[t] = s.hist[(size_t)g * kBins + t];
     __syncthreads();
-    if (t == 0) {
-        uint32_t rem = w.st->remaining;
+    if (t == 0 && s.st[g].remaining > 0u) {
+        const uint32_t rem = s.st[g].remaining;
         uint32_t above = 0u;
         int d = kBins - 1;
         for (; d > 0; --d) {
             if (above + h[d] >= rem) break;
             above += h[d];
         }
-        w.st->n_gt += above;
-        w.st->remaining = rem - above;
-        w.st->prefix = (w.st->prefix << 8) | (uint32_t)d;
+        s.st[g].remaining = rem - above;
+        s.st[g].prefix = (s.st[g].prefix << 8) | (uint32_t)d;
     }
     __syncthreads();
-    w.hist[t] = 0u;
+    s.hist[(size_t)g * kBins + t] = 0u;
 }
 
-__global__ __launch_bounds__(kThreads) void split_kernel(const float* __restrict__ score,
-                                                         const int64_t* __restrict__ index,
-                                                         int64_t n, Work w, uint32_t k_cap)
+__global__ __launch_bounds__(kThreads) void split_kernel(Seg s)
 {
-    const uint32_t T = w.st->prefix;
-    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n;
+    const int g = blockIdx.y;
+    const uint32_t k_eff = s.st[g].k_eff;
+    if (k_eff == 0u) return;
+    const uint32_t T = s.st[g].prefix;
+    const int64_t lo = s.off[g], hi = s.off[g + 1];
+    for (int64_t e = lo + (int64_t)blockIdx.x * kThreads + threadIdx.x; e < hi;
          e += (int64_t)gridDim.x * kThreads) {
-        const float sc = score[e];
-        const uint32_t key = score_key(sc);
-        if (key > T) {
-            const uint32_t pos = atomicAdd(&w.st->n_sel, 1u);
-            if (pos < k_cap) {
-                w.sel_score[pos] = sc;
-                w.sel_index[pos] = entry_index(index, e);
+        const float sc = s.score[e];
+        if (score_key(sc) > T) {
+            const uint32_t pos = atomicAdd(&s.st[g].n_sel, 1u);
+            if (pos < k_eff) {
+                s.sel_score[(size_t)g * s.k + pos] = sc;
+                s.sel_index[(size_t)g * s.k + pos] = entry_index(s, g, e, lo);
             }
-        } else if (key == T) {
-            const uint32_t pos = atomicAdd(&w.st->n_tie, 1u);
-            w.tie[pos] = entry_index(index, e);
         }
     }
 }
 
-__global__ void tie_init_kernel(Work w)
+__global__ void tie_init_kernel(Seg s)
 {
+    const int g = blockIdx.x;
     if (threadIdx.x == 0) {
-        w.st->iprefix = 0ull;
-        w.st->iremaining = w.st->remaining;
-        w.st->n_lt = 0u;
+        s.st[g].iprefix = 0ull;
+        s.st[g].iremaining = s.st[g].remaining;
     }
-    for (int b = threadIdx.x; b < kBins; b += blockDim.x) w.hist[b] = 0u;
+    for (int b = threadIdx.x; b < kBins; b += blockDim.x) s.hist[(size_t)g * kBins + b] = 0u;
 }
 
-// Histogram of index digit `pass` (0 = most significant byte of the 64-bit index).
-__global__ __launch_bounds__(kThreads) void tie_hist_kernel(Work w, int pass)
+// Histogram of index digit `pass` over entries whose key equals T.  The digits cover the
+// low idx_bits of the index (rounded up to bytes); the bits above are equal in a segment.
+__global__ __launch_bounds__(kThreads) void tie_hist_kernel(Seg s, int pass, int n_pass)
 {
     __shared__ uint32_t h[kBins];
+    const int g = blockIdx.y;
+    if (s.st[g].iremaining == 0u) return;
     for (int b = threadIdx.x; b < kBins; b += kThreads) h[b] = 0u;
     __syncthreads();
-    const uint32_t nt = w.st->n_tie;
-    const unsigned long long prefix = w.st->iprefix;
-    const int shift = 56 - 8 * pass;
-    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < (int64_t)nt;
+    const int64_t lo = s.off[g], hi = s.off[g + 1];
+    const uint32_t T = s.st[g].prefix;
+    const unsigned long long prefix = s.st[g].iprefix;
+    const int shift = 8 * (n_pass - 1 - pass);
+    for (int64_t e = lo + (int64_t)blockIdx.x * kThreads + threadIdx.x; e < hi;
          e += (int64_t)gridDim.x * kThreads) {
-        const unsigned long long ix = (unsigned long long)w.tie[e];
+        if (score_key(s.score[e]) != T) continue;
+        unsigned long long ix = (unsigned long long)entry_index(s, g, e, lo);
+        if (n_pass < 8) ix &= (1ull << (8 * n_pass)) - 1ull;
         if (pass == 0 || (ix >> (shift + 8)) == prefix) atomicAdd(&h[(ix >> shift) & 0xffull], 1u);
     }
     __syncthreads();
     for (int b = threadIdx.x; b < kBins; b += kThreads)
-        if (h[b]) atomicAdd(&w.hist[b], h[b]);
+        if (h[b]) atomicAdd(&s.hist[(size_t)g * kBins + b], h[b]);
 }
 
 // Smallest indices win: take digits from the low end.
-__global__ void tie_pick_kernel(Work w)
+__global__ void tie_pick_kernel(Seg s)
 {
     __shared__ uint32_t h[kBins];
+    const int g = blockIdx.x;
     const int t = threadIdx.x;
-    h[t] = w.hist[t];
+    h[t] = s.hist[(size_t)g * kBins + t];
     __syncthreads();
-    if (t == 0) {
-        uint32_t rem = w.st->iremaining;
+    if (t == 0 && s.st[g].iremaining > 0u) {
+        const uint32_t rem = s.st[g].iremaining;
         uint32_t below = 0u;
         int d = 0;
         for (; d < kBins - 1; ++d) {
             if (below + h[d] >= rem) break;
             below += h[d];
         }
-        w.st->n_lt += below;
-        w.st->iremaining = rem - below;
-        w.st->iprefix = (w.st->iprefix << 8) | (unsigned long long)d;
+        s.st[g].iremaining = rem - below;
+        s.st[g].iprefix = (s.st[g].iprefix << 8) | (unsigned long long)d;
     }
     __syncthreads();
-    w.hist[t] = 0u;
+    s.hist[(size_t)g * kBins + t] = 0u;
 }
 
-__global__ __launch_bounds__(kThreads) void tie_take_kernel(Work w, uint32_t k_cap)
+__global__ __launch_bounds__(kThreads) void tie_take_kernel(Seg s, int n_pass)
 {
-    const uint32_t nt = w.st->n_tie;
-    const uint32_t need = w.st->remaining;
-    if (need == 0u) return;
-    const unsigned long long cut = w.st->iprefix;    // last index that makes the cut
-    const float sc = key_score(w.st->prefix);
-    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < (int64_t)nt;
+    const int g = blockIdx.y;
+    const uint32_t k_eff = s.st[g].k_eff;
+    if (k_eff == 0u || s.st[g].remaining == 0u) return;
+    const int64_t lo = s.off[g], hi = s.off[g + 1];
+    const uint32_t T = s.st[g].prefix;
+    const unsigned long long cut = s.st[g].iprefix;    // largest index (low bits) that makes the cut
+    const float sc = key_score(T);
+    for (int64_t e = lo + (int64_t)blockIdx.x * kThreads + threadIdx.x; e < hi;
          e += (int64_t)gridDim.x * kThreads) {
-        const int64_t ix = w.tie[e];
-        if ((unsigned long long)ix <= cut) {
-            const uint32_t pos = atomicAdd(&w.st->n_sel, 1u);
-            if (pos < k_cap) {
-                w.sel_score[pos] = sc;
-                w.sel_index[pos] = ix;
+        if (score_key(s.score[e]) != T) continue;
+        const int64_t ix = entry_index(s, g, e, lo);
+        unsigned long long low = (unsigned long long)ix;
+        if (n_pass < 8) low &= (1ull << (8 * n_pass)) - 1ull;
+        if (low <= cut) {
+            const uint32_t pos = atomicAdd(&s.st[g].n_sel, 1u);
+            if (pos < k_eff) {
+                s.sel_score[(size_t)g * s.k + pos] = sc;
+                s.sel_index[(size_t)g * s.k + pos] = ix;
             }
         }
     }
@@ -244,48 +262,125 @@ __device__ __forceinline__ bool precedes(float sa, int64_t ia, float sb, int64_t
     return ka > kb || (ka == kb && ia < ib);
 }
 
-// out[rank(e)] = e, rank(e) = number of chosen entries preceding e.
-__global__ __launch_bounds__(kThreads) void rank_kernel(Work w, uint32_t k_eff,
-                                                        float* __restrict__ out_score,
+// out[g][rank(e)] = e, rank(e) = number of chosen entries of segment g preceding e.
+__global__ __launch_bounds__(kThreads) void rank_kernel(Seg s, float* __restrict__ out_score,
                                                         int64_t* __restrict__ out_index)
 {
     __shared__ float ts[kThreads];
     __shared__ int64_t ti[kThreads];
+    const int g = blockIdx.y;
+    const uint32_t k_eff = s.st[g].k_eff;
+    if (blockIdx.x * kThreads >= k_eff) return;
+    const float* ss = s.sel_score + (size_t)g * s.k;
+    const int64_t* si = s.sel_index + (size_t)g * s.k;
     const uint32_t e = blockIdx.x * kThreads + threadIdx.x;
     const bool mine = e < k_eff;
-    const float s = mine ? w.sel_score[e] : 0.f;
-    const int64_t ix = mine ? w.sel_index[e] : 0;
+    const float sc = mine ? ss[e] : 0.f;
+    const int64_t ix = mine ? si[e] : 0;
     uint32_t rank = 0u;
     for (uint32_t base = 0; base < k_eff; base += kThreads) {
         __syncthreads();
         const uint32_t f = base + threadIdx.x;
-        if (f < k_eff) { ts[threadIdx.x] = w.sel_score[f]; ti[threadIdx.x] = w.sel_index[f]; }
+        if (f < k_eff) { ts[threadIdx.x] = ss[f]; ti[threadIdx.x] = si[f]; }
         __syncthreads();
         const uint32_t m = min((uint32_t)kThreads, k_eff - base);
         if (mine)
-            for (uint32_t q = 0; q < m; ++q) rank += precedes(ts[q], ti[q], s, ix) ? 1u : 0u;
+            for (uint32_t q = 0; q < m; ++q) rank += precedes(ts[q], ti[q], sc, ix) ? 1u : 0u;
     }
     if (mine && rank < k_eff) {
-        out_score[rank] = s;
-        out_index[rank] = ix;
+        out_score[(size_t)g * s.k + rank] = sc;
+        out_index[(size_t)g * s.k + rank] = ix;
     }
 }
 
-__global__ void fill_tail_kernel(uint32_t k_eff, int32_t k, float* out_score, int64_t* out_index)
+__global__ void fill_tail_kernel(Seg s, float* out_score, int64_t* out_index)
 {
-    const uint32_t e = k_eff + blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < (uint32_t)k) {
-        out_score[e] = -__builtin_huge_valf();
-        out_index[e] = -1;
+    const int g = blockIdx.y;
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < (uint32_t)s.k && e >= s.st[g].k_eff) {
+        out_score[(size_t)g * s.k + e] = -__builtin_huge_valf();
+        out_index[(size_t)g * s.k + e] = -1;
     }
+}
+
+__global__ void set_offsets_kernel(int64_t* off, int64_t n)
+{
+    off[0] = 0;
+    off[1] = n;
+}
+
+int topk_launch(Seg s, int64_t max_len, float* out_score, int64_t* out_index, hipStream_t st)
+{
+    int bps = (int)((max_len + kThreads - 1) / kThreads);
+    if (bps > kMaxBlocksPerSeg) bps = kMaxBlocksPerSeg;
+    if (bps < 1) bps = 1;
+    if (s.n_segs > 65535) return fail_inval("more than 65535 segments");
+    const dim3 grid2(bps, s.n_segs);
+    // index digits to resolve: 64 bits for explicit indices, the position bits otherwise
+    int bits = 64;
+    if (!s.index) {
+        bits = 1;
+        while (bits < 63 && ((int64_t)1 << bits) < max_len) ++bits;
+    }
+    const int n_pass = (bits + 7) / 8;
+    s.idx_bits = bits;
+
+    hipLaunchKernelGGL(init_kernel, dim3(s.n_segs), dim3(kBins), 0, st, s);
+    for (int pass = 0; pass < 4; ++pass) {
+        hipLaunchKernelGGL(key_hist_kernel, grid2, dim3(kThreads), 0, st, s, pass);
+        hipLaunchKernelGGL(key_pick_kernel, dim3(s.n_segs), dim3(kBins), 0, st, s);
+    }
+    hipLaunchKernelGGL(split_kernel, grid2, dim3(kThreads), 0, st, s);
+    hipLaunchKernelGGL(tie_init_kernel, dim3(s.n_segs), dim3(kBins), 0, st, s);
+    for (int pass = 0; pass < n_pass; ++pass) {
+        hipLaunchKernelGGL(tie_hist_kernel, grid2, dim3(kThreads), 0, st, s, pass, n_pass);
+        hipLaunchKernelGGL(tie_pick_kernel, dim3(s.n_segs), dim3(kBins), 0, st, s);
+    }
+    hipLaunchKernelGGL(tie_take_kernel, grid2, dim3(kThreads), 0, st, s, n_pass);
+    hipLaunchKernelGGL(rank_kernel, dim3((s.k + kThreads - 1) / kThreads, s.n_segs), dim3(kThreads), 0,
+                       st, s, out_score, out_index);
+    hipLaunchKernelGGL(fill_tail_kernel, dim3((s.k + 255) / 256, s.n_segs), dim3(256), 0, st, s,
+                       out_score, out_index);
+    return check_launch("bsh_topk");
 }
 
 }  // namespace
 
+namespace bsh {
+
+size_t topk_workspace_bytes(int32_t n_segs, int32_t k) { return workspace_bytes(n_segs, k); }
+
+// Segmented top-k for library-internal callers (the batched plan); offsets on the device,
+// the longest segment given by the host.
+int topk_segmented(const float* score, const int64_t* index, const int64_t* offsets, int32_t n_segs,
+                   int64_t max_len, int32_t shift, int32_t k, float* out_score, int64_t* out_index,
+                   void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (n_segs < 1 || k < 1) return fail_inval("n_segs and k must be >= 1");
+    if (ws_bytes < workspace_bytes(n_segs, k)) {
+        set_error("workspace %zu < %zu bytes", ws_bytes, workspace_bytes(n_segs, k));
+        return BSH_ENOMEM;
+    }
+    if (max_len >= (int64_t)0xffffffff) return fail_inval("segments must be shorter than 2^32 - 1");
+    Seg s;
+    std::memset(&s, 0, sizeof(s));
+    s.score = score;
+    s.index = index;
+    s.off = offsets;
+    s.n_segs = n_segs;
+    s.shift = shift;
+    s.k = k;
+    carve(ws, s);
+    return topk_launch(s, max_len, out_score, out_index, stream);
+}
+
+}  // namespace bsh
+
 extern "C" size_t bsh_topk_workspace(int64_t n, int32_t k)
 {
     if (n < 0 || k < 0) return 0;
-    return workspace_bytes(n, k);
+    // one segment plus its two offsets
+    return workspace_bytes(1, k > 0 ? k : 1) + 256;
 }
 
 extern "C" int bsh_topk(const float* score, const int64_t* index, int64_t n, int32_t k,
@@ -299,35 +394,44 @@ extern "C" int bsh_topk(const float* score, const int64_t* index, int64_t n, int
     if (!out_score || !out_index) return fail_inval("NULL output");
     if (n > 0 && !score) return fail_inval("score is NULL");
     if (!ws) return fail_inval("workspace is NULL");
-    if (ws_bytes < workspace_bytes(n, k)) {
-        set_error("workspace %zu < %zu bytes", ws_bytes, workspace_bytes(n, k));
+    const size_t need = bsh_topk_workspace(n, k);
+    if (ws_bytes < need) {
+        set_error("workspace %zu < %zu bytes", ws_bytes, need);
         return BSH_ENOMEM;
     }
     hipStream_t s = (hipStream_t)stream;
-    const uint32_t k_eff = (uint32_t)(n < (int64_t)k ? n : (int64_t)k);
-    Work w = carve(ws, n, k);
-    int blocks = (int)((n + kThreads - 1) / kThreads);
-    if (blocks > 2048) blocks = 2048;
-    if (blocks < 1) blocks = 1;
+    // the two offsets {0, n} live in the first 256 bytes of the workspace
+    int64_t* off = (int64_t*)ws;
+    hipLaunchKernelGGL(set_offsets_kernel, dim3(1), dim3(1), 0, s, off, n);
+    int rc = check_launch("bsh_topk offsets");
+    if (rc) return rc;
+    return bsh::topk_segmented(score, index, off, 1, n, 0, k, out_score, out_index,
+                               (char*)ws + 256, ws_bytes - 256, s);
+}
 
-    if (k_eff > 0) {
-        hipLaunchKernelGGL(init_kernel, dim3(1), dim3(kBins), 0, s, w, k_eff);
-        for (int pass = 0; pass < 4; ++pass) {
-            hipLaunchKernelGGL(key_hist_kernel, dim3(blocks), dim3(kThreads), 0, s, score, n, w, pass);
-            hipLaunchKernelGGL(key_pick_kernel, dim3(1), dim3(kBins), 0, s, w);
-        }
-        hipLaunchKernelGGL(split_kernel, dim3(blocks), dim3(kThreads), 0, s, score, index, n, w, k_eff);
-        hipLaunchKernelGGL(tie_init_kernel, dim3(1), dim3(kBins), 0, s, w);
-        for (int pass = 0; pass < 8; ++pass) {
-            hipLaunchKernelGGL(tie_hist_kernel, dim3(blocks), dim3(kThreads), 0, s, w, pass);
-            hipLaunchKernelGGL(tie_pick_kernel, dim3(1), dim3(kBins), 0, s, w);
-        }
-        hipLaunchKernelGGL(tie_take_kernel, dim3(blocks), dim3(kThreads), 0, s, w, k_eff);
-        hipLaunchKernelGGL(rank_kernel, dim3((k_eff + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
-                           w, k_eff, out_score, out_index);
+extern "C" size_t bsh_topk_segmented_workspace(int32_t n_segs, int32_t k)
+{
+    if (n_segs < 1 || k < 1) return 0;
+    return workspace_bytes(n_segs, k);
+}
+
+extern "C" int bsh_topk_segmented(const float* score, const int64_t* index, const int64_t* offsets,
+                                  const int64_t* offsets_host, int32_t n_segs, int32_t k,
+                                  int32_t index_shift, float* out_score, int64_t* out_index,
+                                  void* ws, size_t ws_bytes, bsh_stream stream)
+{
+    clear_error();
+    if (n_segs < 1 || k < 1) return fail_inval("n_segs and k must be >= 1");
+    if (!score || !offsets || !offsets_host || !out_score || !out_index || !ws)
+        return fail_inval("NULL pointer");
+    if (index_shift < 0 || index_shift > 62) return fail_inval("index_shift out of 0..62");
+    int64_t max_len = 0;
+    if (offsets_host[0] < 0) return fail_inval("offsets[0] < 0");
+    for (int32_t g = 0; g < n_segs; ++g) {
+        const int64_t len = offsets_host[g + 1] - offsets_host[g];
+        if (len < 0) return fail_inval("offsets not monotone");
+        if (len > max_len) max_len = len;
     }
-    if ((uint32_t)k > k_eff)
-        hipLaunchKernelGGL(fill_tail_kernel, dim3((k - k_eff + 255) / 256), dim3(256), 0, s, k_eff, k,
-                           out_score, out_index);
-    return check_launch("bsh_topk");
+    return bsh::topk_segmented(score, index, offsets, n_segs, max_len, index_shift, k, out_score,
+                               out_index, ws, ws_bytes, (hipStream_t)stream);
 }

@@ -137,9 +137,42 @@ def test_other_entry_points_reject_bad_arguments():
     assert L.bsh_power_stat(ctypes.byref(seg), fake, 1, fake, fake, 0, 0, fake, None, None, None, None) == N.BSH_OK
 
 
-def test_topk_workspace_grows_with_n_and_k():
+def test_topk_workspace_is_order_k():
+    """The tie resolution re-reads the scores, so the workspace does not grow with n."""
     L = _lib()
     a = L.bsh_topk_workspace(1000, 10)
-    b = L.bsh_topk_workspace(100000, 10)
+    b = L.bsh_topk_workspace(10**9, 10)
     c = L.bsh_topk_workspace(1000, 5000)
-    assert b > a and c > a and a >= 8 * 1000
+    assert a == b and c > a and c >= 12 * 5000
+    assert L.bsh_topk_segmented_workspace(100, 10) > L.bsh_topk_segmented_workspace(1, 10)
+
+
+def test_plan_rejects_bad_items_on_host():
+    from paper_1904_04873_amd import _native as N
+    L = _lib()
+    seg, grid, keep = _structs()
+    fake = ctypes.c_void_p(0x2000)
+    items = (N.Item * 2)()
+    items[0] = N.Item(seg=seg, grid=0, sky_lo=0, n_sky=1, band=1)
+    items[1] = N.Item(seg=seg, grid=0, sky_lo=0, n_sky=1, band=0)     # bands out of order
+    grids = (N.Grid * 1)(grid)
+    h = ctypes.c_void_p()
+    opts = N.PlanOpts()
+    assert L.bsh_plan_create(items, 2, grids, 1, 2, ctypes.byref(opts), fake, 10**9, None, None, None,
+                             None, None, ctypes.byref(h)) == N.BSH_EINVAL
+    assert b"ordered by band" in L.bsh_last_error()
+    items[1] = N.Item(seg=seg, grid=3, sky_lo=0, n_sky=1, band=1)     # grid index out of range
+    assert L.bsh_plan_create(items, 2, grids, 1, 2, ctypes.byref(opts), fake, 10**9, None, None, None,
+                             None, None, ctypes.byref(h)) == N.BSH_EINVAL
+    items[1] = N.Item(seg=seg, grid=0, sky_lo=1, n_sky=1, band=1)     # pixel outside the grid's sky
+    assert L.bsh_plan_create(items, 2, grids, 1, 2, ctypes.byref(opts), fake, 10**9, None, None, None,
+                             None, None, ctypes.byref(h)) == N.BSH_EINVAL
+    items[1] = N.Item(seg=seg, grid=0, sky_lo=0, n_sky=1, band=1)
+    assert L.bsh_items_map_floats(items, 2, grids, 1) == 2 * 46080
+    assert L.bsh_plan_create(items, 2, grids, 1, 2, ctypes.byref(opts), fake, 1000, None, None, None,
+                             None, None, ctypes.byref(h)) == N.BSH_ENOMEM
+    bad = N.PlanOpts(lanes=96)
+    assert L.bsh_plan_create(items, 2, grids, 1, 2, ctypes.byref(bad), fake, 10**9, None, None, None,
+                             None, None, ctypes.byref(h)) == N.BSH_EINVAL
+    assert L.bsh_plan_destroy(None) == N.BSH_OK
+    assert L.bsh_plan_units(None) == -1

@@ -1,0 +1,165 @@
+"""The batched plan: one persistent launch over uneven work items, replayed from a HIP graph.
+
+Integer-exact and FP32-bitwise claims: the per-lane accumulation order does not depend on the
+launch form or the tile shape, so batched, plain and single-item maps are bitwise identical.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import bsh_synth as S
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+ITEMS = [0, 1, 2, 256, 257, 1023]   # band 0 patches 0-2, band 1 patches 0-1, band 3 patch 255
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    from paper_1904_04873_amd import bsh
+    w = S.config3(build_items=ITEMS)
+    dsegs, grids, items, hosts = [], [], [], []
+    bands = sorted({w.item_grid[i] for i in ITEMS})
+    for q, it in enumerate(ITEMS):
+        seg = w.segments[it]
+        band = w.item_grid[it]
+        g = bsh.DeviceGrid.build(w.grids[band], seg.t_span_mid(), w.sky)
+        ds = bsh.DeviceSegments.from_host(seg)
+        p_lo, _ = w.item_sky[it]
+        items.append((ds, q, p_lo, 1, bands.index(band)))
+        dsegs.append(ds)
+        grids.append(g)
+        hosts.append((seg, w.grids[band]))
+    torch.cuda.synchronize()
+    return w, bsh, items, grids, hosts, len(bands)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def test_batched_equals_plain_and_single_item(setup):
+    import torch
+    w, bsh, items, grids, hosts, n_bands = setup
+    _say("batched vs plain vs single")
+    plan = bsh.Plan(items, grids, n_bands, k_item=500, k_band=300, use_graph=False)
+    plan.run()
+    torch.cuda.synchronize()
+    plan.status.raise_if_set("batched")
+    m_b = plan.maps.clone()
+    li_b = (plan.item_score.clone(), plan.item_index.clone())
+    lb_b = (plan.band_score.clone(), plan.band_index.clone())
+    plan.maps.fill_(-1.0)
+    plan.run_plain()
+    torch.cuda.synchronize()
+    plan.status.raise_if_set("plain")
+    assert torch.equal(plan.maps, m_b)
+    assert torch.equal(plan.item_score, li_b[0]) and torch.equal(plan.item_index, li_b[1])
+    assert torch.equal(plan.band_score, lb_b[0]) and torch.equal(plan.band_index, lb_b[1])
+    # each item's map equals a standalone bsh_hough_count of that item (its pixel only)
+    for q, (ds, gi, lo, ns, band) in enumerate(items):
+        g = grids[gi]
+        g1 = bsh.DeviceGrid.from_tables(_np(g.sky)[lo:lo + 1], g.k0, g.n_f0, g.a_p, g.period, g.tasc_off,
+                                        _np(g.t_asc_dev))
+        ws, _ = bsh.bsh_hough_count(ds, g1)
+        torch.cuda.synchronize()
+        assert torch.equal(ws, plan.item_map(q)), f"item {q}"
+    plan.close()
+
+
+def test_lists_are_exact_topk_of_maps(setup):
+    import torch
+    w, bsh, items, grids, hosts, n_bands = setup
+    _say("plan lists vs sort")
+    plan = bsh.Plan(items, grids, n_bands, k_item=700, k_band=900, use_graph=True)
+    plan.run()
+    torch.cuda.synchronize()
+    allsc, allix = [], []
+    for q in range(len(items)):
+        m = plan.item_map(q)
+        order = torch.sort(m, descending=True, stable=True).indices[:700]
+        assert torch.equal(plan.item_index[q], order | (q << 40))
+        assert torch.equal(plan.item_score[q], m[order])
+    for b in range(n_bands):
+        qs = [q for q, it in enumerate(items) if it[4] == b]
+        sc = torch.cat([plan.item_score[q] for q in qs]).cpu().numpy()
+        ix = torch.cat([plan.item_index[q] for q in qs]).cpu().numpy()
+        rv, ri = O.topk(sc, 900, ix)
+        k = min(900, sc.size)
+        assert np.array_equal(_np(plan.band_index[b])[:k], ri)
+        assert np.array_equal(_np(plan.band_score[b])[:k], rv)
+    plan.close()
+
+
+def test_item_maps_match_oracle_on_samples(setup):
+    import torch
+    w, bsh, items, grids, hosts, n_bands = setup
+    _say("plan maps vs oracle samples")
+    plan = bsh.Plan(items, grids, n_bands, use_graph=False)
+    plan.run()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3)
+    for q, (ds, gi, lo, ns, band) in enumerate(items):
+        seg, spec = hosts[q]
+        g = grids[gi]
+        m = _np(plan.item_map(q))
+        idx = rng.integers(0, m.size, 400)
+        s, b, i, ia, ip = O.decode_index(idx, g.n_bin, spec.n_f0, g.tasc_off, spec.n_per)
+        o = O.grid_tables(spec, seg.t_span_mid())
+        cand = np.stack([(spec.k0 + i).astype(np.float64), o[0][ia], o[1][ip], o[3][b]], axis=1)
+        _, c_o, nw_o, nt_o = O.power_stat(seg, w.sky[lo:lo + 1], s.astype(np.int32), cand, mode=0)
+        err = np.abs(m[idx].astype(np.float64) - nw_o)
+        assert np.all(err <= 1e-5 * nw_o + nt_o * float(seg.weight.max())), f"item {q}"
+    plan.close()
+
+
+def test_graph_replays_match_eager(setup):
+    import torch
+    w, bsh, items, grids, hosts, n_bands = setup
+    _say("graph replays")
+    eager = bsh.Plan(items, grids, n_bands, k_item=200, k_band=100, use_graph=False)
+    eager.run()
+    torch.cuda.synchronize()
+    ref = (eager.maps.clone(), eager.band_index.clone(), eager.band_score.clone())
+    eager.close()
+    graph = bsh.Plan(items, grids, n_bands, k_item=200, k_band=100, use_graph=True)
+    junk = torch.randn(1 << 20, device="cuda")
+    for rep in range(3):
+        graph.maps.fill_(0.0)
+        graph.band_index.fill_(-7)
+        junk = (junk * 1.0001).sin()          # unrelated eager work between replays
+        graph.run()
+        torch.cuda.synchronize()
+        assert torch.equal(graph.maps, ref[0]), f"replay {rep}"
+        assert torch.equal(graph.band_index, ref[1]) and torch.equal(graph.band_score, ref[2])
+    graph.close()
+
+
+def test_every_tile_shape_gives_identical_maps(setup):
+    import torch
+    w, bsh, items, grids, hosts, n_bands = setup
+    _say("tile shapes")
+    ds, gi, lo, ns, band = items[3]
+    g = grids[gi]
+    g1 = bsh.DeviceGrid.from_tables(_np(g.sky)[lo:lo + 1], g.k0, g.n_f0, g.a_p, g.period, g.tasc_off,
+                                    _np(g.t_asc_dev))
+    ref, rc = bsh.bsh_hough_count(ds, g1, with_count=True)
+    for lanes in (64, 128, 256):
+        for chunk in (128, 256, 512):
+            ws, c = bsh.bsh_hough_count(ds, g1, with_count=True, lanes=lanes, chunk=chunk)
+            torch.cuda.synchronize()
+            assert torch.equal(ws, ref) and torch.equal(c, rc), (lanes, chunk)
+    plan = bsh.Plan([items[3]], [g], 1, lanes=64, chunk=512, use_graph=False, lpt=False)
+    plan.run()
+    torch.cuda.synchronize()
+    assert torch.equal(plan.item_map(0), ref)
+    plan.close()
