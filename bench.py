@@ -9,6 +9,12 @@ Default workload: 4000 segments (2 detectors x 2000, gapped), one sky pixel, ban
 200.0-200.1 Hz (90 f0 bins), a_p 64 x P 32 x t_asc 64 -> 11 796 480 templates; stage-1
 top-10^4 then stage-2 top-100.  Work unit: template x segment of stage 1.
 
+The same line carries the batched-versus-plain comparison on the full batching workload: 256 sky
+patches x 4 bands of 0.1 Hz in 100-300 Hz (1024 items, 3000-6000 gapped segments each, uneven
+t_asc counts per cell; 9.01e9 templates, ~4e13 template x segments), stage 1 plus per-item top-1000
+and per-band top-1000 lists, once as one graph-captured persistent launch and once as one plain
+launch (and top-k) per item.
+
 Prints one JSON line.  The CPU oracle is timed on a bounded sample of the same workload.
 """
 import argparse
@@ -36,6 +42,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-ap", type=int, default=8,
                     help="a_p values (of 64) in the oracle's timed sample")
+    ap.add_argument("--skip-batched", action="store_true",
+                    help="omit the batched-versus-plain comparison")
+    ap.add_argument("--batched-steps", type=int, default=2)
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="before timing, run one plain device copy of this many MiB (a known-size "
                          "kernel for scaling HBM byte counters)")
@@ -124,6 +133,8 @@ def main():
     achieved = OPS_PER_TS * ts_per_step / (count_ms / 1e3)
     print(f"[bench] {ms_step:.3f} ms/step, count kernel {count_ms:.3f} ms", file=sys.stderr, flush=True)
 
+    batched = None if args.skip_batched else run_batched(args)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle as O
@@ -176,8 +187,85 @@ def main():
             "ops_per_template_segment": OPS_PER_TS,
         },
         "cpu_baseline": cpu,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
+
+
+def run_batched(args):
+    """Full batching workload: one graph-captured persistent launch vs one plain launch per item."""
+    import numpy as np
+    import torch
+
+    import bsh_synth as S
+    from paper_1904_04873_amd import autotune, bsh
+
+    dev = torch.device("cuda:0")
+    print("[bench] batching workload: generating 1024 items", file=sys.stderr, flush=True)
+    w = S.config3()
+    items, grids = [], []
+    ts_total = 0
+    for it in range(len(w.segments)):
+        seg = w.segments[it]
+        band = w.item_grid[it]
+        g = bsh.DeviceGrid.build(w.grids[band], seg.t_span_mid(), w.sky, device=dev)
+        ds = bsh.DeviceSegments.from_host(seg, device=dev)
+        lo, hi = w.item_sky[it]
+        items.append((ds, it, lo, hi - lo, band))
+        grids.append(g)
+        ts_total += (hi - lo) * g.n_bin * g.n_f0 * seg.n_seg
+        w.segments[it] = None        # drop the host copy
+    torch.cuda.synchronize()
+    print(f"[bench] batching workload resident: {ts_total:.3e} template*segments; autotuning",
+          file=sys.stderr, flush=True)
+    (lanes, chunk), tune_ms = autotune.tune(items, grids, 4, sample=16, use_cache=False)
+    k_item, k_band = 1000, 1000
+    st = bsh.Status(dev)
+    plan = bsh.Plan(items, grids, 4, k_item=k_item, k_band=k_band, lanes=lanes, chunk=chunk,
+                    use_graph=True, lpt=True, status=st)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        out = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            out.append(a.elapsed_time(b))
+        return float(np.median(out))
+
+    print("[bench] batched runs", file=sys.stderr, flush=True)
+    ms_b = timed(plan.run, args.batched_steps)
+    st.raise_if_set("batched")
+    ref = plan.band_index.clone()
+    print("[bench] plain runs", file=sys.stderr, flush=True)
+    ms_p = timed(plan.run_plain, args.batched_steps)
+    st.raise_if_set("plain")
+    same = bool(torch.equal(ref, plan.band_index))
+    units, blocks = plan.units, plan.blocks
+    plan.close()
+    return {
+        "workload": "256 sky patches x 4 bands of 0.1 Hz (f_lo 100.0/166.6/233.2/299.8 Hz): 1024 items "
+                    "of 3000-6000 gapped segments, a_p 64 x P 32 x t_asc 4-256 per cell, 90 f0; "
+                    "per-item top-1000 and per-band top-1000",
+        "items": len(items),
+        "template_segments": ts_total,
+        "batched_ms": ms_b,
+        "plain_ms": ms_p,
+        "batched_value": ts_total / (ms_b / 1e3),
+        "plain_value": ts_total / (ms_p / 1e3),
+        "speedup": ms_p / ms_b,
+        "lists_identical": same,
+        "tile": {"lanes": lanes, "chunk": chunk},
+        "autotune_ms": {f"{l}x{c}": t for (l, c), t in tune_ms.items()},
+        "units": units,
+        "persistent_blocks": blocks,
+    }
 
 
 if __name__ == "__main__":

@@ -150,12 +150,21 @@ int bsh_hough_count(const bsh_segments* seg, const bsh_grid* grid, uint32_t* cou
                     float* wsum_out, int32_t* status, bsh_stream stream);
 
 /*
- * Same as bsh_hough_count with an explicit tile shape: `lanes` binary templates per block
- * (64, 128 or 256) and `chunk` segments staged in LDS per pass (128, 256 or 512).  Results do
- * not depend on the shape.
+ * Same as bsh_hough_count with an explicit tile shape and accumulation variant: `lanes` binary
+ * templates per block (64, 128 or 256), `chunk` segments staged in LDS per pass (128, 256 or
+ * 512), and `variant`:
+ *   BSH_VARIANT_SELECT  every peak bit selects its weight, which is added;
+ *   BSH_VARIANT_TABLE   segments in groups of four, whose 16 subset sums of weights are looked
+ *                       up with the four peak bits as index (weighted sums only);
+ *   BSH_VARIANT_AUTO    the table unless counts are requested (the default of bsh_hough_count).
+ * Results do not depend on the tile shape; the two variants agree to FP32 rounding.
  */
+#define BSH_VARIANT_AUTO 0
+#define BSH_VARIANT_SELECT 1
+#define BSH_VARIANT_TABLE 2
 int bsh_hough_count_ex(const bsh_segments* seg, const bsh_grid* grid, int32_t lanes, int32_t chunk,
-                       uint32_t* count_out, float* wsum_out, int32_t* status, bsh_stream stream);
+                       int32_t variant, uint32_t* count_out, float* wsum_out, int32_t* status,
+                       bsh_stream stream);
 
 /*
  * Exact top-k under the total order (score descending, index ascending) (Sec. IV.C
@@ -249,6 +258,7 @@ typedef struct bsh_plan_opts {
     int32_t use_graph;    /* 1: capture one run in a HIP graph at creation, replay it */
     int32_t lpt;          /* 1: queue units longest-first */
     int32_t blocks;       /* persistent blocks (0: CUs x resident blocks per CU) */
+    int32_t variant;      /* accumulation variant as in bsh_hough_count_ex */
 } bsh_plan_opts;
 
 typedef struct bsh_plan bsh_plan;

@@ -18,6 +18,9 @@ STATUS_INPUT = 4
 MAX_PER = 256
 MAX_F0 = 90
 MAX_WORDS = 16
+VARIANT_AUTO = 0
+VARIANT_SELECT = 1
+VARIANT_TABLE = 2
 
 _c_i32 = ctypes.c_int32
 _c_i64 = ctypes.c_int64
@@ -96,6 +99,7 @@ class PlanOpts(ctypes.Structure):
         ("use_graph", _c_i32),
         ("lpt", _c_i32),
         ("blocks", _c_i32),
+        ("variant", _c_i32),
     ]
 
 
@@ -109,7 +113,7 @@ SIGNATURES = {
     "bsh_hough_count": (ctypes.c_int, [ctypes.POINTER(Segments), ctypes.POINTER(Grid), _vp, _vp, _vp,
                                        _vp]),
     "bsh_hough_count_ex": (ctypes.c_int, [ctypes.POINTER(Segments), ctypes.POINTER(Grid), _c_i32, _c_i32,
-                                          _vp, _vp, _vp, _vp]),
+                                          _c_i32, _vp, _vp, _vp, _vp]),
     "bsh_items_map_floats": (_c_i64, [ctypes.POINTER(Item), _c_i32, ctypes.POINTER(Grid), _c_i32]),
     "bsh_plan_create": (ctypes.c_int, [ctypes.POINTER(Item), _c_i32, ctypes.POINTER(Grid), _c_i32, _c_i32,
                                        ctypes.POINTER(PlanOpts), _vp, _c_i64, _vp, _vp, _vp, _vp, _vp,

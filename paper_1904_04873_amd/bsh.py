@@ -203,19 +203,20 @@ def bsh_peakgram(power: torch.Tensor, rho_th: float = 1.6, out: Optional[torch.T
 
 def bsh_hough_count(seg: DeviceSegments, grid: DeviceGrid, with_count: bool = False,
                     status: Optional[Status] = None, wsum_out=None, count_out=None,
-                    lanes: int = 0, chunk: int = 0):
+                    lanes: int = 0, chunk: int = 0, variant: int = 0):
     """Stage-1 map: (wsum float32 [n_templates], count int32 [n_templates] or None).
 
-    lanes / chunk select the tile shape (bsh_hough_count_ex); 0 keeps the default."""
+    lanes / chunk select the tile shape and variant the accumulation (bsh_hough_count_ex:
+    0 auto, 1 select-and-add, 2 subset-sum tables); 0 keeps the defaults."""
     dev = seg.t_mid.device
     if wsum_out is None:
         wsum_out = torch.empty(grid.n_templates, dtype=torch.float32, device=dev)
     if with_count and count_out is None:
         count_out = torch.empty(grid.n_templates, dtype=torch.int32, device=dev)
     s_c, g_c = seg.struct(), grid.struct()
-    if lanes or chunk:
+    if lanes or chunk or variant:
         check(N.load().bsh_hough_count_ex(ctypes.byref(s_c), ctypes.byref(g_c), int(lanes or 256),
-                                          int(chunk or 256), _ptr(count_out), _ptr(wsum_out),
+                                          int(chunk or 256), int(variant), _ptr(count_out), _ptr(wsum_out),
                                           status.ptr() if status else None, _stream()),
               "bsh_hough_count_ex")
     else:
@@ -324,7 +325,8 @@ class Plan:
 
     def __init__(self, items, grids: Sequence[DeviceGrid], n_bands: int, k_item: int = 0,
                  k_band: int = 0, lanes: int = 0, chunk: int = 0, use_graph: bool = True,
-                 lpt: bool = True, blocks: int = 0, status: Optional[Status] = None, device="cuda"):
+                 lpt: bool = True, blocks: int = 0, variant: int = 0, status: Optional[Status] = None,
+                 device="cuda"):
         L = N.load()
         self._keep = [items, grids]
         self.n_items = len(items)
@@ -347,7 +349,8 @@ class Plan:
         self.band_index = torch.empty((self.n_bands, max(1, self.k_band)), dtype=torch.int64, device=device)
         self.status = status if status is not None else Status(device)
         opts = N.PlanOpts(lanes=int(lanes), chunk=int(chunk), k_item=self.k_item, k_band=self.k_band,
-                          use_graph=int(bool(use_graph)), lpt=int(bool(lpt)), blocks=int(blocks))
+                          use_graph=int(bool(use_graph)), lpt=int(bool(lpt)), blocks=int(blocks),
+                          variant=int(variant))
         h = ctypes.c_void_p()
         check(L.bsh_plan_create(arr_i, self.n_items, arr_g, len(grids), self.n_bands, ctypes.byref(opts),
                                 _ptr(self.maps), self.maps.numel(), _ptr(self.item_score),

@@ -14,7 +14,8 @@
 struct bsh_plan {
     int32_t n_items = 0, n_bands = 0, k_item = 0, k_band = 0;
     int32_t lanes = bsh::kDefaultLanes, chunk = bsh::kDefaultChunk, blocks = 0;
-    bool with_count = false, use_graph = false;
+    bool use_graph = false;
+    int32_t mode = 2;
     int64_t n_units = 0, max_item_len = 0, max_band_len = 0;
     std::vector<bsh::ItemDesc> items;            // host copies (plain mode)
     std::vector<bsh::PlainLaunch> plain;          // per-item plain launch parameters
@@ -100,7 +101,7 @@ int enqueue_batched(bsh_plan* p, hipStream_t s)
     int rc = zero_words(p->d_counter, 1, s);
     if (rc) return rc;
     rc = launch_batch(p->d_items, p->d_units, p->n_units, p->d_counter, p->blocks, p->lanes, p->chunk,
-                      p->with_count, s);
+                      p->mode, s);
     if (rc) return rc;
     if (p->k_item > 0) {
         rc = topk_segmented(p->maps, nullptr, p->d_item_off, p->n_items, p->max_item_len, kItemShift,
@@ -146,6 +147,7 @@ extern "C" int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh
     const int lanes = o.lanes ? o.lanes : kDefaultLanes;
     const int chunk = o.chunk ? o.chunk : kDefaultChunk;
     if (!valid_tile_shape(lanes, chunk)) return fail_inval("tile shape: lanes 64/128/256, chunk 128/256/512");
+    if (o.variant < BSH_VARIANT_AUTO || o.variant > BSH_VARIANT_TABLE) return fail_inval("variant");
     if (o.k_item < 0 || o.k_band < 0) return fail_inval("k_item / k_band < 0");
     if (o.k_band > 0 && o.k_item == 0) return fail_inval("band lists need item lists");
     if (o.k_band > 0 && (!band_score || !band_index)) return fail_inval("band outputs are NULL");
@@ -164,7 +166,7 @@ extern "C" int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh
     p->k_band = o.k_band;
     p->lanes = lanes;
     p->chunk = chunk;
-    p->with_count = false;
+    p->mode = kernel_mode(o.variant, false);
     p->use_graph = o.use_graph != 0;
     p->maps = maps;
     p->band_score = band_score;
@@ -226,7 +228,7 @@ extern "C" int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh
     int dev = 0, n_cu = 0;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
-    p->blocks = std::max(1, n_cu) * batch_blocks_per_cu(lanes, chunk, p->with_count);
+    p->blocks = std::max(1, n_cu) * batch_blocks_per_cu(lanes, chunk, p->mode);
     if (o.blocks > 0) p->blocks = o.blocks;
 
     rc = dev_alloc(&p->d_items, n_items);
@@ -309,7 +311,7 @@ extern "C" int bsh_plan_run_plain(bsh_plan* p, bsh_stream stream)
         if (p->items[i].n_seg == 0)
             rc = zero_words(p->maps + p->item_off[i], len, s);
         else
-            rc = launch_plain(p->plain[i], p->plain_blocks[i], p->lanes, p->chunk, false, s);
+            rc = launch_plain(p->plain[i], p->plain_blocks[i], p->lanes, p->chunk, p->mode, s);
         if (rc) return rc;
         if (p->k_item > 0) {
             // one list per item, from that item's own launch

@@ -56,6 +56,18 @@ struct WorkUnit {
     int32_t tile;       // tile inside the period group
 };
 
+constexpr int kGroup = 4;            // segments per subset-sum table (table variant)
+constexpr int kFlushGroups = 64;     // groups per register partial sum (table variant)
+
+template <int kChunk>
+struct TileSmemLut {
+    double C[kChunk];
+    double S[kChunk];
+    double D[kChunk];
+    float T[(kChunk / kGroup) * 16];
+    uint32_t row[kChunk * (BSH_MAX_WORDS + kRowPad)];
+};
+
 template <int kChunk>
 struct TileSmem {
     double C[kChunk];
@@ -69,11 +81,12 @@ int64_t plan_tiles(const bsh_grid* g, int lanes, int32_t* tile_start, int64_t* g
 void fill_desc(ItemDesc& d, const bsh_segments* seg, const bsh_grid* grid, int32_t sky_lo,
                int32_t n_sky, uint32_t* count_out, float* wsum_out, int32_t* status);
 int zero_words(void* p, int64_t n_words, hipStream_t stream);
-int launch_plain(const PlainLaunch& p, int64_t blocks, int lanes, int chunk, bool with_count,
-                 hipStream_t stream);
+// mode: 0 select-and-add (weighted sums), 1 select-and-add with counts, 2 subset-sum tables
+int launch_plain(const PlainLaunch& p, int64_t blocks, int lanes, int chunk, int mode, hipStream_t stream);
 int launch_batch(const ItemDesc* items, const WorkUnit* units, int64_t n_units, uint32_t* counter,
-                 int blocks, int lanes, int chunk, bool with_count, hipStream_t stream);
-int batch_blocks_per_cu(int lanes, int chunk, bool with_count);
+                 int blocks, int lanes, int chunk, int mode, hipStream_t stream);
+int batch_blocks_per_cu(int lanes, int chunk, int mode);
+int kernel_mode(int variant, bool with_count);
 bool valid_tile_shape(int lanes, int chunk);
 
 }  // namespace bsh

@@ -38,6 +38,58 @@ __device__ __forceinline__ uint32_t upper_mask(int t)
     return t <= 0 ? 0xffffffffu : (t >= 32 ? 0u : (0xffffffffu << t));
 }
 
+
+// The peak bits of the band's n_f0 templates of one (binary template, segment): bit i of the
+// 96-bit (m0, m1, m2) is the peakgram bit of f0 bin i's track.  Returns false (and flags) when
+// the track leaves the staged row or drifts more than one bin across the band.
+__device__ __forceinline__ bool band_mask(const uint32_t* row, double C, double S, double D, double cb,
+                                          double sb, double apW, double F0, double FL, double klo,
+                                          int last, int n_bins, uint32_t& m0, uint32_t& m1,
+                                          uint32_t& m2, bool& bad_range, bool& bad_model)
+{
+    // same operation order as orbit_phase / track_x: G = D (1 - a_p W cos phi)
+    const double cphi = fma(C, cb, S * sb);
+    const double G = D * (1.0 - apW * cphi);
+    const double kf = floor(F0 * G + 0.5);
+    const double kl = floor(FL * G + 0.5);
+    const int base = (int)(kf - klo);
+    const int top = (int)(kl - klo);
+    const int delta = top - base - last;
+    if (base < 0 || top >= n_bins) { bad_range = true; return false; }
+    if (delta < -1 || delta > 1) { bad_model = true; return false; }
+    const int r0 = (int)(kf - F0);
+    const int qw = base >> 5;
+    const int sh = base & 31;
+    const uint32_t w0 = row[qw], w1 = row[qw + 1], w2 = row[qw + 2], w3 = row[qw + 3];
+    m0 = __builtin_amdgcn_alignbit(w1, w0, sh);
+    m1 = __builtin_amdgcn_alignbit(w2, w1, sh);
+    m2 = __builtin_amdgcn_alignbit(w3, w2, sh);
+    if (delta != 0) {
+        int lo = 0, hi = last;   // r_lo = r0, r_hi = r0 + delta
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            const double Fm = F0 + (double)mid;
+            const int rm = (int)(floor(Fm * G + 0.5) - Fm);
+            if (rm == r0) lo = mid; else hi = mid;
+        }
+        uint32_t n0, n1, n2;
+        if (delta > 0) {
+            n0 = __builtin_amdgcn_alignbit(m1, m0, 1);
+            n1 = __builtin_amdgcn_alignbit(m2, m1, 1);
+            n2 = m2 >> 1;
+        } else {
+            n0 = m0 << 1;
+            n1 = __builtin_amdgcn_alignbit(m1, m0, 31);
+            n2 = __builtin_amdgcn_alignbit(m2, m1, 31);
+        }
+        const uint32_t s0 = upper_mask(hi), s1 = upper_mask(hi - 32), s2 = upper_mask(hi - 64);
+        m0 = (n0 & s0) | (m0 & ~s0);
+        m1 = (n1 & s1) | (m1 & ~s1);
+        m2 = (n2 & s2) | (m2 & ~s2);
+    }
+    return true;
+}
+
 template <bool kCount, int kChunk>
 __device__ __forceinline__ void count_tile(const ItemDesc& d, int s, int ip, int64_t tile,
                                            TileSmem<kChunk>& sm)
@@ -101,48 +153,10 @@ __device__ __forceinline__ void count_tile(const ItemDesc& d, int s, int ip, int
         if (!active) continue;
 
         for (int jj = 0; jj < nj; ++jj) {
-            // same operation order as orbit_phase / track_x: G = D (1 - a_p W cos phi)
-            const double cphi = fma(sm.C[jj], cb, sm.S[jj] * sb);
-            const double G = sm.D[jj] * (1.0 - apW * cphi);
-            const double kf = floor(F0 * G + 0.5);
-            const double kl = floor(FL * G + 0.5);
-            const int r0 = (int)(kf - F0);
-            const int delta = (int)(kl - FL) - r0;
-            const int base = (int)(kf - klo);
-            const int top = (int)(kl - klo);
-            if (base < 0 || top >= d.n_bins) { bad_range = true; continue; }
-            if (delta < -1 || delta > 1) { bad_model = true; continue; }
-
-            const uint32_t* row = sm.row + jj * nwp;
-            const int qw = base >> 5;
-            const int sh = base & 31;
-            const uint32_t w0 = row[qw], w1 = row[qw + 1], w2 = row[qw + 2], w3 = row[qw + 3];
-            uint32_t m0 = __builtin_amdgcn_alignbit(w1, w0, sh);
-            uint32_t m1 = __builtin_amdgcn_alignbit(w2, w1, sh);
-            uint32_t m2 = __builtin_amdgcn_alignbit(w3, w2, sh);
-            if (delta != 0) {
-                int lo = 0, hi = last;   // r_lo = r0, r_hi = r0 + delta
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    const double Fm = F0 + (double)mid;
-                    const int rm = (int)(floor(Fm * G + 0.5) - Fm);
-                    if (rm == r0) lo = mid; else hi = mid;
-                }
-                uint32_t n0, n1, n2;
-                if (delta > 0) {
-                    n0 = __builtin_amdgcn_alignbit(m1, m0, 1);
-                    n1 = __builtin_amdgcn_alignbit(m2, m1, 1);
-                    n2 = m2 >> 1;
-                } else {
-                    n0 = m0 << 1;
-                    n1 = __builtin_amdgcn_alignbit(m1, m0, 31);
-                    n2 = __builtin_amdgcn_alignbit(m2, m1, 31);
-                }
-                const uint32_t s0 = upper_mask(hi), s1 = upper_mask(hi - 32), s2 = upper_mask(hi - 64);
-                m0 = (n0 & s0) | (m0 & ~s0);
-                m1 = (n1 & s1) | (m1 & ~s1);
-                m2 = (n2 & s2) | (m2 & ~s2);
-            }
+            uint32_t m0, m1, m2;
+            if (!band_mask(sm.row + jj * nwp, sm.C[jj], sm.S[jj], sm.D[jj], cb, sb, apW, F0, FL, klo,
+                           last, d.n_bins, m0, m1, m2, bad_range, bad_model))
+                continue;
 
             const uint32_t wb = __float_as_uint(sm.W[jj]);
 #pragma unroll
@@ -173,10 +187,172 @@ __device__ __forceinline__ void count_tile(const ItemDesc& d, int s, int ip, int
     }
 }
 
-template <bool kCount, int kChunk>
-__global__ __launch_bounds__(kMaxLanes) void hough_count_kernel(const PlainLaunch p)
+
+// Table variant of the weighted count.  Segments are taken in groups of four; a 16-entry
+// table per group holds every subset sum of the group's four weights.  For each f0 bin the
+// four peak bits of the group form a 4-bit index, so one table read and one add replace four
+// select-and-add steps.  The indices of all 90 bins come from the four 96-bit masks by a bit
+// interleave: word A[w][r] holds, in nibble n, the four segments' bits of bin 32w + 4n + r.
+// A 16-entry table occupies 16 consecutive LDS banks, so any pattern of reads is free of
+// bank conflicts.  The 90 register partial sums (at most kFlushGroups groups each) are folded
+// into the lane's own slots of the output map, which keeps the register footprint small
+// enough for two waves per SIMD; the error of the two-level sum stays below
+// (kFlushGroups + n_seg / (4 kFlushGroups)) FP32 ulps of the total.
+template <int kChunk>
+__device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip, int64_t tile,
+                                               TileSmemLut<kChunk>& sm)
 {
-    __shared__ TileSmem<kChunk> sm;
+    static_assert(kChunk % kGroup == 0, "chunks hold whole groups");
+    const int tid = threadIdx.x;
+    const int lanes = blockDim.x;
+    const int64_t q = tile * lanes + tid;
+
+    int ia = -1;
+    int64_t j = 0, cum = 0;
+    for (int a = 0; a < d.n_ap; ++a) {
+        const int64_t c0 = d.tasc_off[(int64_t)a * d.n_per + ip];
+        const int64_t n = d.tasc_off[(int64_t)a * d.n_per + ip + 1] - c0;
+        if (ia < 0 && q < cum + n) { ia = a; j = q - cum; }
+        cum += n;
+    }
+    const bool active = ia >= 0;
+    const int64_t b = active ? d.tasc_off[(int64_t)ia * d.n_per + ip] + j : 0;
+    const double W = kTwoPi / d.period[ip];
+    const double apW = active ? d.a_p[ia] * W : 0.0;
+    double sb = 0.0, cb = 1.0;
+    if (active) sincos(W * d.t_asc[b], &sb, &cb);
+
+    const int sg = d.sky_lo + s;
+    const double nx = d.sky[3 * sg], ny = d.sky[3 * sg + 1], nz = d.sky[3 * sg + 2];
+    const float* wrow = d.w + (d.w_per_sky ? (int64_t)s * d.n_seg : 0);
+    const double F0 = (double)d.k0;
+    const int last = d.n_f0 - 1;
+    const double FL = (double)(d.k0 + last);
+    const double klo = (double)d.k_lo;
+    const int nwp = d.n_words + kRowPad;
+
+    float acc[kNF];
+#pragma unroll
+    for (int i = 0; i < kNF; ++i) acc[i] = 0.f;
+    int since_flush = 0;
+    bool flushed = false;
+    float* out = d.wsum_out + ((int64_t)s * d.n_bin + b) * d.n_f0;
+    const int nf = d.n_f0;
+    // fold the register partial sums into the lane's output slots
+    auto flush = [&]() {
+#pragma unroll
+        for (int i = 0; i < kNF; ++i) {
+            if (i < nf) out[i] = flushed ? out[i] + acc[i] : acc[i];
+            acc[i] = 0.f;
+        }
+        flushed = true;
+    };
+    bool bad_range = false, bad_model = false;
+
+    for (int64_t j0 = 0; j0 < d.n_seg; j0 += kChunk) {
+        const int nj = (int)min((int64_t)kChunk, d.n_seg - j0);
+        const int ng = (nj + kGroup - 1) / kGroup;
+        __syncthreads();
+        for (int jj = tid; jj < nj; jj += lanes) {
+            const int64_t J = j0 + jj;
+            double sp, cp;
+            sincos(W * d.t_mid[J], &sp, &cp);
+            sm.C[jj] = cp;
+            sm.S[jj] = sp;
+            sm.D[jj] = doppler_factor(d.v + 3 * J, nx, ny, nz);
+        }
+        for (int e = tid; e < nj * nwp; e += lanes) {
+            const int jj = e / nwp;
+            const int wd = e - jj * nwp;
+            sm.row[e] = wd < d.n_words ? d.bits[(j0 + jj) * d.n_words + wd] : 0u;
+        }
+        for (int g = tid; g < ng; g += lanes) {
+            // subset sums in segment order; missing segments of a last partial group weigh 0
+            float w4[kGroup];
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) {
+                const int jj = g * kGroup + u;
+                w4[u] = jj < nj ? wrow[j0 + jj] : 0.f;
+            }
+            float* T = sm.T + g * 16;
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                float t = 0.f;
+#pragma unroll
+                for (int u = 0; u < kGroup; ++u)
+                    if (m & (1 << u)) t += w4[u];
+                T[m] = t;
+            }
+        }
+        __syncthreads();
+        if (!active) continue;
+
+        for (int g = 0; g < ng; ++g) {
+            uint32_t mk[kGroup][3];
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) {
+                const int jj = g * kGroup + u;
+                mk[u][0] = mk[u][1] = mk[u][2] = 0u;
+                if (jj < nj &&
+                    !band_mask(sm.row + jj * nwp, sm.C[jj], sm.S[jj], sm.D[jj], cb, sb, apW, F0, FL, klo,
+                               last, d.n_bins, mk[u][0], mk[u][1], mk[u][2], bad_range, bad_model)) {
+                    mk[u][0] = mk[u][1] = mk[u][2] = 0u;
+                }
+            }
+            // A[w][r]: nibble n <- bits (4n + r) of the four masks' word w
+            uint32_t A[3][4];
+#pragma unroll
+            for (int w = 0; w < 3; ++w) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const uint32_t sel = 0x11111111u << r;
+                    uint32_t a = 0u;
+#pragma unroll
+                    for (int u = 0; u < kGroup; ++u) {
+                        const uint32_t t = mk[u][w] & sel;
+                        a |= (u >= r) ? (t << (u - r)) : (t >> (r - u));
+                    }
+                    A[w][r] = a;
+                }
+            }
+            const float* T = sm.T + g * 16;
+#pragma unroll
+            for (int i = 0; i < kNF; ++i) {
+                const int w = i >> 5, p = i & 31;
+                const uint32_t nib = (A[w][p & 3] >> (4 * (p >> 2))) & 15u;
+                acc[i] += T[nib];
+            }
+            if (++since_flush == kFlushGroups) {
+                since_flush = 0;
+                flush();
+            }
+        }
+    }
+    if (bad_range) raise_status(d.status, BSH_STATUS_RANGE);
+    if (bad_model) raise_status(d.status, BSH_STATUS_MODEL);
+    if (active && (since_flush > 0 || !flushed)) flush();
+}
+
+// kMode: 0 = select-and-add, weighted sums only; 1 = select-and-add with counts; 2 = table.
+template <int kMode, int kChunk>
+__device__ __forceinline__ void run_tile(const ItemDesc& d, int s, int ip, int64_t tile, void* smem)
+{
+    if constexpr (kMode == 2)
+        count_tile_lut<kChunk>(d, s, ip, tile, *reinterpret_cast<TileSmemLut<kChunk>*>(smem));
+    else
+        count_tile<kMode == 1, kChunk>(d, s, ip, tile, *reinterpret_cast<TileSmem<kChunk>*>(smem));
+}
+
+template <int kMode, int kChunk>
+constexpr size_t smem_bytes()
+{
+    return kMode == 2 ? sizeof(TileSmemLut<kChunk>) : sizeof(TileSmem<kChunk>);
+}
+
+template <int kMode, int kChunk>
+__global__ __launch_bounds__(kMaxLanes, kMode == 2 ? 2 : 1) void hough_count_kernel(const PlainLaunch p)
+{
+    __shared__ __align__(16) unsigned char smem[smem_bytes<kMode, kChunk>()];
     const int blk = blockIdx.x;
     const int s = blk / p.tiles_per_sky;
     const int t = blk - s * p.tiles_per_sky;
@@ -185,15 +361,15 @@ __global__ __launch_bounds__(kMaxLanes) void hough_count_kernel(const PlainLaunc
         const int mid = (lo + hi) >> 1;
         if (p.tile_start[mid] <= t) lo = mid; else hi = mid;
     }
-    count_tile<kCount, kChunk>(p.d, s, lo, t - p.tile_start[lo], sm);
+    run_tile<kMode, kChunk>(p.d, s, lo, t - p.tile_start[lo], smem);
 }
 
-template <bool kCount, int kChunk>
-__global__ __launch_bounds__(kMaxLanes) void hough_batch_kernel(const ItemDesc* __restrict__ items,
+template <int kMode, int kChunk>
+__global__ __launch_bounds__(kMaxLanes, kMode == 2 ? 2 : 1) void hough_batch_kernel(const ItemDesc* __restrict__ items,
                                                                const WorkUnit* __restrict__ units,
                                                                int64_t n_units, uint32_t* counter)
 {
-    __shared__ TileSmem<kChunk> sm;
+    __shared__ __align__(16) unsigned char smem[smem_bytes<kMode, kChunk>()];
     __shared__ int64_t next;
     for (;;) {
         if (threadIdx.x == 0) next = (int64_t)atomicAdd(counter, 1u);
@@ -203,7 +379,7 @@ __global__ __launch_bounds__(kMaxLanes) void hough_batch_kernel(const ItemDesc* 
         if (u >= n_units) break;
         const WorkUnit w = units[u];
         const ItemDesc d = items[w.item];
-        count_tile<kCount, kChunk>(d, w.sky, w.ip, w.tile, sm);
+        run_tile<kMode, kChunk>(d, w.sky, w.ip, w.tile, smem);
     }
 }
 
@@ -272,68 +448,67 @@ int zero_words(void* p, int64_t n_words, hipStream_t stream)
     return check_launch("zero fill");
 }
 
-template <bool kCount, int kChunk>
-static int launch_plain_t(const PlainLaunch& p, int64_t blocks, int lanes, hipStream_t stream)
+// Instantiate a kernel template for every (mode, chunk) and call f with the chosen one.
+#define BSH_DISPATCH(MODE, CHUNK, F)                                                          \
+    switch ((MODE) * 1000 + (CHUNK)) {                                                        \
+    case 128: F(0, 128); break;                                                               \
+    case 256: F(0, 256); break;                                                               \
+    case 512: F(0, 512); break;                                                               \
+    case 1128: F(1, 128); break;                                                              \
+    case 1256: F(1, 256); break;                                                              \
+    case 1512: F(1, 512); break;                                                              \
+    case 2128: F(2, 128); break;                                                              \
+    case 2256: F(2, 256); break;                                                              \
+    case 2512: F(2, 512); break;                                                              \
+    default: return fail_inval("kernel mode / chunk");                                        \
+    }
+
+int launch_plain(const PlainLaunch& p, int64_t blocks, int lanes, int chunk, int mode, hipStream_t stream)
 {
-    hipLaunchKernelGGL((hough_count_kernel<kCount, kChunk>), dim3((unsigned)blocks), dim3(lanes), 0,
-                       stream, p);
+#define BSH_LAUNCH_PLAIN(M, C)                                                                \
+    hipLaunchKernelGGL((hough_count_kernel<M, C>), dim3((unsigned)blocks), dim3(lanes), 0, stream, p)
+    BSH_DISPATCH(mode, chunk, BSH_LAUNCH_PLAIN)
+#undef BSH_LAUNCH_PLAIN
     return check_launch("bsh_hough_count");
 }
 
-int launch_plain(const PlainLaunch& p, int64_t blocks, int lanes, int chunk, bool with_count,
-                 hipStream_t stream)
+int launch_batch(const ItemDesc* items, const WorkUnit* units, int64_t n_units, uint32_t* counter,
+                 int blocks, int lanes, int chunk, int mode, hipStream_t stream)
 {
-    switch (chunk) {
-    case 128: return with_count ? launch_plain_t<true, 128>(p, blocks, lanes, stream)
-                                : launch_plain_t<false, 128>(p, blocks, lanes, stream);
-    case 512: return with_count ? launch_plain_t<true, 512>(p, blocks, lanes, stream)
-                                : launch_plain_t<false, 512>(p, blocks, lanes, stream);
-    default: return with_count ? launch_plain_t<true, 256>(p, blocks, lanes, stream)
-                               : launch_plain_t<false, 256>(p, blocks, lanes, stream);
-    }
-}
-
-template <bool kCount, int kChunk>
-static int launch_batch_t(const ItemDesc* items, const WorkUnit* units, int64_t n_units,
-                          uint32_t* counter, int blocks, int lanes, hipStream_t stream)
-{
-    hipLaunchKernelGGL((hough_batch_kernel<kCount, kChunk>), dim3(blocks), dim3(lanes), 0, stream, items,
-                       units, n_units, counter);
+#define BSH_LAUNCH_BATCH(M, C)                                                                \
+    hipLaunchKernelGGL((hough_batch_kernel<M, C>), dim3(blocks), dim3(lanes), 0, stream, items, units, \
+                       n_units, counter)
+    BSH_DISPATCH(mode, chunk, BSH_LAUNCH_BATCH)
+#undef BSH_LAUNCH_BATCH
     return check_launch("batched count");
 }
 
-int launch_batch(const ItemDesc* items, const WorkUnit* units, int64_t n_units, uint32_t* counter,
-                 int blocks, int lanes, int chunk, bool with_count, hipStream_t stream)
-{
-    switch (chunk) {
-    case 128: return with_count ? launch_batch_t<true, 128>(items, units, n_units, counter, blocks, lanes, stream)
-                                : launch_batch_t<false, 128>(items, units, n_units, counter, blocks, lanes, stream);
-    case 512: return with_count ? launch_batch_t<true, 512>(items, units, n_units, counter, blocks, lanes, stream)
-                                : launch_batch_t<false, 512>(items, units, n_units, counter, blocks, lanes, stream);
-    default: return with_count ? launch_batch_t<true, 256>(items, units, n_units, counter, blocks, lanes, stream)
-                               : launch_batch_t<false, 256>(items, units, n_units, counter, blocks, lanes, stream);
-    }
-}
-
-int batch_blocks_per_cu(int lanes, int chunk, bool with_count)
+int batch_blocks_per_cu(int lanes, int chunk, int mode)
 {
     int n = 0;
     hipError_t e = hipSuccess;
-    switch (chunk) {
-    case 128:
-        e = with_count ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, hough_batch_kernel<true, 128>, lanes, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, hough_batch_kernel<false, 128>, lanes, 0);
-        break;
-    case 512:
-        e = with_count ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, hough_batch_kernel<true, 512>, lanes, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, hough_batch_kernel<false, 512>, lanes, 0);
-        break;
-    default:
-        e = with_count ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, hough_batch_kernel<true, 256>, lanes, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, hough_batch_kernel<false, 256>, lanes, 0);
+#define BSH_OCC(M, C) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, hough_batch_kernel<M, C>, lanes, 0)
+    switch (mode * 1000 + chunk) {
+    case 128: BSH_OCC(0, 128); break;
+    case 256: BSH_OCC(0, 256); break;
+    case 512: BSH_OCC(0, 512); break;
+    case 1128: BSH_OCC(1, 128); break;
+    case 1256: BSH_OCC(1, 256); break;
+    case 1512: BSH_OCC(1, 512); break;
+    case 2128: BSH_OCC(2, 128); break;
+    case 2256: BSH_OCC(2, 256); break;
+    case 2512: BSH_OCC(2, 512); break;
+    default: break;
     }
+#undef BSH_OCC
     if (e != hipSuccess || n < 1) n = 1;
     return n;
+}
+
+int kernel_mode(int variant, bool with_count)
+{
+    if (with_count) return 1;
+    return variant == BSH_VARIANT_SELECT ? 0 : 2;
 }
 
 bool valid_tile_shape(int lanes, int chunk)
@@ -346,7 +521,7 @@ bool valid_tile_shape(int lanes, int chunk)
 using namespace bsh;
 
 extern "C" int bsh_hough_count_ex(const bsh_segments* seg, const bsh_grid* grid, int32_t lanes,
-                                  int32_t chunk, uint32_t* count_out, float* wsum_out,
+                                  int32_t chunk, int32_t variant, uint32_t* count_out, float* wsum_out,
                                   int32_t* status, bsh_stream stream)
 {
     clear_error();
@@ -356,6 +531,7 @@ extern "C" int bsh_hough_count_ex(const bsh_segments* seg, const bsh_grid* grid,
     if (rc) return rc;
     if (!count_out && !wsum_out) return fail_inval("both outputs are NULL");
     if (!valid_tile_shape(lanes, chunk)) return fail_inval("tile shape: lanes 64/128/256, chunk 128/256/512");
+    if (variant < BSH_VARIANT_AUTO || variant > BSH_VARIANT_TABLE) return fail_inval("variant");
     rc = check_window(seg, grid);
     if (rc) return rc;
 
@@ -375,11 +551,12 @@ extern "C" int bsh_hough_count_ex(const bsh_segments* seg, const bsh_grid* grid,
         if (rc) return rc;
         return zero_words(count_out, count_out ? n_t : 0, s);
     }
-    return launch_plain(p, blocks, lanes, chunk, count_out != nullptr, s);
+    return launch_plain(p, blocks, lanes, chunk, kernel_mode(variant, count_out != nullptr), s);
 }
 
 extern "C" int bsh_hough_count(const bsh_segments* seg, const bsh_grid* grid, uint32_t* count_out,
                                float* wsum_out, int32_t* status, bsh_stream stream)
 {
-    return bsh_hough_count_ex(seg, grid, kDefaultLanes, kDefaultChunk, count_out, wsum_out, status, stream);
+    return bsh_hough_count_ex(seg, grid, kDefaultLanes, kDefaultChunk, BSH_VARIANT_AUTO, count_out, wsum_out,
+                              status, stream);
 }

@@ -153,13 +153,17 @@ def test_every_tile_shape_gives_identical_maps(setup):
     g1 = bsh.DeviceGrid.from_tables(_np(g.sky)[lo:lo + 1], g.k0, g.n_f0, g.a_p, g.period, g.tasc_off,
                                     _np(g.t_asc_dev))
     ref, rc = bsh.bsh_hough_count(ds, g1, with_count=True)
+    ref_t, _ = bsh.bsh_hough_count(ds, g1, variant=2)
     for lanes in (64, 128, 256):
         for chunk in (128, 256, 512):
             ws, c = bsh.bsh_hough_count(ds, g1, with_count=True, lanes=lanes, chunk=chunk)
+            wt, _ = bsh.bsh_hough_count(ds, g1, lanes=lanes, chunk=chunk, variant=2)
             torch.cuda.synchronize()
             assert torch.equal(ws, ref) and torch.equal(c, rc), (lanes, chunk)
-    plan = bsh.Plan([items[3]], [g], 1, lanes=64, chunk=512, use_graph=False, lpt=False)
-    plan.run()
-    torch.cuda.synchronize()
-    assert torch.equal(plan.item_map(0), ref)
-    plan.close()
+            assert torch.equal(wt, ref_t), (lanes, chunk)
+    for variant, want in ((1, ref), (2, ref_t)):
+        plan = bsh.Plan([items[3]], [g], 1, lanes=64, chunk=512, use_graph=False, lpt=False, variant=variant)
+        plan.run()
+        torch.cuda.synchronize()
+        assert torch.equal(plan.item_map(0), want), variant
+        plan.close()

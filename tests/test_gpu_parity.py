@@ -110,11 +110,15 @@ def test_count_weighted_several_tiles(B):
     ds, g, o, ws, cnt = _run_count(B, seg, spec, w.sky)
     cnt_o, nw_o, nt_o, ntw_o = O.hough_count(seg, w.sky, spec.k0, spec.n_f0, *o)
     _check_counts(cnt, ws, cnt_o, nw_o, nt_o, ntw_o)
-    # the count-free kernel gives the same weighted sums
+    # both accumulation variants without counts: same oracle bar, and the select variant
+    # without counts sums in the same order as with counts
     import torch
-    ws2, _ = B.bsh_hough_count(ds, g, with_count=False)
-    torch.cuda.synchronize()
-    assert np.array_equal(_np(ws2), ws)
+    for variant in (1, 2):
+        ws2, _ = B.bsh_hough_count(ds, g, with_count=False, variant=variant)
+        torch.cuda.synchronize()
+        _check_counts(cnt_o, _np(ws2), cnt_o, nw_o, nt_o, ntw_o)
+        if variant == 1:
+            assert np.array_equal(_np(ws2), ws)
 
 
 def test_count_ragged_rule_grid_multisky_per_sky_weights(B):
@@ -133,6 +137,10 @@ def test_count_ragged_rule_grid_multisky_per_sky_weights(B):
                        k_lo=base.k_lo, n_bins=base.n_bins)
     cnt_o, nw_o, nt_o, ntw_o = O.hough_count(seg_o, sky, spec.k0, spec.n_f0, *o, weight_per_sky=True)
     _check_counts(cnt, ws, cnt_o, nw_o, nt_o, ntw_o)
+    import torch
+    ws_t, _ = B.bsh_hough_count(ds, g, variant=2)
+    torch.cuda.synchronize()
+    _check_counts(cnt_o, _np(ws_t), cnt_o, nw_o, nt_o, ntw_o)
 
 
 def test_count_config2_full_size_sampled(B):
@@ -152,6 +160,11 @@ def test_count_config2_full_size_sampled(B):
     _, c_o, nw_o, nt_o = O.power_stat(seg, w.sky, s.astype(np.int32), cand, mode=0)
     ntw_o = nt_o * float(seg.weight.max())
     _check_counts(cnt[idx], ws[idx], c_o, nw_o, nt_o, ntw_o)
+    ws_t, _ = B.bsh_hough_count(ds, g)          # default: table variant, as the benchmark runs it
+    torch.cuda.synchronize()
+    ws_t = _np(ws_t)
+    _check_counts(c_o, ws_t[idx], c_o, nw_o, nt_o, ntw_o)
+    assert np.max(np.abs(ws_t - ws) / np.maximum(ws, 1e-30)) < 2e-5
     # mean count under noise ~ N exp(-1.6) (statistical sanity at full size)
     assert abs(cnt.mean() / 4000 - math.exp(-1.6)) < 0.01
 
