@@ -225,6 +225,18 @@ int bsh_power_stat_grad(const bsh_segments* seg, const double* sky, int32_t n_sk
                         double* grad_params, int32_t* status, bsh_stream stream);
 
 /*
+ * Stage-2 statistic on the low-eccentricity (ELL1) track of eq:frequencyevo (Sec. II), for
+ * orbits the circular model only approximates (Sec. IV.E bounds when that matters):
+ *   x = F (1 + v.n) (1 - a_p W [cos psi + (e cos w) cos 2psi - (e sin w) sin 2psi]),
+ *   psi = W (t - t_asc).
+ * cand_params [n][6] = (F, a_p, P, t_asc, e cos w, e sin w); modes as bsh_power_stat (P only).
+ * With zero eccentricity the result equals bsh_power_stat bit for bit.
+ */
+int bsh_power_stat_ecc(const bsh_segments* seg, const double* sky, int32_t n_sky,
+                       const int32_t* cand_sky, const double* cand_params, int64_t n, int32_t mode,
+                       float* P_out, int32_t* status, bsh_stream stream);
+
+/*
  * Absolute bins k_J of each candidate's track: bins_out [n][n_seg] int32.  The same
  * evaluation as bsh_power_stat; for inspection and for placing injected signals.  No row
  * is read, so no window applies; a bad sky index gives bins of -1 and BSH_STATUS_INPUT.

@@ -19,6 +19,8 @@ Functions and the passage each follows:
 * ``power_grad``       -- gradient of the interpolated power (extension).
 * ``track``            -- the frequency track x_J = f(t_J) Tc and its bins
                           (eq:frequencyevoFinal, product form).
+* ``track_ecc`` / ``power_stat_ecc`` -- the low-eccentricity (ELL1) track of
+                          eq:frequencyevo and the stage-2 power on it.
 * ``peakgram``         -- thresholded peakgram (Sec. IV.A).
 * ``significance_h`` / ``significance_p`` -- eq:hough2 / eq:hough3 with the
                           noise moments that follow from p(rho) = exp(-rho).
@@ -76,6 +78,10 @@ def lib():
         L.orc_power_stat.restype = ctypes.c_int
         L.orc_power_grad.argtypes = [i64, P, P, P, i32, i64, i32, P, P, i64, P, P, P, P, P]
         L.orc_power_grad.restype = ctypes.c_int
+        L.orc_track_ecc.argtypes = [i64, P, P, P, i64, P, P, P, P]
+        L.orc_track_ecc.restype = None
+        L.orc_power_stat_ecc.argtypes = [i64, P, P, P, i32, i64, i32, P, P, i64, P, P, i32, P, P]
+        L.orc_power_stat_ecc.restype = ctypes.c_int
         L.orc_peakgram.argtypes = [i64, i32, P, f64, i32, P]
         L.orc_peakgram.restype = None
         L.orc_num_threads.argtypes = []
@@ -251,6 +257,38 @@ def power_grad(seg, sky, cand_sky, cand, grad_p=None, weight_per_sky: bool = Fal
     if rc != 0:
         raise OracleRangeError("a track left the staged bins")
     return (g, a) if with_abs else g
+
+
+def track_ecc(seg, sky, cand_sky, cand: np.ndarray):
+    """ELL1 track: x and bins [n_cand, n_seg] for rows (F, a_p, P, t_asc, e cos w, e sin w)."""
+    t = _c(seg.t_mid, np.float64)
+    v = _c(seg.v_over_c, np.float64)
+    sky = _c(sky, np.float64)
+    cand = _c(cand, np.float64).reshape(-1, 6)
+    cs = _c(cand_sky, np.int32).reshape(-1)
+    x = np.empty((cand.shape[0], t.size), np.float64)
+    k = np.empty((cand.shape[0], t.size), np.int64)
+    lib().orc_track_ecc(t.size, _p(t), _p(v), _p(sky), cand.shape[0], _p(cs), _p(cand), _p(x), _p(k))
+    return x, k
+
+
+def power_stat_ecc(seg, sky, cand_sky, cand, mode: int = 0, weight_per_sky: bool = False):
+    """Stage-2 power on the ELL1 track: (P, near-tie count) per candidate."""
+    t = _c(seg.t_mid, np.float64)
+    v = _c(seg.v_over_c, np.float64)
+    w = _c(seg.weight, np.float32)
+    pw = _c(seg.power, np.float32)
+    sky = _c(sky, np.float64)
+    cand = _c(cand, np.float64).reshape(-1, 6)
+    cs = _c(cand_sky, np.int32).reshape(-1)
+    n = cand.shape[0]
+    P = np.zeros(n, np.float64)
+    nt = np.zeros(n, np.uint32)
+    rc = lib().orc_power_stat_ecc(t.size, _p(t), _p(v), _p(w), int(weight_per_sky), seg.k_lo, seg.n_bins,
+                                  _p(pw), _p(sky), n, _p(cs), _p(cand), int(mode), _p(P), _p(nt))
+    if rc != 0:
+        raise OracleRangeError("a track left the staged bins")
+    return P, nt
 
 
 def peakgram(power: np.ndarray, rho_th: float = P_PEAK_DEFAULT_TH) -> np.ndarray:

@@ -260,6 +260,77 @@ int orc_power_grad(int64_t n_seg, const double* t_mid, const double* v_over_c,
     return err;
 }
 
+/*
+ * Low-eccentricity (ELL1) track, eq:frequencyevo (Sec. II), in the product form:
+ *   x = F (1 + v.n) (1 - a_p W [cos psi + (e cos w) cos 2psi - (e sin w) sin 2psi]),
+ *   psi = W (t - t_asc).
+ * Candidates are rows (F, a_p, P, t_asc, e cos w, e sin w).  Outputs as orc_track, and the
+ * nearest-bin power P = sum w rho (mode 0) or the interpolated power (mode 1) per candidate.
+ */
+static double orbit_factor_ecc(double t, double a_p, double period, double t_asc, double ec, double es)
+{
+    double w = TWO_PI / period;
+    double psi = w * (t - t_asc);
+    double c1 = cos(psi);
+    double c2 = cos(2.0 * psi);
+    double s2 = sin(2.0 * psi);
+    return 1.0 - (a_p * w) * (c1 + (ec * c2 - es * s2));
+}
+
+void orc_track_ecc(int64_t n_seg, const double* t_mid, const double* v_over_c, const double* sky,
+                   int64_t n_cand, const int32_t* cand_sky, const double* cand, double* out_x,
+                   int64_t* out_k)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < n_cand; ++c) {
+        const double* th = cand + 6 * c;
+        for (int64_t J = 0; J < n_seg; ++J) {
+            double D = doppler_factor(v_over_c + 3 * J, sky + 3 * cand_sky[c]);
+            double B = orbit_factor_ecc(t_mid[J], th[1], th[2], th[3], th[4], th[5]);
+            double x = th[0] * (D * B);
+            if (out_x) out_x[c * n_seg + J] = x;
+            if (out_k) out_k[c * n_seg + J] = (int64_t)floor(x + 0.5);
+        }
+    }
+}
+
+int orc_power_stat_ecc(int64_t n_seg, const double* t_mid, const double* v_over_c,
+                       const float* weight, int32_t weight_per_sky, int64_t k_lo, int32_t n_bins,
+                       const float* power, const double* sky, int64_t n_cand,
+                       const int32_t* cand_sky, const double* cand, int32_t mode, double* p_out,
+                       uint32_t* ntie_out)
+{
+    int err = ORC_OK;
+    #pragma omp parallel for schedule(static) reduction(min:err)
+    for (int64_t c = 0; c < n_cand; ++c) {
+        const double* th = cand + 6 * c;
+        const float* w = weight + (weight_per_sky ? (int64_t)cand_sky[c] * n_seg : 0);
+        double P = 0.0;
+        uint32_t nt = 0;
+        for (int64_t J = 0; J < n_seg; ++J) {
+            double D = doppler_factor(v_over_c + 3 * J, sky + 3 * cand_sky[c]);
+            double B = orbit_factor_ecc(t_mid[J], th[1], th[2], th[3], th[4], th[5]);
+            double x = th[0] * (D * B);
+            const float* row = power + J * n_bins;
+            if (mode == 0) {
+                int64_t col = (int64_t)floor(x + 0.5) - k_lo;
+                if (col < 0 || col >= n_bins) { err = ORC_ERANGE; continue; }
+                P += (double)w[J] * (double)row[col];
+                if (is_near_tie(x)) nt += 1;
+            } else {
+                double kf = floor(x);
+                int64_t col = (int64_t)kf - k_lo;
+                if (col < 0 || col + 1 >= n_bins) { err = ORC_ERANGE; continue; }
+                double a = x - kf;
+                P += (double)w[J] * ((1.0 - a) * (double)row[col] + a * (double)row[col + 1]);
+            }
+        }
+        if (p_out) p_out[c] = P;
+        if (ntie_out) ntie_out[c] = nt;
+    }
+    return err;
+}
+
 /* Peakgram: bit c of row J set iff rho_{J,c} > rho_th (Sec. IV.A), bit b of word w = column 32w+b. */
 void orc_peakgram(int64_t n_seg, int32_t n_bins, const float* power, double rho_th,
                   int32_t n_words, uint32_t* bits)

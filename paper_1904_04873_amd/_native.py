@@ -131,6 +131,8 @@ SIGNATURES = {
     "bsh_decode_templates": (ctypes.c_int, [ctypes.POINTER(Grid), _vp, _c_i64, _vp, _vp, _vp]),
     "bsh_power_stat": (ctypes.c_int, [ctypes.POINTER(Segments), _vp, _c_i32, _vp, _vp, _c_i64, _c_i32,
                                       _vp, _vp, _vp, _vp, _vp]),
+    "bsh_power_stat_ecc": (ctypes.c_int, [ctypes.POINTER(Segments), _vp, _c_i32, _vp, _vp, _c_i64, _c_i32,
+                                          _vp, _vp, _vp]),
     "bsh_power_stat_grad": (ctypes.c_int, [ctypes.POINTER(Segments), _vp, _c_i32, _vp, _vp, _c_i64,
                                            _vp, _vp, _vp, _vp]),
     "bsh_track_bins": (ctypes.c_int, [ctypes.POINTER(Segments), _vp, _c_i32, _vp, _vp, _c_i64, _vp,

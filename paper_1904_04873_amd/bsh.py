@@ -285,6 +285,18 @@ def bsh_power_stat(seg: DeviceSegments, sky: torch.Tensor, cand_sky: torch.Tenso
     return (P, cnt, ws) if with_counts else P
 
 
+def bsh_power_stat_ecc(seg: DeviceSegments, sky: torch.Tensor, cand_sky: torch.Tensor,
+                       cand_params: torch.Tensor, mode: int = 0, status: Optional[Status] = None):
+    """Stage-2 statistic on the ELL1 track; cand_params [n, 6] = (F, a_p, P, t_asc, e cos w, e sin w)."""
+    n = int(cand_sky.numel())
+    P = torch.empty(n, dtype=torch.float32, device=cand_sky.device)
+    s_c = seg.struct()
+    check(N.load().bsh_power_stat_ecc(ctypes.byref(s_c), _ptr(sky), int(sky.shape[0]), _ptr(cand_sky),
+                                      _ptr(cand_params.contiguous()), n, int(mode), _ptr(P),
+                                      status.ptr() if status else None, _stream()), "bsh_power_stat_ecc")
+    return P
+
+
 def bsh_power_stat_grad(seg: DeviceSegments, sky: torch.Tensor, cand_sky: torch.Tensor,
                         cand_params: torch.Tensor, grad_P: Optional[torch.Tensor] = None,
                         status: Optional[Status] = None):

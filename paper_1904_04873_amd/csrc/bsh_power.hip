@@ -135,6 +135,62 @@ __global__ __launch_bounds__(kThreads) void power_grad_kernel(
     }
 }
 
+
+// Low-eccentricity (ELL1) track of eq:frequencyevo in the product form: the orbit factor gains
+// (e cos w) cos 2psi - (e sin w) sin 2psi inside the a_p W bracket; cos 2psi and sin 2psi come
+// from cos psi and sin psi.  At e = 0 it is bit-identical to the circular track.
+__global__ __launch_bounds__(kThreads) void power_stat_ecc_kernel(
+    const double* __restrict__ t_mid, const double* __restrict__ v, const float* __restrict__ w,
+    int32_t w_per_sky, const float* __restrict__ power, int32_t n_bins, int64_t k_lo, int64_t n_seg,
+    const double* __restrict__ sky, int32_t n_sky, const int32_t* __restrict__ cand_sky,
+    const double* __restrict__ cand, int64_t n, int32_t mode, float* __restrict__ P_out, int32_t* status)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t c = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (c >= n) return;
+    const int32_t s = cand_sky[c];
+    if (s < 0 || s >= n_sky) {
+        if (lane == 0) {
+            P_out[c] = 0.f;
+            raise_status(status, BSH_STATUS_INPUT);
+        }
+        return;
+    }
+    const double* th = cand + 6 * c;
+    const Cand cd = load_cand(th);
+    const double ec = th[4], es = th[5];
+    const double nx = sky[3 * s], ny = sky[3 * s + 1], nz = sky[3 * s + 2];
+    const float* wr = w + (w_per_sky ? (int64_t)s * n_seg : 0);
+    const double klo = (double)k_lo;
+    float P = 0.f;
+    bool bad = false;
+    for (int64_t J = lane; J < n_seg; J += 64) {
+        double st, ct, cphi, sphi;
+        sincos(cd.W * t_mid[J], &st, &ct);
+        orbit_phase(ct, st, cd, cphi, sphi);
+        const double c2 = (cphi - sphi) * (cphi + sphi);
+        const double s2 = 2.0 * (sphi * cphi);
+        const double D = doppler_factor(v + 3 * J, nx, ny, nz);
+        const double x = track_x(cd.F, D, cd.apW, cphi + (ec * c2 - es * s2));
+        const float wj = wr[J];
+        if (mode == 0) {
+            const int col = (int)(floor(x + 0.5) - klo);
+            if (col < 0 || col >= n_bins) { bad = true; continue; }
+            P += wj * power[J * n_bins + col];
+        } else {
+            const double kf = floor(x);
+            const int col = (int)(kf - klo);
+            if (col < 0 || col + 1 >= n_bins) { bad = true; continue; }
+            const float a = (float)(x - kf);
+            const float* row = power + J * n_bins + col;
+            P += wj * ((1.f - a) * row[0] + a * row[1]);
+        }
+    }
+    if (bad) raise_status(status, BSH_STATUS_RANGE);
+    P = wave_sum(P);
+    if (lane == 0) P_out[c] = P;
+}
+
 }  // namespace
 
 extern "C" int bsh_power_stat(const bsh_segments* seg, const double* sky, int32_t n_sky,
@@ -183,4 +239,26 @@ extern "C" int bsh_power_stat_grad(const bsh_segments* seg, const double* sky, i
                        seg->weight_per_sky, seg->power, seg->n_bins, seg->k_lo, seg->n_seg, sky,
                        n_sky, cand_sky, cand_params, n, grad_P, grad_params, status);
     return check_launch("bsh_power_stat_grad");
+}
+
+extern "C" int bsh_power_stat_ecc(const bsh_segments* seg, const double* sky, int32_t n_sky,
+                                  const int32_t* cand_sky, const double* cand_params, int64_t n,
+                                  int32_t mode, float* P_out, int32_t* status, bsh_stream stream)
+{
+    clear_error();
+    if (mode != 0 && mode != 1) return fail_inval("mode must be 0 or 1");
+    if (!P_out) return fail_inval("P_out is NULL");
+    int rc = check_segments(seg, false, true);
+    if (rc) return rc;
+    if (n < 0) return fail_inval("n < 0");
+    if (n_sky < 1) return fail_inval("n_sky < 1");
+    if (n == 0) return BSH_OK;
+    if (!sky || !cand_sky || !cand_params) return fail_inval("NULL pointer");
+    const int64_t blocks = (n + kWaves - 1) / kWaves;
+    if (blocks > 0x7fffffff) return fail_inval("too many candidates");
+    hipLaunchKernelGGL(power_stat_ecc_kernel, dim3((unsigned)blocks), dim3(kThreads), 0,
+                       (hipStream_t)stream, seg->t_mid, seg->v_over_c, seg->weight, seg->weight_per_sky,
+                       seg->power, seg->n_bins, seg->k_lo, seg->n_seg, sky, n_sky, cand_sky, cand_params,
+                       n, mode, P_out, status);
+    return check_launch("bsh_power_stat_ecc");
 }

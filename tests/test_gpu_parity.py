@@ -499,3 +499,31 @@ def test_pipeline_config2_recovers_injections(B):
         assert np.any(np.all(d <= 2.0, axis=1)), f"injection {q} (snr {snr[q]:.2f}) not in stage-1 top-10^4"
     s_p = O.significance_p(_np(v2).astype(np.float64), seg.weight)
     assert s_p[0] > 20
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_power_stat_ecc_matches_oracle(B, mode):
+    """ELL1 track (eq:frequencyevo): eccentric candidates vs the oracle; e = 0 equals the circular call."""
+    import torch
+    _say(f"power_stat_ecc mode={mode}")
+    w = S.config2()
+    seg = w.segments[0]
+    ds = B.DeviceSegments.from_host(seg)
+    sky = torch.from_numpy(w.sky).cuda()
+    cand, cs = _cands(seg, 2000, 180000, seed=20 + mode)
+    rng = np.random.default_rng(mode)
+    e = 10 ** rng.uniform(-6, -2, 2000)
+    om = rng.uniform(0, 2 * np.pi, 2000)
+    ce = np.concatenate([cand, np.stack([e * np.cos(om), e * np.sin(om)], axis=1)], axis=1)
+    st = _status(B)
+    P = _np(B.bsh_power_stat_ecc(ds, sky, *_dev_cands(ce, cs), mode=mode, status=st))
+    torch.cuda.synchronize()
+    st.raise_if_set()
+    P_o, nt_o = O.power_stat_ecc(seg, w.sky, cs, ce, mode=mode)
+    tol = REL * np.abs(P_o) + (nt_o * float(seg.weight.max()) * float(seg.power.max()) if mode == 0 else 0)
+    assert np.all(np.abs(P.astype(np.float64) - P_o) <= tol)
+    z = np.concatenate([cand, np.zeros((2000, 2))], axis=1)
+    P0 = B.bsh_power_stat_ecc(ds, sky, *_dev_cands(z, cs), mode=mode)
+    Pc = B.bsh_power_stat(ds, sky, *_dev_cands(cand, cs), mode=mode)
+    torch.cuda.synchronize()
+    assert torch.equal(P0, Pc)

@@ -466,3 +466,61 @@ def test_grid_tasc_inside_one_period_around_mid():
         seg = ta[off[cell]:off[cell + 1]]
         assert seg.min() >= t_mid - P / 2 and seg.max() < t_mid + P / 2
         assert np.all(np.diff(seg) > 0)
+
+
+# ---------------------------------------------------------------- low-eccentricity track
+
+def test_ecc_track_reduces_to_circular_at_zero_eccentricity():
+    seg = _segments(200, 180000, 90, 22, seed=31)
+    cand, cs = _cands(seg, 30, 180000, 5)
+    x_c, k_c = O.track(seg, S.fixed_pixel(), cs, cand)
+    ce = np.concatenate([cand, np.zeros((30, 2))], axis=1)
+    x_e, k_e = O.track_ecc(seg, S.fixed_pixel(), cs, ce)
+    assert np.array_equal(x_e, x_c) and np.array_equal(k_e, k_c)
+
+
+def test_ecc_track_max_deviation_is_e_f0_ap_omega():
+    """|f_ecc - f_circ| reaches e f0 a_p W over an orbit (eq:frequencyevoerror, its maximum)."""
+    F, ap, P, ta, e, om = 270040.0, 2.7, 19 * S.DAY, 0.3e6, 0.004, 1.1
+    W = 2 * math.pi / P
+    t = ta + np.linspace(0, P, 4001)
+    seg = S.Segments(t_mid=t, v_over_c=np.zeros((t.size, 3)), weight=np.ones(t.size, np.float32),
+                     power=np.zeros((t.size, 1), np.float32), k_lo=0, n_bins=1)
+    sky = np.array([[0, 0, 1.0]])
+    x_c, _ = O.track(seg, sky, [0], np.array([[F, ap, P, ta]]))
+    x_e, _ = O.track_ecc(seg, sky, [0], np.array([[F, ap, P, ta, e * math.cos(om), e * math.sin(om)]]))
+    dev = np.abs(x_e - x_c)[0]
+    assert dev.max() == pytest.approx(F * ap * W * e, rel=1e-5)
+    # at the eccentricity bound of eq:frequencyevoerror2 the deviation is half a bin
+    e_max = 1.0 / (2 * TC * (F / TC) * ap * W)
+    x_m, _ = O.track_ecc(seg, sky, [0], np.array([[F, ap, P, ta, e_max, 0.0]]))
+    assert np.abs(x_m - x_c).max() == pytest.approx(0.5, rel=1e-5)
+
+
+def test_ecc_track_is_derivative_of_eccentric_phase_model():
+    """v = 0: x / Tc equals (1/2pi) d phi/dt of eq:phaseMethod with its two eccentric terms."""
+    f0, ap, P, ta, e, om = 250.03, 1.9, 23 * S.DAY, 0.8e6, 0.008, 2.2
+    W = 2 * math.pi / P
+    ec, es = e * math.cos(om), e * math.sin(om)
+    times = np.linspace(0.2e6, 2.6e6, 29)
+
+    def phase(t):   # cycles
+        psi = W * (t - ta)
+        return f0 * (t - ap * math.sin(psi) - ap * ec / 2 * math.sin(2 * psi) - ap * es / 2 * math.cos(2 * psi))
+
+    h = 1.0
+    f_num = np.array([(phase(t + h) - phase(t - h)) / (2 * h) for t in times])
+    seg = S.Segments(t_mid=times, v_over_c=np.zeros((times.size, 3)), weight=np.ones(times.size, np.float32),
+                     power=np.zeros((times.size, 1), np.float32), k_lo=0, n_bins=1)
+    x, _ = O.track_ecc(seg, np.array([[0, 0, 1.0]]), [0], np.array([[f0 * TC, ap, P, ta, ec, es]]))
+    assert np.max(np.abs(x[0] - f_num * TC)) < 2e-4
+
+
+def test_ecc_power_zero_eccentricity_matches_circular_power():
+    seg = _segments(300, 180000, 90, 22, seed=32)
+    cand, cs = _cands(seg, 40, 180000, 6)
+    ce = np.concatenate([cand, np.zeros((40, 2))], axis=1)
+    for mode in (0, 1):
+        P_c = O.power_stat(seg, S.fixed_pixel(), cs, cand, mode=mode)[0]
+        P_e = O.power_stat_ecc(seg, S.fixed_pixel(), cs, ce, mode=mode)[0]
+        assert np.array_equal(P_c, P_e)
