@@ -140,6 +140,18 @@ def exp1_powers(rng: np.random.Generator, n_seg: int, n_bins: int) -> np.ndarray
     return rng.standard_exponential((n_seg, n_bins), dtype=np.float32)
 
 
+def raw_sft_powers(rng: np.random.Generator, n_seg: int, n_raw: int, k_first: int,
+                   level_spread: float = 0.5) -> np.ndarray:
+    """Un-normalized SFT powers |x_k|^2 [n_seg, n_raw] float32: Exp(1) draws times a noise floor
+    that varies smoothly with frequency and from segment to segment (a stand-in for
+    (Tc/2) S_n(f) of each SFT)."""
+    k = np.arange(n_raw, dtype=np.float64) + k_first
+    seg_level = np.exp(level_spread * rng.standard_normal(n_seg))[:, None]
+    shape = 1.0 + 0.3 * np.sin(2 * np.pi * k / 173.0) + 0.1 * np.cos(2 * np.pi * k / 31.0)
+    floor = 1e-3 * seg_level * shape[None, :]
+    return (floor * rng.standard_exponential((n_seg, n_raw))).astype(np.float32)
+
+
 def inject(power: np.ndarray, rng: np.random.Generator, cols_list: Sequence[np.ndarray],
            snrs: Sequence[float]) -> None:
     """Add signals in place.

@@ -132,6 +132,17 @@ int bsh_grid_build(const bsh_grid_spec* spec, double t_mid, double* a_p, double*
                    int64_t* tasc_off, double* t_asc, int64_t t_asc_cap, int64_t* n_bin_out);
 
 /*
+ * Normalized power (eq:HoughPower, Sec. IV.A): rho_k = P_k / <n_k>^2 with the noise level
+ * <n_k>^2 = median(P_{k-m} .. P_{k+m}) / beta, window = 2m+1 (odd; the paper uses 101) and
+ * beta = sum_{i=m+1}^{2m+1} 1/i, the expected median of 2m+1 unit exponentials, so that noise
+ * normalizes to unit mean.  raw [n_seg][n_raw] un-normalized SFT powers (n_raw <= 4096);
+ * rho_out [n_seg][n_raw - 2m], column c centred on raw column c + m;
+ * rho = (float)((P * beta) / median) evaluated in double precision.
+ */
+int bsh_normalize(const float* raw, int64_t n_seg, int32_t n_raw, int32_t window, float* rho_out,
+                  bsh_stream stream);
+
+/*
  * Peakgram (Sec. IV.A): bits[J][w] bit b = [power[J][32w+b] > rho_th], compared in double
  * precision; unused high bits of the last word are zero.
  * power [n_seg][n_bins] float32, bits [n_seg][(n_bins+31)/32] uint32.

@@ -21,6 +21,8 @@ Functions and the passage each follows:
                           (eq:frequencyevoFinal, product form).
 * ``track_ecc`` / ``power_stat_ecc`` -- the low-eccentricity (ELL1) track of
                           eq:frequencyevo and the stage-2 power on it.
+* ``normalize``        -- normalized power rho = |x|^2 / <n>^2 with the noise level from a
+                          running median over 101 bins (eq:HoughPower).
 * ``peakgram``         -- thresholded peakgram (Sec. IV.A).
 * ``significance_h`` / ``significance_p`` -- eq:hough2 / eq:hough3 with the
                           noise moments that follow from p(rho) = exp(-rho).
@@ -289,6 +291,25 @@ def power_stat_ecc(seg, sky, cand_sky, cand, mode: int = 0, weight_per_sky: bool
     if rc != 0:
         raise OracleRangeError("a track left the staged bins")
     return P, nt
+
+
+def median_bias(window: int) -> float:
+    """Expected median of `window` (odd) i.i.d. Exp(1) values: sum_{i=m+1}^{2m+1} 1/i, window = 2m+1."""
+    m = (window - 1) // 2
+    return float(sum(1.0 / i for i in range(m + 1, 2 * m + 2)))
+
+
+def normalize(raw: np.ndarray, window: int = 101) -> np.ndarray:
+    """eq:HoughPower: rho_k = P_k / <n_k>^2 with <n_k>^2 = median(P_{k-m..k+m}) / beta, beta the
+    expected median of `window` unit exponentials.  Output column c is raw column c + m;
+    rho = (float32)((P * beta) / median) evaluated in double precision."""
+    from numpy.lib.stride_tricks import sliding_window_view
+    raw = np.asarray(raw, np.float32)
+    m = (window - 1) // 2
+    med = np.median(sliding_window_view(raw, window, axis=1), axis=2)      # exact: odd window
+    beta = median_bias(window)
+    centre = raw[:, m:raw.shape[1] - m].astype(np.float64)
+    return ((centre * beta) / med.astype(np.float64)).astype(np.float32)
 
 
 def peakgram(power: np.ndarray, rho_th: float = P_PEAK_DEFAULT_TH) -> np.ndarray:

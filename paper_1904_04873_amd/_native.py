@@ -109,6 +109,7 @@ SIGNATURES = {
     "bsh_last_error": (ctypes.c_char_p, []),
     "bsh_grid_build": (ctypes.c_int, [ctypes.POINTER(GridSpec), _c_f64, _vp, _vp, _vp, _vp, _c_i64,
                                       ctypes.POINTER(_c_i64)]),
+    "bsh_normalize": (ctypes.c_int, [_vp, _c_i64, _c_i32, _c_i32, _vp, _vp]),
     "bsh_peakgram": (ctypes.c_int, [_vp, _c_i64, _c_i32, _c_f64, _vp, _vp]),
     "bsh_hough_count": (ctypes.c_int, [ctypes.POINTER(Segments), ctypes.POINTER(Grid), _vp, _vp, _vp,
                                        _vp]),

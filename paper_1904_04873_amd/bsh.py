@@ -188,6 +188,17 @@ def bsh_grid_build(spec, t_mid: float):
     return a_p, per, off, t_asc[:n_bin.value]
 
 
+def bsh_normalize(raw: torch.Tensor, window: int = 101, out: Optional[torch.Tensor] = None):
+    """Normalized power [n_seg, n_raw - window + 1] from raw SFT powers by a running median."""
+    assert raw.is_cuda and raw.dtype == torch.float32 and raw.dim() == 2
+    raw = raw.contiguous()
+    n_seg, n_raw = raw.shape
+    if out is None:
+        out = torch.empty((n_seg, n_raw - window + 1), dtype=torch.float32, device=raw.device)
+    check(N.load().bsh_normalize(_ptr(raw), n_seg, n_raw, int(window), _ptr(out), _stream()), "bsh_normalize")
+    return out
+
+
 def bsh_peakgram(power: torch.Tensor, rho_th: float = 1.6, out: Optional[torch.Tensor] = None):
     """Bit-packed peakgram [n_seg, ceil(n_bins/32)] int32 (bit patterns of uint32 words)."""
     assert power.is_cuda and power.dtype == torch.float32 and power.dim() == 2

@@ -144,6 +144,58 @@ extern "C" int bsh_grid_build(const bsh_grid_spec* spec, double t_mid, double* a
     return BSH_OK;
 }
 
+// ---------------------------------------------------------------- normalized power
+
+// eq:HoughPower: rho_k = P_k / <n_k>^2, the noise level <n_k>^2 estimated from the running median
+// of the window [k - m, k + m] divided by the expected median of 2m+1 unit exponentials.
+// One block per segment; the raw row sits in LDS and every output finds its window's median by
+// rank counting (the value v with #{< v} <= m < #{<= v}).
+constexpr int kMaxRaw = 4096;
+
+__global__ __launch_bounds__(256) void normalize_kernel(const float* __restrict__ raw, int32_t n_raw,
+                                                        int32_t m, double beta, float* __restrict__ rho)
+{
+    __shared__ float row[kMaxRaw];
+    const int64_t J = blockIdx.x;
+    const float* src = raw + J * n_raw;
+    for (int i = threadIdx.x; i < n_raw; i += blockDim.x) row[i] = src[i];
+    __syncthreads();
+    const int win = 2 * m + 1;
+    const int n_out = n_raw - 2 * m;
+    for (int c = threadIdx.x; c < n_out; c += blockDim.x) {
+        const float* w = row + c;
+        float med = w[m];
+        for (int j = 0; j < win; ++j) {
+            const float v = w[j];
+            int lt = 0, le = 0;
+            for (int i = 0; i < win; ++i) {
+                lt += w[i] < v ? 1 : 0;
+                le += w[i] <= v ? 1 : 0;
+            }
+            if (lt <= m && le > m) { med = v; break; }
+        }
+        rho[J * n_out + c] = (float)(((double)w[m] * beta) / (double)med);
+    }
+}
+
+extern "C" int bsh_normalize(const float* raw, int64_t n_seg, int32_t n_raw, int32_t window,
+                             float* rho_out, bsh_stream stream)
+{
+    clear_error();
+    if (n_seg < 0) return fail_inval("n_seg < 0");
+    if (window < 1 || (window & 1) == 0) return fail_inval("window must be odd and >= 1");
+    if (n_raw < window || n_raw > kMaxRaw) return fail_inval("n_raw must be in window .. 4096");
+    if (n_seg == 0) return BSH_OK;
+    if (n_seg > 0x7fffffff) return fail_inval("too many segments");
+    if (!raw || !rho_out) return fail_inval("NULL pointer");
+    const int32_t m = (window - 1) / 2;
+    double beta = 0.0;                       // expected median of `window` unit exponentials
+    for (int32_t i = 2 * m + 1; i >= m + 1; --i) beta += 1.0 / (double)i;
+    hipLaunchKernelGGL(normalize_kernel, dim3((unsigned)n_seg), dim3(256), 0, (hipStream_t)stream, raw,
+                       n_raw, m, beta, rho_out);
+    return check_launch("bsh_normalize");
+}
+
 // ---------------------------------------------------------------- peakgram
 
 __global__ void peakgram_kernel(const float* __restrict__ power, int64_t n_seg, int32_t n_bins,

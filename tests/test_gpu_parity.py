@@ -527,3 +527,18 @@ def test_power_stat_ecc_matches_oracle(B, mode):
     Pc = B.bsh_power_stat(ds, sky, *_dev_cands(cand, cs), mode=mode)
     torch.cuda.synchronize()
     assert torch.equal(P0, Pc)
+
+
+@pytest.mark.parametrize("window,n_raw", [(101, 234), (101, 101), (11, 40), (1, 7), (101, 4096)])
+def test_normalize_bit_exact(B, window, n_raw):
+    """Running-median normalization (eq:HoughPower) and the peakgram built from it, bit for bit."""
+    import torch
+    _say(f"normalize window={window} n_raw={n_raw}")
+    raw = S.raw_sft_powers(np.random.default_rng(window + n_raw), 257, n_raw, 180000)
+    raw[5, :20] = raw[5, 0]                    # ties inside windows
+    rho = B.bsh_normalize(torch.from_numpy(raw).cuda(), window)
+    bits = B.bsh_peakgram(rho, 1.6)
+    torch.cuda.synchronize()
+    ref = O.normalize(raw, window)
+    assert np.array_equal(_np(rho), ref)
+    assert np.array_equal(_np(bits).view(np.uint32), O.peakgram(ref, 1.6))

@@ -524,3 +524,36 @@ def test_ecc_power_zero_eccentricity_matches_circular_power():
         P_c = O.power_stat(seg, S.fixed_pixel(), cs, cand, mode=mode)[0]
         P_e = O.power_stat_ecc(seg, S.fixed_pixel(), cs, ce, mode=mode)[0]
         assert np.array_equal(P_c, P_e)
+
+
+# ---------------------------------------------------------------- spectrogram normalization
+
+def test_median_bias_matches_expected_exponential_median():
+    """beta(2m+1) is the mean of the sample median of 2m+1 unit exponentials (order statistics)."""
+    rng = np.random.default_rng(4)
+    for window in (3, 11, 101):
+        x = rng.standard_exponential((40000, window))
+        assert np.median(x, axis=1).mean() == pytest.approx(O.median_bias(window), rel=4e-3)
+    assert O.median_bias(101) == pytest.approx(np.log(2), rel=0.01)
+
+
+def test_normalize_gives_unit_exponential_noise():
+    """Exp(1) noise on any smooth floor normalizes to mean 1 with P(rho > 1.6) = e^-1.6 (Sec. IV.A)."""
+    raw = S.raw_sft_powers(np.random.default_rng(5), 400, 134 + 100, 180000 - 72)
+    rho = O.normalize(raw)
+    assert rho.shape == (400, 134)
+    assert abs(float(rho.mean()) - 1.0) < 0.01
+    assert abs(float((rho > 1.6).mean()) - np.exp(-1.6)) < 0.005
+    # a pure scale per segment cancels exactly up to float rounding
+    rho2 = O.normalize(raw * np.float32(4.0))
+    assert np.array_equal(rho2, rho)
+
+
+def test_normalize_is_median_of_window_brute_force():
+    raw = np.random.default_rng(6).exponential(1.0, (3, 30)).astype(np.float32)
+    rho = O.normalize(raw, window=11)
+    beta = O.median_bias(11)
+    for J in range(3):
+        for c in range(20):
+            med = sorted(raw[J, c:c + 11].tolist())[5]
+            assert rho[J, c] == np.float32((float(raw[J, c + 5]) * beta) / med)
