@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="enqueue every step eagerly")
     ap.add_argument("--cpu-sample-ap", type=int, default=8,
                     help="a_p values (of 64) in the oracle's timed sample")
     ap.add_argument("--skip-batched", action="store_true",
@@ -86,18 +87,13 @@ def main():
     s2_score = torch.empty(k2, dtype=torch.float32, device=dev)
     s2_pos = torch.empty(k2, dtype=torch.int64, device=dev)
     P = torch.empty(k1, dtype=torch.float32, device=dev)
-    ev_count = []
+    from paper_1904_04873_amd import autotune
+    (lanes, chunk), tune_ms = autotune.tune_plain(ds, g, use_cache=False)
+    print(f"[bench] tile {lanes} x {chunk}", file=sys.stderr, flush=True)
 
-    def step(record):
+    def step():
         bsh.bsh_peakgram(ds.power, 1.6, out=ds.peak_bits)
-        if record:
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-        bsh.bsh_hough_count(ds, g, status=st, wsum_out=ws_map)
-        if record:
-            e1.record()
-            ev_count.append((e0, e1))
+        bsh.bsh_hough_count(ds, g, status=st, wsum_out=ws_map, lanes=lanes, chunk=chunk)
         top1(ws_map, out_score=s1_score, out_index=s1_index)
         cs, cp = bsh.bsh_decode_templates(g, s1_index)
         bsh.bsh_power_stat(ds, g.sky, cs, cp, mode=0, with_counts=True, status=st, out=P)
@@ -112,9 +108,29 @@ def main():
         del src, dst
 
     for _ in range(args.warmup):
-        step(False)
+        step()
     torch.cuda.synchronize()
     st.raise_if_set("warmup")
+
+    # One step is one HIP graph replay: the ~50 launches of a step are enqueued once at capture
+    # time, so host launch latency does not stretch the step.
+    run_step = step
+    if not args.no_graph:
+        graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph):
+            step()
+        torch.cuda.synchronize()
+        run_step = graph.replay
+        for _ in range(args.warmup):
+            run_step()
+        torch.cuda.synchronize()
+        st.raise_if_set("graph warmup")
     print(f"[bench] warmup done, timing {args.steps} steps", file=sys.stderr, flush=True)
 
     t_start = torch.cuda.Event(enable_timing=True)
@@ -122,13 +138,25 @@ def main():
     torch.cuda.synchronize()
     t_start.record()
     for _ in range(args.steps):
-        step(True)
+        run_step()
     t_end.record()
     torch.cuda.synchronize()
     st.raise_if_set("timed steps")
     ms_total = t_start.elapsed_time(t_end)
     ms_step = ms_total / max(args.steps, 1)
-    count_ms = float(np.mean([a.elapsed_time(b) for a, b in ev_count]))
+
+    # The dominant kernel alone: the same stage-1 launch, back to back on the stream it runs on,
+    # bracketed by HIP events.
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    n_count = max(args.steps, 3)
+    c0.record()
+    for _ in range(n_count):
+        bsh.bsh_hough_count(ds, g, status=st, wsum_out=ws_map, lanes=lanes, chunk=chunk)
+    c1.record()
+    torch.cuda.synchronize()
+    st.raise_if_set("count kernel")
+    count_ms = c0.elapsed_time(c1) / n_count
     value = ts_per_step / (ms_step / 1e3)
     achieved = OPS_PER_TS * ts_per_step / (count_ms / 1e3)
     print(f"[bench] {ms_step:.3f} ms/step, count kernel {count_ms:.3f} ms", file=sys.stderr, flush=True)
@@ -174,6 +202,7 @@ def main():
             "topk_stage1": k1,
             "topk_stage2": k2,
             "parallelism": "single GPU",
+            "step_launch": "eager" if args.no_graph else "hip graph replay",
         },
         "roofline": {
             "bound": "alu",
@@ -185,6 +214,8 @@ def main():
             "traffic": None,
             "count_kernel_ms": count_ms,
             "ops_per_template_segment": OPS_PER_TS,
+            "tile": {"lanes": lanes, "chunk": chunk},
+            "autotune_ms": {f"{l}x{c}": t for (l, c), t in tune_ms.items()},
         },
         "cpu_baseline": cpu,
         "batched": batched,

@@ -5,7 +5,7 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libbsh.so")
+LIB_PATH = os.environ.get("BSH_LIBRARY", os.path.join(HERE, "libbsh.so"))
 
 BSH_OK = 0
 BSH_EINVAL = -1

@@ -65,6 +65,41 @@ def time_plan(plan: "bsh.Plan", reps: int = 2) -> float:
     return ts[len(ts) // 2]
 
 
+def tune_plain(seg: "bsh.DeviceSegments", grid: "bsh.DeviceGrid", shapes=SHAPES, reps: int = 3,
+               use_cache: bool = True, verbose: bool = False):
+    """Best (lanes, chunk) for one item's plain launch (bsh_hough_count_ex); ({shape: ms})."""
+    dev = torch.cuda.get_device_name(0)
+    key = (dev + f"|plain|nf0={grid.n_f0}|words={(seg.n_bins + 31) // 32}|seg={seg.n_seg}"
+           f"|sky={grid.n_sky}|bin={grid.n_bin}")
+    db = _load() if use_cache else {}
+    if use_cache and key in db:
+        e = db[key]
+        return (int(e["lanes"]), int(e["chunk"])), {tuple(map(int, k.split("x"))): v
+                                                     for k, v in e.get("times", {}).items()}
+    out = torch.empty(grid.n_templates, dtype=torch.float32, device=seg.t_mid.device)
+    times = {}
+    for shape in shapes:
+        run = lambda: bsh.bsh_hough_count(seg, grid, wsum_out=out, lanes=shape[0], chunk=shape[1])
+        run()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            run()
+        b.record()
+        torch.cuda.synchronize()
+        times[shape] = a.elapsed_time(b) / reps
+        if verbose:
+            print(f"[autotune] plain lanes={shape[0]} chunk={shape[1]}: {times[shape]:.3f} ms", flush=True)
+    best = min(times, key=times.get)
+    if use_cache:
+        db[key] = {"lanes": best[0], "chunk": best[1],
+                   "times": {f"{l}x{c}": t for (l, c), t in times.items()}}
+        _store(db)
+    return best, times
+
+
 def tune(items: Sequence, grids: Sequence["bsh.DeviceGrid"], n_bands: int, sample: int = 16,
          shapes: Sequence[Tuple[int, int]] = SHAPES, use_cache: bool = True, verbose: bool = False):
     """Best (lanes, chunk) for these items; returns (shape, {shape: ms}).

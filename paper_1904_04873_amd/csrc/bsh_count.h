@@ -57,7 +57,7 @@ struct WorkUnit {
 };
 
 constexpr int kGroup = 4;            // segments per subset-sum table (table variant)
-constexpr int kFlushGroups = 64;     // groups per register partial sum (table variant)
+constexpr int kFlushGroups = 128;    // groups per register partial sum (table variant)
 
 template <int kChunk>
 struct TileSmemLut {

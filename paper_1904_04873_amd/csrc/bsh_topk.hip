@@ -48,6 +48,7 @@ struct Seg {
     uint32_t* hist;          // [n_segs][kBins]
     float* sel_score;        // [n_segs][k]
     int64_t* sel_index;      // [n_segs][k]
+    uint32_t* rank;          // [n_segs][k]
 };
 
 __host__ __device__ inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -56,7 +57,8 @@ size_t workspace_bytes(int32_t n_segs, int32_t k)
 {
     const size_t ns = (size_t)(n_segs > 0 ? n_segs : 1);
     return align_up(sizeof(State) * ns) + align_up(sizeof(uint32_t) * kBins * ns) +
-           align_up(sizeof(float) * (size_t)k * ns) + align_up(sizeof(int64_t) * (size_t)k * ns);
+           align_up(sizeof(float) * (size_t)k * ns) + align_up(sizeof(int64_t) * (size_t)k * ns) +
+           align_up(sizeof(uint32_t) * (size_t)k * ns);
 }
 
 void carve(void* ws, Seg& s)
@@ -70,6 +72,8 @@ void carve(void* ws, Seg& s)
     s.sel_score = (float*)p;
     p += align_up(sizeof(float) * (size_t)s.k * ns);
     s.sel_index = (int64_t*)p;
+    p += align_up(sizeof(int64_t) * (size_t)s.k * ns);
+    s.rank = (uint32_t*)p;
 }
 
 // Order-preserving map float -> uint32 (larger float -> larger key); -0 is folded onto +0.
@@ -262,15 +266,25 @@ __device__ __forceinline__ bool precedes(float sa, int64_t ia, float sb, int64_t
     return ka > kb || (ka == kb && ia < ib);
 }
 
-// out[g][rank(e)] = e, rank(e) = number of chosen entries of segment g preceding e.
-__global__ __launch_bounds__(kThreads) void rank_kernel(Seg s, float* __restrict__ out_score,
-                                                        int64_t* __restrict__ out_index)
+// rank(e) = number of chosen entries of segment g preceding e, accumulated over slices of
+// the chosen entries (grid.z) so that large k still fills the device.
+__global__ void rank_zero_kernel(Seg s)
+{
+    const int g = blockIdx.y;
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < (uint32_t)s.k) s.rank[(size_t)g * s.k + e] = 0u;
+}
+
+__global__ __launch_bounds__(kThreads) void rank_kernel(Seg s, uint32_t slice)
 {
     __shared__ float ts[kThreads];
     __shared__ int64_t ti[kThreads];
     const int g = blockIdx.y;
     const uint32_t k_eff = s.st[g].k_eff;
     if (blockIdx.x * kThreads >= k_eff) return;
+    const uint32_t f_lo = blockIdx.z * slice;
+    if (f_lo >= k_eff) return;
+    const uint32_t f_hi = min(k_eff, f_lo + slice);
     const float* ss = s.sel_score + (size_t)g * s.k;
     const int64_t* si = s.sel_index + (size_t)g * s.k;
     const uint32_t e = blockIdx.x * kThreads + threadIdx.x;
@@ -278,18 +292,29 @@ __global__ __launch_bounds__(kThreads) void rank_kernel(Seg s, float* __restrict
     const float sc = mine ? ss[e] : 0.f;
     const int64_t ix = mine ? si[e] : 0;
     uint32_t rank = 0u;
-    for (uint32_t base = 0; base < k_eff; base += kThreads) {
+    for (uint32_t base = f_lo; base < f_hi; base += kThreads) {
         __syncthreads();
         const uint32_t f = base + threadIdx.x;
-        if (f < k_eff) { ts[threadIdx.x] = ss[f]; ti[threadIdx.x] = si[f]; }
+        if (f < f_hi) { ts[threadIdx.x] = ss[f]; ti[threadIdx.x] = si[f]; }
         __syncthreads();
-        const uint32_t m = min((uint32_t)kThreads, k_eff - base);
+        const uint32_t m = min((uint32_t)kThreads, f_hi - base);
         if (mine)
             for (uint32_t q = 0; q < m; ++q) rank += precedes(ts[q], ti[q], sc, ix) ? 1u : 0u;
     }
-    if (mine && rank < k_eff) {
-        out_score[(size_t)g * s.k + rank] = sc;
-        out_index[(size_t)g * s.k + rank] = ix;
+    if (mine && rank) atomicAdd(&s.rank[(size_t)g * s.k + e], rank);
+}
+
+// out[g][rank(e)] = e
+__global__ void scatter_kernel(Seg s, float* __restrict__ out_score, int64_t* __restrict__ out_index)
+{
+    const int g = blockIdx.y;
+    const uint32_t k_eff = s.st[g].k_eff;
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= k_eff) return;
+    const uint32_t r = s.rank[(size_t)g * s.k + e];
+    if (r < k_eff) {
+        out_score[(size_t)g * s.k + r] = s.sel_score[(size_t)g * s.k + e];
+        out_index[(size_t)g * s.k + r] = s.sel_index[(size_t)g * s.k + e];
     }
 }
 
@@ -337,8 +362,13 @@ int topk_launch(Seg s, int64_t max_len, float* out_score, int64_t* out_index, hi
         hipLaunchKernelGGL(tie_pick_kernel, dim3(s.n_segs), dim3(kBins), 0, st, s);
     }
     hipLaunchKernelGGL(tie_take_kernel, grid2, dim3(kThreads), 0, st, s, n_pass);
-    hipLaunchKernelGGL(rank_kernel, dim3((s.k + kThreads - 1) / kThreads, s.n_segs), dim3(kThreads), 0,
-                       st, s, out_score, out_index);
+    // rank counting: k x k comparisons spread over (k/256) x slices blocks
+    const uint32_t kb = (uint32_t)((s.k + kThreads - 1) / kThreads);
+    uint32_t n_slices = kb < 64 ? kb : 64;
+    const uint32_t slice = (uint32_t)((s.k + n_slices - 1) / n_slices);
+    hipLaunchKernelGGL(rank_zero_kernel, dim3(kb, s.n_segs), dim3(kThreads), 0, st, s);
+    hipLaunchKernelGGL(rank_kernel, dim3(kb, s.n_segs, n_slices), dim3(kThreads), 0, st, s, slice);
+    hipLaunchKernelGGL(scatter_kernel, dim3(kb, s.n_segs), dim3(kThreads), 0, st, s, out_score, out_index);
     hipLaunchKernelGGL(fill_tail_kernel, dim3((s.k + 255) / 256, s.n_segs), dim3(256), 0, st, s,
                        out_score, out_index);
     return check_launch("bsh_topk");

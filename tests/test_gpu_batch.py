@@ -162,7 +162,8 @@ def test_every_tile_shape_gives_identical_maps(setup):
             assert torch.equal(ws, ref) and torch.equal(c, rc), (lanes, chunk)
             assert torch.equal(wt, ref_t), (lanes, chunk)
     for variant, want in ((1, ref), (2, ref_t)):
-        plan = bsh.Plan([items[3]], [g], 1, lanes=64, chunk=512, use_graph=False, lpt=False, variant=variant)
+        one = [(ds, 0, lo, ns, 0)]          # the item's grid is the only grid of this plan
+        plan = bsh.Plan(one, [g], 1, lanes=64, chunk=512, use_graph=False, lpt=False, variant=variant)
         plan.run()
         torch.cuda.synchronize()
         assert torch.equal(plan.item_map(0), want), variant

