@@ -241,6 +241,44 @@ def _segments(t_start: np.ndarray, det: np.ndarray, weights: np.ndarray,
                     k_lo=k_lo, n_bins=n_bins, detector=det.astype(np.int8))
 
 
+def half_shifted(seg: Segments, rng: np.random.Generator, sigma: float = 0.3) -> Segments:
+    """The Tc/2-shifted companion of a gapped segment set: one segment starting half a Tc after
+    each segment whose next Tc slot of the same detector is also filled (so it lies inside
+    contiguous data).  Powers are fresh Exp(1) draws over the same row (the correlation between
+    overlapping segments is not modelled) and weights fresh log-normal draws of mean 1."""
+    det = seg.detector if seg.detector is not None else np.zeros(seg.n_seg, np.int8)
+    start = seg.t_mid - 0.5 * seg.t_coh
+    keep = []
+    for d in np.unique(det):
+        idx = np.nonzero(det == d)[0]
+        idx = idx[np.argsort(start[idx], kind="stable")]
+        nxt = np.isclose(np.diff(start[idx]), seg.t_coh, rtol=0, atol=1e-6)
+        keep.append(idx[:-1][nxt])
+    keep = np.sort(np.concatenate(keep)) if keep else np.zeros(0, np.int64)
+    t_mid = seg.t_mid[keep] + 0.5 * seg.t_coh
+    d = det[keep]
+    v = np.empty((t_mid.size, 3))
+    for dd in np.unique(d):
+        m = d == dd
+        v[m] = velocity_over_c(t_mid[m], int(dd))
+    return Segments(t_mid=t_mid, v_over_c=v, weight=lognormal_weights(rng, t_mid.size, sigma),
+                    power=exp1_powers(rng, t_mid.size, seg.n_bins), k_lo=seg.k_lo, n_bins=seg.n_bins,
+                    t_coh=seg.t_coh, detector=d.astype(np.int8))
+
+
+def concat_segments(a: Segments, b: Segments) -> Segments:
+    """One table holding the segments of a followed by those of b (same row window)."""
+    assert a.k_lo == b.k_lo and a.n_bins == b.n_bins and a.t_coh == b.t_coh
+    det = None
+    if a.detector is not None and b.detector is not None:
+        det = np.concatenate([a.detector, b.detector])
+    return Segments(t_mid=np.concatenate([a.t_mid, b.t_mid]),
+                    v_over_c=np.concatenate([a.v_over_c, b.v_over_c]),
+                    weight=np.concatenate([a.weight, b.weight]),
+                    power=np.concatenate([a.power, b.power]), k_lo=a.k_lo, n_bins=a.n_bins,
+                    t_coh=a.t_coh, detector=det)
+
+
 def two_detector_starts(rng: np.random.Generator, n_per_det: Sequence[int],
                         n_slots: int) -> Tuple[np.ndarray, np.ndarray]:
     starts, det = [], []

@@ -557,3 +557,29 @@ def test_normalize_is_median_of_window_brute_force():
         for c in range(20):
             med = sorted(raw[J, c:c + 11].tolist())[5]
             assert rho[J, c] == np.float32((float(raw[J, c + 5]) * beta) / med)
+
+
+def test_stage2_on_doubled_set_is_sum_over_both_sets():
+    """Stage 2 over the segments plus their Tc/2-shifted companions (Sec. IV.C, second step) is
+    the sum of the two sets' statistics, in both modes; counts and near-ties add exactly."""
+    w = S.config2(n_per_det=5)
+    r = np.random.default_rng(3)
+    t0, det = S.two_detector_starts(r, (80, 80), 100)
+    a = S._segments(t0, det, S.lognormal_weights(r, t0.size), r, w.segments[0].k_lo, w.segments[0].n_bins)
+    b = S.half_shifted(a, r)
+    u = S.concat_segments(a, b)
+    assert b.n_seg > 80
+    for d in (0, 1):          # every companion starts Tc/2 after a segment of its detector
+        assert np.all(np.isin(b.t_mid[b.detector == d] - 450.0, a.t_mid[a.detector == d]))
+    rng = np.random.default_rng(8)
+    cand = np.stack([180000 + rng.uniform(0, 89, 300), rng.uniform(0.01, 3, 300),
+                     rng.uniform(15, 45, 300) * S.DAY, rng.uniform(0, 3e6, 300)], axis=1)
+    cs = np.zeros(300, np.int32)
+    for mode in (0, 1):
+        pu, cu, nwu, ntu = O.power_stat(u, w.sky, cs, cand, mode=mode)
+        pa, ca, nwa, nta = O.power_stat(a, w.sky, cs, cand, mode=mode)
+        pb, cb, nwb, ntb = O.power_stat(b, w.sky, cs, cand, mode=mode)
+        assert np.allclose(pu, pa + pb, rtol=1e-12, atol=0)
+        if mode == 0:
+            assert np.array_equal(cu, ca + cb) and np.array_equal(ntu, nta + ntb)
+            assert np.allclose(nwu, nwa + nwb, rtol=1e-12, atol=0)
