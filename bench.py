@@ -29,9 +29,45 @@ sys.path.insert(0, ROOT)
 METRIC = "Hough templates·segments/s on 1 GPU, batched vs plain, at oracle-exact top-k"
 # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: 32-bit VALU lane-operations per second
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
-# algorithmic VALU lane-ops per template x segment of the weighted count: extract the peak
-# bit, select the weight, add
-OPS_PER_TS = 3
+# VALU lane-operations per template x segment on the fast path of the subset-sum table count
+# (counted in its gfx950 ISA): per group of 4 segments x 90 f0 bins, 383 for the 90 table
+# lookups (nibble, table address, add) and the interleave of the four masks, plus about 40 per
+# segment for the track's bin and 96-bit mask: (383 + 4 x 40) / 360 = 1.5
+TABLE_OPS_PER_TS = 1.5
+# the same figure for plain select-and-add: extract the peak bit, select the weight, add
+SELECT_OPS_PER_TS = 3
+# HBM bytes per count launch, measured with rocprofv3 counters for one kernel source and tile
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hough_count_table_band200Hz_traffic.txt")
+COUNT_SOURCES = ("paper_1904_04873_amd/csrc/bsh_count.hip", "paper_1904_04873_amd/csrc/bsh_count.h",
+                 "paper_1904_04873_amd/csrc/bsh_internal.h")
+
+
+def count_sources_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in COUNT_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(lanes: int, chunk: int):
+    """HBM bytes per launch from the committed counter summary, or None when the count kernel's
+    sources or the tile differ from those the counters were taken on."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                parts = line.split()
+                if len(parts) == 2 and not line.startswith("#"):
+                    kv[parts[0]] = parts[1]
+        if kv.get("sources_sha256") != count_sources_digest():
+            return None
+        if (int(kv["lanes"]), int(kv["chunk"])) != (lanes, chunk):
+            return None
+        return float(kv["traffic_bytes"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -41,7 +77,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="enqueue every step eagerly")
-    ap.add_argument("--cpu-sample-ap", type=int, default=8,
+    ap.add_argument("--cpu-sample-ap", type=int, default=32,
                     help="a_p values (of 64) in the oracle's timed sample")
     ap.add_argument("--skip-batched", action="store_true",
                     help="omit the batched-versus-plain comparison")
@@ -158,7 +194,8 @@ def main():
     st.raise_if_set("count kernel")
     count_ms = c0.elapsed_time(c1) / n_count
     value = ts_per_step / (ms_step / 1e3)
-    achieved = OPS_PER_TS * ts_per_step / (count_ms / 1e3)
+    achieved = TABLE_OPS_PER_TS * ts_per_step / (count_ms / 1e3)
+    achieved_select = SELECT_OPS_PER_TS * ts_per_step / (count_ms / 1e3)
     print(f"[bench] {ms_step:.3f} ms/step, count kernel {count_ms:.3f} ms", file=sys.stderr, flush=True)
 
     batched = None if args.skip_batched else run_batched(args)
@@ -206,14 +243,17 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "hough_count_kernel",
+            "kernel": f"hough_count_kernel<2, {chunk}> (subset-sum tables)",
             "achieved": achieved / 1e12,
             "peak": VALU_PEAK_OPS / 1e12,
             "unit": "TOP/s",
             "frac": achieved / VALU_PEAK_OPS,
-            "traffic": None,
+            "traffic": measured_traffic(lanes, chunk),
             "count_kernel_ms": count_ms,
-            "ops_per_template_segment": OPS_PER_TS,
+            "ops_per_template_segment": TABLE_OPS_PER_TS,
+            "select_add_equivalent": {"ops_per_template_segment": SELECT_OPS_PER_TS,
+                                      "achieved": achieved_select / 1e12,
+                                      "frac": achieved_select / VALU_PEAK_OPS},
             "tile": {"lanes": lanes, "chunk": chunk},
             "autotune_ms": {f"{l}x{c}": t for (l, c), t in tune_ms.items()},
         },

@@ -43,21 +43,23 @@ __device__ __forceinline__ uint32_t upper_mask(int t)
 // 96-bit (m0, m1, m2) is the peakgram bit of f0 bin i's track.  Returns false (and flags) when
 // the track leaves the staged row or drifts more than one bin across the band.
 __device__ __forceinline__ bool band_mask(const uint32_t* row, double C, double S, double D, double cb,
-                                          double sb, double apW, double F0, double FL, double klo,
+                                          double sb, double apW, double F0, double FL, int klo,
                                           int last, int n_bins, uint32_t& m0, uint32_t& m1,
                                           uint32_t& m2, bool& bad_range, bool& bad_model)
 {
     // same operation order as orbit_phase / track_x: G = D (1 - a_p W cos phi)
     const double cphi = fma(C, cb, S * sb);
     const double G = D * (1.0 - apW * cphi);
-    const double kf = floor(F0 * G + 0.5);
-    const double kl = floor(FL * G + 0.5);
-    const int base = (int)(kf - klo);
-    const int top = (int)(kl - klo);
+    // floor(x + 1/2) of a positive track value is its truncation to an integer
+    const double y0 = F0 * G + 0.5;
+    const int kf = (int)y0;
+    const int kl = (int)(FL * G + 0.5);
+    const int base = kf - klo;
+    const int top = kl - klo;
     const int delta = top - base - last;
     if (base < 0 || top >= n_bins) { bad_range = true; return false; }
     if (delta < -1 || delta > 1) { bad_model = true; return false; }
-    const int r0 = (int)(kf - F0);
+    const int r0 = kf - (int)F0;
     const int qw = base >> 5;
     const int sh = base & 31;
     const uint32_t w0 = row[qw], w1 = row[qw + 1], w2 = row[qw + 2], w3 = row[qw + 3];
@@ -65,12 +67,28 @@ __device__ __forceinline__ bool band_mask(const uint32_t* row, double C, double 
     m1 = __builtin_amdgcn_alignbit(w2, w1, sh);
     m2 = __builtin_amdgcn_alignbit(w3, w2, sh);
     if (delta != 0) {
-        int lo = 0, hi = last;   // r_lo = r0, r_hi = r0 + delta
+        // The residual r_i = k_i - (k0 + i) steps once, where y0 + i (G - 1) crosses an integer.
+        // A single-precision guess of that offset is checked with exact evaluations; the
+        // bisection below only runs when the guess is off.
+        auto resid = [&](int i) { return (int)((F0 + (double)i) * G + 0.5) - ((int)F0 + i); };
+        const double num = delta > 0 ? (double)(kf + 1) - y0 : y0 - (double)kf;
+        const float den = (float)((double)delta * (G - 1.0));
+        const float q = fminf(fmaxf((float)num * __builtin_amdgcn_rcpf(den), 0.f), (float)last);
+        const int g = min(max((int)q + 1, 1), last);
+        int lo, hi;              // r_lo = r0, r_hi != r0
+        if (g < last && resid(g) == r0) {
+            lo = g;
+            hi = last;
+        } else if (g == 1 || resid(g - 1) == r0) {
+            lo = g - 1;
+            hi = g;
+        } else {
+            lo = 0;
+            hi = g - 1;
+        }
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
-            const double Fm = F0 + (double)mid;
-            const int rm = (int)(floor(Fm * G + 0.5) - Fm);
-            if (rm == r0) lo = mid; else hi = mid;
+            if (resid(mid) == r0) lo = mid; else hi = mid;
         }
         uint32_t n0, n1, n2;
         if (delta > 0) {
@@ -120,7 +138,7 @@ __device__ __forceinline__ void count_tile(const ItemDesc& d, int s, int ip, int
     const double F0 = (double)d.k0;
     const int last = d.n_f0 - 1;
     const double FL = (double)(d.k0 + last);
-    const double klo = (double)d.k_lo;
+    const int klo = (int)d.k_lo;
     const int nwp = d.n_words + kRowPad;
 
     float acc[kNF], tot[kNF];
@@ -228,7 +246,7 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
     const double F0 = (double)d.k0;
     const int last = d.n_f0 - 1;
     const double FL = (double)(d.k0 + last);
-    const double klo = (double)d.k_lo;
+    const int klo = (int)d.k_lo;
     const int nwp = d.n_words + kRowPad;
 
     float acc[kNF];
@@ -299,28 +317,43 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
                     mk[u][0] = mk[u][1] = mk[u][2] = 0u;
                 }
             }
-            // A[w][r]: nibble n <- bits (4n + r) of the four masks' word w
+            // A[w][r]: bit (4n + u) <- bit (4n + r) of mask u's word w, i.e. every nibble column
+            // of the 4 x 32 bit matrix (mk[0..3][w]) transposed: swap the off-diagonal 2 x 2
+            // blocks, then the off-diagonal bits of each 2 x 2 block.
             uint32_t A[3][4];
 #pragma unroll
             for (int w = 0; w < 3; ++w) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const uint32_t sel = 0x11111111u << r;
-                    uint32_t a = 0u;
-#pragma unroll
-                    for (int u = 0; u < kGroup; ++u) {
-                        const uint32_t t = mk[u][w] & sel;
-                        a |= (u >= r) ? (t << (u - r)) : (t >> (r - u));
-                    }
-                    A[w][r] = a;
-                }
+                uint32_t x0 = mk[0][w], x1 = mk[1][w], x2 = mk[2][w], x3 = mk[3][w];
+                uint32_t t;
+                t = ((x0 >> 2) ^ x2) & 0x33333333u; x2 ^= t; x0 ^= t << 2;
+                t = ((x1 >> 2) ^ x3) & 0x33333333u; x3 ^= t; x1 ^= t << 2;
+                t = ((x0 >> 1) ^ x1) & 0x55555555u; x1 ^= t; x0 ^= t << 1;
+                t = ((x2 >> 1) ^ x3) & 0x55555555u; x3 ^= t; x2 ^= t << 1;
+                A[w][0] = x0;
+                A[w][1] = x1;
+                A[w][2] = x2;
+                A[w][3] = x3;
             }
+            // Look the bins up word by word: the table reads of word k are issued before the
+            // adds of word k-1, so one word's LDS latency overlaps the next word's reads.
             const float* T = sm.T + g * 16;
+            float v[2][8];
 #pragma unroll
-            for (int i = 0; i < kNF; ++i) {
-                const int w = i >> 5, p = i & 31;
-                const uint32_t nib = (A[w][p & 3] >> (4 * (p >> 2))) & 15u;
-                acc[i] += T[nib];
+            for (int k = 0; k <= 12; ++k) {
+                if (k < 12) {
+                    const int w = k >> 2, r = k & 3;
+#pragma unroll
+                    for (int n = 0; n < 8; ++n)
+                        if (32 * w + 4 * n + r < kNF) v[k & 1][n] = T[(A[w][r] >> (4 * n)) & 15u];
+                }
+                if (k > 0) {
+                    const int w = (k - 1) >> 2, r = (k - 1) & 3;
+#pragma unroll
+                    for (int n = 0; n < 8; ++n) {
+                        const int i = 32 * w + 4 * n + r;
+                        if (i < kNF) acc[i] += v[(k - 1) & 1][n];
+                    }
+                }
             }
             if (++since_flush == kFlushGroups) {
                 since_flush = 0;
