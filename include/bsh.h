@@ -314,6 +314,90 @@ int32_t bsh_plan_blocks(const bsh_plan* plan);
 
 int bsh_plan_destroy(bsh_plan* plan);
 
+/* ------------------------------------------------------------------ post-processing
+ *
+ * The steps after the search (Sec. V.E) on the top-lists: coincidences between two lists,
+ * clustering of one list, and significance-weighted centroids with the most significant
+ * cluster of the list (one per 0.1 Hz band).  Templates are rows [n][6] FP64 of
+ * (f in Hz, x, y, a_p in lt-s, Omega = 2 pi / P in rad/s, t_asc in s); x and y project the
+ * sky direction on the plane of the detector's orbital velocity (the ecliptic).
+ *
+ * Distance (eq:postdist): d^2 = sum over the six parameters of (difference / resolution)^2 with
+ * delta f = 1/Tc and delta Theta = c/(v Tc f P_F) (Sec. IV.C) and the binary resolutions of
+ * eq:binaryres, each point-dependent resolution taken as the mean of its values at the two
+ * templates.  "Closer than w" means d^2 < w^2 evaluated in FP64 in the fixed operation order
+ * written in bsh_post.hip, so that the decisions are reproducible.
+ */
+typedef struct bsh_post_params {
+    double t_coh;         /* Tc in s */
+    double t_obs;         /* observation time in s (delta Omega) */
+    double m_a;           /* mismatch parameters of eq:binaryres */
+    double m_omega;
+    double m_t;
+    double pixel_factor;  /* P_F of the sky resolution */
+    double v_over_c;      /* |v|/c of the sky resolution (the orbital speed, about 1e-4) */
+} bsh_post_params;
+
+/*
+ * Post-processing rows of stage-2 candidates: rows_out[i] = (F/Tc, sky[s][0], sky[s][1], a_p,
+ * 2 pi / P, t_asc) for s = cand_sky[i] (cand_params as bsh_power_stat; sky indices are not
+ * range-checked here: they must come from the search).
+ */
+int bsh_post_rows(const double* sky, const int32_t* cand_sky, const double* cand_params, int64_t n,
+                  double t_coh, double* rows_out, bsh_stream stream);
+
+/*
+ * Significance of stage-1 or stage-2 scores (eq:hough2, eq:hough3) for noise with normalized
+ * power p(rho) = exp(-rho): with W1 = sum_J w_J and W2 = sum_J w_J^2 over weight[n_seg],
+ *   kind 0 (s_H): (n_w - p0 W1) / sqrt(p0 (1 - p0) W2),  p0 = exp(-rho_th)
+ *   kind 1 (s_P): (P - W1) / sqrt(W2)
+ * sig_out [n] FP64.
+ */
+int bsh_significance(const float* score, int64_t n, const float* weight, int64_t n_seg, int32_t kind,
+                     double rho_th, double* sig_out, bsh_stream stream);
+
+/* Device workspace bytes of bsh_coincidences for a first list of na rows. */
+size_t bsh_coincidences_workspace(int64_t na);
+
+/*
+ * Coincidences between two top-lists (Sec. V.E, step 1): every pair (i of a, j of b) with
+ * d < window, in (i, j) order.  Pair q gets pairs_out[q] = (i, j), the significance-weighted
+ * centroid rows_out[q] = (s_a[i] row_a[i] + s_b[j] row_b[j]) / (s_a[i] + s_b[j]) and the
+ * significance sig_out[q] = s_a[i] + s_b[j].  Only the first `cap` pairs are written;
+ * *n_pairs_out (device int64) receives the full count.
+ */
+int bsh_coincidences(const bsh_post_params* pp, const double* rows_a, const double* sig_a, int64_t na,
+                     const double* rows_b, const double* sig_b, int64_t nb, double window, int64_t cap,
+                     int64_t* pairs_out, double* rows_out, double* sig_out, int64_t* n_pairs_out,
+                     void* ws, size_t ws_bytes, bsh_stream stream);
+
+/*
+ * Clusters of one list (Sec. V.E, step 2): templates closer than `window` share a cluster and
+ * clusters that share a template merge, i.e. the connected components of the "d < window"
+ * graph.  label_out[i] = smallest index of i's cluster (int32; n < 2^31).
+ */
+int bsh_cluster(const bsh_post_params* pp, const double* rows, int64_t n, double window,
+                int32_t* label_out, bsh_stream stream);
+
+/* Device workspace bytes of bsh_cluster_centroids for n rows. */
+size_t bsh_cluster_centroids_workspace(int64_t n);
+
+/*
+ * Per cluster of `label` (as bsh_cluster writes it: every label is the index of a member
+ * labelled by itself): the most significant member top_out[r] (lowest index on ties); if
+ * cut > 0, the members closer than `cut` to it (the option-B cut of step 2; the top member is
+ * always kept); and over the kept members the summed significance weight_out[r] and the
+ * significance-weighted centroid centroid_out[r][6] (step 3).  Row r of each output is set for
+ * cluster roots r; other rows get weight 0, centroid 0 and top -1.  best_out[0] = root of the
+ * cluster with the largest summed significance (lowest root on ties).  Significances must be
+ * finite and positive, and labels valid, else BSH_STATUS_INPUT is raised.  The sums use
+ * device atomics, so their rounding may differ between runs in the last bits.
+ */
+int bsh_cluster_centroids(const bsh_post_params* pp, const double* rows, const double* sig,
+                          const int32_t* label, int64_t n, double cut, double* centroid_out,
+                          double* weight_out, int32_t* top_out, int32_t* best_out, int32_t* status,
+                          void* ws, size_t ws_bytes, bsh_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

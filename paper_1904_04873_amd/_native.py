@@ -104,6 +104,19 @@ class PlanOpts(ctypes.Structure):
 
 
 # name -> (restype, argtypes); the complete exported surface of include/bsh.h
+class PostParams(ctypes.Structure):
+    """bsh_post_params: resolutions of the post-processing distance (eq:postdist)."""
+    _fields_ = [
+        ("t_coh", _c_f64),
+        ("t_obs", _c_f64),
+        ("m_a", _c_f64),
+        ("m_omega", _c_f64),
+        ("m_t", _c_f64),
+        ("pixel_factor", _c_f64),
+        ("v_over_c", _c_f64),
+    ]
+
+
 SIGNATURES = {
     "bsh_version": (ctypes.c_int, []),
     "bsh_last_error": (ctypes.c_char_p, []),
@@ -136,6 +149,15 @@ SIGNATURES = {
                                           _vp, _vp, _vp]),
     "bsh_power_stat_grad": (ctypes.c_int, [ctypes.POINTER(Segments), _vp, _c_i32, _vp, _vp, _c_i64,
                                            _vp, _vp, _vp, _vp]),
+    "bsh_post_rows": (ctypes.c_int, [_vp, _vp, _vp, _c_i64, _c_f64, _vp, _vp]),
+    "bsh_significance": (ctypes.c_int, [_vp, _c_i64, _vp, _c_i64, _c_i32, _c_f64, _vp, _vp]),
+    "bsh_coincidences_workspace": (ctypes.c_size_t, [_c_i64]),
+    "bsh_coincidences": (ctypes.c_int, [ctypes.POINTER(PostParams), _vp, _vp, _c_i64, _vp, _vp, _c_i64,
+                                        _c_f64, _c_i64, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "bsh_cluster": (ctypes.c_int, [ctypes.POINTER(PostParams), _vp, _c_i64, _c_f64, _vp, _vp]),
+    "bsh_cluster_centroids_workspace": (ctypes.c_size_t, [_c_i64]),
+    "bsh_cluster_centroids": (ctypes.c_int, [ctypes.POINTER(PostParams), _vp, _vp, _vp, _c_i64, _c_f64,
+                                             _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "bsh_track_bins": (ctypes.c_int, [ctypes.POINTER(Segments), _vp, _c_i32, _vp, _vp, _c_i64, _vp,
                                       _vp, _vp]),
 }

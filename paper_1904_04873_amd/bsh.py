@@ -335,6 +335,81 @@ def bsh_track_bins(seg: DeviceSegments, sky: torch.Tensor, cand_sky: torch.Tenso
     return out
 
 
+# ---------------------------------------------------------------- post-processing
+
+
+def post_params(t_coh: float = 900.0, t_obs: float = 86400.0 * 120, m_a: float = 0.4,
+                m_omega: float = 0.4, m_t: float = 0.4, pixel_factor: float = 1.0,
+                v_over_c: float = 1.0e-4) -> N.PostParams:
+    """bsh_post_params: resolutions of the post-processing distance."""
+    return N.PostParams(t_coh=t_coh, t_obs=t_obs, m_a=m_a, m_omega=m_omega, m_t=m_t,
+                        pixel_factor=pixel_factor, v_over_c=v_over_c)
+
+
+def bsh_post_rows(sky: torch.Tensor, cand_sky: torch.Tensor, cand_params: torch.Tensor,
+                  t_coh: float = 900.0):
+    """Rows (f, x, y, a_p, Omega, t_asc) [n, 6] float64 of stage-2 candidates."""
+    n = int(cand_sky.numel())
+    out = torch.empty((n, 6), dtype=torch.float64, device=cand_sky.device)
+    check(N.load().bsh_post_rows(_ptr(sky), _ptr(cand_sky), _ptr(cand_params), n, float(t_coh),
+                                 _ptr(out), _stream()), "bsh_post_rows")
+    return out
+
+
+def bsh_significance(score: torch.Tensor, weight: torch.Tensor, kind: int, rho_th: float = 1.6):
+    """s_H (kind 0) or s_P (kind 1) of float32 scores: float64 [n]."""
+    n = int(score.numel())
+    out = torch.empty(n, dtype=torch.float64, device=score.device)
+    check(N.load().bsh_significance(_ptr(score), n, _ptr(weight), int(weight.numel()), int(kind),
+                                    float(rho_th), _ptr(out), _stream()), "bsh_significance")
+    return out
+
+
+def bsh_coincidences(pp: N.PostParams, rows_a: torch.Tensor, sig_a: torch.Tensor,
+                     rows_b: torch.Tensor, sig_b: torch.Tensor, window: float, cap: int):
+    """Pairs closer than `window`: (n_pairs device int64 [1], pairs [cap, 2], rows [cap, 6],
+    sig [cap]); the first min(n_pairs, cap) rows are valid."""
+    L = N.load()
+    dev = rows_a.device
+    na, nb = int(rows_a.shape[0]), int(rows_b.shape[0])
+    ws = torch.empty(max(1, int(L.bsh_coincidences_workspace(na))), dtype=torch.uint8, device=dev)
+    pairs = torch.empty((cap, 2), dtype=torch.int64, device=dev)
+    rows = torch.empty((cap, 6), dtype=torch.float64, device=dev)
+    sig = torch.empty(cap, dtype=torch.float64, device=dev)
+    n_pairs = torch.empty(1, dtype=torch.int64, device=dev)
+    check(L.bsh_coincidences(ctypes.byref(pp), _ptr(rows_a), _ptr(sig_a), na, _ptr(rows_b), _ptr(sig_b), nb,
+                             float(window), int(cap), _ptr(pairs), _ptr(rows), _ptr(sig), _ptr(n_pairs),
+                             _ptr(ws), ws.numel(), _stream()), "bsh_coincidences")
+    return n_pairs, pairs, rows, sig
+
+
+def bsh_cluster(pp: N.PostParams, rows: torch.Tensor, window: float):
+    """Cluster label (smallest member index) of every row: int32 [n]."""
+    n = int(rows.shape[0])
+    out = torch.empty(n, dtype=torch.int32, device=rows.device)
+    check(N.load().bsh_cluster(ctypes.byref(pp), _ptr(rows), n, float(window), _ptr(out), _stream()),
+          "bsh_cluster")
+    return out
+
+
+def bsh_cluster_centroids(pp: N.PostParams, rows: torch.Tensor, sig: torch.Tensor, label: torch.Tensor,
+                          cut: float = 0.0, status: Optional[Status] = None):
+    """(centroid [n, 6], weight [n], top [n], best [1]) per cluster root (see the C header)."""
+    L = N.load()
+    n = int(rows.shape[0])
+    dev = rows.device
+    ws = torch.empty(max(1, int(L.bsh_cluster_centroids_workspace(n))), dtype=torch.uint8, device=dev)
+    cen = torch.empty((n, 6), dtype=torch.float64, device=dev)
+    weight = torch.empty(n, dtype=torch.float64, device=dev)
+    top = torch.empty(n, dtype=torch.int32, device=dev)
+    best = torch.empty(1, dtype=torch.int32, device=dev)
+    check(L.bsh_cluster_centroids(ctypes.byref(pp), _ptr(rows), _ptr(sig), _ptr(label), n, float(cut),
+                                  _ptr(cen), _ptr(weight), _ptr(top), _ptr(best),
+                                  status.ptr() if status else None, _ptr(ws), ws.numel(), _stream()),
+          "bsh_cluster_centroids")
+    return cen, weight, top, best
+
+
 # ---------------------------------------------------------------- batched plan
 
 ITEM_SHIFT = 40

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbsh.so")
-SOURCES = ["bsh_api.hip", "bsh_count.hip", "bsh_batch.hip", "bsh_power.hip", "bsh_topk.hip"]
+SOURCES = ["bsh_api.hip", "bsh_count.hip", "bsh_batch.hip", "bsh_power.hip", "bsh_topk.hip", "bsh_post.hip"]
 ARCH = os.environ.get("BSH_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -176,3 +176,31 @@ def test_plan_rejects_bad_items_on_host():
                              None, None, ctypes.byref(h)) == N.BSH_EINVAL
     assert L.bsh_plan_destroy(None) == N.BSH_OK
     assert L.bsh_plan_units(None) == -1
+
+
+def test_post_processing_entry_points_reject_bad_arguments():
+    from paper_1904_04873_amd import _native as N
+    L = _lib()
+    fake = ctypes.c_void_p(0x2000)
+    pp = N.PostParams(t_coh=900.0, t_obs=1e7, m_a=0.4, m_omega=0.4, m_t=0.4, pixel_factor=1.0, v_over_c=1e-4)
+    bad = N.PostParams(t_coh=900.0, t_obs=1e7, m_a=0.0, m_omega=0.4, m_t=0.4, pixel_factor=1.0, v_over_c=1e-4)
+    assert L.bsh_cluster(ctypes.byref(bad), fake, 10, 3.0, fake, None) == N.BSH_EINVAL
+    assert L.bsh_cluster(None, fake, 10, 3.0, fake, None) == N.BSH_EINVAL
+    assert L.bsh_cluster(ctypes.byref(pp), fake, 10, float("nan"), fake, None) == N.BSH_EINVAL
+    assert L.bsh_cluster(ctypes.byref(pp), None, 10, 3.0, fake, None) == N.BSH_EINVAL
+    assert L.bsh_cluster(ctypes.byref(pp), fake, 1 << 31, 3.0, fake, None) == N.BSH_EINVAL
+    assert L.bsh_cluster(ctypes.byref(pp), None, 0, 3.0, None, None) == N.BSH_OK
+    assert L.bsh_coincidences_workspace(100) >= 8 * 201
+    assert L.bsh_coincidences(ctypes.byref(pp), fake, fake, 100, fake, fake, 50, 3.0, 10, fake, fake, fake,
+                              fake, fake, 16, None) == N.BSH_ENOMEM
+    assert L.bsh_coincidences(ctypes.byref(pp), fake, fake, 100, fake, fake, 50, 3.0, 10, None, fake, fake,
+                              fake, fake, 1 << 20, None) == N.BSH_EINVAL
+    assert L.bsh_coincidences(ctypes.byref(pp), fake, fake, 100, fake, fake, 50, -1.0, 10, fake, fake, fake,
+                              fake, fake, 1 << 20, None) == N.BSH_EINVAL
+    assert L.bsh_cluster_centroids(ctypes.byref(pp), fake, fake, fake, 100, 0.0, fake, fake, fake, fake,
+                                   None, fake, 8, None) == N.BSH_ENOMEM
+    assert L.bsh_cluster_centroids(ctypes.byref(pp), fake, fake, fake, 100, float("nan"), fake, fake, fake,
+                                   fake, None, fake, 1 << 20, None) == N.BSH_EINVAL
+    assert L.bsh_significance(fake, 10, fake, 10, 2, 1.6, fake, None) == N.BSH_EINVAL
+    assert L.bsh_significance(fake, 10, fake, 0, 1, 1.6, fake, None) == N.BSH_EINVAL
+    assert L.bsh_post_rows(fake, fake, fake, 10, 0.0, fake, None) == N.BSH_EINVAL
