@@ -30,10 +30,13 @@ METRIC = "Hough templates·segments/s on 1 GPU, batched vs plain, at oracle-exac
 # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: 32-bit VALU lane-operations per second
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # VALU lane-operations per template x segment on the fast path of the subset-sum table count
-# (counted in its gfx950 ISA): per group of 4 segments x 90 f0 bins, 383 for the 90 table
-# lookups (nibble, table address, add) and the interleave of the four masks, plus about 40 per
-# segment for the track's bin and 96-bit mask: (383 + 4 x 40) / 360 = 1.5
-TABLE_OPS_PER_TS = 1.5
+# (counted in its gfx950 ISA), per group of 4 segments x 90 f0 bins: about 45 per segment for
+# the track's bin and 96-bit mask, 60 for the bit transpose of the four masks, and the lookups:
+# with 16-entry tables (chunks over 128 segments) 90 x (nibble, address, add), 335 with the
+# transpose, so (335 + 4 x 45) / 360 = 1.43; with 256-entry pair tables (chunks of at most 128)
+# 46 x (byte, address) + 90 adds, 247 with the transpose, so (247 + 4 x 45) / 360 = 1.19.
+TABLE_OPS_PER_TS = {"pair": 1.19, "nibble": 1.43}
+PAIR_CHUNK = 128
 # the same figure for plain select-and-add: extract the peak bit, select the weight, add
 SELECT_OPS_PER_TS = 3
 # HBM bytes per count launch, measured with rocprofv3 counters for one kernel source and tile
@@ -194,7 +197,9 @@ def main():
     st.raise_if_set("count kernel")
     count_ms = c0.elapsed_time(c1) / n_count
     value = ts_per_step / (ms_step / 1e3)
-    achieved = TABLE_OPS_PER_TS * ts_per_step / (count_ms / 1e3)
+    table = "pair" if chunk <= PAIR_CHUNK else "nibble"
+    ops_per_ts = TABLE_OPS_PER_TS[table]
+    achieved = ops_per_ts * ts_per_step / (count_ms / 1e3)
     achieved_select = SELECT_OPS_PER_TS * ts_per_step / (count_ms / 1e3)
     print(f"[bench] {ms_step:.3f} ms/step, count kernel {count_ms:.3f} ms", file=sys.stderr, flush=True)
 
@@ -243,14 +248,14 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": f"hough_count_kernel<2, {chunk}> (subset-sum tables)",
+            "kernel": f"hough_count_kernel<2, {chunk}> (subset-sum {table} tables)",
             "achieved": achieved / 1e12,
             "peak": VALU_PEAK_OPS / 1e12,
             "unit": "TOP/s",
             "frac": achieved / VALU_PEAK_OPS,
             "traffic": measured_traffic(lanes, chunk),
             "count_kernel_ms": count_ms,
-            "ops_per_template_segment": TABLE_OPS_PER_TS,
+            "ops_per_template_segment": ops_per_ts,
             "select_add_equivalent": {"ops_per_template_segment": SELECT_OPS_PER_TS,
                                       "achieved": achieved_select / 1e12,
                                       "frac": achieved_select / VALU_PEAK_OPS},

@@ -130,6 +130,8 @@ extern "C" int64_t bsh_items_map_floats(const bsh_item* items, int32_t n_items, 
     return tot;
 }
 
+static hipError_t release_plan(bsh_plan* p);
+
 extern "C" int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh_grid* grids,
                                int32_t n_grids, int32_t n_bands, const bsh_plan_opts* opts,
                                float* maps, int64_t maps_floats, float* item_score,
@@ -226,8 +228,12 @@ extern "C" int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh
     p->n_units = (int64_t)units.size();
 
     int dev = 0, n_cu = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        set_error("bsh_plan_create: cannot query the current device");
+        delete p;
+        return BSH_EHIP;
+    }
     p->blocks = std::max(1, n_cu) * batch_blocks_per_cu(lanes, chunk, p->mode);
     if (o.blocks > 0) p->blocks = o.blocks;
 
@@ -273,7 +279,7 @@ extern "C" int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh
         }
     }
     if (rc) {
-        bsh_plan_destroy(p);
+        (void)release_plan(p);   // keeps the error text of the step that failed
         return rc;
     }
     *out = p;
@@ -340,19 +346,32 @@ extern "C" int64_t bsh_plan_units(const bsh_plan* p) { return p ? p->n_units : -
 
 extern "C" int32_t bsh_plan_blocks(const bsh_plan* p) { return p ? p->blocks : -1; }
 
+// Release everything a plan owns, even if one release fails; returns the first failure.
+static hipError_t release_plan(bsh_plan* p)
+{
+    hipError_t first = hipSuccess;
+    auto keep = [&](hipError_t e) {
+        if (first == hipSuccess && e != hipSuccess) first = e;
+    };
+    if (p->exec) keep(hipGraphExecDestroy(p->exec));
+    if (p->graph) keep(hipGraphDestroy(p->graph));
+    if (p->capture_stream) keep(hipStreamDestroy(p->capture_stream));
+    void* bufs[] = {p->d_items, p->d_units, p->d_counter, p->d_item_off, p->d_band_off, p->d_ws_item,
+                    p->d_ws_band};
+    for (void* b : bufs)
+        if (b) keep(hipFree(b));
+    delete p;
+    return first;
+}
+
 extern "C" int bsh_plan_destroy(bsh_plan* p)
 {
+    clear_error();
     if (!p) return BSH_OK;
-    if (p->exec) hipGraphExecDestroy(p->exec);
-    if (p->graph) hipGraphDestroy(p->graph);
-    if (p->capture_stream) hipStreamDestroy(p->capture_stream);
-    hipFree(p->d_items);
-    hipFree(p->d_units);
-    hipFree(p->d_counter);
-    hipFree(p->d_item_off);
-    hipFree(p->d_band_off);
-    hipFree(p->d_ws_item);
-    hipFree(p->d_ws_band);
-    delete p;
+    const hipError_t e = release_plan(p);
+    if (e != hipSuccess) {
+        set_error("bsh_plan_destroy: %s", hipGetErrorString(e));
+        return BSH_EHIP;
+    }
     return BSH_OK;
 }

@@ -59,11 +59,16 @@ struct WorkUnit {
 constexpr int kGroup = 4;            // segments per subset-sum table (table variant)
 constexpr int kFlushGroups = 128;    // groups per register partial sum (table variant)
 
+// Chunks of at most kPairChunk segments also hold, per group, the 256-entry table of pairs
+// (T[b & 15], T[b >> 4]) so that one 8-byte read serves two f0 bins (64 KB at 128 segments).
+constexpr int kPairChunk = 128;
+
 template <int kChunk>
 struct TileSmemLut {
     double C[kChunk];
     double S[kChunk];
     double D[kChunk];
+    float2 T2[kChunk <= kPairChunk ? (kChunk / kGroup) * 256 : 1];
     float T[(kChunk / kGroup) * 16];
     uint32_t row[kChunk * (BSH_MAX_WORDS + kRowPad)];
 };

@@ -40,8 +40,9 @@ __device__ __forceinline__ uint32_t upper_mask(int t)
 
 
 // The peak bits of the band's n_f0 templates of one (binary template, segment): bit i of the
-// 96-bit (m0, m1, m2) is the peakgram bit of f0 bin i's track.  Returns false (and flags) when
-// the track leaves the staged row or drifts more than one bin across the band.
+// 96-bit (m0, m1, m2) is the peakgram bit of f0 bin i's track.  Returns false, with zero masks,
+// and flags when the track leaves the staged row or drifts more than one bin across the band.
+// The common case (no f0-shift step) runs without branches.
 __device__ __forceinline__ bool band_mask(const uint32_t* row, double C, double S, double D, double cb,
                                           double sb, double apW, double F0, double FL, int klo,
                                           int last, int n_bins, uint32_t& m0, uint32_t& m1,
@@ -57,16 +58,19 @@ __device__ __forceinline__ bool band_mask(const uint32_t* row, double C, double 
     const int base = kf - klo;
     const int top = kl - klo;
     const int delta = top - base - last;
-    if (base < 0 || top >= n_bins) { bad_range = true; return false; }
-    if (delta < -1 || delta > 1) { bad_model = true; return false; }
+    const bool in_range = (base >= 0) & (top < n_bins);
+    const bool ok = in_range & ((unsigned)(delta + 1) <= 2u);
+    bad_range |= !in_range;
+    bad_model |= in_range & !ok;
     const int r0 = kf - (int)F0;
-    const int qw = base >> 5;
-    const int sh = base & 31;
+    const int at = ok ? base : 0;          // a failed track still reads inside the row
+    const int qw = at >> 5;
+    const int sh = at & 31;
     const uint32_t w0 = row[qw], w1 = row[qw + 1], w2 = row[qw + 2], w3 = row[qw + 3];
-    m0 = __builtin_amdgcn_alignbit(w1, w0, sh);
-    m1 = __builtin_amdgcn_alignbit(w2, w1, sh);
-    m2 = __builtin_amdgcn_alignbit(w3, w2, sh);
-    if (delta != 0) {
+    m0 = ok ? __builtin_amdgcn_alignbit(w1, w0, sh) : 0u;
+    m1 = ok ? __builtin_amdgcn_alignbit(w2, w1, sh) : 0u;
+    m2 = ok ? __builtin_amdgcn_alignbit(w3, w2, sh) : 0u;
+    if (ok && delta != 0) {
         // The residual r_i = k_i - (k0 + i) steps once, where y0 + i (G - 1) crosses an integer.
         // A single-precision guess of that offset is checked with exact evaluations; the
         // bisection below only runs when the guess is off.
@@ -105,7 +109,7 @@ __device__ __forceinline__ bool band_mask(const uint32_t* row, double C, double 
         m1 = (n1 & s1) | (m1 & ~s1);
         m2 = (n2 & s2) | (m2 & ~s2);
     }
-    return true;
+    return ok;
 }
 
 template <bool kCount, int kChunk>
@@ -212,7 +216,10 @@ __device__ __forceinline__ void count_tile(const ItemDesc& d, int s, int ip, int
 // select-and-add steps.  The indices of all 90 bins come from the four 96-bit masks by a bit
 // interleave: word A[w][r] holds, in nibble n, the four segments' bits of bin 32w + 4n + r.
 // A 16-entry table occupies 16 consecutive LDS banks, so any pattern of reads is free of
-// bank conflicts.  The 90 register partial sums (at most kFlushGroups groups each) are folded
+// bank conflicts.  With chunks of at most kPairChunk segments the group also gets a 256-entry
+// table of value pairs indexed by a whole byte of A[w][r] (two nibbles, two bins), which halves
+// the table reads and their address arithmetic; the values, and so the sums, are the same
+// floats in the same order.  The 90 register partial sums (at most kFlushGroups groups each) are folded
 // into the lane's own slots of the output map, which keeps the register footprint small
 // enough for two waves per SIMD; the error of the two-level sum stays below
 // (kFlushGroups + n_seg / (4 kFlushGroups)) FP32 ulps of the total.
@@ -221,6 +228,7 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
                                                TileSmemLut<kChunk>& sm)
 {
     static_assert(kChunk % kGroup == 0, "chunks hold whole groups");
+    constexpr bool kPair = kChunk <= kPairChunk;
     const int tid = threadIdx.x;
     const int lanes = blockDim.x;
     const int64_t q = tile * lanes + tid;
@@ -271,18 +279,20 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
         const int nj = (int)min((int64_t)kChunk, d.n_seg - j0);
         const int ng = (nj + kGroup - 1) / kGroup;
         __syncthreads();
-        for (int jj = tid; jj < nj; jj += lanes) {
-            const int64_t J = j0 + jj;
+        // slots past the chunk's last segment (up to a whole group) repeat its tables with an
+        // empty row and zero weight, so that every group holds four in-range segments
+        for (int jj = tid; jj < ng * kGroup; jj += lanes) {
+            const int64_t J = j0 + min(jj, nj - 1);
             double sp, cp;
             sincos(W * d.t_mid[J], &sp, &cp);
             sm.C[jj] = cp;
             sm.S[jj] = sp;
             sm.D[jj] = doppler_factor(d.v + 3 * J, nx, ny, nz);
         }
-        for (int e = tid; e < nj * nwp; e += lanes) {
+        for (int e = tid; e < ng * kGroup * nwp; e += lanes) {
             const int jj = e / nwp;
             const int wd = e - jj * nwp;
-            sm.row[e] = wd < d.n_words ? d.bits[(j0 + jj) * d.n_words + wd] : 0u;
+            sm.row[e] = (jj < nj && wd < d.n_words) ? d.bits[(j0 + jj) * d.n_words + wd] : 0u;
         }
         for (int g = tid; g < ng; g += lanes) {
             // subset sums in segment order; missing segments of a last partial group weigh 0
@@ -302,6 +312,13 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
                 T[m] = t;
             }
         }
+        if constexpr (kPair) {
+            __syncthreads();
+            for (int e = tid; e < ng * 256; e += lanes) {
+                const int g = e >> 8, m = e & 255;
+                sm.T2[e] = make_float2(sm.T[g * 16 + (m & 15)], sm.T[g * 16 + (m >> 4)]);
+            }
+        }
         __syncthreads();
         if (!active) continue;
 
@@ -310,12 +327,8 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
 #pragma unroll
             for (int u = 0; u < kGroup; ++u) {
                 const int jj = g * kGroup + u;
-                mk[u][0] = mk[u][1] = mk[u][2] = 0u;
-                if (jj < nj &&
-                    !band_mask(sm.row + jj * nwp, sm.C[jj], sm.S[jj], sm.D[jj], cb, sb, apW, F0, FL, klo,
-                               last, d.n_bins, mk[u][0], mk[u][1], mk[u][2], bad_range, bad_model)) {
-                    mk[u][0] = mk[u][1] = mk[u][2] = 0u;
-                }
+                band_mask(sm.row + jj * nwp, sm.C[jj], sm.S[jj], sm.D[jj], cb, sb, apW, F0, FL, klo, last,
+                          d.n_bins, mk[u][0], mk[u][1], mk[u][2], bad_range, bad_model);
             }
             // A[w][r]: bit (4n + u) <- bit (4n + r) of mask u's word w, i.e. every nibble column
             // of the 4 x 32 bit matrix (mk[0..3][w]) transposed: swap the off-diagonal 2 x 2
@@ -336,22 +349,46 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
             }
             // Look the bins up word by word: the table reads of word k are issued before the
             // adds of word k-1, so one word's LDS latency overlaps the next word's reads.
-            const float* T = sm.T + g * 16;
-            float v[2][8];
+            if constexpr (kPair) {
+                // byte m of A[w][r] holds the nibbles of bins 32w + 8m + r and 32w + 8m + 4 + r
+                const float2* T2 = sm.T2 + g * 256;
+                float2 v[2][4];
 #pragma unroll
-            for (int k = 0; k <= 12; ++k) {
-                if (k < 12) {
-                    const int w = k >> 2, r = k & 3;
+                for (int k = 0; k <= 12; ++k) {
+                    if (k < 12) {
+                        const int w = k >> 2, r = k & 3;
 #pragma unroll
-                    for (int n = 0; n < 8; ++n)
-                        if (32 * w + 4 * n + r < kNF) v[k & 1][n] = T[(A[w][r] >> (4 * n)) & 15u];
+                        for (int m = 0; m < 4; ++m)
+                            if (32 * w + 8 * m + r < kNF) v[k & 1][m] = T2[(A[w][r] >> (8 * m)) & 255u];
+                    }
+                    if (k > 0) {
+                        const int w = (k - 1) >> 2, r = (k - 1) & 3;
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) {
+                            const int i = 32 * w + 8 * m + r;
+                            if (i < kNF) acc[i] += v[(k - 1) & 1][m].x;
+                            if (i + 4 < kNF) acc[i + 4] += v[(k - 1) & 1][m].y;
+                        }
+                    }
                 }
-                if (k > 0) {
-                    const int w = (k - 1) >> 2, r = (k - 1) & 3;
+            } else {
+                const float* T = sm.T + g * 16;
+                float v[2][8];
 #pragma unroll
-                    for (int n = 0; n < 8; ++n) {
-                        const int i = 32 * w + 4 * n + r;
-                        if (i < kNF) acc[i] += v[(k - 1) & 1][n];
+                for (int k = 0; k <= 12; ++k) {
+                    if (k < 12) {
+                        const int w = k >> 2, r = k & 3;
+#pragma unroll
+                        for (int n = 0; n < 8; ++n)
+                            if (32 * w + 4 * n + r < kNF) v[k & 1][n] = T[(A[w][r] >> (4 * n)) & 15u];
+                    }
+                    if (k > 0) {
+                        const int w = (k - 1) >> 2, r = (k - 1) & 3;
+#pragma unroll
+                        for (int n = 0; n < 8; ++n) {
+                            const int i = 32 * w + 4 * n + r;
+                            if (i < kNF) acc[i] += v[(k - 1) & 1][n];
+                        }
                     }
                 }
             }

@@ -293,12 +293,20 @@ __global__ void __launch_bounds__(kPostThreads) hook_kernel(PostConst c, const d
     }
 }
 
+// Final labels: every row walks to its root with loads only and stores that root in its own
+// slot.  (Path splitting here could overwrite a slot that its owner has already set to the
+// root with a stale, non-root ancestor.)
 __global__ void flatten_kernel(int32_t* parent, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int32_t r = find_root(parent, (int32_t)i);
-    st(parent + i, r);
+    int32_t x = (int32_t)i;
+    int32_t p = ld(parent + x);
+    while (p != x) {
+        x = p;
+        p = ld(parent + x);
+    }
+    st(parent + i, x);
 }
 
 // ---------------------------------------------------------------- centroids
