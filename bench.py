@@ -203,6 +203,8 @@ def main():
     achieved_select = SELECT_OPS_PER_TS * ts_per_step / (count_ms / 1e3)
     print(f"[bench] {ms_step:.3f} ms/step, count kernel {count_ms:.3f} ms", file=sys.stderr, flush=True)
 
+    post = run_post(bsh, ds, g, s1_score, s1_index, seg.t_coh, seg.t_span_mid(), st)
+
     batched = None if args.skip_batched else run_batched(args)
 
     cpu = None
@@ -263,9 +265,40 @@ def main():
             "autotune_ms": {f"{l}x{c}": t for (l, c), t in tune_ms.items()},
         },
         "cpu_baseline": cpu,
+        "post": post,
         "batched": batched,
     }
     print(json.dumps(out), flush=True)
+
+
+def run_post(bsh, ds, g, s1_score, s1_index, t_coh, t_mid, st):
+    """Post-processing of the stage-1 top-10^4 (not part of the step): rows, s_H significances,
+    clusters in a sqrt(14) window and their centroids, timed with HIP events."""
+    import torch
+    seg_w = ds.weight
+    pp = bsh.post_params(t_coh=t_coh, t_obs=2.0 * (t_mid - float(ds.t_mid.min().item())) + t_coh)
+
+    def run():
+        cs, cp = bsh.bsh_decode_templates(g, s1_index)
+        rows = bsh.bsh_post_rows(g.sky, cs, cp, t_coh)
+        sig = bsh.bsh_significance(s1_score, seg_w, 0, 1.6)
+        lab = bsh.bsh_cluster(pp, rows, 14.0 ** 0.5)
+        return lab, bsh.bsh_cluster_centroids(pp, rows, sig, lab, status=st)
+
+    run()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    reps = 5
+    a.record()
+    for _ in range(reps):
+        lab, (cen, weight, top, best) = run()
+    b.record()
+    torch.cuda.synchronize()
+    st.raise_if_set("post-processing")
+    n_clusters = int((lab == torch.arange(lab.numel(), device=lab.device, dtype=lab.dtype)).sum().item())
+    return {"candidates": int(s1_index.numel()), "clusters": n_clusters, "ms": a.elapsed_time(b) / reps,
+            "window": "sqrt(14)", "best_cluster_weight": float(weight[int(best.item())].item())}
 
 
 def run_batched(args):

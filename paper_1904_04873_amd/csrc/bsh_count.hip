@@ -39,77 +39,112 @@ __device__ __forceinline__ uint32_t upper_mask(int t)
 }
 
 
+// One (binary template, segment) track across the band: G = D (1 - a_p W cos phi) and the
+// canonical bins of the band's lowest and highest f0.
+struct BandTrack {
+    double G, y0;
+    int kf, delta;
+    bool ok;
+};
+
+// The canonical evaluations (no branches).  ok is false, and a flag is raised, when the track
+// leaves the staged row or drifts more than one bin across the band.
+__device__ __forceinline__ BandTrack band_track(double C, double S, double D, double cb, double sb,
+                                                double apW, double F0, double FL, int klo, int last,
+                                                int n_bins, bool& bad_range, bool& bad_model)
+{
+    BandTrack t;
+    // same operation order as orbit_phase / track_x: G = D (1 - a_p W cos phi)
+    const double cphi = fma(C, cb, S * sb);
+    t.G = D * (1.0 - apW * cphi);
+    // floor(x + 1/2) of a positive track value is its truncation to an integer
+    t.y0 = F0 * t.G + 0.5;
+    t.kf = (int)t.y0;
+    const int kl = (int)(FL * t.G + 0.5);
+    const int base = t.kf - klo;
+    const int top = kl - klo;
+    t.delta = top - base - last;
+    const bool in_range = (base >= 0) & (top < n_bins);
+    t.ok = in_range & ((unsigned)(t.delta + 1) <= 2u);
+    bad_range |= !in_range;
+    bad_model |= in_range & !t.ok;
+    return t;
+}
+
+// Bit i of the 96-bit (m0, m1, m2) is the peakgram bit of f0 bin i as if the band had no f0-shift
+// step: one funnel-shifted window of the LDS row (zero when the track failed; a failed track
+// still reads inside the row).
+__device__ __forceinline__ void band_window(const uint32_t* row, const BandTrack& t, int klo, uint32_t& m0,
+                                            uint32_t& m1, uint32_t& m2)
+{
+    const int at = t.ok ? t.kf - klo : 0;
+    const int qw = at >> 5;
+    const int sh = at & 31;
+    const uint32_t w0 = row[qw], w1 = row[qw + 1], w2 = row[qw + 2], w3 = row[qw + 3];
+    m0 = t.ok ? __builtin_amdgcn_alignbit(w1, w0, sh) : 0u;
+    m1 = t.ok ? __builtin_amdgcn_alignbit(w2, w1, sh) : 0u;
+    m2 = t.ok ? __builtin_amdgcn_alignbit(w3, w2, sh) : 0u;
+}
+
+// Where the band has an f0-shift step (t.ok and t.delta != 0), take the bins above it one bit
+// further (delta = +1) or nearer (delta = -1).
+__device__ __forceinline__ void band_step(const BandTrack& t, double F0, int last, uint32_t& m0, uint32_t& m1,
+                                          uint32_t& m2)
+{
+    const double G = t.G, y0 = t.y0;
+    const int kf = t.kf, delta = t.delta;
+    const int r0 = kf - (int)F0;
+    // The residual r_i = k_i - (k0 + i) steps once, where y0 + i (G - 1) crosses an integer.
+    // A single-precision guess of that offset is checked with exact evaluations; the
+    // bisection below only runs when the guess is off.
+    auto resid = [&](int i) { return (int)((F0 + (double)i) * G + 0.5) - ((int)F0 + i); };
+    const double num = delta > 0 ? (double)(kf + 1) - y0 : y0 - (double)kf;
+    const float den = (float)((double)delta * (G - 1.0));
+    const float q = fminf(fmaxf((float)num * __builtin_amdgcn_rcpf(den), 0.f), (float)last);
+    const int g = min(max((int)q + 1, 1), last);
+    int lo, hi;              // r_lo = r0, r_hi != r0
+    if (g < last && resid(g) == r0) {
+        lo = g;
+        hi = last;
+    } else if (g == 1 || resid(g - 1) == r0) {
+        lo = g - 1;
+        hi = g;
+    } else {
+        lo = 0;
+        hi = g - 1;
+    }
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (resid(mid) == r0) lo = mid; else hi = mid;
+    }
+    uint32_t n0, n1, n2;
+    if (delta > 0) {
+        n0 = __builtin_amdgcn_alignbit(m1, m0, 1);
+        n1 = __builtin_amdgcn_alignbit(m2, m1, 1);
+        n2 = m2 >> 1;
+    } else {
+        n0 = m0 << 1;
+        n1 = __builtin_amdgcn_alignbit(m1, m0, 31);
+        n2 = __builtin_amdgcn_alignbit(m2, m1, 31);
+    }
+    const uint32_t s0 = upper_mask(hi), s1 = upper_mask(hi - 32), s2 = upper_mask(hi - 64);
+    m0 = (n0 & s0) | (m0 & ~s0);
+    m1 = (n1 & s1) | (m1 & ~s1);
+    m2 = (n2 & s2) | (m2 & ~s2);
+}
+
 // The peak bits of the band's n_f0 templates of one (binary template, segment): bit i of the
 // 96-bit (m0, m1, m2) is the peakgram bit of f0 bin i's track.  Returns false, with zero masks,
-// and flags when the track leaves the staged row or drifts more than one bin across the band.
-// The common case (no f0-shift step) runs without branches.
+// when the track failed.
 __device__ __forceinline__ bool band_mask(const uint32_t* row, double C, double S, double D, double cb,
                                           double sb, double apW, double F0, double FL, int klo,
                                           int last, int n_bins, uint32_t& m0, uint32_t& m1,
                                           uint32_t& m2, bool& bad_range, bool& bad_model)
 {
-    // same operation order as orbit_phase / track_x: G = D (1 - a_p W cos phi)
-    const double cphi = fma(C, cb, S * sb);
-    const double G = D * (1.0 - apW * cphi);
-    // floor(x + 1/2) of a positive track value is its truncation to an integer
-    const double y0 = F0 * G + 0.5;
-    const int kf = (int)y0;
-    const int kl = (int)(FL * G + 0.5);
-    const int base = kf - klo;
-    const int top = kl - klo;
-    const int delta = top - base - last;
-    const bool in_range = (base >= 0) & (top < n_bins);
-    const bool ok = in_range & ((unsigned)(delta + 1) <= 2u);
-    bad_range |= !in_range;
-    bad_model |= in_range & !ok;
-    const int r0 = kf - (int)F0;
-    const int at = ok ? base : 0;          // a failed track still reads inside the row
-    const int qw = at >> 5;
-    const int sh = at & 31;
-    const uint32_t w0 = row[qw], w1 = row[qw + 1], w2 = row[qw + 2], w3 = row[qw + 3];
-    m0 = ok ? __builtin_amdgcn_alignbit(w1, w0, sh) : 0u;
-    m1 = ok ? __builtin_amdgcn_alignbit(w2, w1, sh) : 0u;
-    m2 = ok ? __builtin_amdgcn_alignbit(w3, w2, sh) : 0u;
-    if (ok && delta != 0) {
-        // The residual r_i = k_i - (k0 + i) steps once, where y0 + i (G - 1) crosses an integer.
-        // A single-precision guess of that offset is checked with exact evaluations; the
-        // bisection below only runs when the guess is off.
-        auto resid = [&](int i) { return (int)((F0 + (double)i) * G + 0.5) - ((int)F0 + i); };
-        const double num = delta > 0 ? (double)(kf + 1) - y0 : y0 - (double)kf;
-        const float den = (float)((double)delta * (G - 1.0));
-        const float q = fminf(fmaxf((float)num * __builtin_amdgcn_rcpf(den), 0.f), (float)last);
-        const int g = min(max((int)q + 1, 1), last);
-        int lo, hi;              // r_lo = r0, r_hi != r0
-        if (g < last && resid(g) == r0) {
-            lo = g;
-            hi = last;
-        } else if (g == 1 || resid(g - 1) == r0) {
-            lo = g - 1;
-            hi = g;
-        } else {
-            lo = 0;
-            hi = g - 1;
-        }
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (resid(mid) == r0) lo = mid; else hi = mid;
-        }
-        uint32_t n0, n1, n2;
-        if (delta > 0) {
-            n0 = __builtin_amdgcn_alignbit(m1, m0, 1);
-            n1 = __builtin_amdgcn_alignbit(m2, m1, 1);
-            n2 = m2 >> 1;
-        } else {
-            n0 = m0 << 1;
-            n1 = __builtin_amdgcn_alignbit(m1, m0, 31);
-            n2 = __builtin_amdgcn_alignbit(m2, m1, 31);
-        }
-        const uint32_t s0 = upper_mask(hi), s1 = upper_mask(hi - 32), s2 = upper_mask(hi - 64);
-        m0 = (n0 & s0) | (m0 & ~s0);
-        m1 = (n1 & s1) | (m1 & ~s1);
-        m2 = (n2 & s2) | (m2 & ~s2);
-    }
-    return ok;
+    const BandTrack t = band_track(C, S, D, cb, sb, apW, F0, FL, klo, last, n_bins, bad_range, bad_model);
+    band_window(row, t, klo, m0, m1, m2);
+    if (t.ok && t.delta != 0) band_step(t, F0, last, m0, m1, m2);
+    return t.ok;
 }
 
 template <bool kCount, int kChunk>
@@ -323,13 +358,22 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
         if (!active) continue;
 
         for (int g = 0; g < ng; ++g) {
+            // the four tracks and windows without branches (independent chains the scheduler
+            // can interleave), then the rare f0-shift steps
             uint32_t mk[kGroup][3];
+            BandTrack tr[kGroup];
 #pragma unroll
             for (int u = 0; u < kGroup; ++u) {
                 const int jj = g * kGroup + u;
-                band_mask(sm.row + jj * nwp, sm.C[jj], sm.S[jj], sm.D[jj], cb, sb, apW, F0, FL, klo, last,
-                          d.n_bins, mk[u][0], mk[u][1], mk[u][2], bad_range, bad_model);
+                tr[u] = band_track(sm.C[jj], sm.S[jj], sm.D[jj], cb, sb, apW, F0, FL, klo, last, d.n_bins,
+                                   bad_range, bad_model);
             }
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u)
+                band_window(sm.row + (g * kGroup + u) * nwp, tr[u], klo, mk[u][0], mk[u][1], mk[u][2]);
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u)
+                if (tr[u].ok && tr[u].delta != 0) band_step(tr[u], F0, last, mk[u][0], mk[u][1], mk[u][2]);
             // A[w][r]: bit (4n + u) <- bit (4n + r) of mask u's word w, i.e. every nibble column
             // of the 4 x 32 bit matrix (mk[0..3][w]) transposed: swap the off-diagonal 2 x 2
             // blocks, then the off-diagonal bits of each 2 x 2 block.
