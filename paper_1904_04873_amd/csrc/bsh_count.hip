@@ -81,9 +81,11 @@ __device__ __forceinline__ void band_window(const uint32_t* row, const BandTrack
     const int qw = at >> 5;
     const int sh = at & 31;
     const uint32_t w0 = row[qw], w1 = row[qw + 1], w2 = row[qw + 2], w3 = row[qw + 3];
-    m0 = t.ok ? __builtin_amdgcn_alignbit(w1, w0, sh) : 0u;
-    m1 = t.ok ? __builtin_amdgcn_alignbit(w2, w1, sh) : 0u;
-    m2 = t.ok ? __builtin_amdgcn_alignbit(w3, w2, sh) : 0u;
+    // a mask rather than a select, so that the row reads stay unconditional
+    const uint32_t keep = 0u - (uint32_t)t.ok;
+    m0 = __builtin_amdgcn_alignbit(w1, w0, sh) & keep;
+    m1 = __builtin_amdgcn_alignbit(w2, w1, sh) & keep;
+    m2 = __builtin_amdgcn_alignbit(w3, w2, sh) & keep;
 }
 
 // Where the band has an f0-shift step (t.ok and t.delta != 0), take the bins above it one bit
