@@ -97,6 +97,50 @@ __device__ __forceinline__ int64_t entry_index(const Seg& s, int g, int64_t e, i
     return s.shift > 0 ? (((int64_t)g << s.shift) | pos) : pos;
 }
 
+// Count `bin` for every active lane whose `take` is set: lanes sharing the first taker's bin
+// are added with one atomic (scores concentrate in few digit values, so this takes most of
+// the LDS atomic traffic off the hottest bins).
+__device__ __forceinline__ void wave_hist_add(uint32_t* h, bool take, uint32_t bin)
+{
+    const unsigned long long any = __ballot(take);
+    if (!any) return;
+    const int leader = __ffsll((long long)any) - 1;
+    const uint32_t lb = __shfl(bin, leader);
+    const unsigned long long same = __ballot(take && bin == lb);
+    if ((int)(threadIdx.x & 63) == leader) atomicAdd(&h[lb], (uint32_t)__popcll(same));
+    if (take && bin != lb) atomicAdd(&h[bin], 1u);
+}
+
+// Slot in the segment's output pool for every active lane whose `take` is set: one atomic
+// per wave.
+__device__ __forceinline__ uint32_t wave_claim(uint32_t* n_sel, bool take)
+{
+    const unsigned long long m = __ballot(take);
+    if (!m) return 0u;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)m) - 1;
+    uint32_t base = 0u;
+    if (lane == leader) base = atomicAdd(n_sel, (uint32_t)__popcll(m));
+    base = __shfl(base, leader);
+    return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+}
+
+// Grid-stride walk over scores [lo, hi) with four independent loads in flight per lane.
+template <typename F>
+__device__ __forceinline__ void for_each_score(const float* __restrict__ score, int64_t lo, int64_t hi, F f)
+{
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    int64_t e = lo + (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    for (; e + 3 * stride < hi; e += 4 * stride) {
+        const float a = score[e], b = score[e + stride], c = score[e + 2 * stride], d = score[e + 3 * stride];
+        f(e, a);
+        f(e + stride, b);
+        f(e + 2 * stride, c);
+        f(e + 3 * stride, d);
+    }
+    for (; e < hi; e += stride) f(e, score[e]);
+}
+
 __global__ void init_kernel(Seg s)
 {
     const int g = blockIdx.x;
@@ -124,11 +168,10 @@ __global__ __launch_bounds__(kThreads) void key_hist_kernel(Seg s, int pass)
     const int64_t lo = s.off[g], hi = s.off[g + 1];
     const uint32_t prefix = s.st[g].prefix;
     const int shift = 24 - 8 * pass;
-    for (int64_t e = lo + (int64_t)blockIdx.x * kThreads + threadIdx.x; e < hi;
-         e += (int64_t)gridDim.x * kThreads) {
-        const uint32_t key = score_key(s.score[e]);
-        if (pass == 0 || (key >> (shift + 8)) == prefix) atomicAdd(&h[(key >> shift) & 0xffu], 1u);
-    }
+    for_each_score(s.score, lo, hi, [&](int64_t, float sc) {
+        const uint32_t key = score_key(sc);
+        wave_hist_add(h, pass == 0 || (key >> (shift + 8)) == prefix, (key >> shift) & 0xffu);
+    });
     __syncthreads();
     for (int b = threadIdx.x; b < kBins; b += kThreads)
         if (h[b]) atomicAdd(&s.hist[(size_t)g * kBins + b], h[b]);
@@ -157,22 +200,48 @@ __global__ void key_pick_kernel(Seg s)
     s.hist[(size_t)g * kBins + t] = 0u;
 }
 
+// Entries with key > T go to the output pool.  Each block gathers its entries in LDS and
+// reserves pool slots with one atomic (a single pool counter hit once per entry serializes at
+// the L2); entries beyond the LDS buffer reserve their slots directly.
 __global__ __launch_bounds__(kThreads) void split_kernel(Seg s)
 {
+    constexpr uint32_t kCap = 1024;
+    __shared__ float lsc[kCap];
+    __shared__ int64_t lix[kCap];
+    __shared__ uint32_t lcount, gbase;
     const int g = blockIdx.y;
     const uint32_t k_eff = s.st[g].k_eff;
     if (k_eff == 0u) return;
+    if (threadIdx.x == 0) lcount = 0u;
+    __syncthreads();
     const uint32_t T = s.st[g].prefix;
     const int64_t lo = s.off[g], hi = s.off[g + 1];
-    for (int64_t e = lo + (int64_t)blockIdx.x * kThreads + threadIdx.x; e < hi;
-         e += (int64_t)gridDim.x * kThreads) {
-        const float sc = s.score[e];
-        if (score_key(sc) > T) {
-            const uint32_t pos = atomicAdd(&s.st[g].n_sel, 1u);
-            if (pos < k_eff) {
-                s.sel_score[(size_t)g * s.k + pos] = sc;
-                s.sel_index[(size_t)g * s.k + pos] = entry_index(s, g, e, lo);
+    for_each_score(s.score, lo, hi, [&](int64_t e, float sc) {
+        const bool take = score_key(sc) > T;
+        const uint32_t pos = wave_claim(&lcount, take);
+        if (take) {
+            const int64_t ix = entry_index(s, g, e, lo);
+            if (pos < kCap) {
+                lsc[pos] = sc;
+                lix[pos] = ix;
+            } else {
+                const uint32_t gp = atomicAdd(&s.st[g].n_sel, 1u);
+                if (gp < k_eff) {
+                    s.sel_score[(size_t)g * s.k + gp] = sc;
+                    s.sel_index[(size_t)g * s.k + gp] = ix;
+                }
             }
+        }
+    });
+    __syncthreads();
+    const uint32_t n_local = min(lcount, kCap);
+    if (threadIdx.x == 0) gbase = n_local ? atomicAdd(&s.st[g].n_sel, n_local) : 0u;
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < n_local; q += kThreads) {
+        const uint32_t pos = gbase + q;
+        if (pos < k_eff) {
+            s.sel_score[(size_t)g * s.k + pos] = lsc[q];
+            s.sel_index[(size_t)g * s.k + pos] = lix[q];
         }
     }
 }
@@ -200,13 +269,12 @@ __global__ __launch_bounds__(kThreads) void tie_hist_kernel(Seg s, int pass, int
     const uint32_t T = s.st[g].prefix;
     const unsigned long long prefix = s.st[g].iprefix;
     const int shift = 8 * (n_pass - 1 - pass);
-    for (int64_t e = lo + (int64_t)blockIdx.x * kThreads + threadIdx.x; e < hi;
-         e += (int64_t)gridDim.x * kThreads) {
-        if (score_key(s.score[e]) != T) continue;
-        unsigned long long ix = (unsigned long long)entry_index(s, g, e, lo);
+    for_each_score(s.score, lo, hi, [&](int64_t e, float sc) {
+        const bool tie = score_key(sc) == T;
+        unsigned long long ix = tie ? (unsigned long long)entry_index(s, g, e, lo) : 0ull;
         if (n_pass < 8) ix &= (1ull << (8 * n_pass)) - 1ull;
-        if (pass == 0 || (ix >> (shift + 8)) == prefix) atomicAdd(&h[(ix >> shift) & 0xffull], 1u);
-    }
+        wave_hist_add(h, tie && (pass == 0 || (ix >> (shift + 8)) == prefix), (uint32_t)((ix >> shift) & 0xffull));
+    });
     __syncthreads();
     for (int b = threadIdx.x; b < kBins; b += kThreads)
         if (h[b]) atomicAdd(&s.hist[(size_t)g * kBins + b], h[b]);
@@ -244,20 +312,18 @@ __global__ __launch_bounds__(kThreads) void tie_take_kernel(Seg s, int n_pass)
     const uint32_t T = s.st[g].prefix;
     const unsigned long long cut = s.st[g].iprefix;    // largest index (low bits) that makes the cut
     const float sc = key_score(T);
-    for (int64_t e = lo + (int64_t)blockIdx.x * kThreads + threadIdx.x; e < hi;
-         e += (int64_t)gridDim.x * kThreads) {
-        if (score_key(s.score[e]) != T) continue;
-        const int64_t ix = entry_index(s, g, e, lo);
+    for_each_score(s.score, lo, hi, [&](int64_t e, float v) {
+        const bool tie = score_key(v) == T;
+        const int64_t ix = tie ? entry_index(s, g, e, lo) : 0;
         unsigned long long low = (unsigned long long)ix;
         if (n_pass < 8) low &= (1ull << (8 * n_pass)) - 1ull;
-        if (low <= cut) {
-            const uint32_t pos = atomicAdd(&s.st[g].n_sel, 1u);
-            if (pos < k_eff) {
-                s.sel_score[(size_t)g * s.k + pos] = sc;
-                s.sel_index[(size_t)g * s.k + pos] = ix;
-            }
+        const bool take = tie && low <= cut;
+        const uint32_t pos = wave_claim(&s.st[g].n_sel, take);
+        if (take && pos < k_eff) {
+            s.sel_score[(size_t)g * s.k + pos] = sc;
+            s.sel_index[(size_t)g * s.k + pos] = ix;
         }
-    }
+    });
 }
 
 __device__ __forceinline__ bool precedes(float sa, int64_t ia, float sb, int64_t ib)
