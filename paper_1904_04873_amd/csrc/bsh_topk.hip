@@ -141,6 +141,33 @@ __device__ __forceinline__ void for_each_score(const float* __restrict__ score, 
     for (; e < hi; e += stride) f(e, score[e]);
 }
 
+// The digit that holds the rem-th entry when the 256 bins of h are taken in order (from the top
+// for scores, from the bottom for tie indices), and how many entries the bins before it hold.
+// A block scan over the bins (every thread of the block calls this; at least 256 threads).
+// When the bins hold fewer than rem entries the last bin in take order is returned.
+__device__ void pick_digit(const uint32_t* h, uint32_t rem, bool from_top, uint32_t* scan, int* d_out,
+                           uint32_t* before_out)
+{
+    const int t = threadIdx.x;
+    const uint32_t v = t < kBins ? h[from_top ? kBins - 1 - t : t] : 0u;
+    if (t < kBins) scan[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kBins; off <<= 1) {
+        const uint32_t add = (t < kBins && t >= off) ? scan[t - off] : 0u;
+        __syncthreads();
+        if (t < kBins) scan[t] += add;
+        __syncthreads();
+    }
+    if (t < kBins) {
+        const uint32_t incl = scan[t], excl = incl - v;
+        if ((excl < rem && rem <= incl) || (t == kBins - 1 && incl < rem)) {
+            *d_out = from_top ? kBins - 1 - t : t;
+            *before_out = excl;
+        }
+    }
+    __syncthreads();
+}
+
 __global__ void init_kernel(Seg s)
 {
     const int g = blockIdx.x;
@@ -180,23 +207,21 @@ __global__ __launch_bounds__(kThreads) void key_hist_kernel(Seg s, int pass)
 // Pick the digit holding the remaining-th best entry; entries with larger digits are taken.
 __global__ void key_pick_kernel(Seg s)
 {
-    __shared__ uint32_t h[kBins];
+    __shared__ uint32_t h[kBins], scan[kBins];
+    __shared__ int d;
+    __shared__ uint32_t above;
     const int g = blockIdx.x;
     const int t = threadIdx.x;   // kBins threads
     h[t] = s.hist[(size_t)g * kBins + t];
+    const uint32_t rem = s.st[g].remaining;
     __syncthreads();
-    if (t == 0 && s.st[g].remaining > 0u) {
-        const uint32_t rem = s.st[g].remaining;
-        uint32_t above = 0u;
-        int d = kBins - 1;
-        for (; d > 0; --d) {
-            if (above + h[d] >= rem) break;
-            above += h[d];
+    if (rem > 0u) {
+        pick_digit(h, rem, true, scan, &d, &above);
+        if (t == 0) {
+            s.st[g].remaining = rem - above;
+            s.st[g].prefix = (s.st[g].prefix << 8) | (uint32_t)d;
         }
-        s.st[g].remaining = rem - above;
-        s.st[g].prefix = (s.st[g].prefix << 8) | (uint32_t)d;
     }
-    __syncthreads();
     s.hist[(size_t)g * kBins + t] = 0u;
 }
 
@@ -283,23 +308,21 @@ __global__ __launch_bounds__(kThreads) void tie_hist_kernel(Seg s, int pass, int
 // Smallest indices win: take digits from the low end.
 __global__ void tie_pick_kernel(Seg s)
 {
-    __shared__ uint32_t h[kBins];
+    __shared__ uint32_t h[kBins], scan[kBins];
+    __shared__ int d;
+    __shared__ uint32_t below;
     const int g = blockIdx.x;
     const int t = threadIdx.x;
     h[t] = s.hist[(size_t)g * kBins + t];
+    const uint32_t rem = s.st[g].iremaining;
     __syncthreads();
-    if (t == 0 && s.st[g].iremaining > 0u) {
-        const uint32_t rem = s.st[g].iremaining;
-        uint32_t below = 0u;
-        int d = 0;
-        for (; d < kBins - 1; ++d) {
-            if (below + h[d] >= rem) break;
-            below += h[d];
+    if (rem > 0u) {
+        pick_digit(h, rem, false, scan, &d, &below);
+        if (t == 0) {
+            s.st[g].iremaining = rem - below;
+            s.st[g].iprefix = (s.st[g].iprefix << 8) | (unsigned long long)d;
         }
-        s.st[g].iremaining = rem - below;
-        s.st[g].iprefix = (s.st[g].iprefix << 8) | (unsigned long long)d;
     }
-    __syncthreads();
     s.hist[(size_t)g * kBins + t] = 0u;
 }
 
@@ -394,6 +417,130 @@ __global__ void fill_tail_kernel(Seg s, float* out_score, int64_t* out_index)
     }
 }
 
+// The whole selection for short segments (at most kSmallLen entries, k at most kSmallK) in
+// one block per segment: the same radix select, compaction, tie resolution and rank ordering
+// as the multi-block path, with the passes separated by block barriers instead of launches.
+// Segments of at most kStageLen entries are first copied to LDS, so that the passes after the
+// first read LDS instead of waiting on L2 for every few entries.
+constexpr int kSmallThreads = 1024;
+constexpr int64_t kSmallLen = 1 << 16;
+constexpr int32_t kSmallK = 2048;
+constexpr int kStageLen = 12288;
+
+template <bool kStaged>
+__global__ __launch_bounds__(kSmallThreads) void small_topk_kernel(Seg s, float* __restrict__ out_score,
+                                                                   int64_t* __restrict__ out_index,
+                                                                   int n_pass)
+{
+    __shared__ float sv[kStaged ? kStageLen : 1];
+    __shared__ uint32_t h[kBins], scan[kBins];
+    __shared__ uint32_t prefix, remaining, n_sel, passed;
+    __shared__ int digit;
+    __shared__ unsigned long long iprefix;
+    __shared__ float cs[kSmallK];
+    __shared__ int64_t ci[kSmallK];
+    const int g = blockIdx.x;
+    const int t = threadIdx.x;
+    const int64_t lo = s.off[g], hi = s.off[g + 1];
+    const int64_t len = hi - lo;
+    const uint32_t k_eff = (uint32_t)(len < (int64_t)s.k ? len : (int64_t)s.k);
+    float* os = out_score + (size_t)g * s.k;
+    int64_t* oi = out_index + (size_t)g * s.k;
+    for (uint32_t e = k_eff + t; e < (uint32_t)s.k; e += kSmallThreads) {
+        os[e] = -__builtin_huge_valf();
+        oi[e] = -1;
+    }
+    if (k_eff == 0u) return;
+    if (t == 0) {
+        prefix = 0u;
+        remaining = k_eff;
+        n_sel = 0u;
+        iprefix = 0ull;
+    }
+    if constexpr (kStaged)
+        for (int64_t e = t; e < len; e += kSmallThreads) sv[e] = s.score[lo + e];
+    // score of entry e (absolute position); the staged copy when there is one
+    auto score_at = [&](int64_t e) { return kStaged ? sv[e - lo] : s.score[e]; };
+    // 1. key digits, most significant first
+    for (int pass = 0; pass < 4; ++pass) {
+        for (int b = t; b < kBins; b += kSmallThreads) h[b] = 0u;
+        __syncthreads();
+        const int shift = 24 - 8 * pass;
+        const uint32_t pre = prefix;
+        for (int64_t e = lo + t; e < hi; e += kSmallThreads) {
+            const uint32_t key = score_key(score_at(e));
+            wave_hist_add(h, pass == 0 || (key >> (shift + 8)) == pre, (key >> shift) & 0xffu);
+        }
+        __syncthreads();
+        pick_digit(h, remaining, true, scan, &digit, &passed);
+        if (t == 0) {
+            remaining -= passed;
+            prefix = (prefix << 8) | (uint32_t)digit;
+        }
+        __syncthreads();
+    }
+    const uint32_t T = prefix;
+    // 2. everything strictly better than T
+    for (int64_t e = lo + t; e < hi; e += kSmallThreads) {
+        const float sc = score_at(e);
+        const bool take = score_key(sc) > T;
+        const uint32_t pos = wave_claim(&n_sel, take);
+        if (take && pos < k_eff) {
+            cs[pos] = sc;
+            ci[pos] = entry_index(s, g, e, lo);
+        }
+    }
+    // 3. the smallest indices among the entries equal to T
+    for (int pass = 0; pass < n_pass && remaining > 0u; ++pass) {
+        for (int b = t; b < kBins; b += kSmallThreads) h[b] = 0u;
+        __syncthreads();
+        const int shift = 8 * (n_pass - 1 - pass);
+        const unsigned long long pre = iprefix;
+        for (int64_t e = lo + t; e < hi; e += kSmallThreads) {
+            const bool tie = score_key(score_at(e)) == T;
+            unsigned long long ix = tie ? (unsigned long long)entry_index(s, g, e, lo) : 0ull;
+            if (n_pass < 8) ix &= (1ull << (8 * n_pass)) - 1ull;
+            wave_hist_add(h, tie && (pass == 0 || (ix >> (shift + 8)) == pre),
+                          (uint32_t)((ix >> shift) & 0xffull));
+        }
+        __syncthreads();
+        pick_digit(h, remaining, false, scan, &digit, &passed);
+        if (t == 0) {
+            remaining -= passed;
+            iprefix = (iprefix << 8) | (unsigned long long)digit;
+        }
+        __syncthreads();
+    }
+    if (remaining > 0u) {     // (remaining is block-uniform here)
+        const unsigned long long cut = iprefix;
+        const float sc = key_score(T);
+        for (int64_t e = lo + t; e < hi; e += kSmallThreads) {
+            const bool tie = score_key(score_at(e)) == T;
+            const int64_t ix = tie ? entry_index(s, g, e, lo) : 0;
+            unsigned long long low = (unsigned long long)ix;
+            if (n_pass < 8) low &= (1ull << (8 * n_pass)) - 1ull;
+            const bool take = tie && low <= cut;
+            const uint32_t pos = wave_claim(&n_sel, take);
+            if (take && pos < k_eff) {
+                cs[pos] = sc;
+                ci[pos] = ix;
+            }
+        }
+    }
+    __syncthreads();
+    // 4. order by rank counting
+    for (uint32_t e = t; e < k_eff; e += kSmallThreads) {
+        const float sc = cs[e];
+        const int64_t ix = ci[e];
+        uint32_t rank = 0u;
+        for (uint32_t f = 0; f < k_eff; ++f) rank += precedes(cs[f], ci[f], sc, ix) ? 1u : 0u;
+        if (rank < k_eff) {
+            os[rank] = sc;
+            oi[rank] = ix;
+        }
+    }
+}
+
 __global__ void set_offsets_kernel(int64_t* off, int64_t n)
 {
     off[0] = 0;
@@ -416,6 +563,15 @@ int topk_launch(Seg s, int64_t max_len, float* out_score, int64_t* out_index, hi
     const int n_pass = (bits + 7) / 8;
     s.idx_bits = bits;
 
+    if (max_len <= kSmallLen && s.k <= kSmallK) {
+        if (max_len <= kStageLen)
+            hipLaunchKernelGGL(small_topk_kernel<true>, dim3(s.n_segs), dim3(kSmallThreads), 0, st, s,
+                               out_score, out_index, n_pass);
+        else
+            hipLaunchKernelGGL(small_topk_kernel<false>, dim3(s.n_segs), dim3(kSmallThreads), 0, st, s,
+                               out_score, out_index, n_pass);
+        return check_launch("bsh_topk");
+    }
     hipLaunchKernelGGL(init_kernel, dim3(s.n_segs), dim3(kBins), 0, st, s);
     for (int pass = 0; pass < 4; ++pass) {
         hipLaunchKernelGGL(key_hist_kernel, grid2, dim3(kThreads), 0, st, s, pass);

@@ -267,7 +267,9 @@ def _topk_ref(score, k, index=None):
 
 @pytest.mark.parametrize("n,k,kind", [(1, 1, "float"), (5, 10, "float"), (1000, 1, "int"),
                                       (46080, 100, "int"), (200000, 10000, "int"),
-                                      (300001, 777, "float"), (100000, 5000, "const")])
+                                      (300001, 777, "float"), (100000, 5000, "const"),
+                                      (65536, 2048, "int"), (65537, 2048, "float"),
+                                      (20000, 2049, "int"), (3000, 2048, "const")])
 def test_topk_exact(B, n, k, kind):
     import torch
     _say(f"topk n={n} k={k} {kind}")
