@@ -27,7 +27,9 @@
  *     (the segment is then skipped, never clamped, and the outputs of that call are not
  *     meaningful) and BSH_STATUS_MODEL when a track's drift across the f0 band exceeds one
  *     bin (parameters outside the model's validity), and BSH_STATUS_INPUT when a candidate
- *     names a sky pixel outside [0, n_sky) (that candidate's outputs are then 0).
+ *     names a sky pixel outside [0, n_sky) (that candidate's outputs are then 0) or a
+ *     post-processing input is invalid (a significance that is not finite and positive, or a
+ *     cluster label that does not name a root).
  *   - Template index of the stage-1 grid (f0 fastest):
  *         idx = ((s * n_bin) + b) * n_f0 + i,   b = tasc_off[ia * n_per + ip] + j
  *     with s the sky pixel, i the f0 bin (F = k0 + i), ia/ip the a_p/P indices and j the

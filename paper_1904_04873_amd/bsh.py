@@ -18,9 +18,11 @@ from . import _native as N
 from ._native import BshError, check
 
 __all__ = [
-    "BshError", "DeviceSegments", "DeviceGrid", "Status", "bsh_version", "bsh_grid_build",
-    "bsh_peakgram", "bsh_hough_count", "bsh_topk", "bsh_decode_templates", "bsh_power_stat",
-    "bsh_power_stat_grad", "bsh_track_bins",
+    "BshError", "DeviceSegments", "DeviceGrid", "Status", "TopK", "Plan", "bsh_version",
+    "bsh_grid_build", "bsh_normalize", "bsh_peakgram", "bsh_hough_count", "bsh_topk",
+    "bsh_decode_templates", "bsh_power_stat", "bsh_power_stat_ecc", "bsh_power_stat_grad",
+    "bsh_track_bins", "post_params", "bsh_post_rows", "bsh_significance", "bsh_coincidences",
+    "bsh_cluster", "bsh_cluster_centroids",
 ]
 
 
@@ -62,7 +64,8 @@ class Status:
             if v & N.STATUS_MODEL:
                 what.append("a track drifted more than one bin across the f0 band")
             if v & N.STATUS_INPUT:
-                what.append("a candidate names a sky pixel out of range")
+                what.append("an input is out of range (a candidate's sky pixel, a significance or a "
+                            "cluster label)")
             raise BshError(N.BSH_ERANGE, where, "; ".join(what))
 
 
@@ -480,8 +483,8 @@ class Plan:
     def close(self) -> None:
         if getattr(self, "h", None):
             torch.cuda.synchronize()
-            N.load().bsh_plan_destroy(self.h)
-            self.h = None
+            h, self.h = self.h, None
+            check(N.load().bsh_plan_destroy(h), "bsh_plan_destroy")
 
     def __del__(self):
         try:
