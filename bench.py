@@ -204,6 +204,7 @@ def main():
     print(f"[bench] {ms_step:.3f} ms/step, count kernel {count_ms:.3f} ms", file=sys.stderr, flush=True)
 
     post = run_post(bsh, ds, g, s1_score, s1_index, seg.t_coh, seg.t_span_mid(), st)
+    refine = run_refine(bsh, spec, st)
 
     batched = None if args.skip_batched else run_batched(args)
 
@@ -266,6 +267,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "post": post,
+        "refine": refine,
         "batched": batched,
     }
     print(json.dumps(out), flush=True)
@@ -299,6 +301,56 @@ def run_post(bsh, ds, g, s1_score, s1_index, t_coh, t_mid, st):
     n_clusters = int((lab == torch.arange(lab.numel(), device=lab.device, dtype=lab.dtype)).sum().item())
     return {"candidates": int(s1_index.numel()), "clusters": n_clusters, "ms": a.elapsed_time(b) / reps,
             "window": "sqrt(14)", "best_cluster_weight": float(weight[int(best.item())].item())}
+
+
+def run_refine(bsh, spec, st):
+    """The differentiable stage 2 at its real size (not part of the step): 10^5 off-grid
+    candidates over 4000 segments (the 200 Hz band layout, noise only), one forward
+    (interpolated power), one backward (adjoint kernel) and 20 Adam steps."""
+    import numpy as np
+    import torch
+    import bsh_synth as S
+    from paper_1904_04873_amd.refine import refine
+
+    w = S.config4()
+    seg = w.segments[0]
+    ds = bsh.DeviceSegments.from_host(seg)
+    sky = torch.from_numpy(w.sky).cuda()
+    rng = w.rng["candidates"]
+    n = 100_000
+    centre = np.stack([spec.k0 + rng.uniform(5, 85, 10), rng.uniform(0.5, 2.8, 10),
+                       rng.uniform(spec.per_lo * 1.1, spec.per_hi * 0.9, 10), np.zeros(10)], axis=1)
+    centre[:, 3] = seg.t_span_mid() + rng.uniform(-0.5, 0.5, 10) * centre[:, 2]
+    steps = np.array([1.0, (spec.ap_hi - spec.ap_lo) / (spec.n_ap - 1),
+                      (spec.per_hi - spec.per_lo) / (spec.n_per - 1), 0.0])
+    cand = np.repeat(centre, n // 10, axis=0)
+    st_steps = np.repeat(steps[None, :], n, axis=0)
+    st_steps[:, 3] = cand[:, 2] / 64.0
+    cand = cand + rng.uniform(0, 2, cand.shape) * rng.choice([-1.0, 1.0], cand.shape) * st_steps
+    th = torch.from_numpy(cand).cuda()
+    cs = torch.zeros(n, dtype=torch.int32, device="cuda")
+    stp = torch.from_numpy(st_steps).cuda()
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    fwd = timed(lambda: bsh.bsh_power_stat(ds, sky, cs, th, mode=1, status=st))
+    bwd = timed(lambda: bsh.bsh_power_stat_grad(ds, sky, cs, th, status=st))
+    adam = timed(lambda: refine(th, stp, ds, sky, cs, n_iter=20, lr=0.05, status=st), reps=1)
+    st.raise_if_set("refinement")
+    cs_n = n * seg.n_seg
+    return {"candidates": n, "segments": seg.n_seg, "forward_ms": fwd, "backward_ms": bwd,
+            "adam_20_steps_ms": adam, "forward_cand_seg_per_s": cs_n / (fwd / 1e3),
+            "backward_cand_seg_per_s": cs_n / (bwd / 1e3)}
 
 
 def run_batched(args):

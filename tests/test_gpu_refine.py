@@ -117,3 +117,33 @@ def test_adam_refinement_improves_power_and_distance():
     d0 = np.linalg.norm((cand[:, :3] - tru[:, :3]) / st[:, :3], axis=1)
     d1 = np.linalg.norm((th[:, :3] - tru[:, :3]) / st[:, :3], axis=1)
     assert np.mean(d1) < np.mean(d0)
+
+
+def test_refinement_at_full_size_matches_oracle_on_samples():
+    """10^5 candidates (10^4 per injection) over 4000 segments: P_lin and its adjoint for all of
+    them, 500 sampled against the oracle's FP64 value and CPU adjoint, then 20 Adam steps."""
+    import torch
+    from paper_1904_04873_amd import bsh
+    from paper_1904_04873_amd.refine import refine
+    _say("refinement at 1e5 candidates")
+    w, seg, inj, snr, cand, st = _setup(n_per_inj=10_000, seed=1)
+    assert cand.shape == (100_000, 4)
+    ds = bsh.DeviceSegments.from_host(seg)
+    sky = torch.from_numpy(w.sky).cuda()
+    cs = torch.zeros(cand.shape[0], dtype=torch.int32, device="cuda")
+    th = torch.from_numpy(cand).cuda()
+    status = bsh.Status(torch.device("cuda"))
+    P = bsh.bsh_power_stat(ds, sky, cs, th, mode=1, status=status).cpu().numpy().astype(np.float64)
+    g = bsh.bsh_power_stat_grad(ds, sky, cs, th, status=status).cpu().numpy()
+    torch.cuda.synchronize()
+    status.raise_if_set("full-size forward/backward")
+    pick = np.random.default_rng(2).choice(cand.shape[0], 500, replace=False)
+    P_o, _, _, _ = O.power_stat(seg, w.sky, np.zeros(500, np.int32), cand[pick], mode=1)
+    assert np.all(np.abs(P[pick] - P_o) <= 1e-5 * np.abs(P_o))
+    g_o, a_o = O.power_grad(seg, w.sky, np.zeros(500, np.int32), cand[pick], with_abs=True)
+    assert np.all(np.abs(g[pick] - g_o) <= 1e-5 * a_o + 1e-12)
+    theta, hist = refine(th, torch.from_numpy(st).cuda(), ds, sky, cs, n_iter=20, lr=0.05, status=status)
+    torch.cuda.synchronize()
+    status.raise_if_set("full-size refinement")
+    h = hist.cpu().numpy()
+    assert np.mean(h[-1]) > np.mean(h[0])
