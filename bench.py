@@ -41,8 +41,10 @@ PAIR_CHUNK = 128
 SELECT_OPS_PER_TS = 3
 # HBM bytes per count launch, measured with rocprofv3 counters for one kernel source and tile
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hough_count_table_band200Hz_traffic.txt")
-COUNT_SOURCES = ("paper_1904_04873_amd/csrc/bsh_count.hip", "paper_1904_04873_amd/csrc/bsh_count.h",
-                 "paper_1904_04873_amd/csrc/bsh_internal.h")
+# the plain count kernel's sources and the build script (which holds its compiler flags)
+COUNT_SOURCES = ("paper_1904_04873_amd/csrc/bsh_count.hip", "paper_1904_04873_amd/csrc/bsh_count_tile.h",
+                 "paper_1904_04873_amd/csrc/bsh_count.h", "paper_1904_04873_amd/csrc/bsh_internal.h",
+                 "paper_1904_04873_amd/build.py")
 
 
 def count_sources_digest() -> str:

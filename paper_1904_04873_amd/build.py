@@ -1,16 +1,23 @@
-"""Build libbsh.so (the HIP library behind include/bsh.h) in-tree for gfx950."""
+"""Build libbsh.so (the HIP library behind include/bsh.h) in-tree for gfx950.
+
+Each source is compiled to its own object (in parallel), then the objects are linked into
+the shared library; no device code calls across sources, so no relocatable device code is
+needed."""
 from __future__ import annotations
 
 import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbsh.so")
-SOURCES = ["bsh_api.hip", "bsh_count.hip", "bsh_batch.hip", "bsh_power.hip", "bsh_topk.hip", "bsh_post.hip"]
+SOURCES = ["bsh_api.hip", "bsh_count.hip", "bsh_count_batch.hip", "bsh_batch.hip", "bsh_power.hip", "bsh_topk.hip",
+           "bsh_post.hip"]
 ARCH = os.environ.get("BSH_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -18,7 +25,6 @@ FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # the frequency track is evaluated in one fixed FP64 operation order
     "-ffp-contract=off",
     # no packed FP32 instructions anywhere in the device code
@@ -26,6 +32,13 @@ FLAGS = [
     "-Wno-unused-command-line-argument",
     "-I", os.path.join(ROOT, "include"),
 ]
+
+# Per-source additions.  The stage-1 count's inner loop interleaves four FP64 track chains with
+# LDS table reads; LLVM's iterative ILP scheduler orders it about 5 % faster than the default
+# (same registers per lane class, same occupancy, bitwise identical results).
+SOURCE_FLAGS = {
+    "bsh_count.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
+}
 
 
 def hipcc() -> str:
@@ -35,16 +48,29 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found: the HIP library cannot be built")
 
 
-def build(verbose: bool = False, extra: list | None = None) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc()] + FLAGS + (extra or []) + ["-o", tmp] + srcs
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libbsh.so")
+        raise RuntimeError(f"hipcc failed: {' '.join(cmd[-3:])}")
+
+
+def build(verbose: bool = False, extra: list | None = None) -> str:
+    os.makedirs(OBJ, exist_ok=True)
+    cc = hipcc()
+    jobs = []
+    objs = []
+    for src in SOURCES:
+        obj = os.path.join(OBJ, src.replace(".hip", ".o"))
+        objs.append(obj)
+        jobs.append([cc] + FLAGS + SOURCE_FLAGS.get(src, []) + (extra or []) +
+                    ["-c", "-o", obj, os.path.join(CSRC, src)])
+    with ThreadPoolExecutor(max_workers=min(len(jobs), 8)) as pool:
+        list(pool.map(lambda c: _run(c, verbose), jobs))
+    tmp = LIB + ".tmp"
+    _run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs, verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -1,5 +1,5 @@
-// Shared declarations of the stage-1 count kernels (bsh_count.hip) and the batched plan
-// (bsh_batch.hip).  Internal to libbsh.
+// Shared declarations of the stage-1 count kernels (bsh_count_tile.h, bsh_count.hip,
+// bsh_count_batch.hip) and the batched plan (bsh_batch.hip).  Internal to libbsh.
 #pragma once
 
 #include "bsh_internal.h"

@@ -1,469 +1,11 @@
-// Stage-1 weighted number count (Sec. IV.C eq:hough2; the GPU loop K1 of Sec. IV.B).
-//
-// Work decomposition.  A tile is one sky pixel, one orbital period P and `lanes` binary
-// templates (a_p, t_asc) of that period; each lane owns one binary template and all n_f0
-// (<= 90) frequency bins of the band.  Segments stream through LDS in chunks: per segment the
-// block stages cos(W t_J), sin(W t_J) (shared by every lane, since W is the tile's), the
-// Doppler factor D_J of the pixel, the weight and the bit-packed peakgram row.
-//
-// Per (lane, segment) the orbit factor is B = 1 - a_p W (cos(W t_J) cos(W t_asc) +
-// sin(W t_J) sin(W t_asc)) and G = D B, in the operation order of track_x.  The band's bins
-// follow from G alone:  k_i = floor(fl((k0 + i) G) + 1/2),  i = 0 .. n_f0-1.
-// For |G - 1| < 1/(2 n_f0) the offsets r_i = k_i - (k0 + i) form a monotone step with at
-// most one step (the canonical rounding is monotone in i and the exact offsets drift by
-// (n_f0-1)|G-1| < 1 bin).  So two evaluations (i = 0 and the last) give r_0 and r_last;
-// when they differ a binary search over canonical evaluations finds the first i with
-// r_i = r_last.  The band's n_f0 peak bits are then one funnel-shifted 96-bit window of the
-// row, with the part above the step taken one bit further (or nearer).  This is the exact
-// counterpart of the look-up-table reuse of one Doppler modulation over neighbouring
-// frequencies (Sec. IV.B): every template still reads the bin of its own exact track.
-//
-// Accumulation: per lane, 90 FP32 partial sums of w_J p_J that are folded into 90 running
-// totals every kFlush segments (bounded error for long observations), plus optional uint32
-// counts.  Each bit costs a sign-extending bit-field extract, an AND with the weight's bit
-// pattern and an add.
-//
-// Two launch forms share the tile body: the plain kernel (one block per tile of one work
-// item, bsh_hough_count) and the persistent kernel of the batched plan (bsh_batch.hip), whose
-// blocks pull (item, pixel, period, tile) units from a queue.
+// Stage-1 weighted number count, plain launch form (bsh_hough_count): one block per tile of
+// one work item.  The tile body is in bsh_count_tile.h.  This source is compiled with LLVM's
+// iterative ILP scheduler (see build.py).
 #include <cstring>
 
-#include "bsh_count.h"
+#include "bsh_count_tile.h"
 
 namespace bsh {
-
-__device__ __forceinline__ uint32_t upper_mask(int t)
-{
-    // bits b with b >= t set
-    return t <= 0 ? 0xffffffffu : (t >= 32 ? 0u : (0xffffffffu << t));
-}
-
-
-// One (binary template, segment) track across the band: G = D (1 - a_p W cos phi) and the
-// canonical bins of the band's lowest and highest f0.
-struct BandTrack {
-    double G, y0;
-    int kf, delta;
-    bool ok;
-};
-
-// The canonical evaluations (no branches).  ok is false, and a flag is raised, when the track
-// leaves the staged row or drifts more than one bin across the band.
-__device__ __forceinline__ BandTrack band_track(double C, double S, double D, double cb, double sb,
-                                                double apW, double F0, double FL, int klo, int last,
-                                                int n_bins, bool& bad_range, bool& bad_model)
-{
-    BandTrack t;
-    // same operation order as orbit_phase / track_x: G = D (1 - a_p W cos phi)
-    const double cphi = fma(C, cb, S * sb);
-    t.G = D * (1.0 - apW * cphi);
-    // floor(x + 1/2) of a positive track value is its truncation to an integer
-    t.y0 = F0 * t.G + 0.5;
-    t.kf = (int)t.y0;
-    const int kl = (int)(FL * t.G + 0.5);
-    const int base = t.kf - klo;
-    const int top = kl - klo;
-    t.delta = top - base - last;
-    const bool in_range = (base >= 0) & (top < n_bins);
-    t.ok = in_range & ((unsigned)(t.delta + 1) <= 2u);
-    bad_range |= !in_range;
-    bad_model |= in_range & !t.ok;
-    return t;
-}
-
-// Bit i of the 96-bit (m0, m1, m2) is the peakgram bit of f0 bin i as if the band had no f0-shift
-// step: one funnel-shifted window of the LDS row (zero when the track failed; a failed track
-// still reads inside the row).
-__device__ __forceinline__ void band_window(const uint32_t* row, const BandTrack& t, int klo, uint32_t& m0,
-                                            uint32_t& m1, uint32_t& m2)
-{
-    const int at = t.ok ? t.kf - klo : 0;
-    const int qw = at >> 5;
-    const int sh = at & 31;
-    const uint32_t w0 = row[qw], w1 = row[qw + 1], w2 = row[qw + 2], w3 = row[qw + 3];
-    // a mask rather than a select, so that the row reads stay unconditional
-    const uint32_t keep = 0u - (uint32_t)t.ok;
-    m0 = __builtin_amdgcn_alignbit(w1, w0, sh) & keep;
-    m1 = __builtin_amdgcn_alignbit(w2, w1, sh) & keep;
-    m2 = __builtin_amdgcn_alignbit(w3, w2, sh) & keep;
-}
-
-// Where the band has an f0-shift step (t.ok and t.delta != 0), take the bins above it one bit
-// further (delta = +1) or nearer (delta = -1).
-__device__ __forceinline__ void band_step(const BandTrack& t, double F0, int last, uint32_t& m0, uint32_t& m1,
-                                          uint32_t& m2)
-{
-    const double G = t.G, y0 = t.y0;
-    const int kf = t.kf, delta = t.delta;
-    const int r0 = kf - (int)F0;
-    // The residual r_i = k_i - (k0 + i) steps once, where y0 + i (G - 1) crosses an integer.
-    // A single-precision guess of that offset is checked with exact evaluations; the
-    // bisection below only runs when the guess is off.
-    auto resid = [&](int i) { return (int)((F0 + (double)i) * G + 0.5) - ((int)F0 + i); };
-    const double num = delta > 0 ? (double)(kf + 1) - y0 : y0 - (double)kf;
-    const float den = (float)((double)delta * (G - 1.0));
-    const float q = fminf(fmaxf((float)num * __builtin_amdgcn_rcpf(den), 0.f), (float)last);
-    const int g = min(max((int)q + 1, 1), last);
-    int lo, hi;              // r_lo = r0, r_hi != r0
-    if (g < last && resid(g) == r0) {
-        lo = g;
-        hi = last;
-    } else if (g == 1 || resid(g - 1) == r0) {
-        lo = g - 1;
-        hi = g;
-    } else {
-        lo = 0;
-        hi = g - 1;
-    }
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (resid(mid) == r0) lo = mid; else hi = mid;
-    }
-    uint32_t n0, n1, n2;
-    if (delta > 0) {
-        n0 = __builtin_amdgcn_alignbit(m1, m0, 1);
-        n1 = __builtin_amdgcn_alignbit(m2, m1, 1);
-        n2 = m2 >> 1;
-    } else {
-        n0 = m0 << 1;
-        n1 = __builtin_amdgcn_alignbit(m1, m0, 31);
-        n2 = __builtin_amdgcn_alignbit(m2, m1, 31);
-    }
-    const uint32_t s0 = upper_mask(hi), s1 = upper_mask(hi - 32), s2 = upper_mask(hi - 64);
-    m0 = (n0 & s0) | (m0 & ~s0);
-    m1 = (n1 & s1) | (m1 & ~s1);
-    m2 = (n2 & s2) | (m2 & ~s2);
-}
-
-// The peak bits of the band's n_f0 templates of one (binary template, segment): bit i of the
-// 96-bit (m0, m1, m2) is the peakgram bit of f0 bin i's track.  Returns false, with zero masks,
-// when the track failed.
-__device__ __forceinline__ bool band_mask(const uint32_t* row, double C, double S, double D, double cb,
-                                          double sb, double apW, double F0, double FL, int klo,
-                                          int last, int n_bins, uint32_t& m0, uint32_t& m1,
-                                          uint32_t& m2, bool& bad_range, bool& bad_model)
-{
-    const BandTrack t = band_track(C, S, D, cb, sb, apW, F0, FL, klo, last, n_bins, bad_range, bad_model);
-    band_window(row, t, klo, m0, m1, m2);
-    if (t.ok && t.delta != 0) band_step(t, F0, last, m0, m1, m2);
-    return t.ok;
-}
-
-template <bool kCount, int kChunk>
-__device__ __forceinline__ void count_tile(const ItemDesc& d, int s, int ip, int64_t tile,
-                                           TileSmem<kChunk>& sm)
-{
-    const int tid = threadIdx.x;
-    const int lanes = blockDim.x;
-    const int64_t q = tile * lanes + tid;
-
-    // position q of the period group -> (a_p index, t_asc point)
-    int ia = -1;
-    int64_t j = 0, cum = 0;
-    for (int a = 0; a < d.n_ap; ++a) {
-        const int64_t c0 = d.tasc_off[(int64_t)a * d.n_per + ip];
-        const int64_t n = d.tasc_off[(int64_t)a * d.n_per + ip + 1] - c0;
-        if (ia < 0 && q < cum + n) { ia = a; j = q - cum; }
-        cum += n;
-    }
-    const bool active = ia >= 0;
-    const int64_t b = active ? d.tasc_off[(int64_t)ia * d.n_per + ip] + j : 0;
-    const double W = kTwoPi / d.period[ip];
-    const double apW = active ? d.a_p[ia] * W : 0.0;
-    double sb = 0.0, cb = 1.0;
-    if (active) sincos(W * d.t_asc[b], &sb, &cb);
-
-    const int sg = d.sky_lo + s;
-    const double nx = d.sky[3 * sg], ny = d.sky[3 * sg + 1], nz = d.sky[3 * sg + 2];
-    const float* wrow = d.w + (d.w_per_sky ? (int64_t)s * d.n_seg : 0);
-    const double F0 = (double)d.k0;
-    const int last = d.n_f0 - 1;
-    const double FL = (double)(d.k0 + last);
-    const int klo = (int)d.k_lo;
-    const int nwp = d.n_words + kRowPad;
-
-    float acc[kNF], tot[kNF];
-    uint32_t cnt[kCount ? kNF : 1];
-#pragma unroll
-    for (int i = 0; i < kNF; ++i) { acc[i] = 0.f; tot[i] = 0.f; }
-#pragma unroll
-    for (int i = 0; i < (kCount ? kNF : 1); ++i) cnt[i] = 0u;
-    int since_flush = 0;
-    bool bad_range = false, bad_model = false;
-
-    for (int64_t j0 = 0; j0 < d.n_seg; j0 += kChunk) {
-        const int nj = (int)min((int64_t)kChunk, d.n_seg - j0);
-        __syncthreads();
-        for (int jj = tid; jj < nj; jj += lanes) {
-            const int64_t J = j0 + jj;
-            double sp, cp;
-            sincos(W * d.t_mid[J], &sp, &cp);
-            sm.C[jj] = cp;
-            sm.S[jj] = sp;
-            sm.D[jj] = doppler_factor(d.v + 3 * J, nx, ny, nz);
-            sm.W[jj] = wrow[J];
-        }
-        for (int e = tid; e < nj * nwp; e += lanes) {
-            const int jj = e / nwp;
-            const int wd = e - jj * nwp;
-            sm.row[e] = wd < d.n_words ? d.bits[(j0 + jj) * d.n_words + wd] : 0u;
-        }
-        __syncthreads();
-        if (!active) continue;
-
-        for (int jj = 0; jj < nj; ++jj) {
-            uint32_t m0, m1, m2;
-            if (!band_mask(sm.row + jj * nwp, sm.C[jj], sm.S[jj], sm.D[jj], cb, sb, apW, F0, FL, klo,
-                           last, d.n_bins, m0, m1, m2, bad_range, bad_model))
-                continue;
-
-            const uint32_t wb = __float_as_uint(sm.W[jj]);
-#pragma unroll
-            for (int i = 0; i < kNF; ++i) {
-                const uint32_t m = i < 32 ? m0 : (i < 64 ? m1 : m2);
-                const int bit = ((int)(m << (31 - (i & 31)))) >> 31;   // 0 or -1
-                acc[i] += __uint_as_float((uint32_t)bit & wb);
-                if (kCount) cnt[i] -= (uint32_t)bit;
-            }
-            if (++since_flush == kFlush) {
-                since_flush = 0;
-#pragma unroll
-                for (int i = 0; i < kNF; ++i) { tot[i] += acc[i]; acc[i] = 0.f; }
-            }
-        }
-    }
-    if (bad_range) raise_status(d.status, BSH_STATUS_RANGE);
-    if (bad_model) raise_status(d.status, BSH_STATUS_MODEL);
-    if (!active) return;
-
-    const int64_t base_idx = ((int64_t)s * d.n_bin + b) * d.n_f0;
-#pragma unroll
-    for (int i = 0; i < kNF; ++i) {
-        if (i < d.n_f0) {
-            if (d.wsum_out) d.wsum_out[base_idx + i] = tot[i] + acc[i];
-            if (kCount && d.count_out) d.count_out[base_idx + i] = cnt[kCount ? i : 0];
-        }
-    }
-}
-
-
-// Table variant of the weighted count.  Segments are taken in groups of four; a 16-entry
-// table per group holds every subset sum of the group's four weights.  For each f0 bin the
-// four peak bits of the group form a 4-bit index, so one table read and one add replace four
-// select-and-add steps.  The indices of all 90 bins come from the four 96-bit masks by a bit
-// interleave: word A[w][r] holds, in nibble n, the four segments' bits of bin 32w + 4n + r.
-// A 16-entry table occupies 16 consecutive LDS banks, so any pattern of reads is free of
-// bank conflicts.  With chunks of at most kPairChunk segments the group also gets a 256-entry
-// table of value pairs indexed by a whole byte of A[w][r] (two nibbles, two bins), which halves
-// the table reads and their address arithmetic; the values, and so the sums, are the same
-// floats in the same order.  The 90 register partial sums (at most kFlushGroups groups each) are folded
-// into the lane's own slots of the output map, which keeps the register footprint small
-// enough for two waves per SIMD; the error of the two-level sum stays below
-// (kFlushGroups + n_seg / (4 kFlushGroups)) FP32 ulps of the total.
-template <int kChunk>
-__device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip, int64_t tile,
-                                               TileSmemLut<kChunk>& sm)
-{
-    static_assert(kChunk % kGroup == 0, "chunks hold whole groups");
-    constexpr bool kPair = kChunk <= kPairChunk;
-    const int tid = threadIdx.x;
-    const int lanes = blockDim.x;
-    const int64_t q = tile * lanes + tid;
-
-    int ia = -1;
-    int64_t j = 0, cum = 0;
-    for (int a = 0; a < d.n_ap; ++a) {
-        const int64_t c0 = d.tasc_off[(int64_t)a * d.n_per + ip];
-        const int64_t n = d.tasc_off[(int64_t)a * d.n_per + ip + 1] - c0;
-        if (ia < 0 && q < cum + n) { ia = a; j = q - cum; }
-        cum += n;
-    }
-    const bool active = ia >= 0;
-    const int64_t b = active ? d.tasc_off[(int64_t)ia * d.n_per + ip] + j : 0;
-    const double W = kTwoPi / d.period[ip];
-    const double apW = active ? d.a_p[ia] * W : 0.0;
-    double sb = 0.0, cb = 1.0;
-    if (active) sincos(W * d.t_asc[b], &sb, &cb);
-
-    const int sg = d.sky_lo + s;
-    const double nx = d.sky[3 * sg], ny = d.sky[3 * sg + 1], nz = d.sky[3 * sg + 2];
-    const float* wrow = d.w + (d.w_per_sky ? (int64_t)s * d.n_seg : 0);
-    const double F0 = (double)d.k0;
-    const int last = d.n_f0 - 1;
-    const double FL = (double)(d.k0 + last);
-    const int klo = (int)d.k_lo;
-    const int nwp = d.n_words + kRowPad;
-
-    float acc[kNF];
-#pragma unroll
-    for (int i = 0; i < kNF; ++i) acc[i] = 0.f;
-    int since_flush = 0;
-    bool flushed = false;
-    float* out = d.wsum_out + ((int64_t)s * d.n_bin + b) * d.n_f0;
-    const int nf = d.n_f0;
-    // fold the register partial sums into the lane's output slots
-    auto flush = [&]() {
-#pragma unroll
-        for (int i = 0; i < kNF; ++i) {
-            if (i < nf) out[i] = flushed ? out[i] + acc[i] : acc[i];
-            acc[i] = 0.f;
-        }
-        flushed = true;
-    };
-    bool bad_range = false, bad_model = false;
-
-    for (int64_t j0 = 0; j0 < d.n_seg; j0 += kChunk) {
-        const int nj = (int)min((int64_t)kChunk, d.n_seg - j0);
-        const int ng = (nj + kGroup - 1) / kGroup;
-        __syncthreads();
-        // slots past the chunk's last segment (up to a whole group) repeat its tables with an
-        // empty row and zero weight, so that every group holds four in-range segments
-        for (int jj = tid; jj < ng * kGroup; jj += lanes) {
-            const int64_t J = j0 + min(jj, nj - 1);
-            double sp, cp;
-            sincos(W * d.t_mid[J], &sp, &cp);
-            sm.C[jj] = cp;
-            sm.S[jj] = sp;
-            sm.D[jj] = doppler_factor(d.v + 3 * J, nx, ny, nz);
-        }
-        for (int e = tid; e < ng * kGroup * nwp; e += lanes) {
-            const int jj = e / nwp;
-            const int wd = e - jj * nwp;
-            sm.row[e] = (jj < nj && wd < d.n_words) ? d.bits[(j0 + jj) * d.n_words + wd] : 0u;
-        }
-        for (int g = tid; g < ng; g += lanes) {
-            // subset sums in segment order; missing segments of a last partial group weigh 0
-            float w4[kGroup];
-#pragma unroll
-            for (int u = 0; u < kGroup; ++u) {
-                const int jj = g * kGroup + u;
-                w4[u] = jj < nj ? wrow[j0 + jj] : 0.f;
-            }
-            float* T = sm.T + g * 16;
-#pragma unroll
-            for (int m = 0; m < 16; ++m) {
-                float t = 0.f;
-#pragma unroll
-                for (int u = 0; u < kGroup; ++u)
-                    if (m & (1 << u)) t += w4[u];
-                T[m] = t;
-            }
-        }
-        if constexpr (kPair) {
-            __syncthreads();
-            for (int e = tid; e < ng * 256; e += lanes) {
-                const int g = e >> 8, m = e & 255;
-                sm.T2[e] = make_float2(sm.T[g * 16 + (m & 15)], sm.T[g * 16 + (m >> 4)]);
-            }
-        }
-        __syncthreads();
-        if (!active) continue;
-
-        for (int g = 0; g < ng; ++g) {
-            // the four tracks and windows without branches (independent chains the scheduler
-            // can interleave), then the rare f0-shift steps
-            uint32_t mk[kGroup][3];
-            BandTrack tr[kGroup];
-#pragma unroll
-            for (int u = 0; u < kGroup; ++u) {
-                const int jj = g * kGroup + u;
-                tr[u] = band_track(sm.C[jj], sm.S[jj], sm.D[jj], cb, sb, apW, F0, FL, klo, last, d.n_bins,
-                                   bad_range, bad_model);
-            }
-#pragma unroll
-            for (int u = 0; u < kGroup; ++u)
-                band_window(sm.row + (g * kGroup + u) * nwp, tr[u], klo, mk[u][0], mk[u][1], mk[u][2]);
-#pragma unroll
-            for (int u = 0; u < kGroup; ++u)
-                if (tr[u].ok && tr[u].delta != 0) band_step(tr[u], F0, last, mk[u][0], mk[u][1], mk[u][2]);
-            // A[w][r]: bit (4n + u) <- bit (4n + r) of mask u's word w, i.e. every nibble column
-            // of the 4 x 32 bit matrix (mk[0..3][w]) transposed: swap the off-diagonal 2 x 2
-            // blocks, then the off-diagonal bits of each 2 x 2 block.
-            uint32_t A[3][4];
-#pragma unroll
-            for (int w = 0; w < 3; ++w) {
-                uint32_t x0 = mk[0][w], x1 = mk[1][w], x2 = mk[2][w], x3 = mk[3][w];
-                uint32_t t;
-                t = ((x0 >> 2) ^ x2) & 0x33333333u; x2 ^= t; x0 ^= t << 2;
-                t = ((x1 >> 2) ^ x3) & 0x33333333u; x3 ^= t; x1 ^= t << 2;
-                t = ((x0 >> 1) ^ x1) & 0x55555555u; x1 ^= t; x0 ^= t << 1;
-                t = ((x2 >> 1) ^ x3) & 0x55555555u; x3 ^= t; x2 ^= t << 1;
-                A[w][0] = x0;
-                A[w][1] = x1;
-                A[w][2] = x2;
-                A[w][3] = x3;
-            }
-            // Look the bins up word by word: the table reads of word k are issued before the
-            // adds of word k-1, so one word's LDS latency overlaps the next word's reads.
-            if constexpr (kPair) {
-                // byte m of A[w][r] holds the nibbles of bins 32w + 8m + r and 32w + 8m + 4 + r
-                const float2* T2 = sm.T2 + g * 256;
-                float2 v[2][4];
-#pragma unroll
-                for (int k = 0; k <= 12; ++k) {
-                    if (k < 12) {
-                        const int w = k >> 2, r = k & 3;
-#pragma unroll
-                        for (int m = 0; m < 4; ++m)
-                            if (32 * w + 8 * m + r < kNF) v[k & 1][m] = T2[(A[w][r] >> (8 * m)) & 255u];
-                    }
-                    if (k > 0) {
-                        const int w = (k - 1) >> 2, r = (k - 1) & 3;
-#pragma unroll
-                        for (int m = 0; m < 4; ++m) {
-                            const int i = 32 * w + 8 * m + r;
-                            if (i < kNF) acc[i] += v[(k - 1) & 1][m].x;
-                            if (i + 4 < kNF) acc[i + 4] += v[(k - 1) & 1][m].y;
-                        }
-                    }
-                }
-            } else {
-                const float* T = sm.T + g * 16;
-                float v[2][8];
-#pragma unroll
-                for (int k = 0; k <= 12; ++k) {
-                    if (k < 12) {
-                        const int w = k >> 2, r = k & 3;
-#pragma unroll
-                        for (int n = 0; n < 8; ++n)
-                            if (32 * w + 4 * n + r < kNF) v[k & 1][n] = T[(A[w][r] >> (4 * n)) & 15u];
-                    }
-                    if (k > 0) {
-                        const int w = (k - 1) >> 2, r = (k - 1) & 3;
-#pragma unroll
-                        for (int n = 0; n < 8; ++n) {
-                            const int i = 32 * w + 4 * n + r;
-                            if (i < kNF) acc[i] += v[(k - 1) & 1][n];
-                        }
-                    }
-                }
-            }
-            if (++since_flush == kFlushGroups) {
-                since_flush = 0;
-                flush();
-            }
-        }
-    }
-    if (bad_range) raise_status(d.status, BSH_STATUS_RANGE);
-    if (bad_model) raise_status(d.status, BSH_STATUS_MODEL);
-    if (active && (since_flush > 0 || !flushed)) flush();
-}
-
-// kMode: 0 = select-and-add, weighted sums only; 1 = select-and-add with counts; 2 = table.
-template <int kMode, int kChunk>
-__device__ __forceinline__ void run_tile(const ItemDesc& d, int s, int ip, int64_t tile, void* smem)
-{
-    if constexpr (kMode == 2)
-        count_tile_lut<kChunk>(d, s, ip, tile, *reinterpret_cast<TileSmemLut<kChunk>*>(smem));
-    else
-        count_tile<kMode == 1, kChunk>(d, s, ip, tile, *reinterpret_cast<TileSmem<kChunk>*>(smem));
-}
-
-template <int kMode, int kChunk>
-constexpr size_t smem_bytes()
-{
-    return kMode == 2 ? sizeof(TileSmemLut<kChunk>) : sizeof(TileSmem<kChunk>);
-}
 
 template <int kMode, int kChunk>
 __global__ __launch_bounds__(kMaxLanes, kMode == 2 ? 2 : 1) void hough_count_kernel(const PlainLaunch p)
@@ -478,25 +20,6 @@ __global__ __launch_bounds__(kMaxLanes, kMode == 2 ? 2 : 1) void hough_count_ker
         if (p.tile_start[mid] <= t) lo = mid; else hi = mid;
     }
     run_tile<kMode, kChunk>(p.d, s, lo, t - p.tile_start[lo], smem);
-}
-
-template <int kMode, int kChunk>
-__global__ __launch_bounds__(kMaxLanes, kMode == 2 ? 2 : 1) void hough_batch_kernel(const ItemDesc* __restrict__ items,
-                                                               const WorkUnit* __restrict__ units,
-                                                               int64_t n_units, uint32_t* counter)
-{
-    __shared__ __align__(16) unsigned char smem[smem_bytes<kMode, kChunk>()];
-    __shared__ int64_t next;
-    for (;;) {
-        if (threadIdx.x == 0) next = (int64_t)atomicAdd(counter, 1u);
-        __syncthreads();
-        const int64_t u = next;
-        __syncthreads();
-        if (u >= n_units) break;
-        const WorkUnit w = units[u];
-        const ItemDesc d = items[w.item];
-        run_tile<kMode, kChunk>(d, w.sky, w.ip, w.tile, smem);
-    }
 }
 
 // Tiles of each period group of one item, in tile_start form.
@@ -564,21 +87,6 @@ int zero_words(void* p, int64_t n_words, hipStream_t stream)
     return check_launch("zero fill");
 }
 
-// Instantiate a kernel template for every (mode, chunk) and call f with the chosen one.
-#define BSH_DISPATCH(MODE, CHUNK, F)                                                          \
-    switch ((MODE) * 1000 + (CHUNK)) {                                                        \
-    case 128: F(0, 128); break;                                                               \
-    case 256: F(0, 256); break;                                                               \
-    case 512: F(0, 512); break;                                                               \
-    case 1128: F(1, 128); break;                                                              \
-    case 1256: F(1, 256); break;                                                              \
-    case 1512: F(1, 512); break;                                                              \
-    case 2128: F(2, 128); break;                                                              \
-    case 2256: F(2, 256); break;                                                              \
-    case 2512: F(2, 512); break;                                                              \
-    default: return fail_inval("kernel mode / chunk");                                        \
-    }
-
 int launch_plain(const PlainLaunch& p, int64_t blocks, int lanes, int chunk, int mode, hipStream_t stream)
 {
 #define BSH_LAUNCH_PLAIN(M, C)                                                                \
@@ -586,39 +94,6 @@ int launch_plain(const PlainLaunch& p, int64_t blocks, int lanes, int chunk, int
     BSH_DISPATCH(mode, chunk, BSH_LAUNCH_PLAIN)
 #undef BSH_LAUNCH_PLAIN
     return check_launch("bsh_hough_count");
-}
-
-int launch_batch(const ItemDesc* items, const WorkUnit* units, int64_t n_units, uint32_t* counter,
-                 int blocks, int lanes, int chunk, int mode, hipStream_t stream)
-{
-#define BSH_LAUNCH_BATCH(M, C)                                                                \
-    hipLaunchKernelGGL((hough_batch_kernel<M, C>), dim3(blocks), dim3(lanes), 0, stream, items, units, \
-                       n_units, counter)
-    BSH_DISPATCH(mode, chunk, BSH_LAUNCH_BATCH)
-#undef BSH_LAUNCH_BATCH
-    return check_launch("batched count");
-}
-
-int batch_blocks_per_cu(int lanes, int chunk, int mode)
-{
-    int n = 0;
-    hipError_t e = hipSuccess;
-#define BSH_OCC(M, C) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, hough_batch_kernel<M, C>, lanes, 0)
-    switch (mode * 1000 + chunk) {
-    case 128: BSH_OCC(0, 128); break;
-    case 256: BSH_OCC(0, 256); break;
-    case 512: BSH_OCC(0, 512); break;
-    case 1128: BSH_OCC(1, 128); break;
-    case 1256: BSH_OCC(1, 256); break;
-    case 1512: BSH_OCC(1, 512); break;
-    case 2128: BSH_OCC(2, 128); break;
-    case 2256: BSH_OCC(2, 256); break;
-    case 2512: BSH_OCC(2, 512); break;
-    default: break;
-    }
-#undef BSH_OCC
-    if (e != hipSuccess || n < 1) n = 1;
-    return n;
 }
 
 int kernel_mode(int variant, bool with_count)
