@@ -30,12 +30,12 @@ METRIC = "Hough templates·segments/s on 1 GPU, batched vs plain, at oracle-exac
 # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: 32-bit VALU lane-operations per second
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # VALU lane-operations per template x segment on the fast path of the subset-sum table count
-# (counted in its gfx950 ISA), per group of 4 segments x 90 f0 bins: 146 for the four tracks'
+# (counted in its gfx950 ISA), per group of 4 segments x 90 f0 bins: 129 for the four tracks'
 # bins and 96-bit masks, 60 for the bit transpose of the four masks, and the lookups: with
 # 16-entry tables (chunks over 128 segments) 90 x (nibble, address, add), 335 with the
-# transpose, so (146 + 335) / 360 = 1.34; with 256-entry pair tables (chunks of at most 128)
-# 46 x (byte, address) + 90 adds, 247 with the transpose, so (146 + 247) / 360 = 1.09.
-TABLE_OPS_PER_TS = {"pair": 1.09, "nibble": 1.34}
+# transpose, so (129 + 335) / 360 = 1.29; with 256-entry pair tables (chunks of at most 128)
+# 46 x (byte, address) + 90 adds, 247 with the transpose, so (129 + 247) / 360 = 1.04.
+TABLE_OPS_PER_TS = {"pair": 1.04, "nibble": 1.29}
 PAIR_CHUNK = 128
 # the same figure for plain select-and-add: extract the peak bit, select the weight, add
 SELECT_OPS_PER_TS = 3

@@ -303,11 +303,10 @@ __global__ void track_bins_kernel(const double* __restrict__ t_mid, const double
         return;
     }
     const Cand cd = load_cand(cand + 4 * c);
-    double st, ct, cphi, sphi;
+    double st, ct;
     sincos(cd.W * t_mid[J], &st, &ct);
-    orbit_phase(ct, st, cd, cphi, sphi);
     const double D = doppler_factor(v + 3 * J, sky[3 * s], sky[3 * s + 1], sky[3 * s + 2]);
-    bins[e] = (int32_t)nearest_bin(track_x(cd.F, D, cd.apW, cphi));
+    bins[e] = (int32_t)track_bin(cd.F, track_G(D, D * ct, D * st, cd.Ac, cd.As));
 }
 
 extern "C" int bsh_track_bins(const bsh_segments* seg, const double* sky, int32_t n_sky,

@@ -63,10 +63,11 @@ constexpr int kFlushGroups = 128;    // groups per register partial sum (table v
 // (T[b & 15], T[b >> 4]) so that one 8-byte read serves two f0 bins (64 KB at 128 segments).
 constexpr int kPairChunk = 128;
 
+// Per staged segment: D cos(W t), D sin(W t) and the Doppler factor D of the tile's pixel.
 template <int kChunk>
 struct TileSmemLut {
-    double C[kChunk];
-    double S[kChunk];
+    double DC[kChunk];
+    double DS[kChunk];
     double D[kChunk];
     float2 T2[kChunk <= kPairChunk ? (kChunk / kGroup) * 256 : 1];
     float T[(kChunk / kGroup) * 16];
@@ -75,8 +76,8 @@ struct TileSmemLut {
 
 template <int kChunk>
 struct TileSmem {
-    double C[kChunk];
-    double S[kChunk];
+    double DC[kChunk];
+    double DS[kChunk];
     double D[kChunk];
     float W[kChunk];
     uint32_t row[kChunk * (BSH_MAX_WORDS + kRowPad)];

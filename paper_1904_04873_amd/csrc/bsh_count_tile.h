@@ -5,13 +5,12 @@
 // Work decomposition.  A tile is one sky pixel, one orbital period P and `lanes` binary
 // templates (a_p, t_asc) of that period; each lane owns one binary template and all n_f0
 // (<= 90) frequency bins of the band.  Segments stream through LDS in chunks: per segment the
-// block stages cos(W t_J), sin(W t_J) (shared by every lane, since W is the tile's), the
-// Doppler factor D_J of the pixel, the weight (or the group subset sums) and the bit-packed
-// peakgram row.
+// block stages D cos(W t_J), D sin(W t_J) and D (W is the tile's, D_J the pixel's Doppler
+// factor), the weight (or the group subset sums) and the bit-packed peakgram row.
 //
-// Per (lane, segment) the orbit factor is B = 1 - a_p W (cos(W t_J) cos(W t_asc) +
-// sin(W t_J) sin(W t_asc)) and G = D B, in the operation order of track_x.  The band's bins
-// follow from G alone:  k_i = floor(fl((k0 + i) G) + 1/2),  i = 0 .. n_f0-1.
+// Per (lane, segment) G = D (1 - a_p W cos(W (t_J - t_asc))) is evaluated as track_G does in
+// every kernel, from the staged D C, D S and the lane's a_p W cos / sin(W t_asc).  The band's
+// bins follow from G alone:  k_i = floor(fl((k0 + i) G + 1/2)),  i = 0 .. n_f0-1.
 // For |G - 1| < 1/(2 n_f0) the offsets r_i = k_i - (k0 + i) form a monotone step with at
 // most one step (the canonical rounding is monotone in i and the exact offsets drift by
 // (n_f0-1)|G-1| < 1 bin).  So two evaluations (i = 0 and the last) give r_0 and r_last;
@@ -47,18 +46,16 @@ struct BandTrack {
 
 // The canonical evaluations (no branches).  ok is false, and a flag is raised, when the track
 // leaves the staged row or drifts more than one bin across the band.
-__device__ __forceinline__ BandTrack band_track(double C, double S, double D, double cb, double sb,
-                                                double apW, double F0, double FL, int klo, int last,
-                                                int n_bins, bool& bad_range, bool& bad_model)
+__device__ __forceinline__ BandTrack band_track(double DC, double DS, double D, double Ac, double As,
+                                                double F0, double FL, int klo, int last, int n_bins,
+                                                bool& bad_range, bool& bad_model)
 {
     BandTrack t;
-    // same operation order as orbit_phase / track_x: G = D (1 - a_p W cos phi)
-    const double cphi = fma(C, cb, S * sb);
-    t.G = D * (1.0 - apW * cphi);
-    // floor(x + 1/2) of a positive track value is its truncation to an integer
-    t.y0 = F0 * t.G + 0.5;
+    t.G = track_G(D, DC, DS, Ac, As);
+    // the nearest bin floor(F G + 1/2) of a positive track value is its truncation
+    t.y0 = fma(F0, t.G, 0.5);
     t.kf = (int)t.y0;
-    const int kl = (int)(FL * t.G + 0.5);
+    const int kl = (int)fma(FL, t.G, 0.5);
     const int base = t.kf - klo;
     const int top = kl - klo;
     t.delta = top - base - last;
@@ -97,7 +94,7 @@ __device__ __forceinline__ void band_step(const BandTrack& t, double F0, int las
     // The residual r_i = k_i - (k0 + i) steps once, where y0 + i (G - 1) crosses an integer.
     // A single-precision guess of that offset is checked with exact evaluations; the
     // bisection below only runs when the guess is off.
-    auto resid = [&](int i) { return (int)((F0 + (double)i) * G + 0.5) - ((int)F0 + i); };
+    auto resid = [&](int i) { return (int)fma(F0 + (double)i, G, 0.5) - ((int)F0 + i); };
     const double num = delta > 0 ? (double)(kf + 1) - y0 : y0 - (double)kf;
     const float den = (float)((double)delta * (G - 1.0));
     const float q = fminf(fmaxf((float)num * __builtin_amdgcn_rcpf(den), 0.f), (float)last);
@@ -136,12 +133,12 @@ __device__ __forceinline__ void band_step(const BandTrack& t, double F0, int las
 // The peak bits of the band's n_f0 templates of one (binary template, segment): bit i of the
 // 96-bit (m0, m1, m2) is the peakgram bit of f0 bin i's track.  Returns false, with zero masks,
 // when the track failed.
-__device__ __forceinline__ bool band_mask(const uint32_t* row, double C, double S, double D, double cb,
-                                          double sb, double apW, double F0, double FL, int klo,
-                                          int last, int n_bins, uint32_t& m0, uint32_t& m1,
-                                          uint32_t& m2, bool& bad_range, bool& bad_model)
+__device__ __forceinline__ bool band_mask(const uint32_t* row, double DC, double DS, double D, double Ac,
+                                          double As, double F0, double FL, int klo, int last, int n_bins,
+                                          uint32_t& m0, uint32_t& m1, uint32_t& m2, bool& bad_range,
+                                          bool& bad_model)
 {
-    const BandTrack t = band_track(C, S, D, cb, sb, apW, F0, FL, klo, last, n_bins, bad_range, bad_model);
+    const BandTrack t = band_track(DC, DS, D, Ac, As, F0, FL, klo, last, n_bins, bad_range, bad_model);
     band_window(row, t, klo, m0, m1, m2);
     if (t.ok && t.delta != 0) band_step(t, F0, last, m0, m1, m2);
     return t.ok;
@@ -170,6 +167,7 @@ __device__ __forceinline__ void count_tile(const ItemDesc& d, int s, int ip, int
     const double apW = active ? d.a_p[ia] * W : 0.0;
     double sb = 0.0, cb = 1.0;
     if (active) sincos(W * d.t_asc[b], &sb, &cb);
+    const double Ac = apW * cb, As = apW * sb;
 
     const int sg = d.sky_lo + s;
     const double nx = d.sky[3 * sg], ny = d.sky[3 * sg + 1], nz = d.sky[3 * sg + 2];
@@ -196,9 +194,10 @@ __device__ __forceinline__ void count_tile(const ItemDesc& d, int s, int ip, int
             const int64_t J = j0 + jj;
             double sp, cp;
             sincos(W * d.t_mid[J], &sp, &cp);
-            sm.C[jj] = cp;
-            sm.S[jj] = sp;
-            sm.D[jj] = doppler_factor(d.v + 3 * J, nx, ny, nz);
+            const double D = doppler_factor(d.v + 3 * J, nx, ny, nz);
+            sm.DC[jj] = D * cp;
+            sm.DS[jj] = D * sp;
+            sm.D[jj] = D;
             sm.W[jj] = wrow[J];
         }
         for (int e = tid; e < nj * nwp; e += lanes) {
@@ -211,7 +210,7 @@ __device__ __forceinline__ void count_tile(const ItemDesc& d, int s, int ip, int
 
         for (int jj = 0; jj < nj; ++jj) {
             uint32_t m0, m1, m2;
-            if (!band_mask(sm.row + jj * nwp, sm.C[jj], sm.S[jj], sm.D[jj], cb, sb, apW, F0, FL, klo,
+            if (!band_mask(sm.row + jj * nwp, sm.DC[jj], sm.DS[jj], sm.D[jj], Ac, As, F0, FL, klo,
                            last, d.n_bins, m0, m1, m2, bad_range, bad_model))
                 continue;
 
@@ -282,6 +281,7 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
     const double apW = active ? d.a_p[ia] * W : 0.0;
     double sb = 0.0, cb = 1.0;
     if (active) sincos(W * d.t_asc[b], &sb, &cb);
+    const double Ac = apW * cb, As = apW * sb;
 
     const int sg = d.sky_lo + s;
     const double nx = d.sky[3 * sg], ny = d.sky[3 * sg + 1], nz = d.sky[3 * sg + 2];
@@ -320,9 +320,10 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
             const int64_t J = j0 + min(jj, nj - 1);
             double sp, cp;
             sincos(W * d.t_mid[J], &sp, &cp);
-            sm.C[jj] = cp;
-            sm.S[jj] = sp;
-            sm.D[jj] = doppler_factor(d.v + 3 * J, nx, ny, nz);
+            const double D = doppler_factor(d.v + 3 * J, nx, ny, nz);
+            sm.DC[jj] = D * cp;
+            sm.DS[jj] = D * sp;
+            sm.D[jj] = D;
         }
         for (int e = tid; e < ng * kGroup * nwp; e += lanes) {
             const int jj = e / nwp;
@@ -365,7 +366,7 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
 #pragma unroll
             for (int u = 0; u < kGroup; ++u) {
                 const int jj = g * kGroup + u;
-                tr[u] = band_track(sm.C[jj], sm.S[jj], sm.D[jj], cb, sb, apW, F0, FL, klo, last, d.n_bins,
+                tr[u] = band_track(sm.DC[jj], sm.DS[jj], sm.D[jj], Ac, As, F0, FL, klo, last, d.n_bins,
                                    bad_range, bad_model);
             }
 #pragma unroll

@@ -64,9 +64,9 @@ __device__ __forceinline__ double doppler_factor(const double* v, double nx, dou
 }
 
 // A candidate template (F = f0 Tc, a_p, P, t_asc) with the quantities every segment reuses:
-// W = 2 pi / P, a_p W and cos / sin of W t_asc.
+// W = 2 pi / P, a_p W, cos / sin of W t_asc and A_c = a_p W cos(W t_asc), A_s = a_p W sin(W t_asc).
 struct Cand {
-    double F, ap, P, ta, W, apW, cb, sb;
+    double F, ap, P, ta, W, apW, cb, sb, Ac, As;
 };
 
 __device__ __forceinline__ Cand load_cand(const double* cand)
@@ -79,12 +79,14 @@ __device__ __forceinline__ Cand load_cand(const double* cand)
     c.W = kTwoPi / c.P;
     c.apW = c.ap * c.W;
     sincos(c.W * c.ta, &c.sb, &c.cb);
+    c.Ac = c.apW * c.cb;
+    c.As = c.apW * c.sb;
     return c;
 }
 
 // cos and sin of the orbital phase W (t - t_asc), from cos / sin of W t and W t_asc by the
-// angle-difference formulas.  Every kernel evaluates the phase this way (the stage-1 kernel
-// with cos / sin of W t staged once per block), so all of them select identical bins.
+// angle-difference formulas (for the eccentric track and the derivatives; bins come from
+// track_G).
 __device__ __forceinline__ void orbit_phase(double ct, double st, const Cand& c, double& cphi,
                                             double& sphi)
 {
@@ -92,14 +94,18 @@ __device__ __forceinline__ void orbit_phase(double ct, double st, const Cand& c,
     sphi = fma(st, c.cb, -(ct * c.sb));
 }
 
-// The track x = F D (1 - a_p W cos phi)  (eq:frequencyevoFinal, product form).
-__device__ __forceinline__ double track_x(double F, double D, double apW, double cphi)
+// The track x = F G with G = D (1 - a_p W cos(W (t - t_asc)))  (eq:frequencyevoFinal, product
+// form).  Expanding cos by the angle-difference formula, G = D - (D C A_c + D S A_s) with
+// C, S = cos, sin of W t (per segment) and A_c, A_s of the template; it is evaluated in this
+// one order, D - fma(D C, A_c, (D S) A_s), by every kernel (the stage-1 kernel stages D C and
+// D S once per block), so all of them select identical bins.
+__device__ __forceinline__ double track_G(double D, double DC, double DS, double Ac, double As)
 {
-    return F * (D * (1.0 - apW * cphi));
+    return D - fma(DC, Ac, DS * As);
 }
 
-// Nearest-bin rounding of a track value: floor(x + 1/2).
-__device__ __forceinline__ double nearest_bin(double x) { return floor(x + 0.5); }
+// Nearest bin of the track: floor(F G + 1/2), with F G + 1/2 rounded once.
+__device__ __forceinline__ double track_bin(double F, double G) { return floor(fma(F, G, 0.5)); }
 
 __device__ __forceinline__ void raise_status(int32_t* status, int32_t bit)
 {

@@ -44,14 +44,13 @@ __global__ __launch_bounds__(kThreads) void power_stat_kernel(
     uint32_t cnt = 0u;
     bool bad = false;
     for (int64_t J = lane; J < n_seg; J += 64) {
-        double st, ct, cphi, sphi;
+        double st, ct;
         sincos(cd.W * t_mid[J], &st, &ct);
-        orbit_phase(ct, st, cd, cphi, sphi);
         const double D = doppler_factor(v + 3 * J, nx, ny, nz);
-        const double x = track_x(cd.F, D, cd.apW, cphi);
+        const double G = track_G(D, D * ct, D * st, cd.Ac, cd.As);
         const float wj = wr[J];
         if (mode == 0) {
-            const int col = (int)(floor(x + 0.5) - klo);
+            const int col = (int)(track_bin(cd.F, G) - klo);
             if (col < 0 || col >= n_bins) { bad = true; continue; }
             if (power) P += wj * power[J * n_bins + col];
             if (bits) {
@@ -60,6 +59,7 @@ __global__ __launch_bounds__(kThreads) void power_stat_kernel(
                 ws += bit ? wj : 0.f;
             }
         } else {
+            const double x = cd.F * G;
             const double kf = floor(x);
             const int col = (int)(kf - klo);
             if (col < 0 || col + 1 >= n_bins) { bad = true; continue; }
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(kThreads) void power_grad_kernel(
         orbit_phase(ct, st, cd, cphi, sphi);
         const double D = doppler_factor(v + 3 * J, nx, ny, nz);
         const double B = 1.0 - cd.apW * cphi;
-        const double x = track_x(cd.F, D, cd.apW, cphi);
+        const double x = cd.F * track_G(D, D * ct, D * st, cd.Ac, cd.As);
         const double kf = floor(x);
         const int col = (int)(kf - klo);
         if (col < 0 || col + 1 >= n_bins) { bad = true; continue; }
@@ -171,13 +171,16 @@ __global__ __launch_bounds__(kThreads) void power_stat_ecc_kernel(
         const double c2 = (cphi - sphi) * (cphi + sphi);
         const double s2 = 2.0 * (sphi * cphi);
         const double D = doppler_factor(v + 3 * J, nx, ny, nz);
-        const double x = track_x(cd.F, D, cd.apW, cphi + (ec * c2 - es * s2));
+        // the circular G minus D a_p W (e cos w cos 2psi - e sin w sin 2psi); for e = 0 the
+        // subtracted term is zero and G is the circular track's bit for bit
+        const double G = track_G(D, D * ct, D * st, cd.Ac, cd.As) - (D * cd.apW) * (ec * c2 - es * s2);
         const float wj = wr[J];
         if (mode == 0) {
-            const int col = (int)(floor(x + 0.5) - klo);
+            const int col = (int)(track_bin(cd.F, G) - klo);
             if (col < 0 || col >= n_bins) { bad = true; continue; }
             P += wj * power[J * n_bins + col];
         } else {
+            const double x = cd.F * G;
             const double kf = floor(x);
             const int col = (int)(kf - klo);
             if (col < 0 || col + 1 >= n_bins) { bad = true; continue; }
