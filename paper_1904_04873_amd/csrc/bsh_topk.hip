@@ -33,7 +33,7 @@ struct State {
     uint32_t k_eff;          // min(k, segment length)
     unsigned long long iprefix;    // index digits fixed so far (tie resolution)
     uint32_t iremaining;
-    uint32_t pad;
+    uint32_t tie_all;        // every entry equal to T is taken: no tie resolution needed
 };
 
 struct Seg {
@@ -180,6 +180,7 @@ __global__ void init_kernel(Seg s)
         s.st[g].k_eff = k_eff;
         s.st[g].iprefix = 0ull;
         s.st[g].iremaining = 0u;
+        s.st[g].tie_all = 0u;
     }
     for (int b = threadIdx.x; b < kBins; b += blockDim.x) s.hist[(size_t)g * kBins + b] = 0u;
 }
@@ -205,7 +206,7 @@ __global__ __launch_bounds__(kThreads) void key_hist_kernel(Seg s, int pass)
 }
 
 // Pick the digit holding the remaining-th best entry; entries with larger digits are taken.
-__global__ void key_pick_kernel(Seg s)
+__global__ void key_pick_kernel(Seg s, int last_pass)
 {
     __shared__ uint32_t h[kBins], scan[kBins];
     __shared__ int d;
@@ -218,8 +219,13 @@ __global__ void key_pick_kernel(Seg s)
     if (rem > 0u) {
         pick_digit(h, rem, true, scan, &d, &above);
         if (t == 0) {
-            s.st[g].remaining = rem - above;
+            const uint32_t left = rem - above;
             s.st[g].prefix = (s.st[g].prefix << 8) | (uint32_t)d;
+            // after the last digit h[d] counts the entries equal to T; when all of them are
+            // needed the compaction takes them and the tie resolution has nothing to do
+            const bool all = last_pass && h[d] == left;
+            s.st[g].tie_all = all ? 1u : 0u;
+            s.st[g].remaining = all ? 0u : left;
         }
     }
     s.hist[(size_t)g * kBins + t] = 0u;
@@ -240,9 +246,11 @@ __global__ __launch_bounds__(kThreads) void split_kernel(Seg s)
     if (threadIdx.x == 0) lcount = 0u;
     __syncthreads();
     const uint32_t T = s.st[g].prefix;
+    const bool tie_all = s.st[g].tie_all != 0u;
     const int64_t lo = s.off[g], hi = s.off[g + 1];
     for_each_score(s.score, lo, hi, [&](int64_t e, float sc) {
-        const bool take = score_key(sc) > T;
+        const uint32_t key = score_key(sc);
+        const bool take = key > T || (tie_all && key == T);
         const uint32_t pos = wave_claim(&lcount, take);
         if (take) {
             const int64_t ix = entry_index(s, g, e, lo);
@@ -434,7 +442,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_topk_kernel(Seg s, float*
 {
     __shared__ float sv[kStaged ? kStageLen : 1];
     __shared__ uint32_t h[kBins], scan[kBins];
-    __shared__ uint32_t prefix, remaining, n_sel, passed;
+    __shared__ uint32_t prefix, remaining, n_sel, passed, tie_all;
     __shared__ int digit;
     __shared__ unsigned long long iprefix;
     __shared__ float cs[kSmallK];
@@ -456,6 +464,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_topk_kernel(Seg s, float*
         remaining = k_eff;
         n_sel = 0u;
         iprefix = 0ull;
+        tie_all = 0u;
     }
     if constexpr (kStaged)
         for (int64_t e = t; e < len; e += kSmallThreads) sv[e] = s.score[lo + e];
@@ -476,14 +485,21 @@ __global__ __launch_bounds__(kSmallThreads) void small_topk_kernel(Seg s, float*
         if (t == 0) {
             remaining -= passed;
             prefix = (prefix << 8) | (uint32_t)digit;
+            // h[digit] counts the entries equal to T after the last digit: when all of them
+            // are needed, take them with the rest and skip the tie resolution
+            if (pass == 3 && h[digit] == remaining) {
+                tie_all = 1u;
+                remaining = 0u;
+            }
         }
         __syncthreads();
     }
     const uint32_t T = prefix;
-    // 2. everything strictly better than T
+    // 2. everything better than T (and T itself when all of its entries are taken)
     for (int64_t e = lo + t; e < hi; e += kSmallThreads) {
         const float sc = score_at(e);
-        const bool take = score_key(sc) > T;
+        const uint32_t key = score_key(sc);
+        const bool take = key > T || (tie_all != 0u && key == T);
         const uint32_t pos = wave_claim(&n_sel, take);
         if (take && pos < k_eff) {
             cs[pos] = sc;
@@ -575,7 +591,7 @@ int topk_launch(Seg s, int64_t max_len, float* out_score, int64_t* out_index, hi
     hipLaunchKernelGGL(init_kernel, dim3(s.n_segs), dim3(kBins), 0, st, s);
     for (int pass = 0; pass < 4; ++pass) {
         hipLaunchKernelGGL(key_hist_kernel, grid2, dim3(kThreads), 0, st, s, pass);
-        hipLaunchKernelGGL(key_pick_kernel, dim3(s.n_segs), dim3(kBins), 0, st, s);
+        hipLaunchKernelGGL(key_pick_kernel, dim3(s.n_segs), dim3(kBins), 0, st, s, pass == 3 ? 1 : 0);
     }
     hipLaunchKernelGGL(split_kernel, grid2, dim3(kThreads), 0, st, s);
     hipLaunchKernelGGL(tie_init_kernel, dim3(s.n_segs), dim3(kBins), 0, st, s);
