@@ -4,16 +4,19 @@
 //
 // Per segment:
 // 1. Radix select on the 32-bit order-preserving key of the score: four 8-bit digit passes
-//    (block histograms in LDS, one global histogram per segment, a one-block digit pick) find
-//    the key T of the k-th best score, the number of scores strictly better, and how many
-//    ties at T are still needed.
-// 2. One compaction pass writes every entry with key > T to the segment's output pool.
-// 3. Ties at T are resolved by index with a second radix select over the index bits of the
-//    entries whose key equals T (re-reading the scores instead of buffering the ties, so the
-//    workspace stays O(k) per segment), then a pass appends the chosen ties.
+//    (block histograms in LDS added into one histogram per pass and segment) find the key T of
+//    the k-th best score, the number of scores strictly better, and how many ties at T are
+//    still needed.  Every block of a pass derives the digits chosen so far from the previous
+//    pass's histogram itself (a block scan), so no launch is spent on picking a digit.
+// 2. One compaction pass writes every entry with key > T (and those equal to T when all of
+//    them are needed) to the segment's output pool.
+// 3. Otherwise ties at T are resolved by index with a second radix select over the index bits
+//    of the entries whose key equals T (re-reading the scores instead of buffering the ties,
+//    so the workspace stays O(k) per segment), then a pass appends the chosen ties.
 // 4. The k chosen entries are ordered by rank counting (each entry counts the entries that
 //    precede it), which is exact, deterministic and independent of the arrival order.
-// Everything stays on the stream: no host synchronisation, counts live in the workspace.
+// Short segments run all of this in one block (small_topk_kernel).  Everything stays on the
+// stream: no host synchronisation, counts live in the workspace.
 #include <cstring>
 
 #include "bsh_internal.h"
@@ -26,26 +29,32 @@ constexpr int kThreads = 256;
 constexpr int kBins = 256;
 constexpr int kMaxBlocksPerSeg = 1024;
 
+constexpr int kKeyPasses = 4;
+constexpr int kMaxIdxPasses = 8;
+constexpr int kHists = kKeyPasses + kMaxIdxPasses;
+
 struct State {
-    uint32_t prefix;         // key digits fixed so far (the full key T after four passes)
-    uint32_t remaining;      // entries still to take at the current prefix
-    uint32_t n_sel;          // output-pool fill
     uint32_t k_eff;          // min(k, segment length)
-    unsigned long long iprefix;    // index digits fixed so far (tie resolution)
-    uint32_t iremaining;
+    uint32_t n_sel;          // output-pool fill
     uint32_t tie_all;        // every entry equal to T is taken: no tie resolution needed
+    uint32_t pad;
+    uint32_t prefix[kKeyPasses + 1];      // key digits fixed before pass p; prefix[4] = T
+    uint32_t remaining[kKeyPasses + 1];   // entries still to take before pass p
+    uint32_t iremaining[kMaxIdxPasses + 1];   // ties still to take before index pass p
+    unsigned long long iprefix[kMaxIdxPasses + 1];   // index digits fixed before index pass p
 };
 
 struct Seg {
     const float* score;
     const int64_t* index;    // NULL: implicit index (g << shift) | position
-    const int64_t* off;      // [n_segs + 1] device offsets
+    const int64_t* off;      // [n_segs + 1] device offsets; NULL: one segment [0, n_single)
+    int64_t n_single;
     int32_t n_segs;
     int32_t shift;           // implicit-index segment shift (0: position only)
     int32_t k;
     int32_t idx_bits;        // index bits that can differ inside a segment
     State* st;               // [n_segs]
-    uint32_t* hist;          // [n_segs][kBins]
+    uint32_t* hist;          // [n_segs][kHists][kBins]: key passes, then index passes
     float* sel_score;        // [n_segs][k]
     int64_t* sel_index;      // [n_segs][k]
     uint32_t* rank;          // [n_segs][k]
@@ -56,7 +65,7 @@ __host__ __device__ inline size_t align_up(size_t x) { return (x + 255) & ~(size
 size_t workspace_bytes(int32_t n_segs, int32_t k)
 {
     const size_t ns = (size_t)(n_segs > 0 ? n_segs : 1);
-    return align_up(sizeof(State) * ns) + align_up(sizeof(uint32_t) * kBins * ns) +
+    return align_up(sizeof(State) * ns) + align_up(sizeof(uint32_t) * kHists * kBins * ns) +
            align_up(sizeof(float) * (size_t)k * ns) + align_up(sizeof(int64_t) * (size_t)k * ns) +
            align_up(sizeof(uint32_t) * (size_t)k * ns);
 }
@@ -68,12 +77,28 @@ void carve(void* ws, Seg& s)
     s.st = (State*)p;
     p += align_up(sizeof(State) * ns);
     s.hist = (uint32_t*)p;
-    p += align_up(sizeof(uint32_t) * kBins * ns);
+    p += align_up(sizeof(uint32_t) * kHists * kBins * ns);
     s.sel_score = (float*)p;
     p += align_up(sizeof(float) * (size_t)s.k * ns);
     s.sel_index = (int64_t*)p;
     p += align_up(sizeof(int64_t) * (size_t)s.k * ns);
     s.rank = (uint32_t*)p;
+}
+
+__device__ __forceinline__ void seg_range(const Seg& s, int g, int64_t& lo, int64_t& hi)
+{
+    if (s.off) {
+        lo = s.off[g];
+        hi = s.off[g + 1];
+    } else {
+        lo = 0;
+        hi = s.n_single;
+    }
+}
+
+__device__ __forceinline__ uint32_t* seg_hist(const Seg& s, int g, int h)
+{
+    return s.hist + ((size_t)g * kHists + h) * kBins;
 }
 
 // Order-preserving map float -> uint32 (larger float -> larger key); -0 is folded onto +0.
@@ -168,86 +193,113 @@ __device__ void pick_digit(const uint32_t* h, uint32_t rem, bool from_top, uint3
     __syncthreads();
 }
 
+// State, histograms and ranks of segment blockIdx.y start from zero; grid.x covers the k
+// ranks.
 __global__ void init_kernel(Seg s)
 {
-    const int g = blockIdx.x;
-    const int64_t len = s.off[g + 1] - s.off[g];
-    if (threadIdx.x == 0) {
-        const uint32_t k_eff = (uint32_t)(len < (int64_t)s.k ? len : (int64_t)s.k);
-        s.st[g].prefix = 0u;
-        s.st[g].remaining = k_eff;
-        s.st[g].n_sel = 0u;
-        s.st[g].k_eff = k_eff;
-        s.st[g].iprefix = 0ull;
-        s.st[g].iremaining = 0u;
-        s.st[g].tie_all = 0u;
+    const int g = blockIdx.y;
+    if (blockIdx.x == 0) {
+        int64_t lo, hi;
+        seg_range(s, g, lo, hi);
+        const int64_t len = hi - lo;
+        if (threadIdx.x == 0) {
+            const uint32_t k_eff = (uint32_t)(len < (int64_t)s.k ? len : (int64_t)s.k);
+            s.st[g].k_eff = k_eff;
+            s.st[g].n_sel = 0u;
+            s.st[g].tie_all = 0u;
+            s.st[g].prefix[0] = 0u;
+            s.st[g].remaining[0] = k_eff;
+            s.st[g].iprefix[0] = 0ull;
+            s.st[g].iremaining[0] = 0u;
+        }
+        for (int b = threadIdx.x; b < kHists * kBins; b += blockDim.x) s.hist[(size_t)g * kHists * kBins + b] = 0u;
     }
-    for (int b = threadIdx.x; b < kBins; b += blockDim.x) s.hist[(size_t)g * kBins + b] = 0u;
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < (uint32_t)s.k) s.rank[(size_t)g * s.k + e] = 0u;
+}
+
+// The key digits fixed before pass p (prefix, entries still to take), derived in every block
+// from pass p-1's histogram; block 0 records them.  With `last`, also whether every entry equal
+// to the full key T is needed.
+struct KeyStep {
+    uint32_t prefix, remaining, count_at;
+};
+
+__device__ KeyStep key_step(const Seg& s, int g, int p, uint32_t* scan)
+{
+    __shared__ int d;
+    __shared__ uint32_t before;
+    const uint32_t pre = s.st[g].prefix[p - 1];
+    const uint32_t rem = s.st[g].remaining[p - 1];
+    KeyStep k{pre << 8, 0u, 0u};
+    if (rem == 0u) return k;      // block-uniform
+    const uint32_t* h = seg_hist(s, g, p - 1);
+    pick_digit(h, rem, true, scan, &d, &before);
+    k.prefix = (pre << 8) | (uint32_t)d;
+    k.remaining = rem - before;
+    k.count_at = h[d];
+    return k;
 }
 
 // Histogram of key digit `pass` (0 = most significant byte) over entries matching the prefix.
 __global__ __launch_bounds__(kThreads) void key_hist_kernel(Seg s, int pass)
 {
-    __shared__ uint32_t h[kBins];
+    __shared__ uint32_t h[kBins], scan[kBins];
     const int g = blockIdx.y;
-    if (s.st[g].remaining == 0u) return;
+    uint32_t prefix = 0u, remaining = s.st[g].remaining[0];
+    if (pass > 0) {
+        const KeyStep k = key_step(s, g, pass, scan);
+        prefix = k.prefix;
+        remaining = k.remaining;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            s.st[g].prefix[pass] = prefix;
+            s.st[g].remaining[pass] = remaining;
+        }
+    }
+    if (remaining == 0u) return;
     for (int b = threadIdx.x; b < kBins; b += kThreads) h[b] = 0u;
     __syncthreads();
-    const int64_t lo = s.off[g], hi = s.off[g + 1];
-    const uint32_t prefix = s.st[g].prefix;
+    int64_t lo, hi;
+    seg_range(s, g, lo, hi);
     const int shift = 24 - 8 * pass;
     for_each_score(s.score, lo, hi, [&](int64_t, float sc) {
         const uint32_t key = score_key(sc);
         wave_hist_add(h, pass == 0 || (key >> (shift + 8)) == prefix, (key >> shift) & 0xffu);
     });
     __syncthreads();
+    uint32_t* gh = seg_hist(s, g, pass);
     for (int b = threadIdx.x; b < kBins; b += kThreads)
-        if (h[b]) atomicAdd(&s.hist[(size_t)g * kBins + b], h[b]);
+        if (h[b]) atomicAdd(&gh[b], h[b]);
 }
 
-// Pick the digit holding the remaining-th best entry; entries with larger digits are taken.
-__global__ void key_pick_kernel(Seg s, int last_pass)
-{
-    __shared__ uint32_t h[kBins], scan[kBins];
-    __shared__ int d;
-    __shared__ uint32_t above;
-    const int g = blockIdx.x;
-    const int t = threadIdx.x;   // kBins threads
-    h[t] = s.hist[(size_t)g * kBins + t];
-    const uint32_t rem = s.st[g].remaining;
-    __syncthreads();
-    if (rem > 0u) {
-        pick_digit(h, rem, true, scan, &d, &above);
-        if (t == 0) {
-            const uint32_t left = rem - above;
-            s.st[g].prefix = (s.st[g].prefix << 8) | (uint32_t)d;
-            // after the last digit h[d] counts the entries equal to T; when all of them are
-            // needed the compaction takes them and the tie resolution has nothing to do
-            const bool all = last_pass && h[d] == left;
-            s.st[g].tie_all = all ? 1u : 0u;
-            s.st[g].remaining = all ? 0u : left;
-        }
-    }
-    s.hist[(size_t)g * kBins + t] = 0u;
-}
-
-// Entries with key > T go to the output pool.  Each block gathers its entries in LDS and
-// reserves pool slots with one atomic (a single pool counter hit once per entry serializes at
-// the L2); entries beyond the LDS buffer reserve their slots directly.
+// Entries with key > T go to the output pool (and those equal to T when all of them are
+// needed).  Each block gathers its entries in LDS and reserves pool slots with one atomic (a
+// single pool counter hit once per entry serializes at the L2); entries beyond the LDS buffer
+// reserve their slots directly.
 __global__ __launch_bounds__(kThreads) void split_kernel(Seg s)
 {
     constexpr uint32_t kCap = 1024;
     __shared__ float lsc[kCap];
     __shared__ int64_t lix[kCap];
-    __shared__ uint32_t lcount, gbase;
+    __shared__ uint32_t lcount, gbase, scan[kBins];
     const int g = blockIdx.y;
     const uint32_t k_eff = s.st[g].k_eff;
     if (k_eff == 0u) return;
+    const KeyStep k = key_step(s, g, kKeyPasses, scan);
+    const uint32_t T = k.prefix;
+    // after the last digit count_at is the number of entries equal to T
+    const bool tie_all = k.count_at == k.remaining;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        s.st[g].prefix[kKeyPasses] = T;
+        s.st[g].remaining[kKeyPasses] = tie_all ? 0u : k.remaining;
+        s.st[g].tie_all = tie_all ? 1u : 0u;
+        s.st[g].iprefix[0] = 0ull;
+        s.st[g].iremaining[0] = tie_all ? 0u : k.remaining;
+    }
     if (threadIdx.x == 0) lcount = 0u;
     __syncthreads();
-    const uint32_t T = s.st[g].prefix;
-    const bool tie_all = s.st[g].tie_all != 0u;
-    const int64_t lo = s.off[g], hi = s.off[g + 1];
+    int64_t lo, hi;
+    seg_range(s, g, lo, hi);
     for_each_score(s.score, lo, hi, [&](int64_t e, float sc) {
         const uint32_t key = score_key(sc);
         const bool take = key > T || (tie_all && key == T);
@@ -279,28 +331,51 @@ __global__ __launch_bounds__(kThreads) void split_kernel(Seg s)
     }
 }
 
-__global__ void tie_init_kernel(Seg s)
+// The index digits fixed before tie pass p (smallest indices win: digits are taken from the
+// low end), derived in every block from pass p-1's histogram; block 0 records them.
+struct TieStep {
+    unsigned long long prefix;
+    uint32_t remaining;
+};
+
+__device__ TieStep tie_step(const Seg& s, int g, int p, uint32_t* scan, bool record)
 {
-    const int g = blockIdx.x;
-    if (threadIdx.x == 0) {
-        s.st[g].iprefix = 0ull;
-        s.st[g].iremaining = s.st[g].remaining;
+    __shared__ int d;
+    __shared__ uint32_t below;
+    const unsigned long long pre = s.st[g].iprefix[p - 1];
+    const uint32_t rem = s.st[g].iremaining[p - 1];
+    TieStep t{pre << 8, 0u};
+    if (rem != 0u) {      // block-uniform
+        pick_digit(seg_hist(s, g, kKeyPasses + p - 1), rem, false, scan, &d, &below);
+        t.prefix = (pre << 8) | (unsigned long long)d;
+        t.remaining = rem - below;
     }
-    for (int b = threadIdx.x; b < kBins; b += blockDim.x) s.hist[(size_t)g * kBins + b] = 0u;
+    if (record && blockIdx.x == 0 && threadIdx.x == 0) {
+        s.st[g].iprefix[p] = t.prefix;
+        s.st[g].iremaining[p] = t.remaining;
+    }
+    return t;
 }
 
 // Histogram of index digit `pass` over entries whose key equals T.  The digits cover the
 // low idx_bits of the index (rounded up to bytes); the bits above are equal in a segment.
 __global__ __launch_bounds__(kThreads) void tie_hist_kernel(Seg s, int pass, int n_pass)
 {
-    __shared__ uint32_t h[kBins];
+    __shared__ uint32_t h[kBins], scan[kBins];
     const int g = blockIdx.y;
-    if (s.st[g].iremaining == 0u) return;
+    unsigned long long prefix = 0ull;
+    uint32_t remaining = s.st[g].iremaining[0];
+    if (pass > 0) {
+        const TieStep t = tie_step(s, g, pass, scan, true);
+        prefix = t.prefix;
+        remaining = t.remaining;
+    }
+    if (remaining == 0u) return;
     for (int b = threadIdx.x; b < kBins; b += kThreads) h[b] = 0u;
     __syncthreads();
-    const int64_t lo = s.off[g], hi = s.off[g + 1];
-    const uint32_t T = s.st[g].prefix;
-    const unsigned long long prefix = s.st[g].iprefix;
+    int64_t lo, hi;
+    seg_range(s, g, lo, hi);
+    const uint32_t T = s.st[g].prefix[kKeyPasses];
     const int shift = 8 * (n_pass - 1 - pass);
     for_each_score(s.score, lo, hi, [&](int64_t e, float sc) {
         const bool tie = score_key(sc) == T;
@@ -309,39 +384,22 @@ __global__ __launch_bounds__(kThreads) void tie_hist_kernel(Seg s, int pass, int
         wave_hist_add(h, tie && (pass == 0 || (ix >> (shift + 8)) == prefix), (uint32_t)((ix >> shift) & 0xffull));
     });
     __syncthreads();
+    uint32_t* gh = seg_hist(s, g, kKeyPasses + pass);
     for (int b = threadIdx.x; b < kBins; b += kThreads)
-        if (h[b]) atomicAdd(&s.hist[(size_t)g * kBins + b], h[b]);
-}
-
-// Smallest indices win: take digits from the low end.
-__global__ void tie_pick_kernel(Seg s)
-{
-    __shared__ uint32_t h[kBins], scan[kBins];
-    __shared__ int d;
-    __shared__ uint32_t below;
-    const int g = blockIdx.x;
-    const int t = threadIdx.x;
-    h[t] = s.hist[(size_t)g * kBins + t];
-    const uint32_t rem = s.st[g].iremaining;
-    __syncthreads();
-    if (rem > 0u) {
-        pick_digit(h, rem, false, scan, &d, &below);
-        if (t == 0) {
-            s.st[g].iremaining = rem - below;
-            s.st[g].iprefix = (s.st[g].iprefix << 8) | (unsigned long long)d;
-        }
-    }
-    s.hist[(size_t)g * kBins + t] = 0u;
+        if (h[b]) atomicAdd(&gh[b], h[b]);
 }
 
 __global__ __launch_bounds__(kThreads) void tie_take_kernel(Seg s, int n_pass)
 {
+    __shared__ uint32_t scan[kBins];
     const int g = blockIdx.y;
     const uint32_t k_eff = s.st[g].k_eff;
-    if (k_eff == 0u || s.st[g].remaining == 0u) return;
-    const int64_t lo = s.off[g], hi = s.off[g + 1];
-    const uint32_t T = s.st[g].prefix;
-    const unsigned long long cut = s.st[g].iprefix;    // largest index (low bits) that makes the cut
+    if (k_eff == 0u || s.st[g].remaining[kKeyPasses] == 0u) return;
+    // largest index (low bits) that makes the cut
+    const unsigned long long cut = tie_step(s, g, n_pass, scan, false).prefix;
+    int64_t lo, hi;
+    seg_range(s, g, lo, hi);
+    const uint32_t T = s.st[g].prefix[kKeyPasses];
     const float sc = key_score(T);
     for_each_score(s.score, lo, hi, [&](int64_t e, float v) {
         const bool tie = score_key(v) == T;
@@ -364,14 +422,7 @@ __device__ __forceinline__ bool precedes(float sa, int64_t ia, float sb, int64_t
 }
 
 // rank(e) = number of chosen entries of segment g preceding e, accumulated over slices of
-// the chosen entries (grid.z) so that large k still fills the device.
-__global__ void rank_zero_kernel(Seg s)
-{
-    const int g = blockIdx.y;
-    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < (uint32_t)s.k) s.rank[(size_t)g * s.k + e] = 0u;
-}
-
+// the chosen entries (grid.z) so that large k still fills the device (ranks start at zero).
 __global__ __launch_bounds__(kThreads) void rank_kernel(Seg s, uint32_t slice)
 {
     __shared__ float ts[kThreads];
@@ -401,27 +452,22 @@ __global__ __launch_bounds__(kThreads) void rank_kernel(Seg s, uint32_t slice)
     if (mine && rank) atomicAdd(&s.rank[(size_t)g * s.k + e], rank);
 }
 
-// out[g][rank(e)] = e
+// out[g][rank(e)] = e; the slots past k_eff get (-inf, -1).
 __global__ void scatter_kernel(Seg s, float* __restrict__ out_score, int64_t* __restrict__ out_index)
 {
     const int g = blockIdx.y;
     const uint32_t k_eff = s.st[g].k_eff;
     const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= k_eff) return;
+    if (e >= (uint32_t)s.k) return;
+    if (e >= k_eff) {
+        out_score[(size_t)g * s.k + e] = -__builtin_huge_valf();
+        out_index[(size_t)g * s.k + e] = -1;
+        return;
+    }
     const uint32_t r = s.rank[(size_t)g * s.k + e];
     if (r < k_eff) {
         out_score[(size_t)g * s.k + r] = s.sel_score[(size_t)g * s.k + e];
         out_index[(size_t)g * s.k + r] = s.sel_index[(size_t)g * s.k + e];
-    }
-}
-
-__global__ void fill_tail_kernel(Seg s, float* out_score, int64_t* out_index)
-{
-    const int g = blockIdx.y;
-    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < (uint32_t)s.k && e >= s.st[g].k_eff) {
-        out_score[(size_t)g * s.k + e] = -__builtin_huge_valf();
-        out_index[(size_t)g * s.k + e] = -1;
     }
 }
 
@@ -449,7 +495,8 @@ __global__ __launch_bounds__(kSmallThreads) void small_topk_kernel(Seg s, float*
     __shared__ int64_t ci[kSmallK];
     const int g = blockIdx.x;
     const int t = threadIdx.x;
-    const int64_t lo = s.off[g], hi = s.off[g + 1];
+    int64_t lo, hi;
+    seg_range(s, g, lo, hi);
     const int64_t len = hi - lo;
     const uint32_t k_eff = (uint32_t)(len < (int64_t)s.k ? len : (int64_t)s.k);
     float* os = out_score + (size_t)g * s.k;
@@ -557,12 +604,6 @@ __global__ __launch_bounds__(kSmallThreads) void small_topk_kernel(Seg s, float*
     }
 }
 
-__global__ void set_offsets_kernel(int64_t* off, int64_t n)
-{
-    off[0] = 0;
-    off[1] = n;
-}
-
 int topk_launch(Seg s, int64_t max_len, float* out_score, int64_t* out_index, hipStream_t st)
 {
     int bps = (int)((max_len + kThreads - 1) / kThreads);
@@ -588,27 +629,20 @@ int topk_launch(Seg s, int64_t max_len, float* out_score, int64_t* out_index, hi
                                out_score, out_index, n_pass);
         return check_launch("bsh_topk");
     }
-    hipLaunchKernelGGL(init_kernel, dim3(s.n_segs), dim3(kBins), 0, st, s);
-    for (int pass = 0; pass < 4; ++pass) {
+    // 8 + n_pass launches: the digit picks run at the head of the next pass's kernel
+    const uint32_t kb = (uint32_t)((s.k + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(init_kernel, dim3(kb, s.n_segs), dim3(kThreads), 0, st, s);
+    for (int pass = 0; pass < kKeyPasses; ++pass)
         hipLaunchKernelGGL(key_hist_kernel, grid2, dim3(kThreads), 0, st, s, pass);
-        hipLaunchKernelGGL(key_pick_kernel, dim3(s.n_segs), dim3(kBins), 0, st, s, pass == 3 ? 1 : 0);
-    }
     hipLaunchKernelGGL(split_kernel, grid2, dim3(kThreads), 0, st, s);
-    hipLaunchKernelGGL(tie_init_kernel, dim3(s.n_segs), dim3(kBins), 0, st, s);
-    for (int pass = 0; pass < n_pass; ++pass) {
+    for (int pass = 0; pass < n_pass; ++pass)
         hipLaunchKernelGGL(tie_hist_kernel, grid2, dim3(kThreads), 0, st, s, pass, n_pass);
-        hipLaunchKernelGGL(tie_pick_kernel, dim3(s.n_segs), dim3(kBins), 0, st, s);
-    }
     hipLaunchKernelGGL(tie_take_kernel, grid2, dim3(kThreads), 0, st, s, n_pass);
     // rank counting: k x k comparisons spread over (k/256) x slices blocks
-    const uint32_t kb = (uint32_t)((s.k + kThreads - 1) / kThreads);
-    uint32_t n_slices = kb < 64 ? kb : 64;
+    const uint32_t n_slices = kb < 64 ? kb : 64;
     const uint32_t slice = (uint32_t)((s.k + n_slices - 1) / n_slices);
-    hipLaunchKernelGGL(rank_zero_kernel, dim3(kb, s.n_segs), dim3(kThreads), 0, st, s);
     hipLaunchKernelGGL(rank_kernel, dim3(kb, s.n_segs, n_slices), dim3(kThreads), 0, st, s, slice);
     hipLaunchKernelGGL(scatter_kernel, dim3(kb, s.n_segs), dim3(kThreads), 0, st, s, out_score, out_index);
-    hipLaunchKernelGGL(fill_tail_kernel, dim3((s.k + 255) / 256, s.n_segs), dim3(256), 0, st, s,
-                       out_score, out_index);
     return check_launch("bsh_topk");
 }
 
@@ -619,7 +653,7 @@ namespace bsh {
 size_t topk_workspace_bytes(int32_t n_segs, int32_t k) { return workspace_bytes(n_segs, k); }
 
 // Segmented top-k for library-internal callers (the batched plan); offsets on the device,
-// the longest segment given by the host.
+// the longest segment given by the host.  NULL offsets: one segment [0, max_len).
 int topk_segmented(const float* score, const int64_t* index, const int64_t* offsets, int32_t n_segs,
                    int64_t max_len, int32_t shift, int32_t k, float* out_score, int64_t* out_index,
                    void* ws, size_t ws_bytes, hipStream_t stream)
@@ -630,11 +664,13 @@ int topk_segmented(const float* score, const int64_t* index, const int64_t* offs
         return BSH_ENOMEM;
     }
     if (max_len >= (int64_t)0xffffffff) return fail_inval("segments must be shorter than 2^32 - 1");
+    if (!offsets && n_segs != 1) return fail_inval("NULL offsets need exactly one segment");
     Seg s;
     std::memset(&s, 0, sizeof(s));
     s.score = score;
     s.index = index;
     s.off = offsets;
+    s.n_single = max_len;
     s.n_segs = n_segs;
     s.shift = shift;
     s.k = k;
@@ -647,8 +683,7 @@ int topk_segmented(const float* score, const int64_t* index, const int64_t* offs
 extern "C" size_t bsh_topk_workspace(int64_t n, int32_t k)
 {
     if (n < 0 || k < 0) return 0;
-    // one segment plus its two offsets
-    return workspace_bytes(1, k > 0 ? k : 1) + 256;
+    return workspace_bytes(1, k > 0 ? k : 1);
 }
 
 extern "C" int bsh_topk(const float* score, const int64_t* index, int64_t n, int32_t k,
@@ -667,14 +702,8 @@ extern "C" int bsh_topk(const float* score, const int64_t* index, int64_t n, int
         set_error("workspace %zu < %zu bytes", ws_bytes, need);
         return BSH_ENOMEM;
     }
-    hipStream_t s = (hipStream_t)stream;
-    // the two offsets {0, n} live in the first 256 bytes of the workspace
-    int64_t* off = (int64_t*)ws;
-    hipLaunchKernelGGL(set_offsets_kernel, dim3(1), dim3(1), 0, s, off, n);
-    int rc = check_launch("bsh_topk offsets");
-    if (rc) return rc;
-    return bsh::topk_segmented(score, index, off, 1, n, 0, k, out_score, out_index,
-                               (char*)ws + 256, ws_bytes - 256, s);
+    return bsh::topk_segmented(score, index, nullptr, 1, n, 0, k, out_score, out_index, ws, ws_bytes,
+                               (hipStream_t)stream);
 }
 
 extern "C" size_t bsh_topk_segmented_workspace(int32_t n_segs, int32_t k)
