@@ -29,14 +29,12 @@ sys.path.insert(0, ROOT)
 METRIC = "Hough templates·segments/s on 1 GPU, batched vs plain, at oracle-exact top-k"
 # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: 32-bit VALU lane-operations per second
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
-# VALU lane-operations per template x segment on the fast path of the subset-sum table count
-# (counted in its gfx950 ISA), per group of 4 segments x 90 f0 bins: 129 for the four tracks'
-# bins and 96-bit masks, 60 for the bit transpose of the four masks, and the lookups: with
-# 16-entry tables (chunks over 128 segments) 90 x (nibble, address, add), 335 with the
-# transpose, so (129 + 335) / 360 = 1.29; with 256-entry pair tables (chunks of at most 128)
-# 46 x (byte, address) + 90 adds, 247 with the transpose, so (129 + 247) / 360 = 1.04.
-TABLE_OPS_PER_TS = {"pair": 1.04, "nibble": 1.29}
-PAIR_CHUNK = 128
+# VALU lane-operations per template x segment on the fast path of the subset-sum table count:
+# the VALU instructions of the segment-group loop in its gfx950 assembly along the path with no
+# f0-shift step and no flush (paper_1904_04873_amd/fastpath_ops.py counts them: 676 per group
+# of 8 segments at the 128- and 256-segment chunks), divided by the group's 8 x 90 template x
+# segments.
+TABLE_OPS_PER_TS = 676 / 720
 # the same figure for plain select-and-add: extract the peak bit, select the weight, add
 SELECT_OPS_PER_TS = 3
 # HBM bytes per count launch, measured with rocprofv3 counters for one kernel source and tile
@@ -199,8 +197,7 @@ def main():
     st.raise_if_set("count kernel")
     count_ms = c0.elapsed_time(c1) / n_count
     value = ts_per_step / (ms_step / 1e3)
-    table = "pair" if chunk <= PAIR_CHUNK else "nibble"
-    ops_per_ts = TABLE_OPS_PER_TS[table]
+    ops_per_ts = TABLE_OPS_PER_TS
     achieved = ops_per_ts * ts_per_step / (count_ms / 1e3)
     achieved_select = SELECT_OPS_PER_TS * ts_per_step / (count_ms / 1e3)
     print(f"[bench] {ms_step:.3f} ms/step, count kernel {count_ms:.3f} ms", file=sys.stderr, flush=True)
@@ -253,7 +250,7 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": f"hough_count_kernel<2, {chunk}> (subset-sum {table} tables)",
+            "kernel": f"hough_count_kernel<2, {chunk}> (subset-sum tables of 8 segments)",
             "achieved": achieved / 1e12,
             "peak": VALU_PEAK_OPS / 1e12,
             "unit": "TOP/s",

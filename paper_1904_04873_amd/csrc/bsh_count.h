@@ -56,12 +56,11 @@ struct WorkUnit {
     int32_t tile;       // tile inside the period group
 };
 
-constexpr int kGroup = 4;            // segments per subset-sum table (table variant)
-constexpr int kFlushGroups = 128;    // groups per register partial sum (table variant)
-
-// Chunks of at most kPairChunk segments also hold, per group, the 256-entry table of pairs
-// (T[b & 15], T[b >> 4]) so that one 8-byte read serves two f0 bins (64 KB at 128 segments).
-constexpr int kPairChunk = 128;
+// Table variant: the 16-entry subset-sum tables of groups of four segments are joined in pairs
+// into 256-entry tables of eight segments (1 KB each), which the count reads.
+constexpr int kGroup = 4;
+constexpr int kGroup8 = 2 * kGroup;
+constexpr int kFlushGroups = 64;     // eight-segment groups per register partial sum
 
 // Per staged segment: D cos(W t), D sin(W t) and the Doppler factor D of the tile's pixel.
 template <int kChunk>
@@ -69,7 +68,7 @@ struct TileSmemLut {
     double DC[kChunk];
     double DS[kChunk];
     double D[kChunk];
-    float2 T2[kChunk <= kPairChunk ? (kChunk / kGroup) * 256 : 1];
+    float T8[(kChunk / kGroup8) * 256];
     float T[(kChunk / kGroup) * 16];
     uint32_t row[kChunk * (BSH_MAX_WORDS + kRowPad)];
 };

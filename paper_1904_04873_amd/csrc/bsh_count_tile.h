@@ -14,27 +14,21 @@
 // For |G - 1| < 1/(2 n_f0) the offsets r_i = k_i - (k0 + i) form a monotone step with at
 // most one step (the canonical rounding is monotone in i and the exact offsets drift by
 // (n_f0-1)|G-1| < 1 bin).  So two evaluations (i = 0 and the last) give r_0 and r_last;
-// when they differ, a guess of the step's position checked by exact evaluations (and a
-// bisection when the guess is off) finds the first i with r_i = r_last.  The band's n_f0
+// when they differ, a single-precision guess of the step's position (taken as it is when its
+// error bound cannot move it across an integer, else checked by exact evaluations and a
+// bisection) gives the first i with r_i = r_last.  The band's n_f0
 // peak bits are then one funnel-shifted 96-bit window of the row, with the part above the
 // step taken one bit further (or nearer).  This is the exact counterpart of the
 // look-up-table reuse of one Doppler modulation over neighbouring frequencies (Sec. IV.B):
 // every template still reads the bin of its own exact track.
 //
 // Accumulation: either select-and-add (each bit selects its weight; optional uint32 counts)
-// or subset-sum tables over groups of four segments (see count_tile_lut).
+// or subset-sum tables over groups of segments (see count_tile_lut).
 #pragma once
 
 #include "bsh_count.h"
 
 namespace bsh {
-
-__device__ __forceinline__ uint32_t upper_mask(int t)
-{
-    // bits b with b >= t set
-    return t <= 0 ? 0xffffffffu : (t >= 32 ? 0u : (0xffffffffu << t));
-}
-
 
 // One (binary template, segment) track across the band: G = D (1 - a_p W cos phi) and the
 // canonical bins of the band's lowest and highest f0.
@@ -99,20 +93,29 @@ __device__ __forceinline__ void band_step(const BandTrack& t, double F0, int las
     const float den = (float)((double)delta * (G - 1.0));
     const float q = fminf(fmaxf((float)num * __builtin_amdgcn_rcpf(den), 0.f), (float)last);
     const int g = min(max((int)q + 1, 1), last);
-    int lo, hi;              // r_lo = r0, r_hi != r0
-    if (g < last && resid(g) == r0) {
-        lo = g;
-        hi = last;
-    } else if (g == 1 || resid(g - 1) == r0) {
-        lo = g - 1;
-        hi = g;
-    } else {
-        lo = 0;
-        hi = g - 1;
-    }
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (resid(mid) == r0) lo = mid; else hi = mid;
+    // The step sits at the first index past i* = num / (delta (G - 1)).  q carries a relative
+    // error below 4e-7 (two conversions, the reciprocal, the product), i.e. below 4e-5 for
+    // i* < 96, and the canonical evaluations place the step within 3e-11 / |G - 1| < 3e-5 of
+    // i* when |G - 1| >= 1e-6.  A guess further than 1e-3 from an integer inside (0, last)
+    // is therefore the step itself; only the rest is checked with canonical evaluations.
+    const float fq = q - (float)(int)q;
+    int hi = g;
+    if (!((fq > 1e-3f) & (fq < 1.f - 1e-3f) & (q < (float)last) & (fabsf(den) >= 1e-6f))) {
+        int lo;              // r_lo = r0, r_hi != r0
+        if (g < last && resid(g) == r0) {
+            lo = g;
+            hi = last;
+        } else if (g == 1 || resid(g - 1) == r0) {
+            lo = g - 1;
+            hi = g;
+        } else {
+            lo = 0;
+            hi = g - 1;
+        }
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (resid(mid) == r0) lo = mid; else hi = mid;
+        }
     }
     uint32_t n0, n1, n2;
     if (delta > 0) {
@@ -124,7 +127,11 @@ __device__ __forceinline__ void band_step(const BandTrack& t, double F0, int las
         n1 = __builtin_amdgcn_alignbit(m1, m0, 31);
         n2 = __builtin_amdgcn_alignbit(m2, m1, 31);
     }
-    const uint32_t s0 = upper_mask(hi), s1 = upper_mask(hi - 32), s2 = upper_mask(hi - 64);
+    // bits hi.. of the 96-bit mask (1 <= hi < 96): one shift, placed by word
+    const uint32_t sh = 0xffffffffu << (hi & 31);
+    const uint32_t s0 = hi < 32 ? sh : 0u;
+    const uint32_t s1 = hi < 32 ? 0xffffffffu : (hi < 64 ? sh : 0u);
+    const uint32_t s2 = hi < 64 ? 0xffffffffu : sh;
     m0 = (n0 & s0) | (m0 & ~s0);
     m1 = (n1 & s1) | (m1 & ~s1);
     m2 = (n2 & s2) | (m2 & ~s2);
@@ -244,25 +251,22 @@ __device__ __forceinline__ void count_tile(const ItemDesc& d, int s, int ip, int
 }
 
 
-// Table variant of the weighted count.  Segments are taken in groups of four; a 16-entry
-// table per group holds every subset sum of the group's four weights.  For each f0 bin the
-// four peak bits of the group form a 4-bit index, so one table read and one add replace four
-// select-and-add steps.  The indices of all 90 bins come from the four 96-bit masks by a bit
-// interleave: word A[w][r] holds, in nibble n, the four segments' bits of bin 32w + 4n + r.
-// A 16-entry table occupies 16 consecutive LDS banks, so any pattern of reads is free of
-// bank conflicts.  With chunks of at most kPairChunk segments the group also gets a 256-entry
-// table of value pairs indexed by a whole byte of A[w][r] (two nibbles, two bins), which halves
-// the table reads and their address arithmetic; the values, and so the sums, are the same
-// floats in the same order.  The 90 register partial sums (at most kFlushGroups groups each) are folded
-// into the lane's own slots of the output map, which keeps the register footprint small
-// enough for two waves per SIMD; the error of the two-level sum stays below
-// (kFlushGroups + n_seg / (4 kFlushGroups)) FP32 ulps of the total.
+// Table variant of the weighted count.  Segments are taken in groups of eight; a 256-entry
+// table per group holds every subset sum of the group's eight weights, so that for each f0
+// bin the eight peak bits of the group form a byte index and one table read and one add
+// replace eight select-and-add steps.  The table is built from the 16-entry subset-sum tables
+// of the group's two halves, T8[b] = T_first[b & 15] + T_second[b >> 4].  The byte indices of
+// all 90 bins come from the eight 96-bit masks by a bit interleave of each half, word A[w][r]
+// holding in nibble n the half's four bits of bin 32w + 4n + r, and a merge of the two halves'
+// nibbles into bytes.  The 90 register partial sums (at most kFlushGroups groups each) are
+// folded into the lane's own slots of the output map, which keeps the register footprint
+// small enough for two waves per SIMD; the error of the two-level sum stays below
+// (kFlushGroups + 4 + n_seg / (8 kFlushGroups)) FP32 ulps of the total.
 template <int kChunk>
 __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip, int64_t tile,
                                                TileSmemLut<kChunk>& sm)
 {
-    static_assert(kChunk % kGroup == 0, "chunks hold whole groups");
-    constexpr bool kPair = kChunk <= kPairChunk;
+    static_assert(kChunk % kGroup8 == 0, "chunks hold whole groups");
     const int tid = threadIdx.x;
     const int lanes = blockDim.x;
     const int64_t q = tile * lanes + tid;
@@ -312,7 +316,8 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
 
     for (int64_t j0 = 0; j0 < d.n_seg; j0 += kChunk) {
         const int nj = (int)min((int64_t)kChunk, d.n_seg - j0);
-        const int ng = (nj + kGroup - 1) / kGroup;
+        const int ng8 = (nj + kGroup8 - 1) / kGroup8;
+        const int ng = 2 * ng8;
         __syncthreads();
         // slots past the chunk's last segment (up to a whole group) repeat its tables with an
         // empty row and zero weight, so that every group holds four in-range segments
@@ -348,17 +353,17 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
                 T[m] = t;
             }
         }
-        if constexpr (kPair) {
-            __syncthreads();
-            for (int e = tid; e < ng * 256; e += lanes) {
-                const int g = e >> 8, m = e & 255;
-                sm.T2[e] = make_float2(sm.T[g * 16 + (m & 15)], sm.T[g * 16 + (m >> 4)]);
-            }
+        __syncthreads();
+        for (int e = tid; e < ng8 * 256; e += lanes) {
+            const int g = e >> 8, m = e & 255;
+            sm.T8[e] = sm.T[(2 * g) * 16 + (m & 15)] + sm.T[(2 * g + 1) * 16 + (m >> 4)];
         }
         __syncthreads();
         if (!active) continue;
 
-        for (int g = 0; g < ng; ++g) {
+        // A[w][r] of the four segments of group g: bit (4n + u) holds bit (4n + r) of segment
+        // u's 96-bit band mask word w
+        auto group_bits = [&](int g, uint32_t (&A)[3][4]) {
             // the four tracks and windows without branches (independent chains the scheduler
             // can interleave), then the rare f0-shift steps
             uint32_t mk[kGroup][3];
@@ -375,10 +380,8 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
 #pragma unroll
             for (int u = 0; u < kGroup; ++u)
                 if (tr[u].ok && tr[u].delta != 0) band_step(tr[u], F0, last, mk[u][0], mk[u][1], mk[u][2]);
-            // A[w][r]: bit (4n + u) <- bit (4n + r) of mask u's word w, i.e. every nibble column
-            // of the 4 x 32 bit matrix (mk[0..3][w]) transposed: swap the off-diagonal 2 x 2
-            // blocks, then the off-diagonal bits of each 2 x 2 block.
-            uint32_t A[3][4];
+            // every nibble column of the 4 x 32 bit matrix (mk[0..3][w]) transposed: swap the
+            // off-diagonal 2 x 2 blocks, then the off-diagonal bits of each 2 x 2 block
 #pragma unroll
             for (int w = 0; w < 3; ++w) {
                 uint32_t x0 = mk[0][w], x1 = mk[1][w], x2 = mk[2][w], x3 = mk[3][w];
@@ -392,48 +395,35 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
                 A[w][2] = x2;
                 A[w][3] = x3;
             }
-            // Look the bins up word by word: the table reads of word k are issued before the
-            // adds of word k-1, so one word's LDS latency overlaps the next word's reads.
-            if constexpr (kPair) {
-                // byte m of A[w][r] holds the nibbles of bins 32w + 8m + r and 32w + 8m + 4 + r
-                const float2* T2 = sm.T2 + g * 256;
-                float2 v[2][4];
+        };
+
+        for (int g8 = 0; g8 < ng8; ++g8) {
+            uint32_t L[3][4], H[3][4];
+            group_bits(2 * g8, L);
+            group_bits(2 * g8 + 1, H);
+            // byte j of b0 (b1) indexes the eight segments' bits of bin 32w + 8j + r
+            // (32w + 8j + 4 + r): low nibble from the first four segments, high from the rest
+            const float* T8 = sm.T8 + g8 * 256;
+            float v[2][8];
 #pragma unroll
-                for (int k = 0; k <= 12; ++k) {
-                    if (k < 12) {
-                        const int w = k >> 2, r = k & 3;
+            for (int k = 0; k <= 12; ++k) {
+                if (k < 12) {
+                    const int w = k >> 2, r = k & 3;
+                    const uint32_t b0 = (L[w][r] & 0x0f0f0f0fu) | ((H[w][r] << 4) & 0xf0f0f0f0u);
+                    const uint32_t b1 = ((L[w][r] >> 4) & 0x0f0f0f0fu) | (H[w][r] & 0xf0f0f0f0u);
 #pragma unroll
-                        for (int m = 0; m < 4; ++m)
-                            if (32 * w + 8 * m + r < kNF) v[k & 1][m] = T2[(A[w][r] >> (8 * m)) & 255u];
-                    }
-                    if (k > 0) {
-                        const int w = (k - 1) >> 2, r = (k - 1) & 3;
-#pragma unroll
-                        for (int m = 0; m < 4; ++m) {
-                            const int i = 32 * w + 8 * m + r;
-                            if (i < kNF) acc[i] += v[(k - 1) & 1][m].x;
-                            if (i + 4 < kNF) acc[i + 4] += v[(k - 1) & 1][m].y;
-                        }
+                    for (int j = 0; j < 4; ++j) {
+                        if (32 * w + 8 * j + r < kNF) v[k & 1][2 * j] = T8[(b0 >> (8 * j)) & 255u];
+                        if (32 * w + 8 * j + 4 + r < kNF) v[k & 1][2 * j + 1] = T8[(b1 >> (8 * j)) & 255u];
                     }
                 }
-            } else {
-                const float* T = sm.T + g * 16;
-                float v[2][8];
+                if (k > 0) {
+                    const int w = (k - 1) >> 2, r = (k - 1) & 3;
 #pragma unroll
-                for (int k = 0; k <= 12; ++k) {
-                    if (k < 12) {
-                        const int w = k >> 2, r = k & 3;
-#pragma unroll
-                        for (int n = 0; n < 8; ++n)
-                            if (32 * w + 4 * n + r < kNF) v[k & 1][n] = T[(A[w][r] >> (4 * n)) & 15u];
-                    }
-                    if (k > 0) {
-                        const int w = (k - 1) >> 2, r = (k - 1) & 3;
-#pragma unroll
-                        for (int n = 0; n < 8; ++n) {
-                            const int i = 32 * w + 4 * n + r;
-                            if (i < kNF) acc[i] += v[(k - 1) & 1][n];
-                        }
+                    for (int j = 0; j < 4; ++j) {
+                        const int i = 32 * w + 8 * j + r;
+                        if (i < kNF) acc[i] += v[(k - 1) & 1][2 * j];
+                        if (i + 4 < kNF) acc[i + 4] += v[(k - 1) & 1][2 * j + 1];
                     }
                 }
             }

@@ -1,0 +1,101 @@
+"""VALU instructions per template x segment on the fast path of the stage-1 table count, counted
+in its gfx950 assembly.
+
+The count kernel is compiled to assembly with the library's own flags; in the kernel of the
+given chunk size the loop over segment groups is walked along the path that every group takes
+when no lane of the wave meets an f0-shift step and no partial-sum flush is due (every
+exec-mask skip taken).  Each VALU instruction on that path is one 64-lane wave instruction, so
+its count divided by (segments per group x 90 f0 bins) is the lane-operation cost of one
+template x segment.  This is the floor bench.py prices the count kernel's roofline with.
+
+    python paper_1904_04873_amd/fastpath_ops.py [chunk ...]
+"""
+from __future__ import annotations
+
+import os
+import re
+import subprocess
+import sys
+import tempfile
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+import build  # noqa: E402
+
+N_F0 = 90
+SEGMENTS_PER_GROUP = 8
+
+
+def assembly() -> str:
+    src = "bsh_count.hip"
+    with tempfile.TemporaryDirectory() as tmp:
+        out = os.path.join(tmp, "count.s")
+        cmd = ([build.hipcc()] + build.FLAGS + build.SOURCE_FLAGS.get(src, []) +
+               ["--cuda-device-only", "-S", "-o", out, os.path.join(build.CSRC, src)])
+        subprocess.run(cmd, check=True, capture_output=True)
+        with open(out) as f:
+            return f.read()
+
+
+def kernel_lines(asm: str, chunk: int) -> list[str]:
+    sym = f"_ZN3bsh18hough_count_kernelILi2ELi{chunk}EEEvNS_11PlainLaunchE:"
+    lines = asm.splitlines()
+    start = next(i for i, l in enumerate(lines) if l.startswith(sym))
+    end = next(i for i in range(start, len(lines)) if lines[i].startswith(".Lfunc_end"))
+    return lines[start:end]
+
+
+def walk(lines: list[str], head: int) -> dict[str, int]:
+    labels = {}
+    for i, l in enumerate(lines):
+        m = re.match(r"^(\.LBB\d+_\d+):", l)
+        if m:
+            labels[m.group(1)] = i
+    counts: dict[str, int] = {}
+    i = head + 1
+    for _ in range(100000):
+        if i >= len(lines):
+            break
+        l = lines[i].strip()
+        if not l or l.startswith(";") or l.startswith("."):
+            i += 1
+            continue
+        ins = l.split()[0]
+        counts[ins] = counts.get(ins, 0) + 1
+        if ins == "s_cbranch_execz":
+            i = labels[l.split()[1]]
+            continue
+        if ins == "s_branch" or (ins.startswith("s_cbranch") and ins != "s_cbranch_execnz"):
+            tgt = labels[l.split()[1]]
+            if tgt == head:
+                break
+            if ins == "s_branch":
+                i = tgt
+                continue
+        i += 1
+    return counts
+
+
+def fast_path(chunk: int, asm: str | None = None) -> tuple[int, int]:
+    """(VALU instructions per group on the fast path, segments per group)."""
+    lines = kernel_lines(asm or assembly(), chunk)
+    best = None
+    for i, l in enumerate(lines):
+        if re.match(r"^\.LBB\d+_\d+:", l) and i + 1 < len(lines) and "Loop Header: Depth=2" in lines[i + 1]:
+            c = walk(lines, i)
+            adds = c.get("v_add_f32_e32", 0) + c.get("v_add_f32_e64", 0)
+            valu = sum(n for k, n in c.items() if k.startswith("v_"))
+            if best is None or adds > best[0]:
+                best = (adds, valu)
+    if best is None:
+        raise RuntimeError("segment-group loop not found")
+    return best[1], SEGMENTS_PER_GROUP
+
+
+if __name__ == "__main__":
+    chunks = [int(c) for c in sys.argv[1:]] or [128, 256, 512]
+    asm = assembly()
+    for c in chunks:
+        valu, seg = fast_path(c, asm)
+        print(f"chunk {c}: {valu} VALU per group of {seg} segments x {N_F0} bins = "
+              f"{valu / (seg * N_F0):.3f} per template x segment")
