@@ -33,12 +33,8 @@ FLAGS = [
     "-I", os.path.join(ROOT, "include"),
 ]
 
-# Per-source additions.  The stage-1 count's inner loop interleaves four FP64 track chains with
-# LDS table reads; LLVM's iterative ILP scheduler orders it about 5 % faster than the default
-# (same registers per lane class, same occupancy, bitwise identical results).
-SOURCE_FLAGS = {
-    "bsh_count.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
-}
+# Per-source additions (none at present; kept for flags that suit one kernel only).
+SOURCE_FLAGS: dict[str, list[str]] = {}
 
 
 def hipcc() -> str:

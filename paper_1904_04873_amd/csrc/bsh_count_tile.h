@@ -77,48 +77,58 @@ __device__ __forceinline__ void band_window(const uint32_t* row, const BandTrack
     m2 = __builtin_amdgcn_alignbit(w3, w2, sh) & keep;
 }
 
+// The first f0 index whose residual differs from r0, by canonical evaluations: the guess
+// g = floor(q) + 1 (clamped to 1 .. last) is checked at g and g - 1, and a bisection runs when
+// it is off.
+__device__ __forceinline__ int step_exact(double G, int kf, double F0, int last, float q)
+{
+    const int r0 = kf - (int)F0;
+    auto resid = [&](int i) { return (int)fma(F0 + (double)i, G, 0.5) - ((int)F0 + i); };
+    const float qc = fminf(fmaxf(q, 0.f), (float)last);
+    const int g = min(max((int)qc + 1, 1), last);
+    int lo, hi;              // r_lo = r0, r_hi != r0
+    if (g < last && resid(g) == r0) {
+        lo = g;
+        hi = last;
+    } else if (g == 1 || resid(g - 1) == r0) {
+        lo = g - 1;
+        hi = g;
+    } else {
+        lo = 0;
+        hi = g - 1;
+    }
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (resid(mid) == r0) lo = mid; else hi = mid;
+    }
+    return hi;
+}
+
 // Where the band has an f0-shift step (t.ok and t.delta != 0), take the bins above it one bit
 // further (delta = +1) or nearer (delta = -1).
 __device__ __forceinline__ void band_step(const BandTrack& t, double F0, int last, uint32_t& m0, uint32_t& m1,
                                           uint32_t& m2)
 {
-    const double G = t.G, y0 = t.y0;
-    const int kf = t.kf, delta = t.delta;
-    const int r0 = kf - (int)F0;
-    // The residual r_i = k_i - (k0 + i) steps once, where y0 + i (G - 1) crosses an integer.
-    // A single-precision guess of that offset is checked with exact evaluations; the
-    // bisection below only runs when the guess is off.
-    auto resid = [&](int i) { return (int)fma(F0 + (double)i, G, 0.5) - ((int)F0 + i); };
-    const double num = delta > 0 ? (double)(kf + 1) - y0 : y0 - (double)kf;
-    const float den = (float)((double)delta * (G - 1.0));
-    const float q = fminf(fmaxf((float)num * __builtin_amdgcn_rcpf(den), 0.f), (float)last);
-    const int g = min(max((int)q + 1, 1), last);
-    // The step sits at the first index past i* = num / (delta (G - 1)).  q carries a relative
-    // error below 4e-7 (two conversions, the reciprocal, the product), i.e. below 4e-5 for
-    // i* < 96, and the canonical evaluations place the step within 3e-11 / |G - 1| < 3e-5 of
-    // i* when |G - 1| >= 1e-6.  A guess further than 1e-3 from an integer inside (0, last)
-    // is therefore the step itself; only the rest is checked with canonical evaluations.
-    const float fq = q - (float)(int)q;
-    int hi = g;
-    if (!((fq > 1e-3f) & (fq < 1.f - 1e-3f) & (q < (float)last) & (fabsf(den) >= 1e-6f))) {
-        int lo;              // r_lo = r0, r_hi != r0
-        if (g < last && resid(g) == r0) {
-            lo = g;
-            hi = last;
-        } else if (g == 1 || resid(g - 1) == r0) {
-            lo = g - 1;
-            hi = g;
-        } else {
-            lo = 0;
-            hi = g - 1;
-        }
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (resid(mid) == r0) lo = mid; else hi = mid;
-        }
-    }
+    // The residual r_i = k_i - (k0 + i) steps once, at the first index past the crossing
+    // i* = num / den of y0 + i (G - 1) with the next integer above (delta = +1) or below
+    // (delta = -1): num = 1 - frac(y0) or frac(y0) (exact), den = +-(G - 1).  The single-
+    // precision q = num / den carries a relative error below 4e-7 (two conversions, the
+    // reciprocal, the product), i.e. below 4e-5 for i* < 96, and the canonical evaluations
+    // place the step within 3e-11 / |G - 1| < 3e-5 of i* when den >= 1e-6.  A q further than
+    // 1e-3 from an integer and below last is therefore floor(i*) and the step sits at
+    // floor(q) + 1; the rest (a few in a thousand, or a den of the wrong sign) is decided by
+    // canonical evaluations.
+    const bool up = t.delta > 0;
+    const double f = t.y0 - (double)t.kf;
+    const float num = (float)(up ? 1.0 - f : f);
+    const float gm1 = (float)(t.G - 1.0);
+    const float den = up ? gm1 : -gm1;
+    const float q = num * __builtin_amdgcn_rcpf(den);
+    const bool sure = (fabsf(__builtin_amdgcn_fractf(q) - 0.5f) < 0.499f) & (q < (float)last) & (den >= 1e-6f);
+    int hi = sure ? (int)q + 1 : 0;
+    if (!sure) hi = step_exact(t.G, t.kf, F0, last, q);
     uint32_t n0, n1, n2;
-    if (delta > 0) {
+    if (up) {
         n0 = __builtin_amdgcn_alignbit(m1, m0, 1);
         n1 = __builtin_amdgcn_alignbit(m2, m1, 1);
         n2 = m2 >> 1;
