@@ -304,7 +304,7 @@ __global__ void track_bins_kernel(const double* __restrict__ t_mid, const double
     }
     const Cand cd = load_cand(cand + 4 * c);
     double st, ct;
-    sincos(cd.W * t_mid[J], &st, &ct);
+    track_sincos(cd.W * t_mid[J], st, ct);
     const double D = doppler_factor(v + 3 * J, sky[3 * s], sky[3 * s + 1], sky[3 * s + 2]);
     bins[e] = (int32_t)track_bin(cd.F, track_G(D, D * ct, D * st, cd.Ac, cd.As));
 }

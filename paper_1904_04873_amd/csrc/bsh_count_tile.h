@@ -183,7 +183,7 @@ __device__ __forceinline__ void count_tile(const ItemDesc& d, int s, int ip, int
     const double W = kTwoPi / d.period[ip];
     const double apW = active ? d.a_p[ia] * W : 0.0;
     double sb = 0.0, cb = 1.0;
-    if (active) sincos(W * d.t_asc[b], &sb, &cb);
+    if (active) track_sincos(W * d.t_asc[b], sb, cb);
     const double Ac = apW * cb, As = apW * sb;
 
     const int sg = d.sky_lo + s;
@@ -210,7 +210,7 @@ __device__ __forceinline__ void count_tile(const ItemDesc& d, int s, int ip, int
         for (int jj = tid; jj < nj; jj += lanes) {
             const int64_t J = j0 + jj;
             double sp, cp;
-            sincos(W * d.t_mid[J], &sp, &cp);
+            track_sincos(W * d.t_mid[J], sp, cp);
             const double D = doppler_factor(d.v + 3 * J, nx, ny, nz);
             sm.DC[jj] = D * cp;
             sm.DS[jj] = D * sp;
@@ -294,7 +294,7 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
     const double W = kTwoPi / d.period[ip];
     const double apW = active ? d.a_p[ia] * W : 0.0;
     double sb = 0.0, cb = 1.0;
-    if (active) sincos(W * d.t_asc[b], &sb, &cb);
+    if (active) track_sincos(W * d.t_asc[b], sb, cb);
     const double Ac = apW * cb, As = apW * sb;
 
     const int sg = d.sky_lo + s;
@@ -334,7 +334,7 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
         for (int jj = tid; jj < ng * kGroup; jj += lanes) {
             const int64_t J = j0 + min(jj, nj - 1);
             double sp, cp;
-            sincos(W * d.t_mid[J], &sp, &cp);
+            track_sincos(W * d.t_mid[J], sp, cp);
             const double D = doppler_factor(d.v + 3 * J, nx, ny, nz);
             sm.DC[jj] = D * cp;
             sm.DS[jj] = D * sp;

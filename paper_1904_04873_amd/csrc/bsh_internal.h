@@ -54,6 +54,49 @@ int topk_segmented(const float* score, const int64_t* index, const int64_t* offs
 
 // ---------------------------------------------------------------- device track
 
+// sin and cos of an orbital phase x (|x| < 2^20 rad; the tracks' phases stay below 10^3) by
+// Cody and Waite's additive range reduction: k = nearest integer to x 2/pi, r = x - k pi/2
+// with pi/2 split into three doubles, the first two of 33 significant bits (so k times them is
+// exact for |k| < 2^20 and the first subtraction is exact), then the Taylor series of sin and
+// cos at r in [-pi/4, pi/4] through r^15/15! and r^16/16! (the first omitted terms are below
+// 5e-17 and 3e-18) and the quadrant k mod 4.  Every kernel takes cos and sin of W t and of
+// W t_asc from here, so all of them see the same values.
+__device__ __forceinline__ void track_sincos(double x, double& s, double& c)
+{
+    constexpr double kTwoOverPi = 0x1.45f306dc9c883p-1;
+    constexpr double kP1 = 0x1.921fb544p+0;
+    constexpr double kP2 = 0x1.0b4611a6p-34;
+    constexpr double kP3 = 0x1.3198a2e037073p-69;
+    const double k = rint(x * kTwoOverPi);
+    double r = fma(-k, kP1, x);
+    r = fma(-k, kP2, r);
+    r = fma(-k, kP3, r);
+    const double r2 = r * r;
+    double ps = -0x1.ae7f3e733b81fp-41;          // -1/15!
+    ps = fma(ps, r2, 0x1.6124613a86d09p-33);     //  1/13!
+    ps = fma(ps, r2, -0x1.ae64567f544e4p-26);    // -1/11!
+    ps = fma(ps, r2, 0x1.71de3a556c734p-19);     //  1/9!
+    ps = fma(ps, r2, -0x1.a01a01a01a01ap-13);    // -1/7!
+    ps = fma(ps, r2, 0x1.1111111111111p-7);      //  1/5!
+    ps = fma(ps, r2, -0x1.5555555555555p-3);     // -1/3!
+    const double sr = fma(r * r2, ps, r);
+    double pc = 0x1.ae7f3e733b81fp-45;           //  1/16!
+    pc = fma(pc, r2, -0x1.93974a8c07c9dp-37);    // -1/14!
+    pc = fma(pc, r2, 0x1.1eed8eff8d898p-29);     //  1/12!
+    pc = fma(pc, r2, -0x1.27e4fb7789f5cp-22);    // -1/10!
+    pc = fma(pc, r2, 0x1.a01a01a01a01ap-16);     //  1/8!
+    pc = fma(pc, r2, -0x1.6c16c16c16c17p-10);    // -1/6!
+    pc = fma(pc, r2, 0x1.5555555555555p-5);      //  1/4!
+    pc = fma(pc, r2, -0.5);                      // -1/2!
+    const double cr = fma(r2, pc, 1.0);
+    // x = k pi/2 + r: quadrant 1 swaps sin and cos, quadrants 2 and 3 flip the signs
+    const int q = (int)k & 3;
+    const double s0 = (q & 1) ? cr : sr;
+    const double c0 = (q & 1) ? sr : cr;
+    s = (q & 2) ? -s0 : s0;
+    c = ((q + 1) & 2) ? -c0 : c0;
+}
+
 // Doppler factor D = 1 + v.n, one fixed operation order (no contraction: the library is
 // built with -ffp-contract=off).
 __device__ __forceinline__ double doppler_factor(const double* v, double nx, double ny, double nz)
@@ -78,7 +121,7 @@ __device__ __forceinline__ Cand load_cand(const double* cand)
     c.ta = cand[3];
     c.W = kTwoPi / c.P;
     c.apW = c.ap * c.W;
-    sincos(c.W * c.ta, &c.sb, &c.cb);
+    track_sincos(c.W * c.ta, c.sb, c.cb);
     c.Ac = c.apW * c.cb;
     c.As = c.apW * c.sb;
     return c;
