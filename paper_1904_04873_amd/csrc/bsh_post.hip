@@ -268,28 +268,82 @@ __global__ void iota_kernel(int32_t* parent, int64_t n)
     if (i < n) parent[i] = (int32_t)i;
 }
 
-// One block per (row tile, column tile) with column tile >= row tile; pairs i < j only.
+// Union-find on a tile's nodes in LDS (same hooking rule as the global one: the larger root
+// under the smaller, so every walk ends).
+__device__ __forceinline__ int32_t lds_ld(int32_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Root of x with path halving (a stored grandparent is always an ancestor of x).
+__device__ int32_t lds_find(int32_t* lp, int32_t x)
+{
+    int32_t p = lds_ld(lp + x);
+    while (p != x) {
+        const int32_t g = lds_ld(lp + p);
+        if (g != p) __hip_atomic_store(lp + x, g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        x = p;
+        p = g;
+    }
+    return x;
+}
+
+__device__ void lds_unite(int32_t* lp, int32_t a, int32_t b)
+{
+    while (true) {
+        a = lds_find(lp, a);
+        b = lds_find(lp, b);
+        if (a == b) return;
+        if (a > b) {
+            const int32_t t = a;
+            a = b;
+            b = t;
+        }
+        if (atomicCAS(lp + b, b, a) == b) return;
+    }
+}
+
+// One block per (row tile, column tile) with column tile >= row tile; pairs i < j only.  The
+// tile's close pairs are first joined in an LDS union-find over its nodes (row members
+// 0..kPostThreads-1, column members after them; a diagonal tile has only the row members); then
+// every node that is not its local root is joined to that root in the global structure, at most
+// one global hook per node and tile instead of one per close pair.
 __global__ void __launch_bounds__(kPostThreads) hook_kernel(PostConst c, const double* rows, int64_t n,
                                                             double w2, int32_t* parent)
 {
     __shared__ PRow tile[kPostThreads];
+    __shared__ int32_t lp[2 * kPostThreads];
     const int64_t bidx = blockIdx.x;
     int64_t tj = (int64_t)((sqrt(8.0 * (double)bidx + 1.0) - 1.0) * 0.5);
     while (tj * (tj + 1) / 2 > bidx) --tj;
     while ((tj + 1) * (tj + 2) / 2 <= bidx) ++tj;
     const int64_t ti = bidx - tj * (tj + 1) / 2;
-    const int64_t i = ti * kPostThreads + threadIdx.x;
-    const int64_t j0 = tj * kPostThreads;
+    const bool diag = ti == tj;
+    const int t = threadIdx.x;
+    const int64_t i0 = ti * kPostThreads, j0 = tj * kPostThreads;
+    const int64_t i = i0 + t;
     // the column tile with its resolutions, computed once per block
-    if (j0 + threadIdx.x < n) tile[threadIdx.x] = load_row(rows + 6 * (j0 + threadIdx.x), c);
+    if (j0 + t < n) tile[t] = load_row(rows + 6 * (j0 + t), c);
+    lp[t] = t;
+    lp[kPostThreads + t] = kPostThreads + t;
     __syncthreads();
-    if (i >= n) return;
-    const PRow a = load_row(rows + 6 * i, c);
-    const int64_t jn = min((int64_t)kPostThreads, n - j0);
-    for (int64_t jj = 0; jj < jn; ++jj) {
-        const int64_t j = j0 + jj;
-        if (j <= i) continue;
-        if (dist2(a, tile[jj], c) < w2) unite(parent, (int32_t)i, (int32_t)j);
+    if (i < n) {
+        const PRow a = load_row(rows + 6 * i, c);
+        const int64_t jn = min((int64_t)kPostThreads, n - j0);
+        for (int64_t jj = 0; jj < jn; ++jj) {
+            if (j0 + jj <= i) continue;
+            if (dist2(a, tile[jj], c) < w2) lds_unite(lp, t, diag ? (int32_t)jj : kPostThreads + (int32_t)jj);
+        }
+    }
+    __syncthreads();
+    for (int x = t; x < 2 * kPostThreads; x += kPostThreads) {
+        if (diag && x >= kPostThreads) break;
+        const int64_t gx = x < kPostThreads ? i0 + x : j0 + (x - kPostThreads);
+        if (gx >= n) continue;
+        const int32_t r = lds_find(lp, x);
+        if (r == x) continue;
+        const int64_t gr = r < kPostThreads ? i0 + r : j0 + (r - kPostThreads);
+        unite(parent, (int32_t)gx, (int32_t)gr);
     }
 }
 
@@ -333,19 +387,51 @@ __global__ void cen_init_kernel(int64_t n, uint64_t* key, int32_t* top, double* 
     for (int k = 0; k < 6; ++k) cen[6 * i + k] = 0.0;
 }
 
+// The members of a top-list fall into few, large clusters, so per-member atomics on the same
+// few addresses would serialize: lanes of a wave that hold the same label first combine their
+// values with shuffles, and one lane per (wave, label) performs the atomic.  Returns false when
+// no lane is pending; otherwise the label lr of the wave's first pending lane and that lane.
+__device__ __forceinline__ bool wave_next_label(bool pending, int32_t r, int32_t& lr, int& leader)
+{
+    const unsigned long long m = __ballot(pending);
+    if (!m) return false;
+    leader = __ffsll((long long)m) - 1;
+    lr = __shfl(r, leader);
+    return true;
+}
+
 __global__ void cen_max_kernel(const double* sig, const int32_t* label, int64_t n, uint64_t* key,
                                int32_t* status)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double s = sig[i];
-    if (!(s > 0.0) || !isfinite(s)) raise_status(status, BSH_STATUS_INPUT);
-    const int32_t r = label[i];
-    if (r < 0 || r >= n || label[r] != r) {     // a label must name a member labelled by itself
-        raise_status(status, BSH_STATUS_INPUT);
-        return;
+    const int lane = threadIdx.x & 63;
+    bool pending = false;
+    int32_t r = -1;
+    uint64_t k = 0;
+    if (i < n) {
+        const double s = sig[i];
+        if (!(s > 0.0) || !isfinite(s)) raise_status(status, BSH_STATUS_INPUT);
+        r = label[i];
+        if (r < 0 || r >= n || label[r] != r)      // a label must name a member labelled by itself
+            raise_status(status, BSH_STATUS_INPUT);
+        else {
+            pending = true;
+            k = dkey(s);
+        }
     }
-    atomicMax((unsigned long long*)(key + r), (unsigned long long)dkey(s));
+    int32_t lr;
+    int leader;
+    while (wave_next_label(pending, r, lr, leader)) {
+        const bool mine = pending && r == lr;
+        unsigned long long v = mine ? k : 0ull;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long o = __shfl_xor(v, off, 64);
+            v = o > v ? o : v;
+        }
+        if (lane == leader) atomicMax((unsigned long long*)(key + lr), v);
+        pending = pending && !mine;
+    }
 }
 
 __global__ void cen_top_kernel(const double* sig, const int32_t* label, int64_t n, const uint64_t* key,
@@ -362,21 +448,39 @@ __global__ void cen_sum_kernel(PostConst c, const double* rows, const double* si
                                int64_t n, double cut2, const int32_t* top, double* weight, double* cen)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int32_t r = label[i];
-    if (r < 0 || r >= n || label[r] != r) return;
-    const int32_t t = top[r];
-    if (t < 0 || t >= n) return;
-    bool keep = true;
-    if (cut2 > 0.0 && t != (int32_t)i) {
-        const PRow a = load_row(rows + 6 * (int64_t)t, c);
-        const PRow b = load_row(rows + 6 * i, c);
-        keep = dist2(a, b, c) < cut2;
+    const int lane = threadIdx.x & 63;
+    bool pending = false;
+    int32_t r = -1;
+    double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (i < n) {
+        r = label[i];
+        const int32_t t = (r >= 0 && r < n && label[r] == r) ? top[r] : -1;
+        if (t >= 0 && t < n) {
+            bool keep = true;
+            if (cut2 > 0.0 && t != (int32_t)i) {
+                const PRow a = load_row(rows + 6 * (int64_t)t, c);
+                const PRow b = load_row(rows + 6 * i, c);
+                keep = dist2(a, b, c) < cut2;
+            }
+            if (keep) {
+                pending = true;
+                const double s = sig[i];
+                v[0] = s;
+                for (int k = 0; k < 6; ++k) v[1 + k] = s * rows[6 * i + k];
+            }
+        }
     }
-    if (!keep) return;
-    const double s = sig[i];
-    atomicAdd(weight + r, s);
-    for (int k = 0; k < 6; ++k) atomicAdd(cen + 6 * (int64_t)r + k, s * rows[6 * i + k]);
+    int32_t lr;
+    int leader;
+    while (wave_next_label(pending, r, lr, leader)) {
+        const bool mine = pending && r == lr;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            const double x = wave_sum(mine ? v[k] : 0.0);
+            if (lane == leader) atomicAdd(k == 0 ? weight + lr : cen + 6 * (int64_t)lr + (k - 1), x);
+        }
+        pending = pending && !mine;
+    }
 }
 
 __global__ void cen_final_kernel(const int32_t* label, int64_t n, double* weight, double* cen,
