@@ -3,10 +3,12 @@ in its gfx950 assembly.
 
 The count kernel is compiled to assembly with the library's own flags; in the kernel of the
 given chunk size the loop over segment groups is walked along the path that every group takes
-when no lane of the wave meets an f0-shift step and no partial-sum flush is due (every
-exec-mask skip taken).  Each VALU instruction on that path is one 64-lane wave instruction, so
-its count divided by (segments per group x 90 f0 bins) is the lane-operation cost of one
-template x segment.  This is the floor bench.py prices the count kernel's roofline with.
+when no lane of the wave meets an f0-shift step and no partial-sum flush is due.  Exec-mask
+regions (s_cbranch_execz) are entered, except the innermost ones that hold the step's position
+guess (v_rcp_f32) and the ones that store to global memory (the flush).  Each VALU instruction
+on that path is one 64-lane wave instruction, so its count divided by (segments per group x 90
+f0 bins) is the lane-operation cost of one template x segment.  This is the floor bench.py
+prices the count kernel's roofline with.
 
     python paper_1904_04873_amd/fastpath_ops.py [chunk ...]
 """
@@ -45,12 +47,37 @@ def kernel_lines(asm: str, chunk: int) -> list[str]:
     return lines[start:end]
 
 
-def walk(lines: list[str], head: int) -> dict[str, int]:
-    labels = {}
+def _labels(lines: list[str]) -> dict[str, int]:
+    out = {}
     for i, l in enumerate(lines):
         m = re.match(r"^(\.LBB\d+_\d+):", l)
         if m:
-            labels[m.group(1)] = i
+            out[m.group(1)] = i
+    return out
+
+
+def _rare_regions(lines: list[str], labels: dict[str, int]) -> set[int]:
+    """Lines of the exec-mask branches whose regions the fast path skips."""
+    spans = []
+    for i, l in enumerate(lines):
+        t = l.split()
+        if t and t[0] == "s_cbranch_execz":
+            spans.append((i, labels[t[1]]))
+    has = lambda a, b, what: any(what in lines[k] for k in range(a + 1, b))
+    with_rcp = [(a, b) for a, b in spans if has(a, b, "v_rcp_f32")]
+    rare = set()
+    for a, b in with_rcp:
+        if not any(a < a2 and b2 <= b and (a2, b2) != (a, b) for a2, b2 in with_rcp):
+            rare.add(a)                       # innermost region holding the step's guess
+    for a, b in spans:
+        if has(a, b, "global_store"):
+            rare.add(a)                       # the flush of the partial sums
+    return rare
+
+
+def walk(lines: list[str], head: int) -> dict[str, int]:
+    labels = _labels(lines)
+    rare = _rare_regions(lines, labels)
     counts: dict[str, int] = {}
     i = head + 1
     for _ in range(100000):
@@ -63,7 +90,7 @@ def walk(lines: list[str], head: int) -> dict[str, int]:
         ins = l.split()[0]
         counts[ins] = counts.get(ins, 0) + 1
         if ins == "s_cbranch_execz":
-            i = labels[l.split()[1]]
+            i = labels[l.split()[1]] if i in rare else i + 1
             continue
         if ins == "s_branch" or (ins.startswith("s_cbranch") and ins != "s_cbranch_execnz"):
             tgt = labels[l.split()[1]]
@@ -81,7 +108,7 @@ def fast_path(chunk: int, asm: str | None = None) -> tuple[int, int]:
     lines = kernel_lines(asm or assembly(), chunk)
     best = None
     for i, l in enumerate(lines):
-        if re.match(r"^\.LBB\d+_\d+:", l) and i + 1 < len(lines) and "Loop Header: Depth=2" in lines[i + 1]:
+        if re.match(r"^\.LBB\d+_\d+:", l) and i + 1 < len(lines) and "This Loop Header: Depth=2" in lines[i + 1]:
             c = walk(lines, i)
             adds = c.get("v_add_f32_e32", 0) + c.get("v_add_f32_e64", 0)
             valu = sum(n for k, n in c.items() if k.startswith("v_"))
