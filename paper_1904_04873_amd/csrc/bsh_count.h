@@ -63,23 +63,25 @@ constexpr int kGroup8 = 2 * kGroup;
 constexpr int kFlushGroups = 64;     // eight-segment groups per register partial sum
 
 // Per staged segment: D cos(W t), D sin(W t) and the Doppler factor D of the tile's pixel.
+// The rows come first, so that a window's reads reach them with the small immediate offsets of
+// the paired LDS reads.
 template <int kChunk>
 struct TileSmemLut {
+    uint32_t row[kChunk * (BSH_MAX_WORDS + kRowPad)];
+    float T8[(kChunk / kGroup8) * 256];
+    float T[(kChunk / kGroup) * 16];
     double DC[kChunk];
     double DS[kChunk];
     double D[kChunk];
-    float T8[(kChunk / kGroup8) * 256];
-    float T[(kChunk / kGroup) * 16];
-    uint32_t row[kChunk * (BSH_MAX_WORDS + kRowPad)];
 };
 
 template <int kChunk>
 struct TileSmem {
+    uint32_t row[kChunk * (BSH_MAX_WORDS + kRowPad)];
     double DC[kChunk];
     double DS[kChunk];
     double D[kChunk];
     float W[kChunk];
-    uint32_t row[kChunk * (BSH_MAX_WORDS + kRowPad)];
 };
 
 int64_t plan_tiles(const bsh_grid* g, int lanes, int32_t* tile_start, int64_t* group_sizes);

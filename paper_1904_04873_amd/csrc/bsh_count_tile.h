@@ -31,17 +31,18 @@
 namespace bsh {
 
 // One (binary template, segment) track across the band: G = D (1 - a_p W cos phi) and the
-// canonical bins of the band's lowest and highest f0.
+// canonical bins kf, kf + span of the band's lowest and highest f0 (span = last + the residual's
+// step, -1, 0 or +1, when the track is valid).
 struct BandTrack {
     double G, y0;
-    int kf, delta;
+    int kf, span;
     bool ok;
 };
 
 // The canonical evaluations (no branches).  ok is false, and a flag is raised, when the track
-// leaves the staged row or drifts more than one bin across the band.
+// leaves the staged row [klo, khi) or drifts more than one bin across the band.
 __device__ __forceinline__ BandTrack band_track(double DC, double DS, double D, double Ac, double As,
-                                                double F0, double FL, int klo, int last, int n_bins,
+                                                double F0, double FL, int klo, int khi, int last,
                                                 bool& bad_range, bool& bad_model)
 {
     BandTrack t;
@@ -50,11 +51,9 @@ __device__ __forceinline__ BandTrack band_track(double DC, double DS, double D, 
     t.y0 = fma(F0, t.G, 0.5);
     t.kf = (int)t.y0;
     const int kl = (int)fma(FL, t.G, 0.5);
-    const int base = t.kf - klo;
-    const int top = kl - klo;
-    t.delta = top - base - last;
-    const bool in_range = (base >= 0) & (top < n_bins);
-    t.ok = in_range & ((unsigned)(t.delta + 1) <= 2u);
+    t.span = kl - t.kf;
+    const bool in_range = (t.kf >= klo) & (kl < khi);
+    t.ok = in_range & (t.span >= last - 1) & (t.span <= last + 1);
     bad_range |= !in_range;
     bad_model |= in_range & !t.ok;
     return t;
@@ -104,21 +103,21 @@ __device__ __forceinline__ int step_exact(double G, int kf, double F0, int last,
     return hi;
 }
 
-// Where the band has an f0-shift step (t.ok and t.delta != 0), take the bins above it one bit
-// further (delta = +1) or nearer (delta = -1).
+// Where the band has an f0-shift step (t.ok and t.span != last), take the bins above it one bit
+// further (span = last + 1) or nearer (span = last - 1).
 __device__ __forceinline__ void band_step(const BandTrack& t, double F0, int last, uint32_t& m0, uint32_t& m1,
                                           uint32_t& m2)
 {
     // The residual r_i = k_i - (k0 + i) steps once, at the first index past the crossing
-    // i* = num / den of y0 + i (G - 1) with the next integer above (delta = +1) or below
-    // (delta = -1): num = 1 - frac(y0) or frac(y0) (exact), den = +-(G - 1).  The single-
+    // i* = num / den of y0 + i (G - 1) with the next integer above (a step up) or below (a step
+    // down): num = 1 - frac(y0) or frac(y0) (exact), den = +-(G - 1).  The single-
     // precision q = num / den carries a relative error below 4e-7 (two conversions, the
     // reciprocal, the product), i.e. below 4e-5 for i* < 96, and the canonical evaluations
     // place the step within 3e-11 / |G - 1| < 3e-5 of i* when den >= 1e-6.  A q further than
     // 1e-3 from an integer and below last is therefore floor(i*) and the step sits at
     // floor(q) + 1; the rest (a few in a thousand, or a den of the wrong sign) is decided by
     // canonical evaluations.
-    const bool up = t.delta > 0;
+    const bool up = t.span > last;
     const double f = t.y0 - (double)t.kf;
     const float num = (float)(up ? 1.0 - f : f);
     const float gm1 = (float)(t.G - 1.0);
@@ -151,13 +150,13 @@ __device__ __forceinline__ void band_step(const BandTrack& t, double F0, int las
 // 96-bit (m0, m1, m2) is the peakgram bit of f0 bin i's track.  Returns false, with zero masks,
 // when the track failed.
 __device__ __forceinline__ bool band_mask(const uint32_t* row, double DC, double DS, double D, double Ac,
-                                          double As, double F0, double FL, int klo, int last, int n_bins,
+                                          double As, double F0, double FL, int klo, int khi, int last,
                                           uint32_t& m0, uint32_t& m1, uint32_t& m2, bool& bad_range,
                                           bool& bad_model)
 {
-    const BandTrack t = band_track(DC, DS, D, Ac, As, F0, FL, klo, last, n_bins, bad_range, bad_model);
+    const BandTrack t = band_track(DC, DS, D, Ac, As, F0, FL, klo, khi, last, bad_range, bad_model);
     band_window(row, t, klo, m0, m1, m2);
-    if (t.ok && t.delta != 0) band_step(t, F0, last, m0, m1, m2);
+    if (t.ok && t.span != last) band_step(t, F0, last, m0, m1, m2);
     return t.ok;
 }
 
@@ -228,7 +227,7 @@ __device__ __forceinline__ void count_tile(const ItemDesc& d, int s, int ip, int
         for (int jj = 0; jj < nj; ++jj) {
             uint32_t m0, m1, m2;
             if (!band_mask(sm.row + jj * nwp, sm.DC[jj], sm.DS[jj], sm.D[jj], Ac, As, F0, FL, klo,
-                           last, d.n_bins, m0, m1, m2, bad_range, bad_model))
+                           klo + d.n_bins, last, m0, m1, m2, bad_range, bad_model))
                 continue;
 
             const uint32_t wb = __float_as_uint(sm.W[jj]);
@@ -381,7 +380,7 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
 #pragma unroll
             for (int u = 0; u < kGroup; ++u) {
                 const int jj = g * kGroup + u;
-                tr[u] = band_track(sm.DC[jj], sm.DS[jj], sm.D[jj], Ac, As, F0, FL, klo, last, d.n_bins,
+                tr[u] = band_track(sm.DC[jj], sm.DS[jj], sm.D[jj], Ac, As, F0, FL, klo, klo + d.n_bins, last,
                                    bad_range, bad_model);
             }
 #pragma unroll
@@ -389,7 +388,7 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
                 band_window(sm.row + (g * kGroup + u) * nwp, tr[u], klo, mk[u][0], mk[u][1], mk[u][2]);
 #pragma unroll
             for (int u = 0; u < kGroup; ++u)
-                if (tr[u].ok && tr[u].delta != 0) band_step(tr[u], F0, last, mk[u][0], mk[u][1], mk[u][2]);
+                if (tr[u].ok && tr[u].span != last) band_step(tr[u], F0, last, mk[u][0], mk[u][1], mk[u][2]);
             // every nibble column of the 4 x 32 bit matrix (mk[0..3][w]) transposed: swap the
             // off-diagonal 2 x 2 blocks, then the off-diagonal bits of each 2 x 2 block
 #pragma unroll
