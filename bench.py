@@ -31,10 +31,10 @@ METRIC = "Hough templates·segments/s on 1 GPU, batched vs plain, at oracle-exac
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # VALU lane-operations per template x segment on the fast path of the subset-sum table count:
 # the VALU instructions of the segment-group loop in its gfx950 assembly along the path with no
-# f0-shift step and no flush (paper_1904_04873_amd/fastpath_ops.py counts them: 686 per group
+# f0-shift step and no flush (paper_1904_04873_amd/fastpath_ops.py counts them: 664 per group
 # of 8 segments at the 128- and 256-segment chunks), divided by the group's 8 x 90 template x
 # segments.
-TABLE_OPS_PER_TS = 686 / 720
+TABLE_OPS_PER_TS = 664 / 720
 # the same figure for plain select-and-add: extract the peak bit, select the weight, add
 SELECT_OPS_PER_TS = 3
 # HBM bytes per count launch, measured with rocprofv3 counters for one kernel source and tile

@@ -10,7 +10,7 @@ constexpr int kMaxLanes = 256;       // largest tile (binary templates per block
 constexpr int kDefaultLanes = 256;
 constexpr int kDefaultChunk = 256;   // segments staged per LDS pass
 constexpr int kFlush = 64;           // segments per FP32 partial sum
-constexpr int kRowPad = 3;           // zero words staged after each row
+constexpr int kRowPad = 4;           // zero words staged after each row (a failed track reads them)
 constexpr int kNF = BSH_MAX_F0;
 
 // Everything a tile needs about its work item (one segment set, one band grid, a run of

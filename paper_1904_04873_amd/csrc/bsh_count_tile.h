@@ -60,20 +60,18 @@ __device__ __forceinline__ BandTrack band_track(double DC, double DS, double D, 
 }
 
 // Bit i of the 96-bit (m0, m1, m2) is the peakgram bit of f0 bin i as if the band had no f0-shift
-// step: one funnel-shifted window of the LDS row (zero when the track failed; a failed track
-// still reads inside the row).
-__device__ __forceinline__ void band_window(const uint32_t* row, const BandTrack& t, int klo, uint32_t& m0,
-                                            uint32_t& m1, uint32_t& m2)
+// step: one funnel-shifted window of the LDS row.  A failed track reads the row's zero padding
+// (pad_at = 32 n_words), so its masks are zero without a select.
+__device__ __forceinline__ void band_window(const uint32_t* row, const BandTrack& t, int klo, int pad_at,
+                                            uint32_t& m0, uint32_t& m1, uint32_t& m2)
 {
-    const int at = t.ok ? t.kf - klo : 0;
+    const int at = t.ok ? t.kf - klo : pad_at;
     const int qw = at >> 5;
     const int sh = at & 31;
     const uint32_t w0 = row[qw], w1 = row[qw + 1], w2 = row[qw + 2], w3 = row[qw + 3];
-    // a mask rather than a select, so that the row reads stay unconditional
-    const uint32_t keep = 0u - (uint32_t)t.ok;
-    m0 = __builtin_amdgcn_alignbit(w1, w0, sh) & keep;
-    m1 = __builtin_amdgcn_alignbit(w2, w1, sh) & keep;
-    m2 = __builtin_amdgcn_alignbit(w3, w2, sh) & keep;
+    m0 = __builtin_amdgcn_alignbit(w1, w0, sh);
+    m1 = __builtin_amdgcn_alignbit(w2, w1, sh);
+    m2 = __builtin_amdgcn_alignbit(w3, w2, sh);
 }
 
 // The first f0 index whose residual differs from r0, by canonical evaluations: the guess
@@ -151,11 +149,11 @@ __device__ __forceinline__ void band_step(const BandTrack& t, double F0, int las
 // when the track failed.
 __device__ __forceinline__ bool band_mask(const uint32_t* row, double DC, double DS, double D, double Ac,
                                           double As, double F0, double FL, int klo, int khi, int last,
-                                          uint32_t& m0, uint32_t& m1, uint32_t& m2, bool& bad_range,
+                                          int pad_at, uint32_t& m0, uint32_t& m1, uint32_t& m2, bool& bad_range,
                                           bool& bad_model)
 {
     const BandTrack t = band_track(DC, DS, D, Ac, As, F0, FL, klo, khi, last, bad_range, bad_model);
-    band_window(row, t, klo, m0, m1, m2);
+    band_window(row, t, klo, pad_at, m0, m1, m2);
     if (t.ok && t.span != last) band_step(t, F0, last, m0, m1, m2);
     return t.ok;
 }
@@ -227,7 +225,7 @@ __device__ __forceinline__ void count_tile(const ItemDesc& d, int s, int ip, int
         for (int jj = 0; jj < nj; ++jj) {
             uint32_t m0, m1, m2;
             if (!band_mask(sm.row + jj * nwp, sm.DC[jj], sm.DS[jj], sm.D[jj], Ac, As, F0, FL, klo,
-                           klo + d.n_bins, last, m0, m1, m2, bad_range, bad_model))
+                           klo + d.n_bins, last, 32 * d.n_words, m0, m1, m2, bad_range, bad_model))
                 continue;
 
             const uint32_t wb = __float_as_uint(sm.W[jj]);
@@ -385,7 +383,8 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
             }
 #pragma unroll
             for (int u = 0; u < kGroup; ++u)
-                band_window(sm.row + (g * kGroup + u) * nwp, tr[u], klo, mk[u][0], mk[u][1], mk[u][2]);
+                band_window(sm.row + (g * kGroup + u) * nwp, tr[u], klo, 32 * d.n_words, mk[u][0], mk[u][1],
+                            mk[u][2]);
 #pragma unroll
             for (int u = 0; u < kGroup; ++u)
                 if (tr[u].ok && tr[u].span != last) band_step(tr[u], F0, last, mk[u][0], mk[u][1], mk[u][2]);
