@@ -243,7 +243,9 @@ extern "C" int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh
     if (!rc) rc = dev_alloc(&p->d_item_off, n_items + 1);
     if (!rc) rc = dev_alloc(&p->d_band_off, n_bands + 1);
     if (!rc && p->k_item > 0) {
-        p->ws_item = topk_workspace_bytes(n_items, p->k_item);
+        // the batched run takes one list per item in one segmented call, the plain run one
+        // single-segment call per item: room for either
+        p->ws_item = std::max(topk_workspace_bytes(n_items, p->k_item), topk_workspace_bytes(1, p->k_item));
         if (!rc) rc = dev_alloc((char**)&p->d_ws_item, p->ws_item);
         if (!rc && p->k_band > 0) {
             p->ws_band = topk_workspace_bytes(n_bands, p->k_band);

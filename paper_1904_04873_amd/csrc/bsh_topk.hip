@@ -53,8 +53,9 @@ struct Seg {
     int32_t shift;           // implicit-index segment shift (0: position only)
     int32_t k;
     int32_t idx_bits;        // index bits that can differ inside a segment
+    int32_t copies;          // copies of each global histogram (blocks add to copy b % copies)
     State* st;               // [n_segs]
-    uint32_t* hist;          // [n_segs][kHists][kBins]: key passes, then index passes
+    uint32_t* hist;          // [n_segs][kHists][copies][kBins]: key passes, then index passes
     float* sel_score;        // [n_segs][k]
     int64_t* sel_index;      // [n_segs][k]
     uint32_t* rank;          // [n_segs][k]
@@ -62,10 +63,18 @@ struct Seg {
 
 __host__ __device__ inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// A single long segment has up to kMaxBlocksPerSeg blocks adding their histograms to bins
+// that hold most entries (the scores share their leading bits), and same-address atomics
+// serialize at the L2: each histogram is kept in kHistCopies copies that the blocks spread
+// over, summed when a digit is picked.
+constexpr int kHistCopies = 16;
+__host__ __device__ inline int hist_copies(int32_t n_segs) { return n_segs == 1 ? kHistCopies : 1; }
+
 size_t workspace_bytes(int32_t n_segs, int32_t k)
 {
     const size_t ns = (size_t)(n_segs > 0 ? n_segs : 1);
-    return align_up(sizeof(State) * ns) + align_up(sizeof(uint32_t) * kHists * kBins * ns) +
+    const size_t hb = sizeof(uint32_t) * kHists * kBins * (size_t)hist_copies(n_segs);
+    return align_up(sizeof(State) * ns) + align_up(hb * ns) +
            align_up(sizeof(float) * (size_t)k * ns) + align_up(sizeof(int64_t) * (size_t)k * ns) +
            align_up(sizeof(uint32_t) * (size_t)k * ns);
 }
@@ -76,8 +85,9 @@ void carve(void* ws, Seg& s)
     char* p = (char*)ws;
     s.st = (State*)p;
     p += align_up(sizeof(State) * ns);
+    s.copies = hist_copies(s.n_segs);
     s.hist = (uint32_t*)p;
-    p += align_up(sizeof(uint32_t) * kHists * kBins * ns);
+    p += align_up(sizeof(uint32_t) * kHists * kBins * (size_t)s.copies * ns);
     s.sel_score = (float*)p;
     p += align_up(sizeof(float) * (size_t)s.k * ns);
     s.sel_index = (int64_t*)p;
@@ -96,9 +106,22 @@ __device__ __forceinline__ void seg_range(const Seg& s, int g, int64_t& lo, int6
     }
 }
 
+// Copy 0 of histogram h of segment g; copy c follows at c * kBins.
 __device__ __forceinline__ uint32_t* seg_hist(const Seg& s, int g, int h)
 {
-    return s.hist + ((size_t)g * kHists + h) * kBins;
+    return s.hist + ((size_t)g * kHists + h) * (size_t)s.copies * kBins;
+}
+
+// Histogram h of segment g summed over its copies into LDS (every thread of the block calls this).
+__device__ __forceinline__ void sum_hist(const Seg& s, int g, int h, uint32_t* out)
+{
+    const uint32_t* src = seg_hist(s, g, h);
+    for (int b = threadIdx.x; b < kBins; b += blockDim.x) {
+        uint32_t t = 0u;
+        for (int c = 0; c < s.copies; ++c) t += src[c * kBins + b];
+        out[b] = t;
+    }
+    __syncthreads();
 }
 
 // Order-preserving map float -> uint32 (larger float -> larger key); -0 is folded onto +0.
@@ -212,7 +235,8 @@ __global__ void init_kernel(Seg s)
             s.st[g].iprefix[0] = 0ull;
             s.st[g].iremaining[0] = 0u;
         }
-        for (int b = threadIdx.x; b < kHists * kBins; b += blockDim.x) s.hist[(size_t)g * kHists * kBins + b] = 0u;
+        const size_t per = (size_t)kHists * s.copies * kBins;
+        for (size_t b = threadIdx.x; b < per; b += blockDim.x) s.hist[(size_t)g * per + b] = 0u;
     }
     const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e < (uint32_t)s.k) s.rank[(size_t)g * s.k + e] = 0u;
@@ -233,7 +257,8 @@ __device__ KeyStep key_step(const Seg& s, int g, int p, uint32_t* scan)
     const uint32_t rem = s.st[g].remaining[p - 1];
     KeyStep k{pre << 8, 0u, 0u};
     if (rem == 0u) return k;      // block-uniform
-    const uint32_t* h = seg_hist(s, g, p - 1);
+    __shared__ uint32_t h[kBins];
+    sum_hist(s, g, p - 1, h);
     pick_digit(h, rem, true, scan, &d, &before);
     k.prefix = (pre << 8) | (uint32_t)d;
     k.remaining = rem - before;
@@ -267,7 +292,7 @@ __global__ __launch_bounds__(kThreads) void key_hist_kernel(Seg s, int pass)
         wave_hist_add(h, pass == 0 || (key >> (shift + 8)) == prefix, (key >> shift) & 0xffu);
     });
     __syncthreads();
-    uint32_t* gh = seg_hist(s, g, pass);
+    uint32_t* gh = seg_hist(s, g, pass) + (blockIdx.x % s.copies) * kBins;
     for (int b = threadIdx.x; b < kBins; b += kThreads)
         if (h[b]) atomicAdd(&gh[b], h[b]);
 }
@@ -346,7 +371,9 @@ __device__ TieStep tie_step(const Seg& s, int g, int p, uint32_t* scan, bool rec
     const uint32_t rem = s.st[g].iremaining[p - 1];
     TieStep t{pre << 8, 0u};
     if (rem != 0u) {      // block-uniform
-        pick_digit(seg_hist(s, g, kKeyPasses + p - 1), rem, false, scan, &d, &below);
+        __shared__ uint32_t h[kBins];
+        sum_hist(s, g, kKeyPasses + p - 1, h);
+        pick_digit(h, rem, false, scan, &d, &below);
         t.prefix = (pre << 8) | (unsigned long long)d;
         t.remaining = rem - below;
     }
@@ -384,7 +411,7 @@ __global__ __launch_bounds__(kThreads) void tie_hist_kernel(Seg s, int pass, int
         wave_hist_add(h, tie && (pass == 0 || (ix >> (shift + 8)) == prefix), (uint32_t)((ix >> shift) & 0xffull));
     });
     __syncthreads();
-    uint32_t* gh = seg_hist(s, g, kKeyPasses + pass);
+    uint32_t* gh = seg_hist(s, g, kKeyPasses + pass) + (blockIdx.x % s.copies) * kBins;
     for (int b = threadIdx.x; b < kBins; b += kThreads)
         if (h[b]) atomicAdd(&gh[b], h[b]);
 }
