@@ -16,7 +16,7 @@ import torch
 
 from . import bsh
 
-SHAPES: Tuple[Tuple[int, int], ...] = tuple((l, c) for l in (64, 128, 256) for c in (128, 256, 512))
+SHAPES: Tuple[Tuple[int, int], ...] = tuple((l, c) for l in (64, 128, 256, 512) for c in (128, 256, 512))
 CACHE = os.environ.get("BSH_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "bsh", "tune.json"))
 
 

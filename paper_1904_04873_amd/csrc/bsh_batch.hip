@@ -148,7 +148,7 @@ extern "C" int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh
     if (opts) o = *opts;
     const int lanes = o.lanes ? o.lanes : kDefaultLanes;
     const int chunk = o.chunk ? o.chunk : kDefaultChunk;
-    if (!valid_tile_shape(lanes, chunk)) return fail_inval("tile shape: lanes 64/128/256, chunk 128/256/512");
+    if (!valid_tile_shape(lanes, chunk)) return fail_inval("tile shape: lanes 64/128/256/512, chunk 128/256/512");
     if (o.variant < BSH_VARIANT_AUTO || o.variant > BSH_VARIANT_TABLE) return fail_inval("variant");
     if (o.k_item < 0 || o.k_band < 0) return fail_inval("k_item / k_band < 0");
     if (o.k_band > 0 && o.k_item == 0) return fail_inval("band lists need item lists");

@@ -6,7 +6,7 @@
 
 namespace bsh {
 
-constexpr int kMaxLanes = 256;       // largest tile (binary templates per block)
+constexpr int kMaxLanes = 512;       // largest tile (binary templates per block)
 constexpr int kDefaultLanes = 256;
 constexpr int kDefaultChunk = 256;   // segments staged per LDS pass
 constexpr int kFlush = 64;           // segments per FP32 partial sum

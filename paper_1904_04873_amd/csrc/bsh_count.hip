@@ -104,7 +104,7 @@ int kernel_mode(int variant, bool with_count)
 
 bool valid_tile_shape(int lanes, int chunk)
 {
-    return (lanes == 64 || lanes == 128 || lanes == 256) && (chunk == 128 || chunk == 256 || chunk == 512);
+    return (lanes == 64 || lanes == 128 || lanes == 256 || lanes == 512) && (chunk == 128 || chunk == 256 || chunk == 512);
 }
 
 }  // namespace bsh
@@ -121,7 +121,7 @@ extern "C" int bsh_hough_count_ex(const bsh_segments* seg, const bsh_grid* grid,
     rc = check_grid(grid);
     if (rc) return rc;
     if (!count_out && !wsum_out) return fail_inval("both outputs are NULL");
-    if (!valid_tile_shape(lanes, chunk)) return fail_inval("tile shape: lanes 64/128/256, chunk 128/256/512");
+    if (!valid_tile_shape(lanes, chunk)) return fail_inval("tile shape: lanes 64/128/256/512, chunk 128/256/512");
     if (variant < BSH_VARIANT_AUTO || variant > BSH_VARIANT_TABLE) return fail_inval("variant");
     rc = check_window(seg, grid);
     if (rc) return rc;

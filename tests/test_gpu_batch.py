@@ -154,7 +154,7 @@ def test_every_tile_shape_gives_identical_maps(setup):
                                     _np(g.t_asc_dev))
     ref, rc = bsh.bsh_hough_count(ds, g1, with_count=True)
     ref_t, _ = bsh.bsh_hough_count(ds, g1, variant=2)
-    for lanes in (64, 128, 256):
+    for lanes in (64, 128, 256, 512):
         for chunk in (128, 256, 512):
             ws, c = bsh.bsh_hough_count(ds, g1, with_count=True, lanes=lanes, chunk=chunk)
             wt, _ = bsh.bsh_hough_count(ds, g1, lanes=lanes, chunk=chunk, variant=2)
