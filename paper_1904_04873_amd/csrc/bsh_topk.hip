@@ -452,7 +452,7 @@ __device__ __forceinline__ bool precedes(float sa, int64_t ia, float sb, int64_t
 // the chosen entries (grid.z) so that large k still fills the device (ranks start at zero).
 __global__ __launch_bounds__(kThreads) void rank_kernel(Seg s, uint32_t slice)
 {
-    __shared__ float ts[kThreads];
+    __shared__ uint32_t tk[kThreads];
     __shared__ int64_t ti[kThreads];
     const int g = blockIdx.y;
     const uint32_t k_eff = s.st[g].k_eff;
@@ -464,17 +464,18 @@ __global__ __launch_bounds__(kThreads) void rank_kernel(Seg s, uint32_t slice)
     const int64_t* si = s.sel_index + (size_t)g * s.k;
     const uint32_t e = blockIdx.x * kThreads + threadIdx.x;
     const bool mine = e < k_eff;
-    const float sc = mine ? ss[e] : 0.f;
+    const uint32_t key = mine ? score_key(ss[e]) : 0u;
     const int64_t ix = mine ? si[e] : 0;
     uint32_t rank = 0u;
     for (uint32_t base = f_lo; base < f_hi; base += kThreads) {
         __syncthreads();
         const uint32_t f = base + threadIdx.x;
-        if (f < f_hi) { ts[threadIdx.x] = ss[f]; ti[threadIdx.x] = si[f]; }
+        if (f < f_hi) { tk[threadIdx.x] = score_key(ss[f]); ti[threadIdx.x] = si[f]; }
         __syncthreads();
         const uint32_t m = min((uint32_t)kThreads, f_hi - base);
+        // entry q precedes e: a larger key, or the same key and a smaller index
         if (mine)
-            for (uint32_t q = 0; q < m; ++q) rank += precedes(ts[q], ti[q], sc, ix) ? 1u : 0u;
+            for (uint32_t q = 0; q < m; ++q) rank += (tk[q] > key) | ((tk[q] == key) & (ti[q] < ix)) ? 1u : 0u;
     }
     if (mine && rank) atomicAdd(&s.rank[(size_t)g * s.k + e], rank);
 }
