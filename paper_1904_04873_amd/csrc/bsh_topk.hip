@@ -36,10 +36,9 @@ constexpr int kHists = kKeyPasses + kMaxIdxPasses;
 struct State {
     uint32_t k_eff;          // min(k, segment length)
     uint32_t n_sel;          // output-pool fill
-    uint32_t tie_all;        // every entry equal to T is taken: no tie resolution needed
-    uint32_t pad;
     uint32_t prefix[kKeyPasses + 1];      // key digits fixed before pass p; prefix[4] = T
-    uint32_t remaining[kKeyPasses + 1];   // entries still to take before pass p
+    uint32_t remaining[kKeyPasses + 1];   // entries still to take before pass p; remaining[4]
+                                          // = ties at T still to take (0 when all are taken)
     uint32_t iremaining[kMaxIdxPasses + 1];   // ties still to take before index pass p
     unsigned long long iprefix[kMaxIdxPasses + 1];   // index digits fixed before index pass p
 };
@@ -217,34 +216,32 @@ __device__ void pick_digit(const uint32_t* h, uint32_t rem, bool from_top, uint3
 }
 
 // State, histograms and ranks of segment blockIdx.y start from zero; grid.x covers the k
-// ranks.
+// ranks, and its blocks share the histograms' zeroing.
 __global__ void init_kernel(Seg s)
 {
     const int g = blockIdx.y;
-    if (blockIdx.x == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         int64_t lo, hi;
         seg_range(s, g, lo, hi);
         const int64_t len = hi - lo;
-        if (threadIdx.x == 0) {
-            const uint32_t k_eff = (uint32_t)(len < (int64_t)s.k ? len : (int64_t)s.k);
-            s.st[g].k_eff = k_eff;
-            s.st[g].n_sel = 0u;
-            s.st[g].tie_all = 0u;
-            s.st[g].prefix[0] = 0u;
-            s.st[g].remaining[0] = k_eff;
-            s.st[g].iprefix[0] = 0ull;
-            s.st[g].iremaining[0] = 0u;
-        }
-        const size_t per = (size_t)kHists * s.copies * kBins;
-        for (size_t b = threadIdx.x; b < per; b += blockDim.x) s.hist[(size_t)g * per + b] = 0u;
+        const uint32_t k_eff = (uint32_t)(len < (int64_t)s.k ? len : (int64_t)s.k);
+        s.st[g].k_eff = k_eff;
+        s.st[g].n_sel = 0u;
+        s.st[g].prefix[0] = 0u;
+        s.st[g].remaining[0] = k_eff;
+        s.st[g].iprefix[0] = 0ull;
+        s.st[g].iremaining[0] = 0u;
     }
+    const size_t per = (size_t)kHists * s.copies * kBins;
+    for (size_t b = (size_t)blockIdx.x * blockDim.x + threadIdx.x; b < per; b += (size_t)gridDim.x * blockDim.x)
+        s.hist[(size_t)g * per + b] = 0u;
     const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e < (uint32_t)s.k) s.rank[(size_t)g * s.k + e] = 0u;
 }
 
 // The key digits fixed before pass p (prefix, entries still to take), derived in every block
-// from pass p-1's histogram; block 0 records them.  With `last`, also whether every entry equal
-// to the full key T is needed.
+// from pass p-1's histogram; block 0 records them.  After the last pass, count_at is the
+// number of entries equal to the full key T.
 struct KeyStep {
     uint32_t prefix, remaining, count_at;
 };
@@ -317,7 +314,6 @@ __global__ __launch_bounds__(kThreads) void split_kernel(Seg s)
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         s.st[g].prefix[kKeyPasses] = T;
         s.st[g].remaining[kKeyPasses] = tie_all ? 0u : k.remaining;
-        s.st[g].tie_all = tie_all ? 1u : 0u;
         s.st[g].iprefix[0] = 0ull;
         s.st[g].iremaining[0] = tie_all ? 0u : k.remaining;
     }
