@@ -414,6 +414,54 @@ def test_power_stat_grad_matches_oracle(B):
     assert np.all(np.abs(g - g_o) <= REL * a_o + 1e-300)
 
 
+@pytest.mark.parametrize("n_seg,n", [(1, 1), (5, 7), (70, 13), (130, 1001)])
+def test_stage2_ragged_shapes(B, n_seg, n):
+    """Candidate counts that leave a block partly empty and segment counts below, at and above the
+    kernels' phase counts; one candidate with an invalid sky index (flagged, outputs zero)."""
+    import torch
+    _say(f"stage 2 ragged n_seg={n_seg} n={n}")
+    seg = S.tiny_segments(n_seg=n_seg, k0=180000, n_f0=90, margin=24, seed=n_seg, span_days=120)
+    sky = S.fibonacci_sphere(2)
+    ds = B.DeviceSegments.from_host(seg)
+    sk = torch.from_numpy(sky).cuda()
+    cand, cs = _cands(seg, n, 180000, seed=n, n_sky=2)
+    bad = n // 2
+    cs_bad = cs.copy()
+    cs_bad[bad] = 2
+    ok = np.arange(n) != bad
+    for mode in (0, 1):
+        st = _status(B)
+        out = B.bsh_power_stat(ds, sk, *_dev_cands(cand, cs_bad), mode=mode, with_counts=(mode == 0), status=st)
+        torch.cuda.synchronize()
+        assert st.value() & 4
+        P_o, c_o, nw_o, nt_o = O.power_stat(seg, sky, cs, cand, mode=mode)
+        if mode == 0:
+            P, cnt, ws = (_np(x) for x in out)
+            _check_counts(cnt.view(np.uint32)[ok], ws[ok], c_o[ok], nw_o[ok], nt_o[ok],
+                          nt_o[ok] * float(seg.weight.max()))
+            assert cnt[bad] == 0 and ws[bad] == 0.0
+            tol = REL * np.abs(P_o) + nt_o * float(seg.weight.max()) * float(seg.power.max())
+        else:
+            P = _np(out)
+            tol = REL * np.abs(P_o)
+        assert P[bad] == 0.0
+        assert np.all(np.abs(P.astype(np.float64) - P_o)[ok] <= tol[ok])
+    gp = np.random.default_rng(n).standard_normal(n)
+    st = _status(B)
+    g = _np(B.bsh_power_stat_grad(ds, sk, *_dev_cands(cand, cs_bad), torch.from_numpy(gp).cuda(), status=st))
+    torch.cuda.synchronize()
+    assert st.value() & 4 and np.all(g[bad] == 0.0)
+    g_o, a_o = O.power_grad(seg, sky, cs, cand, grad_p=gp, with_abs=True)
+    assert np.all(np.abs(g - g_o)[ok] <= REL * a_o[ok] + 1e-300)
+    ce = np.concatenate([cand, np.tile([[1e-3, -2e-3]], (n, 1))], axis=1)
+    st = _status(B)
+    Pe = _np(B.bsh_power_stat_ecc(ds, sk, *_dev_cands(ce, cs_bad), mode=1, status=st))
+    torch.cuda.synchronize()
+    assert st.value() & 4 and Pe[bad] == 0.0
+    Pe_o, _ = O.power_stat_ecc(seg, sky, cs, ce, mode=1)
+    assert np.all(np.abs(Pe.astype(np.float64) - Pe_o)[ok] <= REL * np.abs(Pe_o)[ok])
+
+
 def test_track_bins_match_oracle(B):
     import torch
     _say("track bins")
