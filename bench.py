@@ -73,6 +73,31 @@ def measured_traffic(lanes: int, chunk: int):
         return None
 
 
+def oracle_one_thread(n_ap: int) -> dict:
+    """The same oracle count on one host thread (OMP_NUM_THREADS=1 in a child process), over the
+    first n_ap a_p values of the 200 Hz band grid."""
+    import subprocess
+    code = (
+        "import json, sys, time\n"
+        f"sys.path.insert(0, {ROOT!r})\n"
+        "import bsh_synth as S\n"
+        "import oracle as O\n"
+        "w = S.config2(); seg, spec = w.segments[0], w.grids[0]\n"
+        "a_p, per, off, t_asc = O.grid_tables(spec, seg.t_span_mid())\n"
+        f"n_ap = max(1, min({n_ap}, spec.n_ap)); sub = off[:n_ap * spec.n_per + 1]\n"
+        "t0 = time.perf_counter()\n"
+        "O.hough_count(seg, w.sky, spec.k0, spec.n_f0, a_p[:n_ap], per, sub, t_asc[:sub[-1]])\n"
+        "dt = time.perf_counter() - t0\n"
+        "ts = int(sub[-1]) * spec.n_f0 * seg.n_seg\n"
+        "print(json.dumps({'value': ts / dt, 'threads': O.num_threads(), 'sample': "
+        "f'first {n_ap} a_p values: {ts:.3e} template*segments in {dt:.1f} s'}))\n")
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    res = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+    if res.returncode != 0:
+        raise RuntimeError(f"one-thread oracle run failed: {res.stderr[-2000:]}")
+    return json.loads(res.stdout.strip().splitlines()[-1])
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +105,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="enqueue every step eagerly")
+    ap.add_argument("--cpu-one-thread-ap", type=int, default=1,
+                    help="a_p values of the one-thread oracle sample (0: skip it)")
     ap.add_argument("--cpu-sample-ap", type=int, default=32,
                     help="a_p values (of 64) in the oracle's timed sample")
     ap.add_argument("--skip-batched", action="store_true",
@@ -221,7 +248,10 @@ def main():
         cpu = {"value": ts_cpu / dt, "unit": "template*segments/s", "cores": O.num_threads(),
                "kind": "oracle",
                "sample": f"stage-1 count of the first {n_ap} of {spec.n_ap} a_p values (all P, t_asc, f0 "
-                         f"and {seg.n_seg} segments): {ts_cpu:.3e} template*segments in {dt:.1f} s"}
+                         f"and {seg.n_seg} segments): {ts_cpu:.3e} template*segments in {dt:.1f} s",
+               "affinity": sorted(os.sched_getaffinity(0))}
+        if args.cpu_one_thread_ap > 0:
+            cpu["one_thread"] = oracle_one_thread(args.cpu_one_thread_ap)
 
     out = {
         "metric": METRIC,
