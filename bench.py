@@ -112,6 +112,8 @@ def parse():
     ap.add_argument("--skip-batched", action="store_true",
                     help="omit the batched-versus-plain comparison")
     ap.add_argument("--batched-steps", type=int, default=2)
+    ap.add_argument("--allsky-pixels", type=int, default=16,
+                    help="pixels of the all-sky slice to time (0: skip it)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="before timing, run one plain device copy of this many MiB (a known-size "
                          "kernel for scaling HBM byte counters)")
@@ -233,6 +235,7 @@ def main():
     refine = run_refine(bsh, spec, st)
 
     batched = None if args.skip_batched else run_batched(args)
+    allsky = run_allsky(args) if (args.allsky_pixels > 0 and not args.skip_batched) else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -298,6 +301,7 @@ def main():
         "post": post,
         "refine": refine,
         "batched": batched,
+        "allsky": allsky,
     }
     print(json.dumps(out), flush=True)
 
@@ -380,6 +384,50 @@ def run_refine(bsh, spec, st):
     return {"candidates": n, "segments": seg.n_seg, "forward_ms": fwd, "backward_ms": bwd,
             "adam_20_steps_ms": adam, "forward_cand_seg_per_s": cs_n / (fwd / 1e3),
             "backward_cand_seg_per_s": cs_n / (bwd / 1e3)}
+
+
+def run_allsky(args):
+    """The all-sky slice's shape (2 x 4000 segments over 240 d, band 300.0-300.1 Hz, 128 a_p x 64 P
+    x rule t_asc = 581 531 binary templates per pixel) on `allsky_pixels` of its 2000 pixels, one
+    batched plan with per-pixel and per-band top-10^5."""
+    import numpy as np
+    import torch
+
+    import bsh_synth as S
+    from paper_1904_04873_amd import bsh
+
+    dev = torch.device("cuda:0")
+    n_pix = args.allsky_pixels
+    print(f"[bench] all-sky slice: {n_pix} pixels", file=sys.stderr, flush=True)
+    w = S.config5()
+    seg, spec = w.segments[0], w.grids[0]
+    ds = bsh.DeviceSegments.from_host(seg, device=dev)
+    g = bsh.DeviceGrid.build(spec, seg.t_span_mid(), w.sky, device=dev)
+    pixels = [int(p) for p in np.linspace(0, len(w.sky) - 1, n_pix).round()]
+    items = [(ds, 0, p, 1, 0) for p in pixels]
+    k = 100000
+    st = bsh.Status(dev)
+    plan = bsh.Plan(items, [g], 1, k_item=k, k_band=k, use_graph=True, lpt=True, status=st)
+    plan.run()
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(max(1, args.batched_steps)):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        plan.run()
+        b.record()
+        torch.cuda.synchronize()
+        out.append(a.elapsed_time(b))
+    st.raise_if_set("all-sky plan")
+    plan.close()
+    ms = float(np.median(out))
+    ts = n_pix * g.n_bin * g.n_f0 * seg.n_seg
+    return {"workload": f"band 300.0-300.1 Hz, 2 x 4000 segments over 240 d, {n_pix} of 2000 pixels, "
+                        f"90 f0 x 128 a_p x 64 P x rule t_asc = {g.n_bin} binary templates per pixel; "
+                        "per-pixel and per-band top-10^5",
+            "pixels": n_pix, "template_segments": ts, "ms": ms, "value": ts / (ms / 1e3),
+            "unit": "template*segments/s", "k": k}
 
 
 def run_batched(args):
