@@ -165,6 +165,11 @@ def test_count_config2_full_size_sampled(B):
     ws_t = _np(ws_t)
     _check_counts(c_o, ws_t[idx], c_o, nw_o, nt_o, ntw_o)
     assert np.max(np.abs(ws_t - ws) / np.maximum(ws, 1e-30)) < 2e-5
+    # every tile shape the benchmark's autotuner may pick gives this same map, bit for bit
+    for lanes, chunk in ((512, 512), (512, 256), (256, 256), (128, 128)):
+        ws_s, _ = B.bsh_hough_count(ds, g, lanes=lanes, chunk=chunk, variant=2)
+        torch.cuda.synchronize()
+        assert np.array_equal(_np(ws_s), ws_t), (lanes, chunk)
     # mean count under noise ~ N exp(-1.6) (statistical sanity at full size)
     assert abs(cnt.mean() / 4000 - math.exp(-1.6)) < 0.01
 
