@@ -36,6 +36,7 @@ constexpr int kHists = kKeyPasses + kMaxIdxPasses;
 struct State {
     uint32_t k_eff;          // min(k, segment length)
     uint32_t n_sel;          // output-pool fill
+    uint32_t kmax;           // largest chosen key (bucketed ordering)
     uint32_t prefix[kKeyPasses + 1];      // key digits fixed before pass p; prefix[4] = T
     uint32_t remaining[kKeyPasses + 1];   // entries still to take before pass p; remaining[4]
                                           // = ties at T still to take (0 when all are taken)
@@ -58,6 +59,14 @@ struct Seg {
     float* sel_score;        // [n_segs][k]
     int64_t* sel_index;      // [n_segs][k]
     uint32_t* rank;          // [n_segs][k]
+    // bucketed ordering (k > kRankDirect), else NULL
+    int32_t bucket_log2;     // log2 of the buckets per segment
+    uint32_t* bcnt;          // [n_segs][buckets] entries per bucket
+    uint32_t* bbase;         // [n_segs][buckets] entries in the buckets before
+    uint32_t* bfill;         // [n_segs][buckets] scatter cursors
+    uint32_t* tkey;          // [n_segs][k] chosen entries grouped by bucket
+    float* tscore;           // [n_segs][k]
+    int64_t* tindex;         // [n_segs][k]
 };
 
 __host__ __device__ inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -69,13 +78,35 @@ __host__ __device__ inline size_t align_up(size_t x) { return (x + 255) & ~(size
 constexpr int kHistCopies = 16;
 __host__ __device__ inline int hist_copies(int32_t n_segs) { return n_segs == 1 ? kHistCopies : 1; }
 
+// Ordering the k chosen entries: up to kRankDirect by counting, for each entry, the entries
+// that precede it (k^2 comparisons spread over the device); beyond, the entries are first
+// grouped into about k/4 buckets of equal key width between T and the largest chosen key, and
+// an entry only counts within its bucket (the buckets before it precede it as a whole).
+constexpr int32_t kRankDirect = 16384;
+
+__host__ __device__ inline int bucket_log2(int32_t k)
+{
+    int b = 8;
+    while (b < 16 && (1 << (b + 2)) < k) ++b;
+    return b;
+}
+
+size_t bucket_bytes(int32_t n_segs, int32_t k)
+{
+    if (k <= kRankDirect) return 0;
+    const size_t ns = (size_t)(n_segs > 0 ? n_segs : 1);
+    const size_t nb = (size_t)1 << bucket_log2(k);
+    return 3 * align_up(sizeof(uint32_t) * nb * ns) + align_up(sizeof(uint32_t) * (size_t)k * ns) +
+           align_up(sizeof(float) * (size_t)k * ns) + align_up(sizeof(int64_t) * (size_t)k * ns);
+}
+
 size_t workspace_bytes(int32_t n_segs, int32_t k)
 {
     const size_t ns = (size_t)(n_segs > 0 ? n_segs : 1);
     const size_t hb = sizeof(uint32_t) * kHists * kBins * (size_t)hist_copies(n_segs);
     return align_up(sizeof(State) * ns) + align_up(hb * ns) +
            align_up(sizeof(float) * (size_t)k * ns) + align_up(sizeof(int64_t) * (size_t)k * ns) +
-           align_up(sizeof(uint32_t) * (size_t)k * ns);
+           align_up(sizeof(uint32_t) * (size_t)k * ns) + bucket_bytes(n_segs, k);
 }
 
 void carve(void* ws, Seg& s)
@@ -92,6 +123,26 @@ void carve(void* ws, Seg& s)
     s.sel_index = (int64_t*)p;
     p += align_up(sizeof(int64_t) * (size_t)s.k * ns);
     s.rank = (uint32_t*)p;
+    p += align_up(sizeof(uint32_t) * (size_t)s.k * ns);
+    s.bucket_log2 = 0;
+    s.bcnt = s.bbase = s.bfill = s.tkey = nullptr;
+    s.tscore = nullptr;
+    s.tindex = nullptr;
+    if (s.k > kRankDirect) {
+        s.bucket_log2 = bucket_log2(s.k);
+        const size_t nb = (size_t)1 << s.bucket_log2;
+        s.bcnt = (uint32_t*)p;
+        p += align_up(sizeof(uint32_t) * nb * ns);
+        s.bbase = (uint32_t*)p;
+        p += align_up(sizeof(uint32_t) * nb * ns);
+        s.bfill = (uint32_t*)p;
+        p += align_up(sizeof(uint32_t) * nb * ns);
+        s.tkey = (uint32_t*)p;
+        p += align_up(sizeof(uint32_t) * (size_t)s.k * ns);
+        s.tscore = (float*)p;
+        p += align_up(sizeof(float) * (size_t)s.k * ns);
+        s.tindex = (int64_t*)p;
+    }
 }
 
 __device__ __forceinline__ void seg_range(const Seg& s, int g, int64_t& lo, int64_t& hi)
@@ -227,6 +278,7 @@ __global__ void init_kernel(Seg s)
         const uint32_t k_eff = (uint32_t)(len < (int64_t)s.k ? len : (int64_t)s.k);
         s.st[g].k_eff = k_eff;
         s.st[g].n_sel = 0u;
+        s.st[g].kmax = 0u;
         s.st[g].prefix[0] = 0u;
         s.st[g].remaining[0] = k_eff;
         s.st[g].iprefix[0] = 0ull;
@@ -235,6 +287,13 @@ __global__ void init_kernel(Seg s)
     const size_t per = (size_t)kHists * s.copies * kBins;
     for (size_t b = (size_t)blockIdx.x * blockDim.x + threadIdx.x; b < per; b += (size_t)gridDim.x * blockDim.x)
         s.hist[(size_t)g * per + b] = 0u;
+    if (s.bcnt) {
+        const size_t nb = (size_t)1 << s.bucket_log2;
+        for (size_t b = (size_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (size_t)gridDim.x * blockDim.x) {
+            s.bcnt[(size_t)g * nb + b] = 0u;
+            s.bfill[(size_t)g * nb + b] = 0u;
+        }
+    }
     const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e < (uint32_t)s.k) s.rank[(size_t)g * s.k + e] = 0u;
 }
@@ -495,6 +554,110 @@ __global__ void scatter_kernel(Seg s, float* __restrict__ out_score, int64_t* __
     }
 }
 
+// ---------------------------------------------------------------- bucketed ordering (k > kRankDirect)
+
+__global__ __launch_bounds__(kThreads) void winners_max_kernel(Seg s)
+{
+    const int g = blockIdx.y;
+    const uint32_t k_eff = s.st[g].k_eff;
+    const uint32_t e = blockIdx.x * kThreads + threadIdx.x;
+    uint32_t key = e < k_eff ? score_key(s.sel_score[(size_t)g * s.k + e]) : 0u;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t o = __shfl_xor(key, off, 64);
+        key = o > key ? o : key;
+    }
+    if ((threadIdx.x & 63) == 0 && key) atomicMax(&s.st[g].kmax, key);
+}
+
+// Bucket of a chosen key: (kmax - key) scaled to the bucket count, so that a lower bucket holds
+// larger keys only.
+__device__ __forceinline__ uint32_t bucket_of(const Seg& s, int g, uint32_t key)
+{
+    const uint32_t kmax = s.st[g].kmax, range = kmax - s.st[g].prefix[kKeyPasses];
+    const int bits = range ? 32 - __clz(range) : 0;
+    const int shift = bits > s.bucket_log2 ? bits - s.bucket_log2 : 0;
+    return (kmax - key) >> shift;
+}
+
+__global__ __launch_bounds__(kThreads) void bucket_count_kernel(Seg s)
+{
+    const int g = blockIdx.y;
+    const uint32_t e = blockIdx.x * kThreads + threadIdx.x;
+    if (e >= s.st[g].k_eff) return;
+    const uint32_t b = bucket_of(s, g, score_key(s.sel_score[(size_t)g * s.k + e]));
+    atomicAdd(&s.bcnt[((size_t)g << s.bucket_log2) + b], 1u);
+}
+
+// Exclusive prefix of the bucket counts, one block per segment.
+__global__ __launch_bounds__(1024) void bucket_scan_kernel(Seg s)
+{
+    __shared__ uint32_t part[1024];
+    const int g = blockIdx.x;
+    const int t = threadIdx.x;
+    const uint32_t nb = 1u << s.bucket_log2;
+    const uint32_t per = (nb + 1023) / 1024;
+    const uint32_t* cnt = s.bcnt + ((size_t)g << s.bucket_log2);
+    uint32_t* base = s.bbase + ((size_t)g << s.bucket_log2);
+    uint32_t sum = 0u;
+    for (uint32_t i = t * per; i < min(nb, (t + 1) * per); ++i) sum += cnt[i];
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t add = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += add;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - sum;
+    for (uint32_t i = t * per; i < min(nb, (t + 1) * per); ++i) {
+        base[i] = run;
+        run += cnt[i];
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void bucket_scatter_kernel(Seg s)
+{
+    const int g = blockIdx.y;
+    const uint32_t e = blockIdx.x * kThreads + threadIdx.x;
+    if (e >= s.st[g].k_eff) return;
+    const float sc = s.sel_score[(size_t)g * s.k + e];
+    const uint32_t key = score_key(sc);
+    const size_t bb = ((size_t)g << s.bucket_log2) + bucket_of(s, g, key);
+    const uint32_t pos = s.bbase[bb] + atomicAdd(&s.bfill[bb], 1u);
+    s.tkey[(size_t)g * s.k + pos] = key;
+    s.tscore[(size_t)g * s.k + pos] = sc;
+    s.tindex[(size_t)g * s.k + pos] = s.sel_index[(size_t)g * s.k + e];
+}
+
+// out[g][rank] with rank = entries of the buckets before + entries of its own bucket that
+// precede it; the slots past k_eff get (-inf, -1).
+__global__ __launch_bounds__(kThreads) void bucket_rank_kernel(Seg s, float* __restrict__ out_score,
+                                                               int64_t* __restrict__ out_index)
+{
+    const int g = blockIdx.y;
+    const uint32_t k_eff = s.st[g].k_eff;
+    const uint32_t p = blockIdx.x * kThreads + threadIdx.x;
+    if (p >= (uint32_t)s.k) return;
+    if (p >= k_eff) {
+        out_score[(size_t)g * s.k + p] = -__builtin_huge_valf();
+        out_index[(size_t)g * s.k + p] = -1;
+        return;
+    }
+    const uint32_t* tk = s.tkey + (size_t)g * s.k;
+    const int64_t* ti = s.tindex + (size_t)g * s.k;
+    const uint32_t key = tk[p];
+    const int64_t ix = ti[p];
+    const size_t bb = ((size_t)g << s.bucket_log2) + bucket_of(s, g, key);
+    const uint32_t lo = s.bbase[bb], hi = lo + s.bcnt[bb];
+    uint32_t r = lo;
+    for (uint32_t q = lo; q < hi; ++q) r += (tk[q] > key) | ((tk[q] == key) & (ti[q] < ix)) ? 1u : 0u;
+    if (r < k_eff) {
+        out_score[(size_t)g * s.k + r] = s.tscore[(size_t)g * s.k + p];
+        out_index[(size_t)g * s.k + r] = ix;
+    }
+}
+
 // The whole selection for short segments (at most kSmallLen entries, k at most kSmallK) in
 // one block per segment: the same radix select, compaction, tie resolution and rank ordering
 // as the multi-block path, with the passes separated by block barriers instead of launches.
@@ -662,6 +825,16 @@ int topk_launch(Seg s, int64_t max_len, float* out_score, int64_t* out_index, hi
     for (int pass = 0; pass < n_pass; ++pass)
         hipLaunchKernelGGL(tie_hist_kernel, grid2, dim3(kThreads), 0, st, s, pass, n_pass);
     hipLaunchKernelGGL(tie_take_kernel, grid2, dim3(kThreads), 0, st, s, n_pass);
+    if (s.bcnt) {
+        // grouped by key bucket, then ranks within the buckets
+        hipLaunchKernelGGL(winners_max_kernel, dim3(kb, s.n_segs), dim3(kThreads), 0, st, s);
+        hipLaunchKernelGGL(bucket_count_kernel, dim3(kb, s.n_segs), dim3(kThreads), 0, st, s);
+        hipLaunchKernelGGL(bucket_scan_kernel, dim3(s.n_segs), dim3(1024), 0, st, s);
+        hipLaunchKernelGGL(bucket_scatter_kernel, dim3(kb, s.n_segs), dim3(kThreads), 0, st, s);
+        hipLaunchKernelGGL(bucket_rank_kernel, dim3(kb, s.n_segs), dim3(kThreads), 0, st, s, out_score,
+                           out_index);
+        return check_launch("bsh_topk");
+    }
     // rank counting: k x k comparisons spread over (k/256) x slices blocks
     const uint32_t n_slices = kb < 64 ? kb : 64;
     const uint32_t slice = (uint32_t)((s.k + n_slices - 1) / n_slices);

@@ -274,7 +274,10 @@ def _topk_ref(score, k, index=None):
                                       (46080, 100, "int"), (200000, 10000, "int"),
                                       (300001, 777, "float"), (100000, 5000, "const"),
                                       (65536, 2048, "int"), (65537, 2048, "float"),
-                                      (20000, 2049, "int"), (3000, 2048, "const")])
+                                      (20000, 2049, "int"), (3000, 2048, "const"),
+                                      # k > 16384: ordered within key buckets
+                                      (400000, 50000, "float"), (120000, 17000, "const"),
+                                      (20000, 30000, "float"), (1000000, 100000, "int")])
 def test_topk_exact(B, n, k, kind):
     import torch
     _say(f"topk n={n} k={k} {kind}")
@@ -297,27 +300,28 @@ def test_topk_exact(B, n, k, kind):
         assert np.all(_np(ix)[n:] == -1) and np.all(np.isneginf(_np(vs)[n:]))
 
 
-def test_topk_with_index_array_merges_lists(B):
+@pytest.mark.parametrize("per,k", [(3000, 1234), (30000, 20000)])
+def test_topk_with_index_array_merges_lists(B, per, k):
     """Merging per-item lists: top-k of a concatenation with explicit (large) indices."""
     import torch
-    _say("topk merge")
+    _say(f"topk merge per={per} k={k}")
     rng = np.random.default_rng(1)
     parts = []
     for item in range(6):
-        sc = rng.integers(0, 50, 3000).astype(np.float32)
-        idx = (np.int64(item) << 40) | rng.permutation(10**6)[:3000].astype(np.int64)
+        sc = rng.integers(0, 50, per).astype(np.float32)
+        idx = (np.int64(item) << 40) | rng.permutation(10**6)[:per].astype(np.int64)
         parts.append((sc, idx))
     allsc = np.concatenate([p[0] for p in parts])
     allix = np.concatenate([p[1] for p in parts])
-    vs, ix = B.bsh_topk(torch.from_numpy(allsc).cuda(), 1234, torch.from_numpy(allix).cuda())
+    vs, ix = B.bsh_topk(torch.from_numpy(allsc).cuda(), k, torch.from_numpy(allix).cuda())
     # merge of per-part top-k equals top-k of the union
     sub_s, sub_i = [], []
     for sc, idx in parts:
-        a, b = B.bsh_topk(torch.from_numpy(sc).cuda(), 1234, torch.from_numpy(idx).cuda())
+        a, b = B.bsh_topk(torch.from_numpy(sc).cuda(), k, torch.from_numpy(idx).cuda())
         sub_s.append(a); sub_i.append(b)
-    vs2, ix2 = B.bsh_topk(torch.cat(sub_s), 1234, torch.cat(sub_i))
+    vs2, ix2 = B.bsh_topk(torch.cat(sub_s), k, torch.cat(sub_i))
     torch.cuda.synchronize()
-    rv, ri = _topk_ref(allsc, 1234, allix)
+    rv, ri = _topk_ref(allsc, k, allix)
     assert np.array_equal(_np(ix), ri) and np.array_equal(_np(vs), rv)
     assert np.array_equal(_np(ix2), ri)
 
