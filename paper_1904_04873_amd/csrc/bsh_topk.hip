@@ -182,11 +182,6 @@ __device__ __forceinline__ uint32_t score_key(float f)
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-__device__ __forceinline__ float key_score(uint32_t k)
-{
-    const uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
-    return __uint_as_float(u);
-}
 
 __device__ __forceinline__ int64_t entry_index(const Seg& s, int g, int64_t e, int64_t lo)
 {
@@ -482,7 +477,6 @@ __global__ __launch_bounds__(kThreads) void tie_take_kernel(Seg s, int n_pass)
     int64_t lo, hi;
     seg_range(s, g, lo, hi);
     const uint32_t T = s.st[g].prefix[kKeyPasses];
-    const float sc = key_score(T);
     for_each_score(s.score, lo, hi, [&](int64_t e, float v) {
         const bool tie = score_key(v) == T;
         const int64_t ix = tie ? entry_index(s, g, e, lo) : 0;
@@ -491,16 +485,10 @@ __global__ __launch_bounds__(kThreads) void tie_take_kernel(Seg s, int n_pass)
         const bool take = tie && low <= cut;
         const uint32_t pos = wave_claim(&s.st[g].n_sel, take);
         if (take && pos < k_eff) {
-            s.sel_score[(size_t)g * s.k + pos] = sc;
+            s.sel_score[(size_t)g * s.k + pos] = v;
             s.sel_index[(size_t)g * s.k + pos] = ix;
         }
     });
-}
-
-__device__ __forceinline__ bool precedes(float sa, int64_t ia, float sb, int64_t ib)
-{
-    const uint32_t ka = score_key(sa), kb = score_key(sb);
-    return ka > kb || (ka == kb && ia < ib);
 }
 
 // rank(e) = number of chosen entries of segment g preceding e, accumulated over slices of
@@ -673,12 +661,13 @@ __global__ __launch_bounds__(kSmallThreads) void small_topk_kernel(Seg s, float*
                                                                    int64_t* __restrict__ out_index,
                                                                    int n_pass)
 {
-    __shared__ float sv[kStaged ? kStageLen : 1];
+    __shared__ uint32_t sv[kStaged ? kStageLen : 1];
     __shared__ uint32_t h[kBins], scan[kBins];
     __shared__ uint32_t prefix, remaining, n_sel, passed, tie_all;
     __shared__ int digit;
     __shared__ unsigned long long iprefix;
     __shared__ float cs[kSmallK];
+    __shared__ uint32_t ck[kSmallK];
     __shared__ int64_t ci[kSmallK];
     const int g = blockIdx.x;
     const int t = threadIdx.x;
@@ -701,9 +690,9 @@ __global__ __launch_bounds__(kSmallThreads) void small_topk_kernel(Seg s, float*
         tie_all = 0u;
     }
     if constexpr (kStaged)
-        for (int64_t e = t; e < len; e += kSmallThreads) sv[e] = s.score[lo + e];
-    // score of entry e (absolute position); the staged copy when there is one
-    auto score_at = [&](int64_t e) { return kStaged ? sv[e - lo] : s.score[e]; };
+        for (int64_t e = t; e < len; e += kSmallThreads) sv[e] = score_key(s.score[lo + e]);
+    // order-preserving key of entry e (absolute position); the staged copy when there is one
+    auto key_at = [&](int64_t e) { return kStaged ? sv[e - lo] : score_key(s.score[e]); };
     // 1. key digits, most significant first
     for (int pass = 0; pass < 4; ++pass) {
         for (int b = t; b < kBins; b += kSmallThreads) h[b] = 0u;
@@ -711,7 +700,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_topk_kernel(Seg s, float*
         const int shift = 24 - 8 * pass;
         const uint32_t pre = prefix;
         for (int64_t e = lo + t; e < hi; e += kSmallThreads) {
-            const uint32_t key = score_key(score_at(e));
+            const uint32_t key = key_at(e);
             wave_hist_add(h, pass == 0 || (key >> (shift + 8)) == pre, (key >> shift) & 0xffu);
         }
         __syncthreads();
@@ -731,12 +720,12 @@ __global__ __launch_bounds__(kSmallThreads) void small_topk_kernel(Seg s, float*
     const uint32_t T = prefix;
     // 2. everything better than T (and T itself when all of its entries are taken)
     for (int64_t e = lo + t; e < hi; e += kSmallThreads) {
-        const float sc = score_at(e);
-        const uint32_t key = score_key(sc);
+        const uint32_t key = key_at(e);
         const bool take = key > T || (tie_all != 0u && key == T);
         const uint32_t pos = wave_claim(&n_sel, take);
         if (take && pos < k_eff) {
-            cs[pos] = sc;
+            cs[pos] = s.score[e];
+            ck[pos] = key;
             ci[pos] = entry_index(s, g, e, lo);
         }
     }
@@ -747,7 +736,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_topk_kernel(Seg s, float*
         const int shift = 8 * (n_pass - 1 - pass);
         const unsigned long long pre = iprefix;
         for (int64_t e = lo + t; e < hi; e += kSmallThreads) {
-            const bool tie = score_key(score_at(e)) == T;
+            const bool tie = key_at(e) == T;
             unsigned long long ix = tie ? (unsigned long long)entry_index(s, g, e, lo) : 0ull;
             if (n_pass < 8) ix &= (1ull << (8 * n_pass)) - 1ull;
             wave_hist_add(h, tie && (pass == 0 || (ix >> (shift + 8)) == pre),
@@ -763,16 +752,16 @@ __global__ __launch_bounds__(kSmallThreads) void small_topk_kernel(Seg s, float*
     }
     if (remaining > 0u) {     // (remaining is block-uniform here)
         const unsigned long long cut = iprefix;
-        const float sc = key_score(T);
         for (int64_t e = lo + t; e < hi; e += kSmallThreads) {
-            const bool tie = score_key(score_at(e)) == T;
+            const bool tie = key_at(e) == T;
             const int64_t ix = tie ? entry_index(s, g, e, lo) : 0;
             unsigned long long low = (unsigned long long)ix;
             if (n_pass < 8) low &= (1ull << (8 * n_pass)) - 1ull;
             const bool take = tie && low <= cut;
             const uint32_t pos = wave_claim(&n_sel, take);
             if (take && pos < k_eff) {
-                cs[pos] = sc;
+                cs[pos] = s.score[e];
+                ck[pos] = T;
                 ci[pos] = ix;
             }
         }
@@ -780,12 +769,12 @@ __global__ __launch_bounds__(kSmallThreads) void small_topk_kernel(Seg s, float*
     __syncthreads();
     // 4. order by rank counting
     for (uint32_t e = t; e < k_eff; e += kSmallThreads) {
-        const float sc = cs[e];
+        const uint32_t key = ck[e];
         const int64_t ix = ci[e];
         uint32_t rank = 0u;
-        for (uint32_t f = 0; f < k_eff; ++f) rank += precedes(cs[f], ci[f], sc, ix) ? 1u : 0u;
+        for (uint32_t f = 0; f < k_eff; ++f) rank += (ck[f] > key) | ((ck[f] == key) & (ci[f] < ix)) ? 1u : 0u;
         if (rank < k_eff) {
-            os[rank] = sc;
+            os[rank] = cs[e];
             oi[rank] = ix;
         }
     }

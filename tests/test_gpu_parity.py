@@ -295,7 +295,8 @@ def test_topk_exact(B, n, k, kind):
     rv, ri = _topk_ref(sc, k)
     kk = min(n, k)
     assert np.array_equal(_np(ix)[:kk], ri)
-    assert np.array_equal(_np(vs)[:kk], rv.astype(np.float32))
+    # the listed scores are the input floats bit for bit (-0.0 included)
+    assert np.array_equal(_np(vs)[:kk].view(np.uint32), rv.astype(np.float32).view(np.uint32))
     if k > n:
         assert np.all(_np(ix)[n:] == -1) and np.all(np.isneginf(_np(vs)[n:]))
 
