@@ -124,8 +124,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU sharding is "
-                                   "described in DESIGN.md but not part of it", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; sharding the "
+                                   "items over several GPUs is not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np

@@ -64,15 +64,16 @@ constexpr int kFlushGroups = 64;     // eight-segment groups per register partia
 
 // Per staged segment: D cos(W t), D sin(W t) and the Doppler factor D of the tile's pixel.
 // The rows come first, so that a window's reads reach them with the small immediate offsets of
-// the paired LDS reads.
+// the paired LDS reads; the segment tables follow, so that their addresses fit the 16-bit
+// immediate offset of an LDS read at every chunk size (no address moves per segment).
 template <int kChunk>
 struct TileSmemLut {
     uint32_t row[kChunk * (BSH_MAX_WORDS + kRowPad)];
-    float T8[(kChunk / kGroup8) * 256];
-    float T[(kChunk / kGroup) * 16];
     double DC[kChunk];
     double DS[kChunk];
     double D[kChunk];
+    float T8[(kChunk / kGroup8) * 256];
+    float T[(kChunk / kGroup) * 16];
 };
 
 template <int kChunk>

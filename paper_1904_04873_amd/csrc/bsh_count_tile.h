@@ -107,33 +107,32 @@ __device__ __forceinline__ void band_step(const BandTrack& t, double F0, int las
                                           uint32_t& m2)
 {
     // The residual r_i = k_i - (k0 + i) steps once, at the first index past the crossing
-    // i* = num / den of y0 + i (G - 1) with the next integer above (a step up) or below (a step
-    // down): num = 1 - frac(y0) or frac(y0) (exact), den = +-(G - 1).  The single-
-    // precision q = num / den carries a relative error below 4e-7 (two conversions, the
-    // reciprocal, the product), i.e. below 4e-5 for i* < 96, and the canonical evaluations
-    // place the step within 3e-11 / |G - 1| < 3e-5 of i* when den >= 1e-6.  A q further than
-    // 1e-3 from an integer and below last is therefore floor(i*) and the step sits at
-    // floor(q) + 1; the rest (a few in a thousand, or a den of the wrong sign) is decided by
-    // canonical evaluations.
+    // i* = (u - frac(y0)) / (G - 1) of y0 + i (G - 1) with the next integer above (a step up,
+    // u = 1) or below (a step down, u = 0); the numerator is exact (y0 > 0, so frac(y0) =
+    // y0 - kf).  The single-precision q carries a relative error below 4e-7 (two conversions,
+    // the reciprocal, the product), i.e. below 4e-5 for i* < 96, and the canonical evaluations
+    // place the step within 3e-11 / |G - 1| < 3e-5 of i* when |G - 1| >= 1e-6.  A q further
+    // than 1e-3 from an integer, in (0, last), is therefore floor(i*) and the step sits at
+    // floor(q) + 1; the rest (a few in a thousand, or a G - 1 whose sign contradicts the
+    // step's direction, which makes q <= 0) is decided by canonical evaluations.
     const bool up = t.span > last;
-    const double f = t.y0 - (double)t.kf;
-    const float num = (float)(up ? 1.0 - f : f);
+    const double f = __builtin_amdgcn_fract(t.y0);
+    const float num = (float)((up ? 1.0 : 0.0) - f);
     const float gm1 = (float)(t.G - 1.0);
-    const float den = up ? gm1 : -gm1;
-    const float q = num * __builtin_amdgcn_rcpf(den);
-    const bool sure = (fabsf(__builtin_amdgcn_fractf(q) - 0.5f) < 0.499f) & (q < (float)last) & (den >= 1e-6f);
+    const float q = num * __builtin_amdgcn_rcpf(gm1);
+    // 0 <= q < last as one unsigned comparison of the bit patterns (negative q and NaN have the
+    // sign or all exponent bits set); q = 0 fails the distance test
+    const bool in_band = __float_as_uint(q) < __float_as_uint((float)last);
+    const bool sure = (fabsf(__builtin_amdgcn_fractf(q) - 0.5f) < 0.499f) & in_band & (fabsf(gm1) >= 1e-6f);
     int hi = sure ? (int)q + 1 : 0;
     if (!sure) hi = step_exact(t.G, t.kf, F0, last, q);
-    uint32_t n0, n1, n2;
-    if (up) {
-        n0 = __builtin_amdgcn_alignbit(m1, m0, 1);
-        n1 = __builtin_amdgcn_alignbit(m2, m1, 1);
-        n2 = m2 >> 1;
-    } else {
-        n0 = m0 << 1;
-        n1 = __builtin_amdgcn_alignbit(m1, m0, 31);
-        n2 = __builtin_amdgcn_alignbit(m2, m1, 31);
-    }
+    // the 96-bit mask moved by one bin: down a bit (a step up: bin i takes bin i + 1's bit) or
+    // up a bit, as funnel shifts by 1 or 31 of the words (m2, m1, m0) framed by zeros
+    const uint32_t b0 = up ? m0 : 0u, b1 = up ? m1 : m0, b2 = up ? m2 : m1, b3 = up ? 0u : m2;
+    const uint32_t by = up ? 1u : 31u;
+    const uint32_t n0 = __builtin_amdgcn_alignbit(b1, b0, by);
+    const uint32_t n1 = __builtin_amdgcn_alignbit(b2, b1, by);
+    const uint32_t n2 = __builtin_amdgcn_alignbit(b3, b2, by);
     // bits hi.. of the 96-bit mask (1 <= hi < 96): one shift, placed by word
     const uint32_t sh = 0xffffffffu << (hi & 31);
     const uint32_t s0 = hi < 32 ? sh : 0u;
