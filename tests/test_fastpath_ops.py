@@ -1,0 +1,25 @@
+"""The per-unit work bench.py prices the count kernel's roofline with (VALU instructions per group
+of eight segments on the table variant's fast path) is the count that fastpath_ops.py reads from
+the kernel's gfx950 assembly, for every chunk size the autotuner may pick.  Compiles the count
+kernel to assembly on the host (no GPU needed)."""
+import os
+import shutil
+import sys
+
+import pytest
+
+ROOT = os.path.join(os.path.dirname(__file__), "..")
+sys.path.insert(0, ROOT)
+sys.path.insert(0, os.path.join(ROOT, "paper_1904_04873_amd"))
+
+
+@pytest.mark.skipif(not (os.path.exists("/opt/rocm/bin/hipcc") or shutil.which("hipcc")), reason="hipcc not found")
+def test_bench_floor_matches_the_assembly():
+    import bench
+    import fastpath_ops
+
+    asm = fastpath_ops.assembly()
+    for chunk in (128, 256, 512):
+        valu, seg = fastpath_ops.fast_path(chunk, asm)
+        assert seg == 8
+        assert valu / (seg * fastpath_ops.N_F0) == pytest.approx(bench.TABLE_OPS_PER_TS, rel=1e-12), chunk
