@@ -206,6 +206,37 @@ def test_count_edge_cases(B):
     assert float(ws.abs().sum()) == 0.0 and int(cnt.sum()) == 0
 
 
+@pytest.mark.parametrize("n_f0", [1, 2, 32, 33, 64, 65, 89, 90])
+def test_count_widest_row_tracks_at_its_top(B, n_f0):
+    """The widest staged row (BSH_MAX_WORDS words, 512 bins) with the band at its top edge, so the
+    windows reach the last words and the zero padding after them; every f0 count from one bin to
+    the full band and across the 32-bin word boundaries of the masks.  Full map against the
+    oracle."""
+    _say(f"count widest row n_f0={n_f0}")
+    k0, top = 90000, 14                   # the tracks drift by at most about 11 bins here
+    base = S.tiny_segments(n_seg=50, k0=k0, n_f0=n_f0, margin=top, seed=30 + n_f0, span_days=60)
+    n_bins = 512
+    k_lo = k0 + n_f0 + top - n_bins
+    rng = np.random.default_rng(60 + n_f0)
+    seg = S.Segments(t_mid=base.t_mid, v_over_c=base.v_over_c, weight=base.weight,
+                     power=rng.exponential(1.0, (base.n_seg, n_bins)).astype(np.float32), k_lo=k_lo,
+                     n_bins=n_bins)
+    spec = S.GridSpec(k0=k0, n_f0=n_f0, ap_lo=0.05, ap_hi=3.0, n_ap=3, per_lo=15 * S.DAY,
+                      per_hi=45 * S.DAY, n_per=2, tasc_fixed=11)
+    _, g, o, ws, cnt = _run_count(B, seg, spec, S.fixed_pixel())
+    c_o, nw_o, nt_o, ntw_o = O.hough_count(seg, S.fixed_pixel(), k0, n_f0, *o)
+    _check_counts(cnt, ws, c_o, nw_o, nt_o, ntw_o)
+    if nt_o.sum() == 0:
+        assert np.array_equal(cnt, c_o)
+    # the table variant (the default) gives the same weighted sums as select-and-add
+    import torch
+    ds = B.DeviceSegments.from_host(seg)
+    ws_t, _ = B.bsh_hough_count(ds, g)
+    torch.cuda.synchronize()
+    err = np.abs(_np(ws_t).astype(np.float64) - nw_o)
+    assert np.all(err <= REL * np.abs(nw_o) + ntw_o + 1e-30)
+
+
 def test_count_noiseless_injection_full_weight(B):
     import torch
     _say("count noiseless injection")
