@@ -339,7 +339,8 @@ def run_post(bsh, ds, g, s1_score, s1_index, t_coh, t_mid, st):
 def run_refine(bsh, spec, st):
     """The differentiable stage 2 at its real size (not part of the step): 10^5 off-grid
     candidates over 4000 segments (the 200 Hz band layout, noise only), one forward
-    (interpolated power), one backward (adjoint kernel) and 20 Adam steps."""
+    (interpolated power), one backward (adjoint kernel), both from one pass, and 20 Adam steps
+    with the one-pass kernel and through autograd (forward and backward kernels)."""
     import numpy as np
     import torch
     import bsh_synth as S
@@ -378,12 +379,14 @@ def run_refine(bsh, spec, st):
 
     fwd = timed(lambda: bsh.bsh_power_stat(ds, sky, cs, th, mode=1, status=st))
     bwd = timed(lambda: bsh.bsh_power_stat_grad(ds, sky, cs, th, status=st))
+    both = timed(lambda: bsh.bsh_power_stat_value_and_grad(ds, sky, cs, th, status=st))
     adam = timed(lambda: refine(th, stp, ds, sky, cs, n_iter=20, lr=0.05, status=st), reps=1)
+    adam_ag = timed(lambda: refine(th, stp, ds, sky, cs, n_iter=20, lr=0.05, status=st, fused=False), reps=1)
     st.raise_if_set("refinement")
     cs_n = n * seg.n_seg
     return {"candidates": n, "segments": seg.n_seg, "forward_ms": fwd, "backward_ms": bwd,
-            "adam_20_steps_ms": adam, "forward_cand_seg_per_s": cs_n / (fwd / 1e3),
-            "backward_cand_seg_per_s": cs_n / (bwd / 1e3)}
+            "value_and_grad_ms": both, "adam_20_steps_ms": adam, "adam_20_steps_autograd_ms": adam_ag,
+            "forward_cand_seg_per_s": cs_n / (fwd / 1e3), "backward_cand_seg_per_s": cs_n / (bwd / 1e3)}
 
 
 def run_allsky(args):

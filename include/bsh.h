@@ -238,6 +238,22 @@ int bsh_power_stat_grad(const bsh_segments* seg, const double* sky, int32_t n_sk
                         double* grad_params, int32_t* status, bsh_stream stream);
 
 /*
+ * The mode-1 statistic and its vector-Jacobian product in one pass over the segments (both
+ * come from the same track and the same two row values per segment), for gradient ascent
+ * of P_lin, which needs both every step:
+ *   P_out[c] = P_lin of bsh_power_stat mode 1 (its FP32 terms summed in runs as there, the
+ *              partial sums of the candidate's threads then added in FP64: equal to the
+ *              mode-1 result within the FP32 summation bound, not bit for bit);
+ *   grad_params as bsh_power_stat_grad, bit for bit.
+ * P_out and grad_params must not be NULL; grad_P may be NULL (all ones).  Status bits,
+ * errors and the right-hand derivative at integer x are those of bsh_power_stat_grad.
+ */
+int bsh_power_stat_value_and_grad(const bsh_segments* seg, const double* sky, int32_t n_sky,
+                                  const int32_t* cand_sky, const double* cand_params, int64_t n,
+                                  const double* grad_P, float* P_out, double* grad_params,
+                                  int32_t* status, bsh_stream stream);
+
+/*
  * Stage-2 statistic on the low-eccentricity (ELL1) track of eq:frequencyevo (Sec. II), for
  * orbits the circular model only approximates (Sec. IV.E bounds when that matters):
  *   x = F (1 + v.n) (1 - a_p W [cos psi + (e cos w) cos 2psi - (e sin w) sin 2psi]),

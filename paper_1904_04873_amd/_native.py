@@ -149,6 +149,8 @@ SIGNATURES = {
                                           _vp, _vp, _vp]),
     "bsh_power_stat_grad": (ctypes.c_int, [ctypes.POINTER(Segments), _vp, _c_i32, _vp, _vp, _c_i64,
                                            _vp, _vp, _vp, _vp]),
+    "bsh_power_stat_value_and_grad": (ctypes.c_int, [ctypes.POINTER(Segments), _vp, _c_i32, _vp, _vp,
+                                                     _c_i64, _vp, _vp, _vp, _vp, _vp]),
     "bsh_post_rows": (ctypes.c_int, [_vp, _vp, _vp, _c_i64, _c_f64, _vp, _vp]),
     "bsh_significance": (ctypes.c_int, [_vp, _c_i64, _vp, _c_i64, _c_i32, _c_f64, _vp, _vp]),
     "bsh_coincidences_workspace": (ctypes.c_size_t, [_c_i64]),

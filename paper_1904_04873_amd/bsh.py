@@ -21,6 +21,7 @@ __all__ = [
     "BshError", "DeviceSegments", "DeviceGrid", "Status", "TopK", "Plan", "bsh_version",
     "bsh_grid_build", "bsh_normalize", "bsh_peakgram", "bsh_hough_count", "bsh_topk",
     "bsh_decode_templates", "bsh_power_stat", "bsh_power_stat_ecc", "bsh_power_stat_grad",
+    "bsh_power_stat_value_and_grad",
     "bsh_track_bins", "post_params", "bsh_post_rows", "bsh_significance", "bsh_coincidences",
     "bsh_cluster", "bsh_cluster_centroids",
 ]
@@ -324,6 +325,22 @@ def bsh_power_stat_grad(seg: DeviceSegments, sky: torch.Tensor, cand_sky: torch.
                                        status.ptr() if status else None, _stream()),
           "bsh_power_stat_grad")
     return out
+
+
+def bsh_power_stat_value_and_grad(seg: DeviceSegments, sky: torch.Tensor, cand_sky: torch.Tensor,
+                                  cand_params: torch.Tensor, grad_P: Optional[torch.Tensor] = None,
+                                  status: Optional[Status] = None):
+    """(P_lin float32 [n], grad_P * d P_lin / d(F, a_p, P, t_asc) float64 [n, 4]) in one pass."""
+    n = int(cand_sky.numel())
+    P = torch.empty(n, dtype=torch.float32, device=cand_sky.device)
+    out = torch.empty((n, 4), dtype=torch.float64, device=cand_sky.device)
+    gp = None if grad_P is None else grad_P.to(torch.float64).contiguous()
+    s_c = seg.struct()
+    check(N.load().bsh_power_stat_value_and_grad(ctypes.byref(s_c), _ptr(sky), int(sky.shape[0]),
+                                                 _ptr(cand_sky), _ptr(cand_params), n, _ptr(gp), _ptr(P),
+                                                 _ptr(out), status.ptr() if status else None, _stream()),
+          "bsh_power_stat_value_and_grad")
+    return P, out
 
 
 def bsh_track_bins(seg: DeviceSegments, sky: torch.Tensor, cand_sky: torch.Tensor,

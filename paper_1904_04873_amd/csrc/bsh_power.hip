@@ -121,12 +121,16 @@ __global__ __launch_bounds__(kStatC * kStatP) void power_stat_kernel(
     }
 }
 
+// kValue: also P_lin itself (the mode-1 statistic) from the same gathers, so that a gradient
+// step needs one pass over the segments instead of a forward and a backward pass.  The gradient
+// is the same computation, in the same order, with or without it.
+template <bool kValue>
 __global__ __launch_bounds__(kGradC * kGradP) void power_grad_kernel(
     const double* __restrict__ t_mid, const double* __restrict__ v, const float* __restrict__ w,
     int32_t w_per_sky, const float* __restrict__ power, int32_t n_bins, int64_t k_lo, int64_t n_seg,
     const double* __restrict__ sky, int32_t n_sky, const int32_t* __restrict__ cand_sky,
     const double* __restrict__ cand, int64_t n, const double* __restrict__ grad_P,
-    double* __restrict__ grad, int32_t* status)
+    double* __restrict__ grad, float* __restrict__ P_out, int32_t* status)
 {
     __shared__ double red[kGradC * kGradP];
     const int cl = threadIdx.x % kGradC, p = threadIdx.x / kGradC;
@@ -134,6 +138,7 @@ __global__ __launch_bounds__(kGradC * kGradP) void power_grad_kernel(
     int32_t s;
     const bool ok = cand_sky_ok(cand_sky, c, n, n_sky, s);
     double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
+    RunSum P;
     bool bad = false;
     if (ok) {
         const Cand cd = load_cand(cand + 4 * c);
@@ -153,6 +158,10 @@ __global__ __launch_bounds__(kGradC * kGradP) void power_grad_kernel(
             const int col = (int)(kf - klo);
             if (col < 0 || col + 1 >= n_bins) { bad = true; continue; }
             const float* row = power + J * n_bins + col;
+            if (kValue) {
+                const float a = (float)(x - kf);
+                P.add(wr[J] * ((1.f - a) * row[0] + a * row[1]));
+            }
             const double S = (double)wr[J] * ((double)row[1] - (double)row[0]);
             const double FD = cd.F * D;
             g0 += S * (D * B);
@@ -167,12 +176,18 @@ __global__ __launch_bounds__(kGradC * kGradP) void power_grad_kernel(
     g1 = phase_sum<kGradC, kGradP>(g1, red);
     g2 = phase_sum<kGradC, kGradP>(g2, red);
     g3 = phase_sum<kGradC, kGradP>(g3, red);
+    float Pt = 0.f;
+    if (kValue) {
+        // the doubles' LDS tree holds the float partial sums too (converted exactly)
+        Pt = (float)phase_sum<kGradC, kGradP>((double)P.value(), red);
+    }
     if (p == 0 && c < n) {
         const double sc = ok ? (grad_P ? grad_P[c] : 1.0) : 0.0;
         grad[4 * c + 0] = sc * g0;
         grad[4 * c + 1] = sc * g1;
         grad[4 * c + 2] = sc * g2;
         grad[4 * c + 3] = sc * g3;
+        if (kValue) P_out[c] = Pt;
     }
 }
 
@@ -261,10 +276,11 @@ extern "C" int bsh_power_stat(const bsh_segments* seg, const double* sky, int32_
     return check_launch("bsh_power_stat");
 }
 
-extern "C" int bsh_power_stat_grad(const bsh_segments* seg, const double* sky, int32_t n_sky,
-                                   const int32_t* cand_sky, const double* cand_params, int64_t n,
-                                   const double* grad_P, double* grad_params, int32_t* status,
-                                   bsh_stream stream)
+namespace {
+
+int launch_grad(const bsh_segments* seg, const double* sky, int32_t n_sky, const int32_t* cand_sky,
+                const double* cand_params, int64_t n, const double* grad_P, double* grad_params,
+                float* P_out, int32_t* status, bsh_stream stream, const char* what)
 {
     clear_error();
     int rc = check_segments(seg, false, true);
@@ -275,11 +291,36 @@ extern "C" int bsh_power_stat_grad(const bsh_segments* seg, const double* sky, i
     if (!sky || !cand_sky || !cand_params || !grad_params) return fail_inval("NULL pointer");
     const int64_t blocks = (n + kGradC - 1) / kGradC;
     if (blocks > 0x7fffffff) return fail_inval("too many candidates");
-    hipLaunchKernelGGL(power_grad_kernel, dim3((unsigned)blocks), dim3(kGradC * kGradP), 0,
-                       (hipStream_t)stream, seg->t_mid, seg->v_over_c, seg->weight,
-                       seg->weight_per_sky, seg->power, seg->n_bins, seg->k_lo, seg->n_seg, sky,
-                       n_sky, cand_sky, cand_params, n, grad_P, grad_params, status);
-    return check_launch("bsh_power_stat_grad");
+    auto kernel = P_out ? power_grad_kernel<true> : power_grad_kernel<false>;
+    hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kGradC * kGradP), 0, (hipStream_t)stream,
+                       seg->t_mid, seg->v_over_c, seg->weight, seg->weight_per_sky, seg->power,
+                       seg->n_bins, seg->k_lo, seg->n_seg, sky, n_sky, cand_sky, cand_params, n, grad_P,
+                       grad_params, P_out, status);
+    return check_launch(what);
+}
+
+}  // namespace
+
+extern "C" int bsh_power_stat_grad(const bsh_segments* seg, const double* sky, int32_t n_sky,
+                                   const int32_t* cand_sky, const double* cand_params, int64_t n,
+                                   const double* grad_P, double* grad_params, int32_t* status,
+                                   bsh_stream stream)
+{
+    return launch_grad(seg, sky, n_sky, cand_sky, cand_params, n, grad_P, grad_params, nullptr, status,
+                       stream, "bsh_power_stat_grad");
+}
+
+extern "C" int bsh_power_stat_value_and_grad(const bsh_segments* seg, const double* sky, int32_t n_sky,
+                                             const int32_t* cand_sky, const double* cand_params, int64_t n,
+                                             const double* grad_P, float* P_out, double* grad_params,
+                                             int32_t* status, bsh_stream stream)
+{
+    if (!P_out && n > 0) {
+        clear_error();
+        return fail_inval("P_out is NULL");
+    }
+    return launch_grad(seg, sky, n_sky, cand_sky, cand_params, n, grad_P, grad_params, P_out, status,
+                       stream, "bsh_power_stat_value_and_grad");
 }
 
 extern "C" int bsh_power_stat_ecc(const bsh_segments* seg, const double* sky, int32_t n_sky,

@@ -126,6 +126,12 @@ def test_other_entry_points_reject_bad_arguments():
     assert L.bsh_power_stat(ctypes.byref(seg), fake, 1, fake, fake, 10, 1, fake, fake, None, None, None) == N.BSH_EINVAL
     assert L.bsh_power_stat(ctypes.byref(seg), fake, 0, fake, fake, 10, 0, fake, None, None, None, None) == N.BSH_EINVAL
     assert L.bsh_power_stat_grad(ctypes.byref(seg), fake, 1, fake, fake, -1, None, fake, None, None) == N.BSH_EINVAL
+    assert L.bsh_power_stat_value_and_grad(ctypes.byref(seg), fake, 1, fake, fake, 5, None, None, fake, None,
+                                           None) == N.BSH_EINVAL
+    assert L.bsh_power_stat_value_and_grad(ctypes.byref(seg), fake, 1, fake, fake, 5, None, fake, None, None,
+                                           None) == N.BSH_EINVAL
+    assert L.bsh_power_stat_value_and_grad(ctypes.byref(seg), fake, 0, fake, fake, 5, None, fake, fake, None,
+                                           None) == N.BSH_EINVAL
     assert L.bsh_track_bins(ctypes.byref(seg), None, 1, fake, fake, 3, fake, None, None) == N.BSH_EINVAL
     assert L.bsh_peakgram(fake, 10, 0, 1.6, fake, None) == N.BSH_EINVAL
     assert L.bsh_peakgram(fake, 10, 5, float("nan"), fake, None) == N.BSH_EINVAL

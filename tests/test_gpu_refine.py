@@ -58,6 +58,51 @@ def test_autograd_function_matches_adjoint_kernel():
     assert torch.equal(P.float(), P1)
 
 
+def test_value_and_grad_is_one_pass_of_both():
+    """bsh_power_stat_value_and_grad: the gradient equals bsh_power_stat_grad bit for bit, P_lin
+    equals the mode-1 statistic and the oracle within the FP32 summation bound; a bad sky index
+    gives zeros and the input status bit; the fused Adam loop reproduces the autograd loop's
+    iterates exactly."""
+    import torch
+    from paper_1904_04873_amd import _native as N
+    from paper_1904_04873_amd import bsh
+    from paper_1904_04873_amd.refine import refine
+    _say("value and gradient in one pass")
+    w, seg, inj, snr, cand, st = _setup(n_per_inj=50)
+    n = cand.shape[0]
+    ds = bsh.DeviceSegments.from_host(seg)
+    sky = torch.from_numpy(w.sky).cuda()
+    cs_h = np.zeros(n, np.int32)
+    cs_h[7] = 5                                   # no such pixel
+    cs = torch.from_numpy(cs_h).cuda()
+    th = torch.from_numpy(cand).cuda()
+    gp = torch.from_numpy(np.random.default_rng(3).standard_normal(n)).cuda()
+    st_f, st_s = bsh.Status(torch.device("cuda")), bsh.Status(torch.device("cuda"))
+    P, g = bsh.bsh_power_stat_value_and_grad(ds, sky, cs, th, gp, status=st_f)
+    g_sep = bsh.bsh_power_stat_grad(ds, sky, cs, th, gp, status=st_s)
+    P_sep = bsh.bsh_power_stat(ds, sky, cs, th, mode=1, status=st_s)
+    torch.cuda.synchronize()
+    assert torch.equal(g, g_sep)
+    assert st_f.value() == st_s.value() and st_f.value() & N.STATUS_INPUT
+    ok = cs_h == 0
+    Pf, Ps = P.cpu().numpy().astype(np.float64), P_sep.cpu().numpy().astype(np.float64)
+    assert Pf[7] == 0.0 and np.all(g.cpu().numpy()[7] == 0.0)
+    assert np.all(np.abs(Pf[ok] - Ps[ok]) <= 2e-5 * np.abs(Ps[ok]))
+    pick = np.nonzero(ok)[0][::10]
+    P_o, _, _, _ = O.power_stat(seg, w.sky, np.zeros(pick.size, np.int32), cand[pick], mode=1)
+    assert np.all(np.abs(Pf[pick] - P_o) <= 1e-5 * np.abs(P_o))
+    # the two refinement routes: identical iterates (the gradients are identical)
+    cs0 = torch.zeros(n, dtype=torch.int32, device="cuda")
+    stp = torch.from_numpy(st).cuda()
+    t_f, h_f = refine(th, stp, ds, sky, cs0, n_iter=5, fused=True)
+    t_a, h_a = refine(th, stp, ds, sky, cs0, n_iter=5, fused=False)
+    torch.cuda.synchronize()
+    assert torch.equal(t_f, t_a)
+    hf, ha = h_f.cpu().numpy(), h_a.cpu().numpy()
+    assert np.array_equal(hf[-1], ha[-1])
+    assert np.all(np.abs(hf - ha) <= 2e-5 * np.abs(ha))
+
+
 def test_adjoint_matches_frozen_bin_fd_of_oracle():
     """GPU adjoint vs central differences (h = 1e-3 grid step) of the oracle's FP64 P_lin with
     the bins frozen at theta."""
