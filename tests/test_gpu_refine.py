@@ -187,6 +187,12 @@ def test_refinement_at_full_size_matches_oracle_on_samples():
     assert np.all(np.abs(P[pick] - P_o) <= 1e-5 * np.abs(P_o))
     g_o, a_o = O.power_grad(seg, w.sky, np.zeros(500, np.int32), cand[pick], with_abs=True)
     assert np.all(np.abs(g[pick] - g_o) <= 1e-5 * a_o + 1e-12)
+    # the one-pass kernel at full size: the same gradient bit for bit, P_lin within the bound
+    P_f, g_f = bsh.bsh_power_stat_value_and_grad(ds, sky, cs, th, status=status)
+    torch.cuda.synchronize()
+    assert np.array_equal(g_f.cpu().numpy(), g)
+    P_f = P_f.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(P_f[pick] - P_o) <= 1e-5 * np.abs(P_o))
     theta, hist = refine(th, torch.from_numpy(st).cuda(), ds, sky, cs, n_iter=20, lr=0.05, status=status)
     torch.cuda.synchronize()
     status.raise_if_set("full-size refinement")
