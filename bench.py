@@ -434,7 +434,8 @@ def run_allsky(args):
 
 
 def run_batched(args):
-    """Full batching workload: one graph-captured persistent launch vs one plain launch per item."""
+    """Full batching workload: one graph-captured persistent launch vs one plain launch per item,
+    each form with the tile the autotuner finds fastest for it."""
     import numpy as np
     import torch
 
@@ -460,6 +461,8 @@ def run_batched(args):
     print(f"[bench] batching workload resident: {ts_total:.3e} template*segments; autotuning",
           file=sys.stderr, flush=True)
     (lanes, chunk), tune_ms = autotune.tune(items, grids, 4, sample=16, use_cache=False)
+    # the plain baseline runs with the tile that suits one launch per item best
+    (lanes_p, chunk_p), tune_p_ms = autotune.tune(items, grids, 4, sample=16, use_cache=False, plain=True)
     k_item, k_band = 1000, 1000
     st = bsh.Status(dev)
     plan = bsh.Plan(items, grids, 4, k_item=k_item, k_band=k_band, lanes=lanes, chunk=chunk,
@@ -484,11 +487,15 @@ def run_batched(args):
     ms_b = timed(plan.run, args.batched_steps)
     st.raise_if_set("batched")
     ref = plan.band_index.clone()
+    units, blocks = plan.units, plan.blocks
+    if (lanes_p, chunk_p) != (lanes, chunk):
+        plan.close()
+        plan = bsh.Plan(items, grids, 4, k_item=k_item, k_band=k_band, lanes=lanes_p, chunk=chunk_p,
+                        use_graph=True, lpt=True, status=st)
     print("[bench] plain runs", file=sys.stderr, flush=True)
     ms_p = timed(plan.run_plain, args.batched_steps)
     st.raise_if_set("plain")
     same = bool(torch.equal(ref, plan.band_index))
-    units, blocks = plan.units, plan.blocks
     plan.close()
     return {
         "workload": "256 sky patches x 4 bands of 0.1 Hz (f_lo 100.0/166.6/233.2/299.8 Hz): 1024 items "
@@ -503,7 +510,9 @@ def run_batched(args):
         "speedup": ms_p / ms_b,
         "lists_identical": same,
         "tile": {"lanes": lanes, "chunk": chunk},
+        "plain_tile": {"lanes": lanes_p, "chunk": chunk_p},
         "autotune_ms": {f"{l}x{c}": t for (l, c), t in tune_ms.items()},
+        "autotune_plain_ms": {f"{l}x{c}": t for (l, c), t in tune_p_ms.items()},
         "units": units,
         "persistent_blocks": blocks,
     }

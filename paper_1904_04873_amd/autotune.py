@@ -48,16 +48,17 @@ def _store(db: Dict[str, dict]) -> None:
         pass
 
 
-def time_plan(plan: "bsh.Plan", reps: int = 2) -> float:
-    """Median milliseconds of plan.run() over reps runs after one warmup."""
-    plan.run()
+def time_plan(plan: "bsh.Plan", reps: int = 2, plain: bool = False) -> float:
+    """Median milliseconds of plan.run() (or plan.run_plain()) over reps runs after one warmup."""
+    run = plan.run_plain if plain else plan.run
+    run()
     torch.cuda.synchronize()
     ts = []
     for _ in range(reps):
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record()
-        plan.run()
+        run()
         b.record()
         torch.cuda.synchronize()
         ts.append(a.elapsed_time(b))
@@ -101,12 +102,14 @@ def tune_plain(seg: "bsh.DeviceSegments", grid: "bsh.DeviceGrid", shapes=SHAPES,
 
 
 def tune(items: Sequence, grids: Sequence["bsh.DeviceGrid"], n_bands: int, sample: int = 16,
-         shapes: Sequence[Tuple[int, int]] = SHAPES, use_cache: bool = True, verbose: bool = False):
+         shapes: Sequence[Tuple[int, int]] = SHAPES, use_cache: bool = True, verbose: bool = False,
+         plain: bool = False):
     """Best (lanes, chunk) for these items; returns (shape, {shape: ms}).
 
-    Times the batched count (no top-lists) over an evenly spaced sample of the items."""
+    Times the batched count (no top-lists) over an evenly spaced sample of the items, or with
+    ``plain`` the same items as one launch each (the tile that form runs fastest with)."""
     dev = torch.cuda.get_device_name(0)
-    key = dev + "|" + _signature(items, grids)
+    key = dev + ("|plain-items|" if plain else "|") + _signature(items, grids)
     db = _load() if use_cache else {}
     if use_cache and key in db:
         e = db[key]
@@ -120,10 +123,11 @@ def tune(items: Sequence, grids: Sequence["bsh.DeviceGrid"], n_bands: int, sampl
     times = {}
     for shape in shapes:
         plan = bsh.Plan(sub, grids, len(bands), lanes=shape[0], chunk=shape[1], use_graph=False)
-        times[shape] = time_plan(plan)
+        times[shape] = time_plan(plan, plain=plain)
         plan.close()
         if verbose:
-            print(f"[autotune] lanes={shape[0]} chunk={shape[1]}: {times[shape]:.3f} ms", flush=True)
+            print(f"[autotune] {'plain ' if plain else ''}lanes={shape[0]} chunk={shape[1]}: "
+                  f"{times[shape]:.3f} ms", flush=True)
     best = min(times, key=times.get)
     if use_cache:
         db[key] = {"lanes": best[0], "chunk": best[1],
