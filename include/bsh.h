@@ -238,9 +238,10 @@ int bsh_power_stat_grad(const bsh_segments* seg, const double* sky, int32_t n_sk
                         double* grad_params, int32_t* status, bsh_stream stream);
 
 /*
- * The mode-1 statistic and its vector-Jacobian product in one pass over the segments (both
- * come from the same track and the same two row values per segment), for gradient ascent
- * of P_lin, which needs both every step:
+ * The mode-1 statistic (the bin-interpolated extension of Sec. IV.C eq:hough3) and its
+ * vector-Jacobian product in one pass over the segments (both come from the same track and
+ * the same two row values per segment), for gradient ascent of P_lin, which needs both every
+ * step:
  *   P_out[c] = P_lin of bsh_power_stat mode 1 (its FP32 terms summed in runs as there, the
  *              partial sums of the candidate's threads then added in FP64: equal to the
  *              mode-1 result within the FP32 summation bound, not bit for bit);
