@@ -233,6 +233,7 @@ def main():
 
     post = run_post(bsh, ds, g, s1_score, s1_index, seg.t_coh, seg.t_span_mid(), st)
     refine = run_refine(bsh, spec, st)
+    beside = run_beside(bsh, w, st, *bsh.bsh_decode_templates(g, s1_index))
 
     batched = None if args.skip_batched else run_batched(args)
     allsky = run_allsky(args) if (args.allsky_pixels > 0 and not args.skip_batched) else None
@@ -300,6 +301,7 @@ def main():
         "cpu_baseline": cpu,
         "post": post,
         "refine": refine,
+        "beside_path": beside,
         "batched": batched,
         "allsky": allsky,
     }
@@ -387,6 +389,55 @@ def run_refine(bsh, spec, st):
     return {"candidates": n, "segments": seg.n_seg, "forward_ms": fwd, "backward_ms": bwd,
             "value_and_grad_ms": both, "adam_20_steps_ms": adam, "adam_20_steps_autograd_ms": adam_ag,
             "forward_cand_seg_per_s": cs_n / (fwd / 1e3), "backward_cand_seg_per_s": cs_n / (bwd / 1e3)}
+
+
+def run_beside(bsh, w, st, cs, cp):
+    """The steps beside the path, timed on the 200 Hz band layout (not part of the step): the
+    running-median normalization of the raw spectra, stage 2 on the Tc/2-shifted doubled segment
+    set, and stage 2 on the low-eccentricity track, each for the step's 10^4 stage-1 winners."""
+    import numpy as np
+    import torch
+    import bsh_synth as S
+
+    seg = w.segments[0]
+    sky = torch.from_numpy(w.sky).cuda()
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    # normalization: raw rows 100 bins wider than the band's row, window 101
+    raw = torch.from_numpy(S.raw_sft_powers(np.random.default_rng(5), seg.n_seg, seg.n_bins + 100,
+                                            seg.k_lo - 50)).cuda()
+    rho = torch.empty((seg.n_seg, seg.n_bins), dtype=torch.float32, device="cuda")
+    ms_norm = timed(lambda: bsh.bsh_normalize(raw, 101, out=rho))
+    # the doubled set: the band's segments and their Tc/2-shifted companions in one table
+    comp = S.half_shifted(seg, np.random.default_rng(21))
+    du = bsh.DeviceSegments.from_host(S.concat_segments(seg, comp))
+    ms_dbl = timed(lambda: bsh.bsh_power_stat(du, sky, cs, cp, mode=0, status=st))
+    # the ELL1 track: the winners with e cos w = 0.01, e sin w = -0.005
+    n = int(cs.numel())
+    cpe = torch.cat([cp, torch.tensor([[0.01, -0.005]], dtype=torch.float64, device="cuda").expand(n, 2)],
+                    dim=1).contiguous()
+    ds = bsh.DeviceSegments.from_host(seg)
+    ms_ecc = timed(lambda: bsh.bsh_power_stat_ecc(ds, sky, cs, cpe, mode=0, status=st))
+    st.raise_if_set("steps beside the path")
+    return {
+        "normalize": {"segments": seg.n_seg, "raw_bins": seg.n_bins + 100, "window": 101, "ms": ms_norm,
+                      "output_bins_per_s": seg.n_seg * seg.n_bins / (ms_norm / 1e3)},
+        "stage2_doubled_set": {"candidates": n, "segments": du.n_seg, "ms": ms_dbl,
+                               "cand_seg_per_s": n * du.n_seg / (ms_dbl / 1e3)},
+        "stage2_ell1": {"candidates": n, "segments": seg.n_seg, "ms": ms_ecc,
+                        "cand_seg_per_s": n * seg.n_seg / (ms_ecc / 1e3)},
+    }
 
 
 def run_allsky(args):

@@ -148,33 +148,47 @@ extern "C" int bsh_grid_build(const bsh_grid_spec* spec, double t_mid, double* a
 
 // eq:HoughPower: rho_k = P_k / <n_k>^2, the noise level <n_k>^2 estimated from the running median
 // of the window [k - m, k + m] divided by the expected median of 2m+1 unit exponentials.
-// One block per segment; the raw row sits in LDS and every output finds its window's median by
-// rank counting (the value v with #{< v} <= m < #{<= v}).
+// One block per segment; the raw row sits in LDS.  The median of a window is the value v with
+// #{< v} <= m < #{<= v}; instead of counting that for every candidate of every window, each
+// raw position c counts it once for the first window that holds c and then slides the window
+// across the 2m + 1 windows that hold c, updating both counts by the entry that leaves and the
+// one that enters.  A window's median is the first position in window order that meets the
+// condition (an LDS atomic minimum over the positions that do; with finite data they all hold
+// the same value); a window where none does (NaN entries) keeps its centre value.
 constexpr int kMaxRaw = 4096;
 
 __global__ __launch_bounds__(256) void normalize_kernel(const float* __restrict__ raw, int32_t n_raw,
                                                         int32_t m, double beta, float* __restrict__ rho)
 {
     __shared__ float row[kMaxRaw];
+    __shared__ int first[kMaxRaw];
     const int64_t J = blockIdx.x;
     const float* src = raw + J * n_raw;
-    for (int i = threadIdx.x; i < n_raw; i += blockDim.x) row[i] = src[i];
-    __syncthreads();
-    const int win = 2 * m + 1;
     const int n_out = n_raw - 2 * m;
-    for (int c = threadIdx.x; c < n_out; c += blockDim.x) {
-        const float* w = row + c;
-        float med = w[m];
-        for (int j = 0; j < win; ++j) {
-            const float v = w[j];
-            int lt = 0, le = 0;
-            for (int i = 0; i < win; ++i) {
-                lt += w[i] < v ? 1 : 0;
-                le += w[i] <= v ? 1 : 0;
-            }
-            if (lt <= m && le > m) { med = v; break; }
+    for (int i = threadIdx.x; i < n_raw; i += blockDim.x) row[i] = src[i];
+    for (int i = threadIdx.x; i < n_out; i += blockDim.x) first[i] = n_raw;
+    __syncthreads();
+    for (int c = threadIdx.x; c < n_raw; c += blockDim.x) {
+        const float v = row[c];
+        const int w_lo = max(0, c - 2 * m), w_hi = min(c, n_out - 1);   // windows [w, w + 2m] holding c
+        int lt = 0, le = 0;
+        for (int i = w_lo; i <= w_lo + 2 * m; ++i) {
+            lt += row[i] < v ? 1 : 0;
+            le += row[i] <= v ? 1 : 0;
         }
-        rho[J * n_out + c] = (float)(((double)w[m] * beta) / (double)med);
+        for (int w = w_lo;; ++w) {
+            if (lt <= m && le > m) atomicMin(&first[w], c);
+            if (w == w_hi) break;
+            const float out = row[w], in = row[w + 2 * m + 1];
+            lt += (in < v ? 1 : 0) - (out < v ? 1 : 0);
+            le += (in <= v ? 1 : 0) - (out <= v ? 1 : 0);
+        }
+    }
+    __syncthreads();
+    for (int w = threadIdx.x; w < n_out; w += blockDim.x) {
+        const float centre = row[w + m];
+        const float med = first[w] < n_raw ? row[first[w]] : centre;
+        rho[J * n_out + w] = (float)(((double)centre * beta) / (double)med);
     }
 }
 
