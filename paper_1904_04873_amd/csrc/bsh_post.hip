@@ -308,11 +308,28 @@ __device__ void lds_unite(int32_t* lp, int32_t a, int32_t b)
 // 0..kPostThreads-1, column members after them; a diagonal tile has only the row members); then
 // every node that is not its local root is joined to that root in the global structure, at most
 // one global hook per node and tile instead of one per close pair.
+//
+// A pair can only be close when its frequency term alone is below the window (the six terms
+// are non-negative and rounding is monotone), i.e. when |f_b - f_a| < window / Tc up to
+// rounding.  The column tile is therefore ranked by frequency in LDS, and each row tests only
+// the columns inside [f_a - df, f_a + df], df = window / Tc with a relative margin of 1e-9
+// (far above the rounding of the test): the same close pairs as testing every column, with the
+// distance evaluated as before.
+// Ascending order of frequencies as unsigned keys, NaN last (a NaN row is never close to any).
+__device__ __forceinline__ uint64_t freq_key(double x)
+{
+    if (x != x) return ~0ull;
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+
 __global__ void __launch_bounds__(kPostThreads) hook_kernel(PostConst c, const double* rows, int64_t n,
-                                                            double w2, int32_t* parent)
+                                                            double w2, double df, int32_t* parent)
 {
     __shared__ PRow tile[kPostThreads];
     __shared__ int32_t lp[2 * kPostThreads];
+    __shared__ double sf[kPostThreads];      // the column tile's frequencies in ascending order
+    __shared__ int16_t ord[kPostThreads];    // their positions in the tile
     const int64_t bidx = blockIdx.x;
     int64_t tj = (int64_t)((sqrt(8.0 * (double)bidx + 1.0) - 1.0) * 0.5);
     while (tj * (tj + 1) / 2 > bidx) --tj;
@@ -322,17 +339,43 @@ __global__ void __launch_bounds__(kPostThreads) hook_kernel(PostConst c, const d
     const int t = threadIdx.x;
     const int64_t i0 = ti * kPostThreads, j0 = tj * kPostThreads;
     const int64_t i = i0 + t;
+    const int jn = (int)min((int64_t)kPostThreads, n - j0);
     // the column tile with its resolutions, computed once per block
-    if (j0 + t < n) tile[t] = load_row(rows + 6 * (j0 + t), c);
+    if (t < jn) tile[t] = load_row(rows + 6 * (j0 + t), c);
     lp[t] = t;
     lp[kPostThreads + t] = kPostThreads + t;
     __syncthreads();
+    if (t < jn) {
+        // rank by (frequency key, position): a permutation of 0 .. jn-1 whatever the values
+        const double f = tile[t].f;
+        const uint64_t kf = freq_key(f);
+        int r = 0;
+        for (int u = 0; u < jn; ++u) {
+            const uint64_t ku = freq_key(tile[u].f);
+            r += (ku < kf || (ku == kf && u < t)) ? 1 : 0;
+        }
+        sf[r] = f;
+        ord[r] = (int16_t)t;
+    }
+    __syncthreads();
     if (i < n) {
         const PRow a = load_row(rows + 6 * i, c);
-        const int64_t jn = min((int64_t)kPostThreads, n - j0);
-        for (int64_t jj = 0; jj < jn; ++jj) {
+        // first rank with f >= f_a - df, first rank with f > f_a + df
+        const double lo_f = a.f - df, hi_f = a.f + df;
+        int lo = 0, hi = jn;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (sf[mid] < lo_f) lo = mid + 1; else hi = mid;
+        }
+        int end = lo, top = jn;
+        while (end < top) {
+            const int mid = (end + top) >> 1;
+            if (sf[mid] <= hi_f) end = mid + 1; else top = mid;
+        }
+        for (int k = lo; k < end; ++k) {
+            const int jj = ord[k];
             if (j0 + jj <= i) continue;
-            if (dist2(a, tile[jj], c) < w2) lds_unite(lp, t, diag ? (int32_t)jj : kPostThreads + (int32_t)jj);
+            if (dist2(a, tile[jj], c) < w2) lds_unite(lp, t, diag ? jj : kPostThreads + jj);
         }
     }
     __syncthreads();
@@ -602,7 +645,10 @@ extern "C" int bsh_cluster(const bsh_post_params* pp, const double* rows, int64_
     const int64_t tiles = nt * (nt + 1) / 2;
     if (tiles > INT32_MAX) return fail_inval("too many templates for one launch");
     iota_kernel<<<blocks_for(n), kPostThreads, 0, stream>>>(label_out, n);
-    hook_kernel<<<(unsigned)tiles, kPostThreads, 0, stream>>>(c, rows, n, window * window, label_out);
+    // frequency half-width of the window, with a relative margin far above the rounding of the
+    // distance's frequency term
+    const double df = window / c.t_coh * (1.0 + 1e-9);
+    hook_kernel<<<(unsigned)tiles, kPostThreads, 0, stream>>>(c, rows, n, window * window, df, label_out);
     flatten_kernel<<<blocks_for(n), kPostThreads, 0, stream>>>(label_out, n);
     return check_launch("bsh_cluster");
 }
