@@ -375,7 +375,10 @@ __global__ void __launch_bounds__(kPostThreads) hook_kernel(PostConst c, const d
         for (int k = lo; k < end; ++k) {
             const int jj = ord[k];
             if (j0 + jj <= i) continue;
-            if (dist2(a, tile[jj], c) < w2) lds_unite(lp, t, diag ? jj : kPostThreads + jj);
+            const int node = diag ? jj : kPostThreads + jj;
+            // a pair already in one component cannot change the components (they only merge)
+            if (lds_find(lp, t) == lds_find(lp, node)) continue;
+            if (dist2(a, tile[jj], c) < w2) lds_unite(lp, t, node);
         }
     }
     __syncthreads();
