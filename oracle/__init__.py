@@ -28,8 +28,9 @@ Functions and the passage each follows:
                           noise moments that follow from p(rho) = exp(-rho).
 * ``topk``             -- best k under (score descending, index ascending).
 
-Parity is unpinned for the two significance normalizations (the paper defers
-them to the SkyHough paper); everything else is pinned by the CPU tests.
+Every function is pinned by the CPU tests.  The two significance normalizations
+(whose constants the paper defers to the SkyHough paper) are pinned by the noise law
+of Sec. IV.F: under p(rho) = exp(-rho) both have mean 0 and variance 1 for any weights.
 """
 from __future__ import annotations
 

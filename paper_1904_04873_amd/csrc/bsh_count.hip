@@ -1,6 +1,5 @@
 // Stage-1 weighted number count, plain launch form (bsh_hough_count): one block per tile of
-// one work item.  The tile body is in bsh_count_tile.h.  This source is compiled with LLVM's
-// iterative ILP scheduler (see build.py).
+// one work item.  The tile body is in bsh_count_tile.h.
 #include <cstring>
 
 #include "bsh_count_tile.h"

@@ -583,3 +583,99 @@ def test_stage2_on_doubled_set_is_sum_over_both_sets():
         if mode == 0:
             assert np.array_equal(cu, ca + cb) and np.array_equal(ntu, nta + ntb)
             assert np.allclose(nwu, nwa + nwb, rtol=1e-12, atol=0)
+
+
+# ---------------------------------------------------------------- significance normalizations
+
+def _noise_draws(n_seg, n_draws, sigma_w, seed):
+    """n_draws independent noise realizations of one candidate over n_seg segments: a segment set
+    with no detector motion whose rows hold n_draws unit-exponential columns, read by candidates
+    with a_p = 0 at F = each column's absolute bin (so x = F exactly and each candidate reads its
+    own column).  Weights are log-normal(0, sigma_w) normalized to mean 1."""
+    rng = np.random.default_rng(seed)
+    k_lo = 50000
+    t = np.sort(rng.uniform(0, 60 * S.DAY, n_seg)) + 0.5 * TC
+    w = np.exp(sigma_w * rng.standard_normal(n_seg))
+    w = (w / w.mean()).astype(np.float32)
+    seg = S.Segments(t_mid=t, v_over_c=np.zeros((n_seg, 3)), weight=w,
+                     power=rng.standard_exponential((n_seg, n_draws), dtype=np.float32),
+                     k_lo=k_lo, n_bins=n_draws)
+    cand = np.stack([k_lo + np.arange(n_draws, dtype=np.float64), np.zeros(n_draws),
+                     np.full(n_draws, 20 * S.DAY), np.zeros(n_draws)], axis=1)
+    P, cnt, nw, nt = O.power_stat(seg, np.array([[0.0, 0.0, 1.0]]), np.zeros(n_draws, np.int32), cand, mode=0)
+    assert nt.sum() == 0
+    return seg, P, nw
+
+
+@pytest.mark.parametrize("sigma_w", [0.3, 1.0])
+def test_significances_have_unit_normal_moments_under_noise(sigma_w):
+    """Under the noise law p(rho) = exp(-rho) (Sec. IV.F) the peaks are Bernoulli(e^-rho_th) and the
+    powers Exp(1), so s_H (eq:hough2) and s_P (eq:hough3) have mean 0 and variance 1 whatever the
+    weights.  Log-normal weights make sum w and sum w^2 differ (by e^{sigma^2}: 9 % at sigma 0.3,
+    a factor 2.7 at sigma 1), so a normalization that mixes them up moves the variance (or the
+    mean) far outside the sampling error of 2 x 10^4 draws."""
+    n_draws = 20000
+    seg, P, nw = _noise_draws(200, n_draws, sigma_w, seed=int(sigma_w * 10) + 3)
+    sh = O.significance_h(nw, seg.weight)
+    sp = O.significance_p(P, seg.weight)
+    # standard errors: mean 1/sqrt(n); variance about sqrt(2/n) (times a kurtosis factor < 1.5)
+    se_m = 1.0 / math.sqrt(n_draws)
+    se_v = 1.5 * math.sqrt(2.0 / n_draws)
+    for s in (sh, sp):
+        assert abs(s.mean()) < 5 * se_m, s.mean()
+        assert abs(s.var() - 1.0) < 5 * se_v, s.var()
+    # the ratio the pin separates, sum w^2 / sum w, is far from 1 at both widths
+    w = seg.weight.astype(np.float64)
+    assert (w * w).sum() / w.sum() > (2.0 if sigma_w > 0.5 else 1.05)
+
+
+# ---------------------------------------------------------------- ELL1 stage-2 power at e != 0
+
+def test_ecc_power_ramp_follows_ecc_track():
+    """rho_{J,c} = c + k_lo (the absolute bin), e != 0: P_lin = sum w x and P = sum w k with the ELL1
+    track's own x and k, for eccentricities up to 0.05 and both orientations of (e cos w, e sin w)."""
+    seg = _segments(300, 180000, 90, 22, seed=33)
+    seg.power[:] = (np.arange(seg.n_bins, dtype=np.float64) + seg.k_lo)[None, :].astype(np.float32)
+    cand, cs = _cands(seg, 30, 180000, 7)
+    rng = np.random.default_rng(8)
+    e = rng.uniform(0.001, 0.05, 30)
+    om = rng.uniform(0, 2 * math.pi, 30)
+    ce = np.concatenate([cand, np.stack([e * np.cos(om), e * np.sin(om)], axis=1)], axis=1)
+    x, k = O.track_ecc(seg, S.fixed_pixel(), cs, ce)
+    w = seg.weight.astype(np.float64)
+    P_lin = O.power_stat_ecc(seg, S.fixed_pixel(), cs, ce, mode=1)[0]
+    P_near = O.power_stat_ecc(seg, S.fixed_pixel(), cs, ce, mode=0)[0]
+    assert np.allclose(P_lin, x @ w, rtol=1e-13)
+    assert np.allclose(P_near, k.astype(np.float64) @ w, rtol=1e-13)
+
+
+def test_ecc_power_one_segment_equals_phase_model_frequency():
+    """No detector motion, one segment, ramp powers: P_lin / w is the ELL1 frequency (times Tc) at the
+    segment's time, which must equal the central difference of the eccentric phase model of
+    eq:phaseMethod (its two e terms) within 2e-4 bins.  Swapping e cos w and e sin w, or the sign of
+    either term, moves it by up to e F a_p W, about 0.07 bins here."""
+    f0, ap, P = 250.03, 2.6, 16 * S.DAY
+    W = 2 * math.pi / P
+    F = f0 * TC
+    t0 = 1.3e6
+    tas = np.linspace(t0 - P / 2, t0 + P / 2, 41)[:-1]
+    e, om = 0.05, 0.9
+    ec, es = e * math.cos(om), e * math.sin(om)
+    k_lo, n_bins = int(F) - 400, 800
+    seg = S.Segments(t_mid=np.array([t0]), v_over_c=np.zeros((1, 3)), weight=np.array([0.75], np.float32),
+                     power=(np.arange(n_bins, dtype=np.float64) + k_lo)[None, :].astype(np.float32),
+                     k_lo=k_lo, n_bins=n_bins)
+    ce = np.stack([np.full(tas.size, F), np.full(tas.size, ap), np.full(tas.size, P), tas,
+                   np.full(tas.size, ec), np.full(tas.size, es)], axis=1)
+    P_lin = O.power_stat_ecc(seg, np.array([[0, 0, 1.0]]), np.zeros(tas.size, np.int32), ce, mode=1)[0]
+
+    def phase(t, ta):   # cycles
+        psi = W * (t - ta)
+        return f0 * (t - ap * math.sin(psi) - ap * ec / 2 * math.sin(2 * psi) - ap * es / 2 * math.cos(2 * psi))
+
+    h = 1.0
+    x_num = np.array([(phase(t0 + h, ta) - phase(t0 - h, ta)) / (2 * h) * TC for ta in tas])
+    assert np.max(np.abs(P_lin / 0.75 - x_num)) < 2e-4
+    # the e terms really matter at this size
+    x_circ = np.array([F * (1 - ap * W * math.cos(W * (t0 - ta))) for ta in tas])
+    assert np.max(np.abs(x_num - x_circ)) > 0.05
