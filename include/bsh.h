@@ -38,7 +38,10 @@
  *     P in s, t_asc in s) with a sky pixel cand_sky[n]; they need not lie on the grid.
  *     Taking F rather than f0 keeps grid templates bit-identical between the two stages.
  *
- * No exception crosses this ABI; the library allocates no device memory in any call.
+ * No exception crosses this ABI.  No call allocates device memory except bsh_plan_create,
+ * which allocates the plan's own tables, queue and top-k workspaces (released by
+ * bsh_plan_destroy); every other call works in caller-given buffers and workspaces whose sizes
+ * the *_workspace functions give.
  */
 #ifndef BSH_H_
 #define BSH_H_
@@ -180,6 +183,30 @@ int bsh_hough_count_ex(const bsh_segments* seg, const bsh_grid* grid, int32_t la
                        bsh_stream stream);
 
 /*
+ * Stage 1 with its per-band top-list and bounded memory (Sec. IV.C: only the best N_C
+ * templates of a band go on to the second stage, so the full map is never needed; eq:RAM1
+ * counts the map memory this avoids).  The grid's sky pixels are counted in passes of
+ * sky_per_pass pixels (0: all at once) into a map inside the workspace; after each pass the
+ * pass's top-k is merged into the running list, which is exact because the best k of a union
+ * are among the best k of each part.  Results equal bsh_topk over the full bsh_hough_count
+ * map (default tile and accumulation), bit for bit.
+ *   spec->k: list length; out_score[k], out_index[k] as bsh_topk (template index as above;
+ *   the tail is -inf / -1 when the grid has fewer than k templates).
+ *   ws / ws_bytes: at least bsh_hough_count_topk_workspace(grid, spec) bytes: one pass's map
+ *   (sky_per_pass x n_bin x n_f0 floats) plus O(k).  When there are several passes, each must
+ *   hold at least k templates (BSH_EINVAL otherwise).
+ */
+typedef struct bsh_topk_spec {
+    int32_t k;
+    int32_t sky_per_pass;
+} bsh_topk_spec;
+
+size_t bsh_hough_count_topk_workspace(const bsh_grid* grid, const bsh_topk_spec* spec);
+int bsh_hough_count_topk(const bsh_segments* seg, const bsh_grid* grid, const bsh_topk_spec* spec,
+                         float* out_score, int64_t* out_index, void* ws, size_t ws_bytes,
+                         int32_t* status, bsh_stream stream);
+
+/*
  * Exact top-k under the total order (score descending, index ascending) (Sec. IV.C
  * top-lists).  score [n]; index [n] int64 or NULL for 0..n-1 (indices must be distinct and
  * non-negative).
@@ -315,6 +342,13 @@ int64_t bsh_items_map_floats(const bsh_item* items, int32_t n_items, const bsh_g
  * pointer passed in (items' tables, grids, maps, item lists [n_items][k_item], band lists
  * [n_bands][k_band], status) must stay valid for the plan's life.  Two runs of one plan, or
  * other work on the same arrays, must not overlap in time.
+ *
+ * Bounded memory: maps_floats may be smaller than bsh_items_map_floats (but not smaller than
+ * the largest item's map); the items are then split, in order, into passes whose maps fit in
+ * `maps` together, each pass one persistent launch followed by its items' lists, and `maps`
+ * is reused (it then holds the last pass's maps after a run).  This needs k_item > 0; the item
+ * and band lists are the same as with room for every map, because the best k of a band are
+ * among the best k of each of its items.  At most 65535 items.
  */
 int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh_grid* grids, int32_t n_grids,
                     int32_t n_bands, const bsh_plan_opts* opts, float* maps, int64_t maps_floats,
@@ -327,9 +361,14 @@ int bsh_plan_run(bsh_plan* plan, bsh_stream stream);
 /* The same results from one plain launch (plus its own top-k) per item, in item order. */
 int bsh_plan_run_plain(bsh_plan* plan, bsh_stream stream);
 
-/* Number of queued units and persistent blocks of a plan (-1 for NULL). */
+/* The persistent count launches of a run alone (every pass, no lists; not graph-captured):
+ * the maps of the last pass, for timing the count kernel on its own. */
+int bsh_plan_run_count(bsh_plan* plan, bsh_stream stream);
+
+/* Number of queued units, persistent blocks and passes of a plan (-1 for NULL). */
 int64_t bsh_plan_units(const bsh_plan* plan);
 int32_t bsh_plan_blocks(const bsh_plan* plan);
+int32_t bsh_plan_passes(const bsh_plan* plan);
 
 int bsh_plan_destroy(bsh_plan* plan);
 

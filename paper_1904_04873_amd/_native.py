@@ -103,7 +103,13 @@ class PlanOpts(ctypes.Structure):
     ]
 
 
-# name -> (restype, argtypes); the complete exported surface of include/bsh.h
+class TopkSpec(ctypes.Structure):
+    _fields_ = [
+        ("k", _c_i32),
+        ("sky_per_pass", _c_i32),
+    ]
+
+
 class PostParams(ctypes.Structure):
     """bsh_post_params: resolutions of the post-processing distance (eq:postdist)."""
     _fields_ = [
@@ -117,6 +123,7 @@ class PostParams(ctypes.Structure):
     ]
 
 
+# name -> (restype, argtypes); the complete exported surface of include/bsh.h
 SIGNATURES = {
     "bsh_version": (ctypes.c_int, []),
     "bsh_last_error": (ctypes.c_char_p, []),
@@ -128,14 +135,20 @@ SIGNATURES = {
                                        _vp]),
     "bsh_hough_count_ex": (ctypes.c_int, [ctypes.POINTER(Segments), ctypes.POINTER(Grid), _c_i32, _c_i32,
                                           _c_i32, _vp, _vp, _vp, _vp]),
+    "bsh_hough_count_topk_workspace": (ctypes.c_size_t, [ctypes.POINTER(Grid), ctypes.POINTER(TopkSpec)]),
+    "bsh_hough_count_topk": (ctypes.c_int, [ctypes.POINTER(Segments), ctypes.POINTER(Grid),
+                                            ctypes.POINTER(TopkSpec), _vp, _vp, _vp, ctypes.c_size_t, _vp,
+                                            _vp]),
     "bsh_items_map_floats": (_c_i64, [ctypes.POINTER(Item), _c_i32, ctypes.POINTER(Grid), _c_i32]),
     "bsh_plan_create": (ctypes.c_int, [ctypes.POINTER(Item), _c_i32, ctypes.POINTER(Grid), _c_i32, _c_i32,
                                        ctypes.POINTER(PlanOpts), _vp, _c_i64, _vp, _vp, _vp, _vp, _vp,
                                        ctypes.POINTER(_vp)]),
     "bsh_plan_run": (ctypes.c_int, [_vp, _vp]),
     "bsh_plan_run_plain": (ctypes.c_int, [_vp, _vp]),
+    "bsh_plan_run_count": (ctypes.c_int, [_vp, _vp]),
     "bsh_plan_units": (_c_i64, [_vp]),
     "bsh_plan_blocks": (_c_i32, [_vp]),
+    "bsh_plan_passes": (_c_i32, [_vp]),
     "bsh_plan_destroy": (ctypes.c_int, [_vp]),
     "bsh_topk_workspace": (ctypes.c_size_t, [_c_i64, _c_i32]),
     "bsh_topk": (ctypes.c_int, [_vp, _vp, _c_i64, _c_i32, _vp, _vp, _vp, ctypes.c_size_t, _vp]),

@@ -19,7 +19,8 @@ from ._native import BshError, check
 
 __all__ = [
     "BshError", "DeviceSegments", "DeviceGrid", "Status", "TopK", "Plan", "bsh_version",
-    "bsh_grid_build", "bsh_normalize", "bsh_peakgram", "bsh_hough_count", "bsh_topk",
+    "bsh_grid_build", "bsh_normalize", "bsh_peakgram", "bsh_hough_count", "bsh_hough_count_topk",
+    "bsh_topk",
     "bsh_decode_templates", "bsh_power_stat", "bsh_power_stat_ecc", "bsh_power_stat_grad",
     "bsh_power_stat_value_and_grad",
     "bsh_track_bins", "post_params", "bsh_post_rows", "bsh_significance", "bsh_coincidences",
@@ -241,6 +242,39 @@ def bsh_hough_count(seg: DeviceSegments, grid: DeviceGrid, with_count: bool = Fa
     return wsum_out, (count_out if with_count else None)
 
 
+class CountTopK:
+    """Reusable workspace for bsh_hough_count_topk (stage 1 with its top-k and bounded memory)."""
+
+    def __init__(self, grid: "DeviceGrid", k: int, sky_per_pass: int = 0, device="cuda"):
+        self.k, self.sky_per_pass = int(k), int(sky_per_pass)
+        self.spec = N.TopkSpec(k=self.k, sky_per_pass=self.sky_per_pass)
+        g_c = grid.struct()
+        nbytes = int(N.load().bsh_hough_count_topk_workspace(ctypes.byref(g_c), ctypes.byref(self.spec)))
+        if nbytes == 0:
+            raise BshError(N.BSH_EINVAL, "bsh_hough_count_topk_workspace", "bad grid or k")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+    def __call__(self, seg: "DeviceSegments", grid: "DeviceGrid", status: Optional["Status"] = None,
+                 out_score=None, out_index=None):
+        dev = seg.t_mid.device
+        if out_score is None:
+            out_score = torch.empty(self.k, dtype=torch.float32, device=dev)
+        if out_index is None:
+            out_index = torch.empty(self.k, dtype=torch.int64, device=dev)
+        s_c, g_c = seg.struct(), grid.struct()
+        check(N.load().bsh_hough_count_topk(ctypes.byref(s_c), ctypes.byref(g_c), ctypes.byref(self.spec),
+                                            _ptr(out_score), _ptr(out_index), _ptr(self.ws), self.ws.numel(),
+                                            status.ptr() if status else None, _stream()),
+              "bsh_hough_count_topk")
+        return out_score, out_index
+
+
+def bsh_hough_count_topk(seg: "DeviceSegments", grid: "DeviceGrid", k: int, sky_per_pass: int = 0,
+                         status: Optional["Status"] = None):
+    """Stage-1 top-k of the grid without its full map: (scores float32 [k], indices int64 [k])."""
+    return CountTopK(grid, k, sky_per_pass, seg.t_mid.device)(seg, grid, status)
+
+
 class TopK:
     """Reusable workspace for bsh_topk."""
 
@@ -444,7 +478,7 @@ class Plan:
     def __init__(self, items, grids: Sequence[DeviceGrid], n_bands: int, k_item: int = 0,
                  k_band: int = 0, lanes: int = 0, chunk: int = 0, use_graph: bool = True,
                  lpt: bool = True, blocks: int = 0, variant: int = 0, status: Optional[Status] = None,
-                 device="cuda"):
+                 device="cuda", map_floats: Optional[int] = None):
         L = N.load()
         self._keep = [items, grids]
         self.n_items = len(items)
@@ -460,7 +494,9 @@ class Plan:
         n_maps = int(L.bsh_items_map_floats(arr_i, self.n_items, arr_g, len(grids)))
         if n_maps < 0:
             raise BshError(N.BSH_EINVAL, "bsh_items_map_floats", "bad items")
-        self.maps = torch.empty(max(1, n_maps), dtype=torch.float32, device=device)
+        # map_floats below the total runs the items in passes through one reused buffer
+        n_buf = n_maps if map_floats is None else min(int(map_floats), n_maps)
+        self.maps = torch.empty(max(1, n_buf), dtype=torch.float32, device=device)
         self.item_score = torch.empty((self.n_items, max(1, self.k_item)), dtype=torch.float32, device=device)
         self.item_index = torch.empty((self.n_items, max(1, self.k_item)), dtype=torch.int64, device=device)
         self.band_score = torch.empty((self.n_bands, max(1, self.k_band)), dtype=torch.float32, device=device)
@@ -486,8 +522,17 @@ class Plan:
     def run_plain(self) -> None:
         check(N.load().bsh_plan_run_plain(self.h, _stream()), "bsh_plan_run_plain")
 
+    def run_count(self) -> None:
+        check(N.load().bsh_plan_run_count(self.h, _stream()), "bsh_plan_run_count")
+
     def item_map(self, q: int) -> torch.Tensor:
+        if self.passes != 1:
+            raise ValueError("the plan runs in passes: only the last pass's maps are kept")
         return self.maps[int(self.offsets[q]):int(self.offsets[q + 1])]
+
+    @property
+    def passes(self) -> int:
+        return int(N.load().bsh_plan_passes(self.h))
 
     @property
     def units(self) -> int:

@@ -5,6 +5,14 @@
 // The paper splits a search into independent band x sky-patch x binary-block jobs (eq:cost)
 // and notes that the GPU idles while the host prepares the next job; here the whole set of
 // jobs is one device-side queue, so the tail of one item overlaps the start of the next.
+//
+// Bounded memory.  A search keeps only the top candidates of each band (Sec. IV.C), and the
+// stage-1 maps of a whole band of sky patches do not fit in HBM (eq:RAM1 counts them per patch).
+// When the caller's map buffer is smaller than all maps together, the items are split, in
+// order, into passes whose maps fit in it; each pass is one persistent launch followed by the
+// top-k of each of its items, after which the buffer is reused.  The per-band lists are then
+// merged from the item lists, which is exact: the best k of a union are among the best k of
+// each part.
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -16,15 +24,23 @@ struct bsh_plan {
     int32_t lanes = bsh::kDefaultLanes, chunk = bsh::kDefaultChunk, blocks = 0;
     bool use_graph = false;
     int32_t mode = 2;
-    int64_t n_units = 0, max_item_len = 0, max_band_len = 0;
+    int64_t n_units = 0, max_band_len = 0;
     std::vector<bsh::ItemDesc> items;            // host copies (plain mode)
     std::vector<bsh::PlainLaunch> plain;          // per-item plain launch parameters
     std::vector<int64_t> plain_blocks;
-    std::vector<int64_t> item_off, band_off;      // host offsets
+    std::vector<int64_t> band_off;                // host offsets of the band lists' inputs
+    // passes: items [pass_item[q], pass_item[q+1]), units [pass_unit[q], pass_unit[q+1])
+    std::vector<int32_t> pass_item;               // [n_passes + 1]
+    std::vector<int64_t> pass_unit;               // [n_passes + 1]
+    std::vector<int64_t> pass_off_at;             // [n_passes] first entry of the pass in d_pass_off
+    std::vector<int64_t> pass_max_len;            // [n_passes] longest item map of the pass
+    std::vector<int64_t> item_start;              // [n_items] map offset of each item in the buffer
+    std::vector<int64_t> item_len;                // [n_items]
     bsh::ItemDesc* d_items = nullptr;
     bsh::WorkUnit* d_units = nullptr;
-    uint32_t* d_counter = nullptr;
-    int64_t* d_item_off = nullptr;
+    uint32_t* d_counter = nullptr;                // one queue counter per pass
+    int64_t* d_pass_off = nullptr;                // per pass: item offsets inside the buffer, then its end
+    int64_t* d_single_off = nullptr;              // [n_items][2]: (start, end) of each item's map
     int64_t* d_band_off = nullptr;
     float* d_item_score = nullptr;
     int64_t* d_item_index = nullptr;
@@ -37,6 +53,8 @@ struct bsh_plan {
     hipStream_t capture_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+
+    int32_t n_passes() const { return (int32_t)pass_item.size() - 1; }
 };
 
 namespace {
@@ -90,28 +108,45 @@ int dev_alloc(T** p, size_t n)
     return BSH_OK;
 }
 
-__global__ void tag_kernel(int64_t* idx, int64_t n, int32_t k, int32_t shift)
+// Items without segments have all-zero maps; their buffer regions are cleared by a fill
+// kernel inside the pass that holds them (earlier passes may have used the same memory).
+int zero_empty_items(bsh_plan* p, int32_t lo, int32_t hi, hipStream_t s)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < n && idx[e] >= 0) idx[e] |= (e / k) << shift;
+    for (int32_t i = lo; i < hi; ++i)
+        if (p->items[i].n_seg == 0) {
+            const int rc = zero_words(p->maps + p->item_start[i], p->item_len[i], s);
+            if (rc) return rc;
+        }
+    return BSH_OK;
 }
 
-int enqueue_batched(bsh_plan* p, hipStream_t s)
+// The persistent count launches of every pass, each followed (when lists are asked for) by
+// the top-k of each of its items; then the band lists.
+int enqueue_batched(bsh_plan* p, hipStream_t s, bool count_only)
 {
-    int rc = zero_words(p->d_counter, 1, s);
+    int rc = zero_words(p->d_counter, p->n_passes(), s);
     if (rc) return rc;
-    rc = launch_batch(p->d_items, p->d_units, p->n_units, p->d_counter, p->blocks, p->lanes, p->chunk,
-                      p->mode, s);
-    if (rc) return rc;
-    if (p->k_item > 0) {
-        rc = topk_segmented(p->maps, nullptr, p->d_item_off, p->n_items, p->max_item_len, kItemShift,
-                            p->k_item, p->d_item_score, p->d_item_index, p->d_ws_item, p->ws_item, s);
+    for (int32_t q = 0; q < p->n_passes(); ++q) {
+        const int32_t lo = p->pass_item[q], hi = p->pass_item[q + 1];
+        rc = zero_empty_items(p, lo, hi, s);
         if (rc) return rc;
-        if (p->k_band > 0)
-            rc = topk_segmented(p->d_item_score, p->d_item_index, p->d_band_off, p->n_bands,
-                                p->max_band_len, 0, p->k_band, p->band_score, p->band_index,
-                                p->d_ws_band, p->ws_band, s);
+        const int64_t u0 = p->pass_unit[q], nu = p->pass_unit[q + 1] - u0;
+        if (nu > 0) {
+            rc = launch_batch(p->d_items, p->d_units + u0, nu, p->d_counter + q, p->blocks, p->lanes, p->chunk,
+                              p->mode, s);
+            if (rc) return rc;
+        }
+        if (p->k_item > 0 && !count_only) {
+            rc = topk_segmented(p->maps, nullptr, p->d_pass_off + p->pass_off_at[q], hi - lo, p->pass_max_len[q],
+                                kItemShift, p->k_item, p->d_item_score + (size_t)lo * p->k_item,
+                                p->d_item_index + (size_t)lo * p->k_item, p->d_ws_item, p->ws_item, s,
+                                (int64_t)lo << kItemShift);
+            if (rc) return rc;
+        }
     }
+    if (p->k_item > 0 && p->k_band > 0 && !count_only)
+        rc = topk_segmented(p->d_item_score, p->d_item_index, p->d_band_off, p->n_bands, p->max_band_len, 0,
+                            p->k_band, p->band_score, p->band_index, p->d_ws_band, p->ws_band, s);
     return rc;
 }
 
@@ -155,11 +190,18 @@ extern "C" int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh
     if (o.k_band > 0 && (!band_score || !band_index)) return fail_inval("band outputs are NULL");
     if (o.k_item > 0 && (!item_score || !item_index)) return fail_inval("item outputs are NULL");
     if (!maps) return fail_inval("maps is NULL");
+    if (n_items > 65535) return fail_inval("more than 65535 items");
     const int64_t need = bsh_items_map_floats(items, n_items, grids, n_grids);
-    if (maps_floats < need) {
-        set_error("maps holds %lld floats, %lld needed", (long long)maps_floats, (long long)need);
+    int64_t largest = 0;
+    for (int32_t i = 0; i < n_items; ++i)
+        largest = std::max(largest, item_templates(items[i], grids[items[i].grid]));
+    if (maps_floats < largest) {
+        set_error("maps holds %lld floats, the largest item needs %lld", (long long)maps_floats,
+                  (long long)largest);
         return BSH_ENOMEM;
     }
+    if (maps_floats < need && o.k_item == 0)
+        return fail_inval("a map buffer smaller than all maps together needs item lists (k_item > 0)");
 
     bsh_plan* p = new bsh_plan();
     p->n_items = n_items;
@@ -176,54 +218,89 @@ extern "C" int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh
     p->d_item_score = item_score;
     p->d_item_index = item_index;
 
-    // item descriptors, map offsets and the unit queue
+    // passes: consecutive items whose maps fit in the buffer together
+    p->item_start.assign(n_items, 0);
+    p->item_len.assign(n_items, 0);
+    p->pass_item.push_back(0);
+    int64_t fill = 0;
+    for (int32_t i = 0; i < n_items; ++i) {
+        const int64_t n_t = item_templates(items[i], grids[items[i].grid]);
+        if (fill + n_t > maps_floats) {
+            p->pass_item.push_back(i);
+            fill = 0;
+        }
+        p->item_start[i] = fill;
+        p->item_len[i] = n_t;
+        fill += n_t;
+    }
+    p->pass_item.push_back(n_items);
+    const int32_t n_passes = p->n_passes();
+    std::vector<int64_t> pass_off;          // per pass: (hi - lo + 1) offsets
+    for (int32_t q = 0; q < n_passes; ++q) {
+        p->pass_off_at.push_back((int64_t)pass_off.size());
+        int64_t mx = 0;
+        for (int32_t i = p->pass_item[q]; i < p->pass_item[q + 1]; ++i) {
+            pass_off.push_back(p->item_start[i]);
+            mx = std::max(mx, p->item_len[i]);
+        }
+        const int32_t last = p->pass_item[q + 1] - 1;
+        pass_off.push_back(p->item_start[last] + p->item_len[last]);
+        p->pass_max_len.push_back(mx);
+    }
+    std::vector<int64_t> single_off(2 * (size_t)n_items);
+    for (int32_t i = 0; i < n_items; ++i) {
+        single_off[2 * i] = p->item_start[i];
+        single_off[2 * i + 1] = p->item_start[i] + p->item_len[i];
+    }
+
+    // item descriptors and the unit queue, longest-processing-time first inside each pass
+    // (stable, so equal costs keep item order)
     std::vector<WorkUnit> units;
-    std::vector<int64_t> unit_cost;
     p->items.resize(n_items);
     p->plain.resize(n_items);
     p->plain_blocks.resize(n_items);
-    p->item_off.assign(n_items + 1, 0);
     p->band_off.assign(n_bands + 1, 0);
     std::vector<int32_t> tile_start(BSH_MAX_PER + 1);
-    for (int32_t i = 0; i < n_items; ++i) {
-        const bsh_item& it = items[i];
-        const bsh_grid& g = grids[it.grid];
-        const int64_t n_t = item_templates(it, g);
-        fill_desc(p->items[i], &it.seg, &g, it.sky_lo, it.n_sky, nullptr, maps + p->item_off[i], status);
-        p->item_off[i + 1] = p->item_off[i] + n_t;
-        p->max_item_len = std::max(p->max_item_len, n_t);
-        std::vector<int64_t> groups(g.n_per);
-        const int64_t tiles = plan_tiles(&g, lanes, tile_start.data(), groups.data());
-        PlainLaunch& pl = p->plain[i];
-        std::memset(&pl, 0, sizeof(pl));
-        pl.d = p->items[i];
-        pl.tiles_per_sky = (int32_t)tiles;
-        std::copy(tile_start.begin(), tile_start.end(), pl.tile_start);
-        p->plain_blocks[i] = tiles * it.n_sky;
-        if (it.seg.n_seg == 0) continue;   // the map is zero-filled at run time
-        for (int32_t s = 0; s < it.n_sky; ++s)
-            for (int32_t ip = 0; ip < g.n_per; ++ip) {
-                const int64_t nt = (groups[ip] + lanes - 1) / lanes;
-                for (int64_t t = 0; t < nt; ++t) {
-                    units.push_back(WorkUnit{i, s, ip, (int32_t)t});
-                    unit_cost.push_back(it.seg.n_seg);
+    p->pass_unit.push_back(0);
+    for (int32_t q = 0; q < n_passes; ++q) {
+        std::vector<WorkUnit> pu;
+        std::vector<int64_t> cost;
+        for (int32_t i = p->pass_item[q]; i < p->pass_item[q + 1]; ++i) {
+            const bsh_item& it = items[i];
+            const bsh_grid& g = grids[it.grid];
+            fill_desc(p->items[i], &it.seg, &g, it.sky_lo, it.n_sky, nullptr, maps + p->item_start[i], status);
+            std::vector<int64_t> groups(g.n_per);
+            const int64_t tiles = plan_tiles(&g, lanes, tile_start.data(), groups.data());
+            PlainLaunch& pl = p->plain[i];
+            std::memset(&pl, 0, sizeof(pl));
+            pl.d = p->items[i];
+            pl.tiles_per_sky = (int32_t)tiles;
+            std::copy(tile_start.begin(), tile_start.end(), pl.tile_start);
+            p->plain_blocks[i] = tiles * it.n_sky;
+            if (it.seg.n_seg == 0) continue;   // the map is zero-filled at run time
+            for (int32_t sk = 0; sk < it.n_sky; ++sk)
+                for (int32_t ip = 0; ip < g.n_per; ++ip) {
+                    const int64_t nt = (groups[ip] + lanes - 1) / lanes;
+                    for (int64_t t = 0; t < nt; ++t) {
+                        pu.push_back(WorkUnit{i, sk, ip, (int32_t)t});
+                        cost.push_back(it.seg.n_seg);
+                    }
                 }
-            }
+        }
+        if (o.lpt) {
+            std::vector<int64_t> order(pu.size());
+            for (size_t u = 0; u < order.size(); ++u) order[u] = (int64_t)u;
+            std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
+            for (int64_t u : order) units.push_back(pu[u]);
+        } else {
+            units.insert(units.end(), pu.begin(), pu.end());
+        }
+        p->pass_unit.push_back((int64_t)units.size());
     }
     for (int32_t i = 0; i < n_items; ++i) p->band_off[items[i].band + 1] += o.k_item;
     for (int32_t b = 0; b < n_bands; ++b) {
         p->band_off[b + 1] += p->band_off[b];
         p->max_band_len = std::max(p->max_band_len, p->band_off[b + 1] - p->band_off[b]);
-    }
-    // longest-processing-time-first order (stable, so equal costs keep item order)
-    if (o.lpt) {
-        std::vector<int64_t> order(units.size());
-        for (size_t u = 0; u < order.size(); ++u) order[u] = (int64_t)u;
-        std::stable_sort(order.begin(), order.end(),
-                         [&](int64_t a, int64_t b) { return unit_cost[a] > unit_cost[b]; });
-        std::vector<WorkUnit> sorted(units.size());
-        for (size_t u = 0; u < order.size(); ++u) sorted[u] = units[order[u]];
-        units.swap(sorted);
     }
     p->n_units = (int64_t)units.size();
 
@@ -239,13 +316,16 @@ extern "C" int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh
 
     rc = dev_alloc(&p->d_items, n_items);
     if (!rc) rc = dev_alloc(&p->d_units, units.size());
-    if (!rc) rc = dev_alloc(&p->d_counter, 64);
-    if (!rc) rc = dev_alloc(&p->d_item_off, n_items + 1);
+    if (!rc) rc = dev_alloc(&p->d_counter, (size_t)n_passes);
+    if (!rc) rc = dev_alloc(&p->d_pass_off, pass_off.size());
+    if (!rc) rc = dev_alloc(&p->d_single_off, single_off.size());
     if (!rc) rc = dev_alloc(&p->d_band_off, n_bands + 1);
     if (!rc && p->k_item > 0) {
-        // the batched run takes one list per item in one segmented call, the plain run one
-        // single-segment call per item: room for either
-        p->ws_item = std::max(topk_workspace_bytes(n_items, p->k_item), topk_workspace_bytes(1, p->k_item));
+        // the batched run takes one list per item of a pass in one segmented call, the plain run
+        // one single-segment call per item: room for either
+        int32_t widest = 1;
+        for (int32_t q = 0; q < n_passes; ++q) widest = std::max(widest, p->pass_item[q + 1] - p->pass_item[q]);
+        p->ws_item = std::max(topk_workspace_bytes(widest, p->k_item), topk_workspace_bytes(1, p->k_item));
         if (!rc) rc = dev_alloc((char**)&p->d_ws_item, p->ws_item);
         if (!rc && p->k_band > 0) {
             p->ws_band = topk_workspace_bytes(n_bands, p->k_band);
@@ -255,7 +335,9 @@ extern "C" int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh
     if (!rc && (hipMemcpy(p->d_items, p->items.data(), sizeof(ItemDesc) * n_items, hipMemcpyHostToDevice) != hipSuccess ||
                 (!units.empty() && hipMemcpy(p->d_units, units.data(), sizeof(WorkUnit) * units.size(),
                                              hipMemcpyHostToDevice) != hipSuccess) ||
-                hipMemcpy(p->d_item_off, p->item_off.data(), sizeof(int64_t) * (n_items + 1),
+                hipMemcpy(p->d_pass_off, pass_off.data(), sizeof(int64_t) * pass_off.size(),
+                          hipMemcpyHostToDevice) != hipSuccess ||
+                hipMemcpy(p->d_single_off, single_off.data(), sizeof(int64_t) * single_off.size(),
                           hipMemcpyHostToDevice) != hipSuccess ||
                 hipMemcpy(p->d_band_off, p->band_off.data(), sizeof(int64_t) * (n_bands + 1),
                           hipMemcpyHostToDevice) != hipSuccess)) {
@@ -270,7 +352,7 @@ extern "C" int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh
             rc = check_launch("begin capture");
             if (!rc) rc = BSH_EHIP;
         } else {
-            int rc2 = enqueue_batched(p, p->capture_stream);
+            int rc2 = enqueue_batched(p, p->capture_stream, false);
             hipError_t e = hipStreamEndCapture(p->capture_stream, &p->graph);
             if (rc2) rc = rc2;
             else if (e != hipSuccess) { set_error("end capture: %s", hipGetErrorString(e)); rc = BSH_EHIP; }
@@ -293,11 +375,6 @@ extern "C" int bsh_plan_run(bsh_plan* p, bsh_stream stream)
     clear_error();
     if (!p) return fail_inval("plan is NULL");
     hipStream_t s = (hipStream_t)stream;
-    for (int32_t i = 0; i < p->n_items; ++i)
-        if (p->items[i].n_seg == 0) {
-            int rc = zero_words(p->maps + p->item_off[i], p->item_off[i + 1] - p->item_off[i], s);
-            if (rc) return rc;
-        }
     if (p->use_graph && p->exec) {
         if (hipGraphLaunch(p->exec, s) != hipSuccess) {
             int rc = check_launch("graph launch");
@@ -305,7 +382,14 @@ extern "C" int bsh_plan_run(bsh_plan* p, bsh_stream stream)
         }
         return BSH_OK;
     }
-    return enqueue_batched(p, s);
+    return enqueue_batched(p, s, false);
+}
+
+extern "C" int bsh_plan_run_count(bsh_plan* p, bsh_stream stream)
+{
+    clear_error();
+    if (!p) return fail_inval("plan is NULL");
+    return enqueue_batched(p, (hipStream_t)stream, true);
 }
 
 extern "C" int bsh_plan_run_plain(bsh_plan* p, bsh_stream stream)
@@ -314,39 +398,33 @@ extern "C" int bsh_plan_run_plain(bsh_plan* p, bsh_stream stream)
     if (!p) return fail_inval("plan is NULL");
     hipStream_t s = (hipStream_t)stream;
     for (int32_t i = 0; i < p->n_items; ++i) {
-        const int64_t len = p->item_off[i + 1] - p->item_off[i];
+        const int64_t len = p->item_len[i];
         int rc;
         if (p->items[i].n_seg == 0)
-            rc = zero_words(p->maps + p->item_off[i], len, s);
+            rc = zero_words(p->maps + p->item_start[i], len, s);
         else
             rc = launch_plain(p->plain[i], p->plain_blocks[i], p->lanes, p->chunk, p->mode, s);
         if (rc) return rc;
         if (p->k_item > 0) {
-            // one list per item, from that item's own launch
-            rc = topk_segmented(p->maps, nullptr, p->d_item_off + i, 1, len, 0, p->k_item,
+            // one list per item, from that item's own launch, indices tagged with the item
+            rc = topk_segmented(p->maps, nullptr, p->d_single_off + 2 * i, 1, len, 0, p->k_item,
                                 p->d_item_score + (size_t)i * p->k_item,
-                                p->d_item_index + (size_t)i * p->k_item, p->d_ws_item, p->ws_item, s);
+                                p->d_item_index + (size_t)i * p->k_item, p->d_ws_item, p->ws_item, s,
+                                (int64_t)i << kItemShift);
             if (rc) return rc;
         }
     }
-    if (p->k_item > 0) {
-        // the per-item lists carry positions; give them the item prefix, then merge per band
-        const int64_t n = (int64_t)p->n_items * p->k_item;
-        hipLaunchKernelGGL(tag_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p->d_item_index, n,
-                           p->k_item, kItemShift);
-        int rc = check_launch("tag item lists");
-        if (rc) return rc;
-        if (p->k_band > 0)
-            return topk_segmented(p->d_item_score, p->d_item_index, p->d_band_off, p->n_bands,
-                                  p->max_band_len, 0, p->k_band, p->band_score, p->band_index,
-                                  p->d_ws_band, p->ws_band, s);
-    }
+    if (p->k_item > 0 && p->k_band > 0)
+        return topk_segmented(p->d_item_score, p->d_item_index, p->d_band_off, p->n_bands, p->max_band_len, 0,
+                              p->k_band, p->band_score, p->band_index, p->d_ws_band, p->ws_band, s);
     return BSH_OK;
 }
 
 extern "C" int64_t bsh_plan_units(const bsh_plan* p) { return p ? p->n_units : -1; }
 
 extern "C" int32_t bsh_plan_blocks(const bsh_plan* p) { return p ? p->blocks : -1; }
+
+extern "C" int32_t bsh_plan_passes(const bsh_plan* p) { return p ? p->n_passes() : -1; }
 
 // Release everything a plan owns, even if one release fails; returns the first failure.
 static hipError_t release_plan(bsh_plan* p)
@@ -358,8 +436,8 @@ static hipError_t release_plan(bsh_plan* p)
     if (p->exec) keep(hipGraphExecDestroy(p->exec));
     if (p->graph) keep(hipGraphDestroy(p->graph));
     if (p->capture_stream) keep(hipStreamDestroy(p->capture_stream));
-    void* bufs[] = {p->d_items, p->d_units, p->d_counter, p->d_item_off, p->d_band_off, p->d_ws_item,
-                    p->d_ws_band};
+    void* bufs[] = {p->d_items, p->d_units, p->d_counter, p->d_pass_off, p->d_single_off, p->d_band_off,
+                    p->d_ws_item, p->d_ws_band};
     for (void* b : bufs)
         if (b) keep(hipFree(b));
     delete p;

@@ -1,5 +1,6 @@
 // Stage-1 weighted number count, plain launch form (bsh_hough_count): one block per tile of
 // one work item.  The tile body is in bsh_count_tile.h.
+#include <algorithm>
 #include <cstring>
 
 #include "bsh_count_tile.h"
@@ -149,4 +150,134 @@ extern "C" int bsh_hough_count(const bsh_segments* seg, const bsh_grid* grid, ui
 {
     return bsh_hough_count_ex(seg, grid, kDefaultLanes, kDefaultChunk, BSH_VARIANT_AUTO, count_out, wsum_out,
                               status, stream);
+}
+
+// ---------------------------------------------------------------- stage 1 with a bounded top-k
+
+namespace {
+
+struct CountTopkLayout {
+    size_t map, merge_score, merge_index, tmp_score, tmp_index, topk, total;
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+CountTopkLayout count_topk_layout(int64_t pass_templates, int32_t k)
+{
+    CountTopkLayout l;
+    size_t at = 0;
+    l.map = at;
+    at += align256(sizeof(float) * (size_t)pass_templates);
+    l.merge_score = at;
+    at += align256(sizeof(float) * 2 * (size_t)k);
+    l.merge_index = at;
+    at += align256(sizeof(int64_t) * 2 * (size_t)k);
+    l.tmp_score = at;
+    at += align256(sizeof(float) * (size_t)k);
+    l.tmp_index = at;
+    at += align256(sizeof(int64_t) * (size_t)k);
+    l.topk = at;
+    at += align256(topk_workspace_bytes(1, k));
+    l.total = at;
+    return l;
+}
+
+__global__ void copy_list_kernel(const float* __restrict__ src_s, const int64_t* __restrict__ src_i,
+                                 float* __restrict__ dst_s, int64_t* __restrict__ dst_i, int32_t k)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < k) {
+        dst_s[e] = src_s[e];
+        dst_i[e] = src_i[e];
+    }
+}
+
+int copy_list(const float* ss, const int64_t* si, float* ds, int64_t* di, int32_t k, hipStream_t s)
+{
+    hipLaunchKernelGGL(copy_list_kernel, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, s, ss, si, ds, di, k);
+    return check_launch("list copy");
+}
+
+int64_t pass_sky(const bsh_grid* grid, int32_t sky_per_pass)
+{
+    return sky_per_pass > 0 ? std::min<int64_t>(sky_per_pass, grid->n_sky) : grid->n_sky;
+}
+
+}  // namespace
+
+extern "C" size_t bsh_hough_count_topk_workspace(const bsh_grid* grid, const bsh_topk_spec* spec)
+{
+    if (!grid || !spec || spec->k < 1 || grid->n_sky < 1 || !grid->tasc_off_host) return 0;
+    const int64_t per_sky = grid->tasc_off_host[(int64_t)grid->n_ap * grid->n_per] * grid->n_f0;
+    return count_topk_layout(pass_sky(grid, spec->sky_per_pass) * per_sky, spec->k).total;
+}
+
+extern "C" int bsh_hough_count_topk(const bsh_segments* seg, const bsh_grid* grid, const bsh_topk_spec* spec,
+                                    float* out_score, int64_t* out_index, void* ws, size_t ws_bytes,
+                                    int32_t* status, bsh_stream stream)
+{
+    clear_error();
+    int rc = check_segments(seg, true, false);
+    if (rc) return rc;
+    rc = check_grid(grid);
+    if (rc) return rc;
+    if (!spec) return fail_inval("topk spec is NULL");
+    if (spec->k < 1) return fail_inval("k < 1");
+    if (spec->sky_per_pass < 0) return fail_inval("sky_per_pass < 0");
+    if (!out_score || !out_index) return fail_inval("NULL output");
+    if (!ws) return fail_inval("workspace is NULL");
+    rc = check_window(seg, grid);
+    if (rc) return rc;
+    const int32_t k = spec->k;
+    const int64_t n_bin = grid->tasc_off_host[(int64_t)grid->n_ap * grid->n_per];
+    const int64_t per_sky = n_bin * grid->n_f0;
+    const int64_t np = pass_sky(grid, spec->sky_per_pass);
+    if (np * per_sky >= (int64_t)0xffffffff) return fail_inval("a pass holds 2^32 - 1 templates or more");
+    const CountTopkLayout L = count_topk_layout(np * per_sky, k);
+    if (ws_bytes < L.total) {
+        set_error("workspace %zu < %zu bytes", ws_bytes, L.total);
+        return BSH_ENOMEM;
+    }
+    if (np < grid->n_sky && np * per_sky < k) return fail_inval("a pass must hold at least k templates");
+    char* base = (char*)ws;
+    float* map = (float*)(base + L.map);
+    float* m_s = (float*)(base + L.merge_score);
+    int64_t* m_i = (int64_t*)(base + L.merge_index);
+    float* t_s = (float*)(base + L.tmp_score);
+    int64_t* t_i = (int64_t*)(base + L.tmp_index);
+    void* tws = base + L.topk;
+    const size_t tws_bytes = L.total - L.topk;
+    hipStream_t s = (hipStream_t)stream;
+    const bool single = np >= grid->n_sky;
+
+    int32_t lanes = kDefaultLanes, chunk = kDefaultChunk;
+    PlainLaunch p;
+    for (int64_t c0 = 0; c0 < grid->n_sky; c0 += np) {
+        const int32_t nc = (int32_t)std::min<int64_t>(np, grid->n_sky - c0);
+        const int64_t n_t = nc * per_sky;
+        std::memset(&p, 0, sizeof(p));
+        fill_desc(p.d, seg, grid, (int32_t)c0, nc, nullptr, map, status);
+        if (seg->weight_per_sky) p.d.w = seg->weight + c0 * seg->n_seg;
+        const int64_t tiles = plan_tiles(grid, lanes, p.tile_start, nullptr);
+        p.tiles_per_sky = (int32_t)tiles;
+        if (seg->n_seg == 0 || tiles == 0)
+            rc = zero_words(map, n_t, s);
+        else
+            rc = launch_plain(p, tiles * nc, lanes, chunk, kernel_mode(BSH_VARIANT_AUTO, false), s);
+        if (rc) return rc;
+        const int64_t first = c0 * per_sky;
+        if (single)
+            return topk_segmented(map, nullptr, nullptr, 1, n_t, 0, k, out_score, out_index, tws, tws_bytes, s, first);
+        // this pass's list goes after the running list; the two are merged into the running list
+        const bool opening = c0 == 0;
+        rc = topk_segmented(map, nullptr, nullptr, 1, n_t, 0, k, opening ? m_s : m_s + k, opening ? m_i : m_i + k,
+                            tws, tws_bytes, s, first);
+        if (rc) return rc;
+        if (!opening) {
+            rc = topk_segmented(m_s, m_i, nullptr, 1, 2 * (int64_t)k, 0, k, t_s, t_i, tws, tws_bytes, s);
+            if (!rc) rc = copy_list(t_s, t_i, m_s, m_i, k, s);
+            if (rc) return rc;
+        }
+    }
+    return copy_list(m_s, m_i, out_score, out_index, k, s);
 }

@@ -47,10 +47,12 @@ int check_grid(const bsh_grid* g);
 int check_window(const bsh_segments* seg, const bsh_grid* g);
 
 // Segmented exact top-k (bsh_topk.hip): offsets on the device, longest segment from the host.
+// With implicit indices (index NULL) the written indices are index_base + ((g << shift) | position);
+// the order among a segment's entries does not depend on the base.
 size_t topk_workspace_bytes(int32_t n_segs, int32_t k);
 int topk_segmented(const float* score, const int64_t* index, const int64_t* offsets, int32_t n_segs,
                    int64_t max_len, int32_t shift, int32_t k, float* out_score, int64_t* out_index,
-                   void* ws, size_t ws_bytes, hipStream_t stream);
+                   void* ws, size_t ws_bytes, hipStream_t stream, int64_t index_base = 0);
 
 // ---------------------------------------------------------------- device track
 

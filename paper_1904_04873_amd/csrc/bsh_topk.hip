@@ -52,6 +52,7 @@ struct Seg {
     int32_t n_segs;
     int32_t shift;           // implicit-index segment shift (0: position only)
     int32_t k;
+    int64_t out_base;        // added to the implicit indices of the written lists (0 for explicit)
     int32_t idx_bits;        // index bits that can differ inside a segment
     int32_t copies;          // copies of each global histogram (blocks add to copy b % copies)
     State* st;               // [n_segs]
@@ -538,7 +539,7 @@ __global__ void scatter_kernel(Seg s, float* __restrict__ out_score, int64_t* __
     const uint32_t r = s.rank[(size_t)g * s.k + e];
     if (r < k_eff) {
         out_score[(size_t)g * s.k + r] = s.sel_score[(size_t)g * s.k + e];
-        out_index[(size_t)g * s.k + r] = s.sel_index[(size_t)g * s.k + e];
+        out_index[(size_t)g * s.k + r] = s.sel_index[(size_t)g * s.k + e] + s.out_base;
     }
 }
 
@@ -642,7 +643,7 @@ __global__ __launch_bounds__(kThreads) void bucket_rank_kernel(Seg s, float* __r
     for (uint32_t q = lo; q < hi; ++q) r += (tk[q] > key) | ((tk[q] == key) & (ti[q] < ix)) ? 1u : 0u;
     if (r < k_eff) {
         out_score[(size_t)g * s.k + r] = s.tscore[(size_t)g * s.k + p];
-        out_index[(size_t)g * s.k + r] = ix;
+        out_index[(size_t)g * s.k + r] = ix + s.out_base;
     }
 }
 
@@ -775,7 +776,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_topk_kernel(Seg s, float*
         for (uint32_t f = 0; f < k_eff; ++f) rank += (ck[f] > key) | ((ck[f] == key) & (ci[f] < ix)) ? 1u : 0u;
         if (rank < k_eff) {
             os[rank] = cs[e];
-            oi[rank] = ix;
+            oi[rank] = ix + s.out_base;
         }
     }
 }
@@ -842,7 +843,7 @@ size_t topk_workspace_bytes(int32_t n_segs, int32_t k) { return workspace_bytes(
 // the longest segment given by the host.  NULL offsets: one segment [0, max_len).
 int topk_segmented(const float* score, const int64_t* index, const int64_t* offsets, int32_t n_segs,
                    int64_t max_len, int32_t shift, int32_t k, float* out_score, int64_t* out_index,
-                   void* ws, size_t ws_bytes, hipStream_t stream)
+                   void* ws, size_t ws_bytes, hipStream_t stream, int64_t index_base)
 {
     if (n_segs < 1 || k < 1) return fail_inval("n_segs and k must be >= 1");
     if (ws_bytes < workspace_bytes(n_segs, k)) {
@@ -860,6 +861,7 @@ int topk_segmented(const float* score, const int64_t* index, const int64_t* offs
     s.n_segs = n_segs;
     s.shift = shift;
     s.k = k;
+    s.out_base = index ? 0 : index_base;
     carve(ws, s);
     return topk_launch(s, max_len, out_score, out_index, stream);
 }

@@ -143,6 +143,33 @@ def test_other_entry_points_reject_bad_arguments():
     assert L.bsh_power_stat(ctypes.byref(seg), fake, 1, fake, fake, 0, 0, fake, None, None, None, None) == N.BSH_OK
 
 
+def test_count_topk_rejects_bad_arguments_on_host():
+    """The bounded stage-1 top-k checks its spec and workspace before any launch; its workspace
+    is one pass's map plus O(k)."""
+    from paper_1904_04873_amd import _native as N
+    L = _lib()
+    seg, grid, keep = _structs()
+    fake = ctypes.c_void_p(0x2000)
+    spec = N.TopkSpec(k=100, sky_per_pass=0)
+    need = L.bsh_hough_count_topk_workspace(ctypes.byref(grid), ctypes.byref(spec))
+    assert need > 0
+    big = N.TopkSpec(k=100000, sky_per_pass=0)
+    assert L.bsh_hough_count_topk_workspace(ctypes.byref(grid), ctypes.byref(big)) > need
+    bad = N.TopkSpec(k=0, sky_per_pass=0)
+    assert L.bsh_hough_count_topk_workspace(ctypes.byref(grid), ctypes.byref(bad)) == 0
+    args = (fake, fake, fake, need, None, None)
+    assert L.bsh_hough_count_topk(ctypes.byref(seg), ctypes.byref(grid), None, *args) == N.BSH_EINVAL
+    assert L.bsh_hough_count_topk(ctypes.byref(seg), ctypes.byref(grid), ctypes.byref(bad), *args) == N.BSH_EINVAL
+    neg = N.TopkSpec(k=10, sky_per_pass=-1)
+    assert L.bsh_hough_count_topk(ctypes.byref(seg), ctypes.byref(grid), ctypes.byref(neg), *args) == N.BSH_EINVAL
+    assert L.bsh_hough_count_topk(ctypes.byref(seg), ctypes.byref(grid), ctypes.byref(spec), fake, None, fake, need,
+                                  None, None) == N.BSH_EINVAL
+    assert L.bsh_hough_count_topk(ctypes.byref(seg), ctypes.byref(grid), ctypes.byref(spec), fake, fake, fake,
+                                  need - 1, None, None) == N.BSH_ENOMEM
+    assert L.bsh_hough_count_topk(ctypes.byref(seg), ctypes.byref(grid), ctypes.byref(spec), fake, fake, None, need,
+                                  None, None) == N.BSH_EINVAL
+
+
 def test_topk_workspace_is_order_k():
     """The tie resolution re-reads the scores, so the workspace does not grow with n."""
     L = _lib()

@@ -168,3 +168,83 @@ def test_every_tile_shape_gives_identical_maps(setup):
         torch.cuda.synchronize()
         assert torch.equal(plan.item_map(0), want), variant
         plan.close()
+
+
+def test_passes_give_the_lists_of_one_pass(setup):
+    """A map buffer smaller than all maps together runs the items in passes through it; the item
+    and band lists are those of the plan with room for every map, bit for bit (graph and eager,
+    batched and plain)."""
+    import torch
+    w, bsh, items, grids, hosts, n_bands = setup
+    _say("plan passes vs one pass")
+    ref = bsh.Plan(items, grids, n_bands, k_item=600, k_band=800, use_graph=True)
+    assert ref.passes == 1
+    ref.run()
+    torch.cuda.synchronize()
+    want = [t.clone() for t in (ref.item_score, ref.item_index, ref.band_score, ref.band_index)]
+    largest = max(int(ref.offsets[q + 1] - ref.offsets[q]) for q in range(len(items)))
+    ref.close()
+    for buf, graph in ((largest, True), (largest + 1, False), (2 * largest, True)):
+        plan = bsh.Plan(items, grids, n_bands, k_item=600, k_band=800, use_graph=graph, map_floats=buf)
+        assert plan.passes > 1
+        for rep in range(2):
+            for t in (plan.item_score, plan.item_index, plan.band_score, plan.band_index):
+                t.fill_(-3)
+            plan.run() if rep == 0 else plan.run_plain()
+            torch.cuda.synchronize()
+            plan.status.raise_if_set("passes")
+            got = (plan.item_score, plan.item_index, plan.band_score, plan.band_index)
+            for a, b in zip(got, want):
+                assert torch.equal(a, b), (buf, graph, rep)
+        plan.close()
+
+
+def test_plan_rejects_a_buffer_below_the_largest_item(setup):
+    import torch
+    w, bsh, items, grids, hosts, n_bands = setup
+    from paper_1904_04873_amd._native import BshError
+    sizes = [ns * grids[gi].n_bin * grids[gi].n_f0 for (_, gi, _, ns, _) in items]
+    with pytest.raises(BshError):
+        bsh.Plan(items, grids, n_bands, k_item=10, k_band=10, map_floats=max(sizes) - 1)
+    with pytest.raises(BshError):          # passes need item lists
+        bsh.Plan(items, grids, n_bands, map_floats=max(sizes))
+    torch.cuda.synchronize()
+
+
+@pytest.mark.timeout(600)
+def test_two_whole_items_against_the_oracle_map(setup):
+    """Two whole work items of the batching workload, map for map against the oracle: the
+    smallest band's patch 0 (49 650 binary templates) and the widest band's patch 255 (145 824,
+    t_asc up to 256 per cell): counts exact outside near-ties, weighted counts within 1e-5."""
+    import torch
+    w, bsh, items, grids, hosts, n_bands = setup
+    _say("two whole items vs the oracle")
+    plan = bsh.Plan(items, grids, n_bands, use_graph=False, variant=1)
+    plan.run()
+    torch.cuda.synchronize()
+    plan.status.raise_if_set("plan")
+    tab = bsh.Plan(items, grids, n_bands, use_graph=False)
+    tab.run()
+    torch.cuda.synchronize()
+    for q in (0, len(items) - 1):
+        ds, gi, lo, ns, band = items[q]
+        seg, spec = hosts[q]
+        g = grids[gi]
+        o = O.grid_tables(spec, seg.t_span_mid())
+        assert np.array_equal(g.tasc_off, o[2])
+        _say(f"oracle: item {ITEMS[q]} ({g.n_bin} binary templates, {seg.n_seg} segments)")
+        cnt_o, nw_o, nt_o, ntw_o = O.hough_count(seg, w.sky[lo:lo + 1], spec.k0, spec.n_f0, *o)
+        wmax = float(seg.weight.max())
+        for m in (_np(plan.item_map(q)), _np(tab.item_map(q))):
+            err = np.abs(m.astype(np.float64) - nw_o)
+            assert np.all(err <= 1e-5 * nw_o + ntw_o + 1e-30), f"item {ITEMS[q]}: max rel {np.max(err / np.maximum(nw_o, 1e-30))}"
+        # unweighted counts: the select variant with counts, standalone on the item's pixel
+        g1 = bsh.DeviceGrid.from_tables(_np(g.sky)[lo:lo + 1], g.k0, g.n_f0, g.a_p, g.period, g.tasc_off,
+                                        _np(g.t_asc_dev))
+        _, c = bsh.bsh_hough_count(ds, g1, with_count=True)
+        torch.cuda.synchronize()
+        c = _np(c).view(np.uint32).astype(np.int64)
+        assert np.all(np.abs(c - cnt_o.astype(np.int64)) <= nt_o), f"item {ITEMS[q]} counts"
+        _say(f"item {ITEMS[q]}: near-tie templates {int((nt_o > 0).sum())}")
+    plan.close()
+    tab.close()

@@ -143,35 +143,151 @@ def test_count_ragged_rule_grid_multisky_per_sky_weights(B):
     _check_counts(cnt_o, _np(ws_t), cnt_o, nw_o, nt_o, ntw_o)
 
 
-def test_count_config2_full_size_sampled(B):
-    """The full 11.8M-template map at 4000 segments; 3000 sampled templates plus the top 500
-    recomputed one by one by the oracle."""
-    import torch
-    _say("count cfg2 full size")
+@pytest.fixture(scope="module")
+def cfg2_injected():
+    """The 200 Hz band as configured: 4000 gapped segments with 10 injected signals (SNR 1-3,
+    off-grid), and the oracle's full stage-1 map of it (11.8 M templates, every one evaluated
+    on its own track; about 20 s on 16 host threads)."""
     w = S.config2()
     seg, spec = w.segments[0], w.grids[0]
-    ds, g, o, ws, cnt = _run_count(B, seg, spec, w.sky)
-    assert ws.size == 11796480
-    rng = np.random.default_rng(7)
-    top = np.argsort(-ws, kind="stable")[:500]
-    idx = np.concatenate([rng.integers(0, ws.size, 3000), top])
-    s, b, i, ia, ip = O.decode_index(idx, g.n_bin, 90, o[2], spec.n_per)
-    cand = np.stack([(spec.k0 + i).astype(np.float64), o[0][ia], o[1][ip], o[3][b]], axis=1)
-    _, c_o, nw_o, nt_o = O.power_stat(seg, w.sky, s.astype(np.int32), cand, mode=0)
-    ntw_o = nt_o * float(seg.weight.max())
-    _check_counts(cnt[idx], ws[idx], c_o, nw_o, nt_o, ntw_o)
-    ws_t, _ = B.bsh_hough_count(ds, g)          # default: table variant, as the benchmark runs it
+    o = O.grid_tables(spec, seg.t_span_mid())
+    rng = w.rng["injections"]
+    inj = np.stack([spec.k0 + rng.uniform(2, 87, 10), rng.uniform(0.3, 2.9, 10),
+                    rng.uniform(spec.per_lo, spec.per_hi, 10), np.zeros(10)], axis=1)
+    t_mid = seg.t_span_mid()
+    inj[:, 3] = t_mid - inj[:, 2] / 2 + rng.uniform(0, 1, 10) * inj[:, 2]
+    snr = rng.uniform(1, 3, 10)
+    _, k_inj = O.track(seg, w.sky, np.zeros(10, np.int32), inj)
+    S.inject(seg.power, rng, [k - seg.k_lo for k in k_inj], snr)
+    _say(f"oracle: full 200 Hz map on {O.num_threads()} threads")
+    full = O.hough_count(seg, w.sky, spec.k0, spec.n_f0, *o)
+    return w, seg, spec, o, inj, snr, full
+
+
+def _topk_near_tie_ok(got_idx, nw_o, nt_o, wmax, k):
+    """The GPU's top-k indices against the oracle's own top-k of its full map: identical, except
+    that an entry may trade places with one whose oracle score is within 1e-5 relative (plus its
+    near-tie weight) of the oracle's k-th score."""
+    rv, ri = O.topk(nw_o, k)
+    kth = float(rv[-1])
+    diff = set(got_idx.tolist()) ^ set(ri.tolist())
+    for j in diff:
+        assert abs(nw_o[j] - kth) <= REL * kth + nt_o[j] * wmax, (j, nw_o[j], kth)
+    return len(diff)
+
+
+def test_count_config2_full_map_against_oracle(B, cfg2_injected):
+    """Every one of the 11 796 480 templates of the 200 Hz band against the oracle's full map:
+    counts bit-exact outside near-ties, weighted counts (both accumulation variants) within
+    1e-5; the map is the same bit for bit at every tile shape the autotuner may pick."""
+    import torch
+    _say("count cfg2 full map vs oracle")
+    w, seg, spec, o, inj, snr, (cnt_o, nw_o, nt_o, ntw_o) = cfg2_injected
+    ds = B.DeviceSegments.from_host(seg)
+    g, o2 = _grid_pair(B, spec, seg, w.sky)
+    st = _status(B)
+    ws, cnt = B.bsh_hough_count(ds, g, with_count=True, status=st)
+    ws_t, _ = B.bsh_hough_count(ds, g, status=st)          # default: table variant, as the benchmark runs it
     torch.cuda.synchronize()
-    ws_t = _np(ws_t)
-    _check_counts(c_o, ws_t[idx], c_o, nw_o, nt_o, ntw_o)
-    assert np.max(np.abs(ws_t - ws) / np.maximum(ws, 1e-30)) < 2e-5
-    # every tile shape the benchmark's autotuner may pick gives this same map, bit for bit
+    st.raise_if_set("count")
+    ws, cnt, ws_t = _np(ws), _np(cnt).view(np.uint32), _np(ws_t)
+    assert ws.size == 11796480
+    _check_counts(cnt, ws, cnt_o, nw_o, nt_o, ntw_o)
+    _check_counts(cnt_o, ws_t, cnt_o, nw_o, nt_o, ntw_o)
+    n_tie = int((nt_o > 0).sum())
+    _say(f"templates with a near-tie segment: {n_tie}")
+    if n_tie == 0:
+        assert np.array_equal(cnt, cnt_o)
     for lanes, chunk in ((512, 512), (512, 256), (256, 256), (128, 128)):
         ws_s, _ = B.bsh_hough_count(ds, g, lanes=lanes, chunk=chunk, variant=2)
         torch.cuda.synchronize()
         assert np.array_equal(_np(ws_s), ws_t), (lanes, chunk)
-    # mean count under noise ~ N exp(-1.6) (statistical sanity at full size)
-    assert abs(cnt.mean() / 4000 - math.exp(-1.6)) < 0.01
+    # mean count under (mostly) noise ~ N exp(-1.6)
+    assert abs(cnt.mean() / seg.n_seg - math.exp(-1.6)) < 0.01
+
+
+def test_count_topk_config2_against_oracle_list(B, cfg2_injected):
+    """Stage-1 top-10^4 of the 200 Hz band, from the full map (bsh_topk) and from the bounded
+    stage-1 entry point (bsh_hough_count_topk), against the oracle's own top-10^4 of its full map."""
+    import torch
+    _say("cfg2 stage-1 top-10^4 vs the oracle's list")
+    w, seg, spec, o, inj, snr, (cnt_o, nw_o, nt_o, ntw_o) = cfg2_injected
+    ds = B.DeviceSegments.from_host(seg)
+    g = B.DeviceGrid.build(spec, seg.t_span_mid(), w.sky)
+    st = _status(B)
+    ws, _ = B.bsh_hough_count(ds, g, status=st)
+    v1, i1 = B.bsh_topk(ws, 10000)
+    v2, i2 = B.bsh_hough_count_topk(ds, g, 10000, status=st)
+    torch.cuda.synchronize()
+    st.raise_if_set("top-k")
+    assert torch.equal(v1, v2) and torch.equal(i1, i2)
+    n_diff = _topk_near_tie_ok(_np(i1), nw_o, nt_o, float(seg.weight.max()), 10000)
+    _say(f"entries that trade places at the cut: {n_diff}")
+    # listed scores against the oracle's, one by one
+    idx = _np(i1)
+    assert np.all(np.abs(_np(v1).astype(np.float64) - nw_o[idx]) <= REL * nw_o[idx] + ntw_o[idx])
+
+
+@pytest.mark.parametrize("k", [1, 777, 5000, 400000])
+def test_count_topk_in_passes_equals_topk_of_the_map(B, k):
+    """bsh_hough_count_topk over 5 sky pixels (184 320 templates each) with 1, 2, 3 or all pixels
+    per pass: the list is bsh_topk of the full map, bit for bit; a pass smaller than k is
+    refused when there are several passes."""
+    import torch
+    from paper_1904_04873_amd._native import BshError
+    _say(f"bounded stage-1 top-k, k={k}")
+    w = S.config2(n_per_det=300)
+    seg = w.segments[0]
+    spec = S.GridSpec(k0=180000, n_f0=90, ap_lo=0.01, ap_hi=3.0, n_ap=8, per_lo=15 * S.DAY,
+                      per_hi=45 * S.DAY, n_per=4, tasc_fixed=64)
+    sky = S.fibonacci_sphere(5)
+    ds = B.DeviceSegments.from_host(seg)
+    g = B.DeviceGrid.build(spec, seg.t_span_mid(), sky)
+    st = _status(B)
+    ws, _ = B.bsh_hough_count(ds, g, status=st)
+    want = B.bsh_topk(ws, k)
+    per_pixel = g.n_bin * g.n_f0
+    for spp in (0, 1, 2, 3, 5):
+        if 0 < spp < 5 and spp * per_pixel < k:
+            with pytest.raises(BshError):
+                B.bsh_hough_count_topk(ds, g, k, sky_per_pass=spp, status=st)
+            continue
+        got = B.bsh_hough_count_topk(ds, g, k, sky_per_pass=spp, status=st)
+        torch.cuda.synchronize()
+        assert torch.equal(got[0], want[0]) and torch.equal(got[1], want[1]), spp
+    st.raise_if_set("bounded top-k")
+    if k == 777:
+        # the oracle's own list of the full map, up to near-ties at the cut
+        o = O.grid_tables(spec, seg.t_span_mid())
+        cnt_o, nw_o, nt_o, ntw_o = O.hough_count(seg, sky, spec.k0, spec.n_f0, *o)
+        _topk_near_tie_ok(_np(want[1]), nw_o, nt_o, float(seg.weight.max()), k)
+
+
+def test_count_topk_per_sky_weights_and_short_grid(B):
+    """Per-pixel weights follow their pixels across passes; a grid with fewer templates than k
+    gives the whole ranked map and a -inf / -1 tail."""
+    import torch
+    _say("bounded stage-1 top-k, per-pixel weights")
+    rng = np.random.default_rng(11)
+    base = S.tiny_segments(n_seg=200, k0=150000, n_f0=37, margin=19, seed=3, span_days=200)
+    spec = S.GridSpec(k0=150000, n_f0=37, ap_lo=0.05, ap_hi=3.25, n_ap=5, per_lo=15 * S.DAY,
+                      per_hi=45 * S.DAY, n_per=3)
+    sky = S.fibonacci_sphere(4)
+    wps = np.exp(0.3 * rng.standard_normal((4, 200))).astype(np.float32)
+    ds = B.DeviceSegments.from_host(base, weight=wps)
+    g = B.DeviceGrid.build(spec, base.t_span_mid(), sky)
+    ws, _ = B.bsh_hough_count(ds, g)
+    for k in (50, g.n_templates // 4):
+        want = B.bsh_topk(ws, k)
+        got = B.bsh_hough_count_topk(ds, g, k, sky_per_pass=1)
+        torch.cuda.synchronize()
+        assert torch.equal(got[0], want[0]) and torch.equal(got[1], want[1]), k
+    k = g.n_templates + 10
+    got = B.bsh_hough_count_topk(ds, g, k)
+    want = B.bsh_topk(ws, k)
+    torch.cuda.synchronize()
+    assert torch.equal(got[0], want[0]) and torch.equal(got[1], want[1])
+    assert int(got[1][-1].item()) == -1 and float(got[0][-1].item()) == float("-inf")
 
 
 def test_count_edge_cases(B):
@@ -539,27 +655,23 @@ def test_stage2_bins_agree_with_stage1_on_grid(B):
 
 # ---------------------------------------------------------------- two-stage pipeline
 
-def test_pipeline_config2_recovers_injections(B):
-    """Config 2 with 10 injected signals (SNR 1-3, off-grid): stage-1 top-10^4 -> stage 2 ->
-    top-100.  The stage-1 selection equals an exact sort of the GPU map, its scores match the
-    oracle one by one, stage 2 matches the oracle, and every injection is found."""
+def test_pipeline_config2_recovers_injections(B, cfg2_injected):
+    """The 200 Hz band with its 10 injected signals (SNR 1-3, off-grid): stage-1 top-10^4 ->
+    stage 2 -> top-100.  The stage-1 list is the oracle's own top-10^4 (up to near-ties at the
+    cut), the winners' stage-2 power and counts match the oracle, and the stage-2 top-100 is the
+    oracle's ranking of the same candidates.
+
+    Recovery: every injection stands out of the noise in the stage-1 map (a template within two
+    grid steps of it has s_H > 8).  Not every injection reaches the top-10^4: the strongest
+    signals' side lobes in (a_p, P, t_asc) fill most of the list (the post-processing finds them
+    as a few large clusters), which is the crowding that the paper's per-region top-lists and
+    clustering are there to handle."""
     import torch
     _say("pipeline cfg2 injections")
-    w = S.config2()
-    seg, spec = w.segments[0], w.grids[0]
-    o = O.grid_tables(spec, seg.t_span_mid())
-    rng = w.rng["injections"]
+    w, seg, spec, o, inj, snr, (cnt_o, nw_o, nt_o, ntw_o) = cfg2_injected
     steps = np.array([1.0, (spec.ap_hi - spec.ap_lo) / (spec.n_ap - 1), (spec.per_hi - spec.per_lo) / (spec.n_per - 1)])
-    inj = np.stack([spec.k0 + rng.uniform(2, 87, 10), rng.uniform(0.3, 2.9, 10),
-                    rng.uniform(spec.per_lo, spec.per_hi, 10), np.zeros(10)], axis=1)
-    t_mid = seg.t_span_mid()
-    inj[:, 3] = t_mid - inj[:, 2] / 2 + rng.uniform(0, 1, 10) * inj[:, 2]
-    snr = rng.uniform(1, 3, 10)
-    _, k_inj = O.track(seg, w.sky, np.zeros(10, np.int32), inj)
-    S.inject(seg.power, rng, [k - seg.k_lo for k in k_inj], snr)
-
     ds = B.DeviceSegments.from_host(seg)
-    g = B.DeviceGrid.build(spec, t_mid, w.sky)
+    g = B.DeviceGrid.build(spec, seg.t_span_mid(), w.sky)
     st = _status(B)
     ws, _ = B.bsh_hough_count(ds, g, status=st)
     v1, i1 = B.bsh_topk(ws, 10000)
@@ -569,26 +681,31 @@ def test_pipeline_config2_recovers_injections(B):
     torch.cuda.synchronize()
     st.raise_if_set("pipeline")
 
-    # stage-1 selection == exact sort of the GPU map (score desc, index asc)
-    order = torch.sort(ws, descending=True, stable=True).indices[:10000]
-    assert torch.equal(order, i1)
-    # scores of the selected templates against the oracle, one by one
+    wmax = float(seg.weight.max())
+    _topk_near_tie_ok(_np(i1), nw_o, nt_o, wmax, 10000)
+    # the decoded candidates are the listed templates, and their stage-1 values are the map's
+    idx = _np(i1)
+    s_, b_, i_, ia_, ip_ = O.decode_index(idx, g.n_bin, spec.n_f0, o[2], spec.n_per)
+    assert np.array_equal(_np(cp), np.stack([(spec.k0 + i_).astype(np.float64), o[0][ia_], o[1][ip_], o[3][b_]], axis=1))
     cand = _np(cp)
-    P_o, c_o, nw_o, nt_o = O.power_stat(seg, w.sky, _np(cs), cand, mode=0)
-    ntw = nt_o * float(seg.weight.max())
-    _check_counts(_np(c2).view(np.uint32), _np(v1), c_o, nw_o, nt_o, ntw)
-    assert np.all(np.abs(_np(P).astype(np.float64) - P_o) <= REL * P_o + nt_o * float(seg.weight.max() * seg.power.max()))
+    P_o, c_o, nw2_o, nt2_o = O.power_stat(seg, w.sky, _np(cs), cand, mode=0)
+    ntw = nt2_o * wmax
+    _check_counts(_np(c2).view(np.uint32), _np(v1), c_o, nw2_o, nt2_o, ntw)
+    assert np.array_equal(c_o, cnt_o[idx])
+    assert np.all(np.abs(_np(P).astype(np.float64) - P_o) <= REL * P_o + nt2_o * float(seg.weight.max() * seg.power.max()))
     # stage-2 top-100 against the oracle's ranking of the same 10^4 candidates
     rv, ri = O.topk(P_o, 100)
     got = set(_np(pos2).tolist())
     kth = rv[-1]
     for j in got.symmetric_difference(set(ri.tolist())):
         assert abs(P_o[j] - kth) <= REL * kth
-    # every injection stands out of the noise: the best template within two grid steps of it
-    # in F, a_p and P (any t_asc) has a weighted-count significance above 8
-    m4 = _np(ws).reshape(spec.n_ap, spec.n_per, 64, spec.n_f0)
+    # every injection stands out of the noise in the oracle's map: the best template within two
+    # grid steps of it in F, a_p and P (any t_asc) has s_H > 8
+    m4 = nw_o.reshape(spec.n_ap, spec.n_per, 64, spec.n_f0)
     a_p, per = g.a_p, g.period
     s_all = O.significance_h(m4.max(), seg.weight)
+    found = 0
+    listed = set(idx.tolist())
     for q in range(10):
         ia = np.nonzero(np.abs(a_p - inj[q, 1]) <= 2 * steps[1])[0]
         ip = np.nonzero(np.abs(per - inj[q, 2]) <= 2 * steps[2])[0]
@@ -596,6 +713,11 @@ def test_pipeline_config2_recovers_injections(B):
         sub = m4[ia.min():ia.max() + 1, ip.min():ip.max() + 1, :, max(0, i0 - 2):i0 + 3]
         s_best = O.significance_h(sub.max(), seg.weight)
         assert s_best > 8, f"injection {q} (snr {snr[q]:.2f}) peaks at s_H = {s_best:.1f}"
+        a_i, p_i, t_i, f_i = np.unravel_index(int(np.argmax(sub)), sub.shape)
+        best = ((ia.min() + a_i) * spec.n_per + ip.min() + p_i) * 64 * spec.n_f0 + t_i * spec.n_f0 + max(0, i0 - 2) + f_i
+        found += int(best in listed)
+        _say(f"injection {q}: snr {snr[q]:.2f}, s_H {s_best:.1f}, peak template listed: {best in listed}")
+    assert found >= 3
     # and the strongest stage-2 candidates are far above noise
     s_p = O.significance_p(_np(v2).astype(np.float64), seg.weight)
     assert s_p[0] > 20 and s_all > 20
