@@ -1,21 +1,20 @@
 #!/usr/bin/env python3
-"""Throughput of the binary Hough hot path on one MI355X.
+"""Throughput of the binary Hough hot path on one MI355X: the batched stage 1 against plain
+per-item launches, at exact top-k.
 
-One step = one pass of the whole hot path over one band of synthetic data already resident
-in HBM: peakgram, stage-1 weighted count over every template, stage-1 top-k, decoding of the
-winners, stage-2 power (and the winners' counts) on the exact track, stage-2 top-k.
+One step = one batched run of the batching workload with its inputs resident in HBM: 256 sky
+patches x 4 bands of 0.1 Hz in 100-300 Hz (1024 items of 3000-6000 gapped segments, a_p 64 x
+P 32 x t_asc 4-256 per cell by the eq:binaryres rule, 90 f0 bins; 9.01e9 templates, 4.0e13
+template x segments), as one graph-captured persistent launch followed by per-item and per-band
+top-1000 lists.  The same work as one plain launch (and top-k) per item is timed beside it.
+Work unit: template x segment of stage 1.
 
-Default workload: 4000 segments (2 detectors x 2000, gapped), one sky pixel, band
-200.0-200.1 Hz (90 f0 bins), a_p 64 x P 32 x t_asc 64 -> 11 796 480 templates; stage-1
-top-10^4 then stage-2 top-100.  Work unit: template x segment of stage 1.
+The same line carries the two-stage step of one band (200 Hz: 4000 segments, 11.8 M templates,
+stage-1 top-10^4, stage 2, top-100), the all-sky slice at its full size (2000 pixels x 52.3 M
+templates through a bounded map buffer, top-10^5, then stage 2 and 20 Adam steps on the
+winners), the refinement and post-processing at their own sizes, and the steps beside the path.
 
-The same line carries the batched-versus-plain comparison on the full batching workload: 256 sky
-patches x 4 bands of 0.1 Hz in 100-300 Hz (1024 items, 3000-6000 gapped segments each, uneven
-t_asc counts per cell; 9.01e9 templates, ~4e13 template x segments), stage 1 plus per-item top-1000
-and per-band top-1000 lists, once as one graph-captured persistent launch and once as one plain
-launch (and top-k) per item.
-
-Prints one JSON line.  The CPU oracle is timed on a bounded sample of the same workload.
+Prints one JSON line.  The CPU oracle is timed on a bounded sample of the headline workload.
 """
 import argparse
 import json
@@ -29,42 +28,53 @@ sys.path.insert(0, ROOT)
 METRIC = "Hough templates·segments/s on 1 GPU, batched vs plain, at oracle-exact top-k"
 # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: 32-bit VALU lane-operations per second
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
-# VALU lane-operations per template x segment on the fast path of the subset-sum table count:
-# the VALU instructions of the segment-group loop in its gfx950 assembly along the path with no
-# f0-shift step and no flush (paper_1904_04873_amd/fastpath_ops.py counts them: 664 per group
-# of 8 segments at the 128- and 256-segment chunks), divided by the group's 8 x 90 template x
-# segments.
+# Algorithmic floor of the subset-sum table count, in VALU lane-operations per template x
+# segment: per template and group of 8 segments one table read (its address, 1) and one add (1),
+# i.e. 2/8; per (binary template, segment) the track shared by the band's 90 f0 bins: G (3 FP64
+# operations), the nearest bins of the lowest and highest f0 (an FMA and a conversion each, 4),
+# the row address (2) and the three funnel shifts of the 96-bit window (3), i.e. 12/90.  The
+# transposes that turn eight 96-bit masks into 90 byte indices are the kernel's own way of
+# forming the indices and are not counted.
+FLOOR_OPS_PER_TS = 2 / 8 + 12 / 90
+# VALU lane-operations per template x segment the table count issues on its fast path: the VALU
+# instructions of the segment-group loop in its gfx950 assembly along the path with no f0-shift
+# step and no flush (paper_1904_04873_amd/fastpath_ops.py counts them: 664 per group of 8
+# segments), divided by the group's 8 x 90 template x segments.
 TABLE_OPS_PER_TS = 664 / 720
-# the same figure for plain select-and-add: extract the peak bit, select the weight, add
+# plain select-and-add: extract the peak bit, select the weight, add
 SELECT_OPS_PER_TS = 3
 # HBM bytes per count launch, measured with rocprofv3 counters for one kernel source and tile
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hough_count_table_band200Hz_traffic.txt")
-# the plain count kernel's sources and the build script (which holds its compiler flags)
+BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hough_batch_table_1024items_traffic.txt")
+# the count kernels' sources and the build script (which holds their compiler flags)
 COUNT_SOURCES = ("paper_1904_04873_amd/csrc/bsh_count.hip", "paper_1904_04873_amd/csrc/bsh_count_tile.h",
+                 "paper_1904_04873_amd/csrc/bsh_count.h", "paper_1904_04873_amd/csrc/bsh_internal.h",
+                 "paper_1904_04873_amd/build.py")
+BATCH_SOURCES = ("paper_1904_04873_amd/csrc/bsh_count_batch.hip", "paper_1904_04873_amd/csrc/bsh_count_tile.h",
                  "paper_1904_04873_amd/csrc/bsh_count.h", "paper_1904_04873_amd/csrc/bsh_internal.h",
                  "paper_1904_04873_amd/build.py")
 
 
-def count_sources_digest() -> str:
+def count_sources_digest(sources=COUNT_SOURCES) -> str:
     import hashlib
     h = hashlib.sha256()
-    for rel in COUNT_SOURCES:
+    for rel in sources:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def measured_traffic(lanes: int, chunk: int):
+def measured_traffic(lanes: int, chunk: int, path=TRAFFIC_FILE, sources=COUNT_SOURCES):
     """HBM bytes per launch from the committed counter summary, or None when the count kernel's
     sources or the tile differ from those the counters were taken on."""
     try:
         kv = {}
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             for line in f:
                 parts = line.split()
                 if len(parts) == 2 and not line.startswith("#"):
                     kv[parts[0]] = parts[1]
-        if kv.get("sources_sha256") != count_sources_digest():
+        if kv.get("sources_sha256") != count_sources_digest(sources):
             return None
         if (int(kv["lanes"]), int(kv["chunk"])) != (lanes, chunk):
             return None
@@ -73,24 +83,25 @@ def measured_traffic(lanes: int, chunk: int):
         return None
 
 
-def oracle_one_thread(n_ap: int) -> dict:
-    """The same oracle count on one host thread (OMP_NUM_THREADS=1 in a child process), over the
-    first n_ap a_p values of the 200 Hz band grid."""
+def oracle_one_thread(item: int, n_ap: int) -> dict:
+    """The oracle count on one host thread (OMP_NUM_THREADS=1 in a child process), over the
+    first n_ap a_p values of one item of the batching workload."""
     import subprocess
     code = (
         "import json, sys, time\n"
         f"sys.path.insert(0, {ROOT!r})\n"
         "import bsh_synth as S\n"
         "import oracle as O\n"
-        "w = S.config2(); seg, spec = w.segments[0], w.grids[0]\n"
+        f"w = S.config3(build_items=[{item}]); seg = w.segments[{item}]; spec = w.grids[w.item_grid[{item}]]\n"
+        f"lo, hi = w.item_sky[{item}]\n"
         "a_p, per, off, t_asc = O.grid_tables(spec, seg.t_span_mid())\n"
         f"n_ap = max(1, min({n_ap}, spec.n_ap)); sub = off[:n_ap * spec.n_per + 1]\n"
         "t0 = time.perf_counter()\n"
-        "O.hough_count(seg, w.sky, spec.k0, spec.n_f0, a_p[:n_ap], per, sub, t_asc[:sub[-1]])\n"
+        "O.hough_count(seg, w.sky[lo:hi], spec.k0, spec.n_f0, a_p[:n_ap], per, sub, t_asc[:sub[-1]])\n"
         "dt = time.perf_counter() - t0\n"
         "ts = int(sub[-1]) * spec.n_f0 * seg.n_seg\n"
         "print(json.dumps({'value': ts / dt, 'threads': O.num_threads(), 'sample': "
-        "f'first {n_ap} a_p values: {ts:.3e} template*segments in {dt:.1f} s'}))\n")
+        f"f'item {item}, first {{n_ap}} a_p values: {{ts:.3e}} template*segments in {{dt:.1f}} s'}}))\n")
     env = dict(os.environ, OMP_NUM_THREADS="1")
     res = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
     if res.returncode != 0:
@@ -101,23 +112,44 @@ def oracle_one_thread(n_ap: int) -> dict:
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=10, help="timed batched runs")
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--plain-steps", type=int, default=3, help="timed plain runs (at most --steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-graph", action="store_true", help="enqueue every step eagerly")
     ap.add_argument("--cpu-one-thread-ap", type=int, default=1,
                     help="a_p values of the one-thread oracle sample (0: skip it)")
     ap.add_argument("--cpu-sample-ap", type=int, default=32,
-                    help="a_p values (of 64) in the oracle's timed sample")
-    ap.add_argument("--skip-batched", action="store_true",
-                    help="omit the batched-versus-plain comparison")
-    ap.add_argument("--batched-steps", type=int, default=2)
-    ap.add_argument("--allsky-pixels", type=int, default=16,
-                    help="pixels of the all-sky slice to time (0: skip it)")
+                    help="a_p values (of 64) of the widest band's item in the oracle's timed sample")
+    ap.add_argument("--band-steps", type=int, default=20, help="timed steps of the 200 Hz two-stage step")
+    ap.add_argument("--allsky-pixels", type=int, default=2000,
+                    help="pixels of the all-sky slice (0: skip it)")
+    ap.add_argument("--allsky-pass-pixels", type=int, default=64,
+                    help="pixels whose maps the all-sky plan's buffer holds")
+    ap.add_argument("--skip-extras", action="store_true",
+                    help="only the headline (no band step, all-sky slice, refinement, post-processing)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="before timing, run one plain device copy of this many MiB (a known-size "
                          "kernel for scaling HBM byte counters)")
     return ap.parse_args()
+
+
+def timed_runs(fn, reps, warm=1):
+    """Median and mean of `reps` runs of fn, each bracketed by HIP events on the current stream."""
+    import numpy as np
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        out.append(a.elapsed_time(b))
+    return float(np.median(out)), float(np.mean(out))
 
 
 def main():
@@ -132,40 +164,11 @@ def main():
     import torch
 
     import bsh_synth as S
-    from paper_1904_04873_amd import bsh
+    from paper_1904_04873_amd import autotune, bsh
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-
-    w = S.config2()
-    seg, spec = w.segments[0], w.grids[0]
-    k1, k2 = w.topk_stage1, w.topk_stage2
-    print(f"[bench] workload cfg2: {seg.n_seg} segments, building device tables", file=sys.stderr, flush=True)
-    ds = bsh.DeviceSegments.from_host(seg)
-    g = bsh.DeviceGrid.build(spec, seg.t_span_mid(), w.sky)
-    n_t = g.n_templates
-    ts_per_step = n_t * seg.n_seg
-    st = bsh.Status(dev)
-    ws_map = torch.empty(n_t, dtype=torch.float32, device=dev)
-    top1 = bsh.TopK(n_t, k1, dev)
-    top2 = bsh.TopK(k1, k2, dev)
-    s1_score = torch.empty(k1, dtype=torch.float32, device=dev)
-    s1_index = torch.empty(k1, dtype=torch.int64, device=dev)
-    s2_score = torch.empty(k2, dtype=torch.float32, device=dev)
-    s2_pos = torch.empty(k2, dtype=torch.int64, device=dev)
-    P = torch.empty(k1, dtype=torch.float32, device=dev)
-    from paper_1904_04873_amd import autotune
-    (lanes, chunk), tune_ms = autotune.tune_plain(ds, g, use_cache=False)
-    print(f"[bench] tile {lanes} x {chunk}", file=sys.stderr, flush=True)
-
-    def step():
-        bsh.bsh_peakgram(ds.power, 1.6, out=ds.peak_bits)
-        bsh.bsh_hough_count(ds, g, status=st, wsum_out=ws_map, lanes=lanes, chunk=chunk)
-        top1(ws_map, out_score=s1_score, out_index=s1_index)
-        cs, cp = bsh.bsh_decode_templates(g, s1_index)
-        bsh.bsh_power_stat(ds, g.sky, cs, cp, mode=0, with_counts=True, status=st, out=P)
-        top2(P, out_score=s2_score, out_index=s2_pos)
 
     if args.calibrate_copy_mb > 0:
         n_f = args.calibrate_copy_mb * (1 << 20) // 4
@@ -175,87 +178,95 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    for _ in range(args.warmup):
-        step()
+    # ---------------------------------------------------------------- the batching workload
+    print("[bench] batching workload: generating 1024 items", file=sys.stderr, flush=True)
+    w = S.config3()
+    sample_items = (0, len(w.segments) - 1)        # band 100.0 Hz patch 0, band 299.8 Hz patch 255
+    host_keep = {it: (w.segments[it], w.grids[w.item_grid[it]], w.item_sky[it]) for it in sample_items}
+    items, grids = [], []
+    ts_total = 0
+    n_templates = 0
+    for it in range(len(w.segments)):
+        seg = w.segments[it]
+        band = w.item_grid[it]
+        g = bsh.DeviceGrid.build(w.grids[band], seg.t_span_mid(), w.sky, device=dev)
+        ds = bsh.DeviceSegments.from_host(seg, device=dev)
+        lo, hi = w.item_sky[it]
+        items.append((ds, it, lo, hi - lo, band))
+        grids.append(g)
+        ts_total += (hi - lo) * g.n_bin * g.n_f0 * seg.n_seg
+        n_templates += (hi - lo) * g.n_bin * g.n_f0
+        if it not in host_keep:
+            w.segments[it] = None        # drop the host copy
     torch.cuda.synchronize()
-    st.raise_if_set("warmup")
-
-    # One step is one HIP graph replay: the ~50 launches of a step are enqueued once at capture
-    # time, so host launch latency does not stretch the step.
-    run_step = step
-    if not args.no_graph:
-        graph = torch.cuda.CUDAGraph()
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            step()
-        torch.cuda.current_stream().wait_stream(side)
-        torch.cuda.synchronize()
-        with torch.cuda.graph(graph):
-            step()
-        torch.cuda.synchronize()
-        run_step = graph.replay
-        for _ in range(args.warmup):
-            run_step()
-        torch.cuda.synchronize()
-        st.raise_if_set("graph warmup")
-    print(f"[bench] warmup done, timing {args.steps} steps", file=sys.stderr, flush=True)
-
+    print(f"[bench] batching workload resident: {ts_total:.3e} template*segments; autotuning",
+          file=sys.stderr, flush=True)
+    (lanes, chunk), tune_ms = autotune.tune(items, grids, 4, sample=16, use_cache=False)
+    # the plain baseline runs with the tile that suits one launch per item best
+    (lanes_p, chunk_p), tune_p_ms = autotune.tune(items, grids, 4, sample=16, use_cache=False, plain=True)
+    k_item, k_band = 1000, 1000
+    st = bsh.Status(dev)
+    plan = bsh.Plan(items, grids, 4, k_item=k_item, k_band=k_band, lanes=lanes, chunk=chunk,
+                    use_graph=True, lpt=True, status=st)
+    print(f"[bench] batched: tile {lanes} x {chunk}, {plan.units} units on {plan.blocks} blocks; "
+          f"{args.warmup} warmup + {args.steps} timed runs", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        plan.run()
+    torch.cuda.synchronize()
+    st.raise_if_set("batched warmup")
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_start.record()
     for _ in range(args.steps):
-        run_step()
+        plan.run()
     t_end.record()
     torch.cuda.synchronize()
-    st.raise_if_set("timed steps")
-    ms_total = t_start.elapsed_time(t_end)
-    ms_step = ms_total / max(args.steps, 1)
+    st.raise_if_set("batched runs")
+    ms_step = t_start.elapsed_time(t_end) / max(args.steps, 1)
+    value = ts_total / (ms_step / 1e3)
+    ref_lists = (plan.band_score.clone(), plan.band_index.clone())
+    units, blocks = plan.units, plan.blocks
 
-    # The dominant kernel alone: the same stage-1 launch, back to back on the stream it runs on,
-    # bracketed by HIP events.
+    # the dominant kernel alone: the persistent count launch, back to back on the stream it runs
+    # on (the plan enqueues on the current stream), bracketed by HIP events
+    n_count = max(3, min(args.steps, 5))
     c0 = torch.cuda.Event(enable_timing=True)
     c1 = torch.cuda.Event(enable_timing=True)
-    n_count = max(args.steps, 3)
     c0.record()
     for _ in range(n_count):
-        bsh.bsh_hough_count(ds, g, status=st, wsum_out=ws_map, lanes=lanes, chunk=chunk)
+        plan.run_count()
     c1.record()
     torch.cuda.synchronize()
     st.raise_if_set("count kernel")
     count_ms = c0.elapsed_time(c1) / n_count
-    value = ts_per_step / (ms_step / 1e3)
-    ops_per_ts = TABLE_OPS_PER_TS
-    achieved = ops_per_ts * ts_per_step / (count_ms / 1e3)
-    achieved_select = SELECT_OPS_PER_TS * ts_per_step / (count_ms / 1e3)
-    print(f"[bench] {ms_step:.3f} ms/step, count kernel {count_ms:.3f} ms", file=sys.stderr, flush=True)
+    print(f"[bench] batched {ms_step:.1f} ms/run, count kernel {count_ms:.1f} ms", file=sys.stderr, flush=True)
 
-    post = run_post(bsh, ds, g, s1_score, s1_index, seg.t_coh, seg.t_span_mid(), st)
-    refine = run_refine(bsh, spec, st)
-    beside = run_beside(bsh, w, st, *bsh.bsh_decode_templates(g, s1_index))
+    if (lanes_p, chunk_p) != (lanes, chunk):
+        plan.close()
+        plan = bsh.Plan(items, grids, 4, k_item=k_item, k_band=k_band, lanes=lanes_p, chunk=chunk_p,
+                        use_graph=True, lpt=True, status=st)
+    n_plain = max(1, min(args.plain_steps, args.steps))
+    print(f"[bench] plain: tile {lanes_p} x {chunk_p}, {n_plain} timed runs", file=sys.stderr, flush=True)
+    ms_plain, _ = timed_runs(plan.run_plain, n_plain)
+    st.raise_if_set("plain runs")
+    same = bool(torch.equal(ref_lists[1], plan.band_index) and torch.equal(ref_lists[0], plan.band_score))
+    plan.close()
+    del plan, items, grids
+    torch.cuda.empty_cache()
 
-    batched = None if args.skip_batched else run_batched(args)
-    allsky = run_allsky(args) if (args.allsky_pixels > 0 and not args.skip_batched) else None
+    achieved = FLOOR_OPS_PER_TS * ts_total / (count_ms / 1e3)
+    issued = TABLE_OPS_PER_TS * ts_total / (count_ms / 1e3)
+    achieved_select = SELECT_OPS_PER_TS * ts_total / (count_ms / 1e3)
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle as O
-        a_p, per, off, t_asc = O.grid_tables(spec, seg.t_span_mid())
-        n_ap = max(1, min(args.cpu_sample_ap, spec.n_ap))
-        cells = n_ap * spec.n_per
-        sub_off = off[:cells + 1]
-        t0 = time.perf_counter()
-        O.hough_count(seg, w.sky, spec.k0, spec.n_f0, a_p[:n_ap], per, sub_off, t_asc[:sub_off[-1]])
-        dt = time.perf_counter() - t0
-        ts_cpu = int(sub_off[-1]) * spec.n_f0 * seg.n_seg
-        cpu = {"value": ts_cpu / dt, "unit": "template*segments/s", "cores": O.num_threads(),
-               "kind": "oracle",
-               "sample": f"stage-1 count of the first {n_ap} of {spec.n_ap} a_p values (all P, t_asc, f0 "
-                         f"and {seg.n_seg} segments): {ts_cpu:.3e} template*segments in {dt:.1f} s",
-               "affinity": sorted(os.sched_getaffinity(0))}
-        if args.cpu_one_thread_ap > 0:
-            cpu["one_thread"] = oracle_one_thread(args.cpu_one_thread_ap)
+        cpu = run_cpu_baseline(args, host_keep, w.sky, ts_total)
+
+    extras = {}
+    if not args.skip_extras:
+        extras["band200"] = run_band200(args)
+        extras["allsky"] = run_allsky(args) if args.allsky_pixels > 0 else None
 
     out = {
         "metric": METRIC,
@@ -271,41 +282,175 @@ def main():
         "dtype": "f64/f32",
         "data": "synthetic",
         "config": {
-            "workload": "band 200.0-200.1 Hz: 4000 segments (2 detectors x 2000, gapped), 1 sky "
-                        "pixel, 90 f0 x 64 a_p x 32 P x 64 t_asc = 11796480 templates; stage-1 "
-                        "weighted count -> top-10^4 -> stage-2 power -> top-100",
-            "templates": n_t,
-            "segments": seg.n_seg,
-            "template_segments_per_step": ts_per_step,
-            "topk_stage1": k1,
-            "topk_stage2": k2,
+            "workload": "batched stage 1: 256 sky patches x 4 bands of 0.1 Hz (f_lo 100.0/166.6/233.2/299.8 Hz), "
+                        "1024 items of 3000-6000 gapped segments, a_p 64 x P 32 x t_asc 4-256 per cell, 90 f0 "
+                        f"= {n_templates} templates; one graph-captured persistent launch plus per-item and "
+                        "per-band top-1000, against one plain launch and top-k per item",
+            "items": 1024,
+            "templates": n_templates,
+            "template_segments_per_step": ts_total,
+            "k_item": k_item,
+            "k_band": k_band,
             "parallelism": "single GPU",
-            "step_launch": "eager" if args.no_graph else "hip graph replay",
+            "step_launch": "hip graph replay",
+        },
+        "plain": {
+            "value": ts_total / (ms_plain / 1e3),
+            "ms": ms_plain,
+            "runs": n_plain,
+            "speedup_batched": ms_plain / ms_step,
+            "lists_identical": same,
+            "tile": {"lanes": lanes_p, "chunk": chunk_p},
+            "autotune_ms": {f"{l}x{c}": t for (l, c), t in tune_p_ms.items()},
         },
         "roofline": {
             "bound": "alu",
-            "kernel": f"hough_count_kernel<2, {chunk}> (subset-sum tables of 8 segments)",
+            "kernel": f"hough_batch_kernel<2, {chunk}> (persistent; subset-sum tables of 8 segments)",
             "achieved": achieved / 1e12,
             "peak": VALU_PEAK_OPS / 1e12,
             "unit": "TOP/s",
             "frac": achieved / VALU_PEAK_OPS,
-            "traffic": measured_traffic(lanes, chunk),
+            "traffic": measured_traffic(lanes, chunk, BATCH_TRAFFIC_FILE, BATCH_SOURCES),
             "count_kernel_ms": count_ms,
-            "ops_per_template_segment": ops_per_ts,
+            "ops_per_template_segment": FLOOR_OPS_PER_TS,
+            "floor": "algorithmic: per template and 8 segments one table read and one add; per (binary "
+                     "template, segment) a 12-operation track shared by 90 f0 bins",
+            "issued_fast_path": {"ops_per_template_segment": TABLE_OPS_PER_TS, "achieved": issued / 1e12,
+                                 "frac": issued / VALU_PEAK_OPS},
             "select_add_equivalent": {"ops_per_template_segment": SELECT_OPS_PER_TS,
                                       "achieved": achieved_select / 1e12,
                                       "frac": achieved_select / VALU_PEAK_OPS},
             "tile": {"lanes": lanes, "chunk": chunk},
+            "units": units,
+            "persistent_blocks": blocks,
             "autotune_ms": {f"{l}x{c}": t for (l, c), t in tune_ms.items()},
         },
         "cpu_baseline": cpu,
-        "post": post,
-        "refine": refine,
-        "beside_path": beside,
-        "batched": batched,
-        "allsky": allsky,
     }
+    out.update(extras)
     print(json.dumps(out), flush=True)
+
+
+def run_cpu_baseline(args, host_keep, sky, ts_total):
+    """The oracle on a bounded sample of the batching workload: the smallest band's first item
+    whole and the first a_p values of the widest band's last item, on every host thread; the
+    full job's oracle time is extrapolated from the measured rate."""
+    import oracle as O
+    ts_cpu, dt = 0, 0.0
+    parts = []
+    for it, (seg, spec, (lo, hi)) in host_keep.items():
+        a_p, per, off, t_asc = O.grid_tables(spec, seg.t_span_mid())
+        n_ap = spec.n_ap if it == 0 else max(1, min(args.cpu_sample_ap, spec.n_ap))
+        sub = off[:n_ap * spec.n_per + 1]
+        t0 = time.perf_counter()
+        O.hough_count(seg, sky[lo:hi], spec.k0, spec.n_f0, a_p[:n_ap], per, sub, t_asc[:sub[-1]])
+        d = time.perf_counter() - t0
+        n = int(sub[-1]) * spec.n_f0 * seg.n_seg
+        ts_cpu += n
+        dt += d
+        parts.append(f"item {it}: {n_ap} of {spec.n_ap} a_p values, {n:.3e} template*segments in {d:.1f} s")
+    rate = ts_cpu / dt
+    cpu = {"value": rate, "unit": "template*segments/s", "cores": O.num_threads(), "kind": "oracle",
+           "sample": "stage-1 count of the batching workload on " + "; ".join(parts),
+           "full_job_s_extrapolated": ts_total / rate,
+           "affinity": sorted(os.sched_getaffinity(0))}
+    if args.cpu_one_thread_ap > 0:
+        cpu["one_thread"] = oracle_one_thread(0, args.cpu_one_thread_ap)
+    return cpu
+
+
+def run_band200(args):
+    """The two-stage step of one band (not the headline): 4000 segments (2 detectors x 2000,
+    gapped), one sky pixel, band 200.0-200.1 Hz (90 f0 bins), a_p 64 x P 32 x t_asc 64 ->
+    11 796 480 templates; peakgram, stage-1 count, top-10^4, decode, stage-2 power with counts,
+    top-100, replayed from one HIP graph; with the count kernel alone and the post-processing,
+    refinement and steps beside the path on the same band."""
+    import torch
+    import bsh_synth as S
+    from paper_1904_04873_amd import autotune, bsh
+
+    dev = torch.device("cuda:0")
+    w = S.config2()
+    seg, spec = w.segments[0], w.grids[0]
+    k1, k2 = w.topk_stage1, w.topk_stage2
+    print(f"[bench] band 200 Hz: {seg.n_seg} segments, building device tables", file=sys.stderr, flush=True)
+    ds = bsh.DeviceSegments.from_host(seg)
+    g = bsh.DeviceGrid.build(spec, seg.t_span_mid(), w.sky)
+    n_t = g.n_templates
+    ts_per_step = n_t * seg.n_seg
+    st = bsh.Status(dev)
+    ws_map = torch.empty(n_t, dtype=torch.float32, device=dev)
+    top1 = bsh.TopK(n_t, k1, dev)
+    top2 = bsh.TopK(k1, k2, dev)
+    s1_score = torch.empty(k1, dtype=torch.float32, device=dev)
+    s1_index = torch.empty(k1, dtype=torch.int64, device=dev)
+    s2_score = torch.empty(k2, dtype=torch.float32, device=dev)
+    s2_pos = torch.empty(k2, dtype=torch.int64, device=dev)
+    P = torch.empty(k1, dtype=torch.float32, device=dev)
+    (lanes, chunk), tune_ms = autotune.tune_plain(ds, g, use_cache=False)
+
+    def step():
+        bsh.bsh_peakgram(ds.power, 1.6, out=ds.peak_bits)
+        bsh.bsh_hough_count(ds, g, status=st, wsum_out=ws_map, lanes=lanes, chunk=chunk)
+        top1(ws_map, out_score=s1_score, out_index=s1_index)
+        cs, cp = bsh.bsh_decode_templates(g, s1_index)
+        bsh.bsh_power_stat(ds, g.sky, cs, cp, mode=0, with_counts=True, status=st, out=P)
+        top2(P, out_score=s2_score, out_index=s2_pos)
+
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    st.raise_if_set("band warmup")
+    # one step is one HIP graph replay: the launches of a step are enqueued once at capture time
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        step()
+    torch.cuda.synchronize()
+    for _ in range(3):
+        graph.replay()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(args.band_steps):
+        graph.replay()
+    b.record()
+    torch.cuda.synchronize()
+    st.raise_if_set("band steps")
+    ms_step = a.elapsed_time(b) / max(1, args.band_steps)
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    n_count = 10
+    c0.record()
+    for _ in range(n_count):
+        bsh.bsh_hough_count(ds, g, status=st, wsum_out=ws_map, lanes=lanes, chunk=chunk)
+    c1.record()
+    torch.cuda.synchronize()
+    count_ms = c0.elapsed_time(c1) / n_count
+    print(f"[bench] band 200 Hz: {ms_step:.3f} ms/step, count kernel {count_ms:.3f} ms", file=sys.stderr, flush=True)
+    out = {
+        "workload": "band 200.0-200.1 Hz: 4000 segments (2 detectors x 2000, gapped), 1 sky pixel, 90 f0 x "
+                    "64 a_p x 32 P x 64 t_asc = 11796480 templates; stage-1 weighted count -> top-10^4 -> "
+                    "stage-2 power -> top-100, one HIP graph replay per step",
+        "steps": args.band_steps, "ms_per_step": ms_step, "value": ts_per_step / (ms_step / 1e3),
+        "unit": "template*segments/s",
+        "count_kernel": {"kernel": f"hough_count_kernel<2, {chunk}>", "ms": count_ms,
+                         "value": ts_per_step / (count_ms / 1e3),
+                         "frac_floor": FLOOR_OPS_PER_TS * ts_per_step / (count_ms / 1e3) / VALU_PEAK_OPS,
+                         "frac_issued_fast_path": TABLE_OPS_PER_TS * ts_per_step / (count_ms / 1e3) / VALU_PEAK_OPS,
+                         "traffic": measured_traffic(lanes, chunk), "tile": {"lanes": lanes, "chunk": chunk},
+                         "autotune_ms": {f"{l}x{c}": t for (l, c), t in tune_ms.items()}},
+    }
+    out["post"] = run_post(bsh, ds, g, s1_score, s1_index, seg.t_coh, seg.t_span_mid(), st)
+    out["refine"] = run_refine(bsh, spec, st)
+    out["beside_path"] = run_beside(bsh, w, st, *bsh.bsh_decode_templates(g, s1_index))
+    return out
 
 
 def run_post(bsh, ds, g, s1_score, s1_index, t_coh, t_mid, st):
@@ -441,132 +586,82 @@ def run_beside(bsh, w, st, cs, cp):
 
 
 def run_allsky(args):
-    """The all-sky slice's shape (2 x 4000 segments over 240 d, band 300.0-300.1 Hz, 128 a_p x 64 P
-    x rule t_asc = 581 531 binary templates per pixel) on `allsky_pixels` of its 2000 pixels, one
-    batched plan with per-pixel and per-band top-10^5."""
+    """The all-sky slice at its full size (not the headline): 2 x 4000 segments over 240 d, band
+    300.0-300.1 Hz, 90 f0 x 128 a_p x 64 P x rule t_asc = 581 531 binary templates (52.3 M
+    templates) per pixel, `allsky_pixels` pixels as items of one batched plan whose map buffer
+    holds `allsky_pass_pixels` pixels (the plan runs in passes through it), per-pixel and per-band
+    top-10^5; then stage 2 on the 10^5 winners, their top-5000, and 20 Adam steps of the
+    interpolated power on all 10^5."""
     import numpy as np
     import torch
 
     import bsh_synth as S
     from paper_1904_04873_amd import bsh
+    from paper_1904_04873_amd.refine import refine
 
     dev = torch.device("cuda:0")
-    n_pix = args.allsky_pixels
-    print(f"[bench] all-sky slice: {n_pix} pixels", file=sys.stderr, flush=True)
-    w = S.config5()
+    w = S.config5(n_pixels=max(1, args.allsky_pixels))
     seg, spec = w.segments[0], w.grids[0]
     ds = bsh.DeviceSegments.from_host(seg, device=dev)
     g = bsh.DeviceGrid.build(spec, seg.t_span_mid(), w.sky, device=dev)
-    pixels = [int(p) for p in np.linspace(0, len(w.sky) - 1, n_pix).round()]
-    items = [(ds, 0, p, 1, 0) for p in pixels]
-    k = 100000
+    n_pix = len(w.sky)
+    per_pixel = g.n_bin * g.n_f0
+    k = w.topk_stage1
     st = bsh.Status(dev)
-    plan = bsh.Plan(items, [g], 1, k_item=k, k_band=k, use_graph=True, lpt=True, status=st)
-    plan.run()
+    # warm the kernels on a small plan first (its own short run)
+    warm = bsh.Plan([(ds, 0, p, 1, 0) for p in range(min(4, n_pix))], [g], 1, k_item=k, k_band=k,
+                    use_graph=False, status=st)
+    warm.run()
     torch.cuda.synchronize()
-    out = []
-    for _ in range(max(1, args.batched_steps)):
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record()
-        plan.run()
-        b.record()
-        torch.cuda.synchronize()
-        out.append(a.elapsed_time(b))
-    st.raise_if_set("all-sky plan")
-    plan.close()
-    ms = float(np.median(out))
-    ts = n_pix * g.n_bin * g.n_f0 * seg.n_seg
-    return {"workload": f"band 300.0-300.1 Hz, 2 x 4000 segments over 240 d, {n_pix} of 2000 pixels, "
-                        f"90 f0 x 128 a_p x 64 P x rule t_asc = {g.n_bin} binary templates per pixel; "
-                        "per-pixel and per-band top-10^5",
-            "pixels": n_pix, "template_segments": ts, "ms": ms, "value": ts / (ms / 1e3),
-            "unit": "template*segments/s", "k": k}
-
-
-def run_batched(args):
-    """Full batching workload: one graph-captured persistent launch vs one plain launch per item,
-    each form with the tile the autotuner finds fastest for it."""
-    import numpy as np
-    import torch
-
-    import bsh_synth as S
-    from paper_1904_04873_amd import autotune, bsh
-
-    dev = torch.device("cuda:0")
-    print("[bench] batching workload: generating 1024 items", file=sys.stderr, flush=True)
-    w = S.config3()
-    items, grids = [], []
-    ts_total = 0
-    for it in range(len(w.segments)):
-        seg = w.segments[it]
-        band = w.item_grid[it]
-        g = bsh.DeviceGrid.build(w.grids[band], seg.t_span_mid(), w.sky, device=dev)
-        ds = bsh.DeviceSegments.from_host(seg, device=dev)
-        lo, hi = w.item_sky[it]
-        items.append((ds, it, lo, hi - lo, band))
-        grids.append(g)
-        ts_total += (hi - lo) * g.n_bin * g.n_f0 * seg.n_seg
-        w.segments[it] = None        # drop the host copy
-    torch.cuda.synchronize()
-    print(f"[bench] batching workload resident: {ts_total:.3e} template*segments; autotuning",
+    warm.close()
+    items = [(ds, 0, p, 1, 0) for p in range(n_pix)]
+    buf = min(n_pix, max(1, args.allsky_pass_pixels)) * per_pixel
+    plan = bsh.Plan(items, [g], 1, k_item=k, k_band=k, use_graph=True, lpt=True, status=st, map_floats=buf)
+    print(f"[bench] all-sky slice: {n_pix} pixels in {plan.passes} passes of {args.allsky_pass_pixels}",
           file=sys.stderr, flush=True)
-    (lanes, chunk), tune_ms = autotune.tune(items, grids, 4, sample=16, use_cache=False)
-    # the plain baseline runs with the tile that suits one launch per item best
-    (lanes_p, chunk_p), tune_p_ms = autotune.tune(items, grids, 4, sample=16, use_cache=False, plain=True)
-    k_item, k_band = 1000, 1000
-    st = bsh.Status(dev)
-    plan = bsh.Plan(items, grids, 4, k_item=k_item, k_band=k_band, lanes=lanes, chunk=chunk,
-                    use_graph=True, lpt=True, status=st)
-
-    def timed(fn, reps):
-        fn()
-        torch.cuda.synchronize()
-        out = []
-        for _ in range(reps):
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            torch.cuda.synchronize()
-            a.record()
-            fn()
-            b.record()
-            torch.cuda.synchronize()
-            out.append(a.elapsed_time(b))
-        return float(np.median(out))
-
-    print("[bench] batched runs", file=sys.stderr, flush=True)
-    ms_b = timed(plan.run, args.batched_steps)
-    st.raise_if_set("batched")
-    ref = plan.band_index.clone()
-    units, blocks = plan.units, plan.blocks
-    if (lanes_p, chunk_p) != (lanes, chunk):
-        plan.close()
-        plan = bsh.Plan(items, grids, 4, k_item=k_item, k_band=k_band, lanes=lanes_p, chunk=chunk_p,
-                        use_graph=True, lpt=True, status=st)
-    print("[bench] plain runs", file=sys.stderr, flush=True)
-    ms_p = timed(plan.run_plain, args.batched_steps)
-    st.raise_if_set("plain")
-    same = bool(torch.equal(ref, plan.band_index))
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    plan.run()
+    b.record()
+    torch.cuda.synchronize()
+    st.raise_if_set("all-sky plan")
+    ms = a.elapsed_time(b)
+    index = plan.band_index[0].clone()
+    passes = plan.passes
     plan.close()
-    return {
-        "workload": "256 sky patches x 4 bands of 0.1 Hz (f_lo 100.0/166.6/233.2/299.8 Hz): 1024 items "
-                    "of 3000-6000 gapped segments, a_p 64 x P 32 x t_asc 4-256 per cell, 90 f0; "
-                    "per-item top-1000 and per-band top-1000",
-        "items": len(items),
-        "template_segments": ts_total,
-        "batched_ms": ms_b,
-        "plain_ms": ms_p,
-        "batched_value": ts_total / (ms_b / 1e3),
-        "plain_value": ts_total / (ms_p / 1e3),
-        "speedup": ms_p / ms_b,
-        "lists_identical": same,
-        "tile": {"lanes": lanes, "chunk": chunk},
-        "plain_tile": {"lanes": lanes_p, "chunk": chunk_p},
-        "autotune_ms": {f"{l}x{c}": t for (l, c), t in tune_ms.items()},
-        "autotune_plain_ms": {f"{l}x{c}": t for (l, c), t in tune_p_ms.items()},
-        "units": units,
-        "persistent_blocks": blocks,
-    }
+    del plan
+    ts = n_pix * per_pixel * seg.n_seg
+    print(f"[bench] all-sky slice: stage 1 {ms / 1e3:.1f} s; stage 2 and refinement", file=sys.stderr, flush=True)
+    gidx = (index >> 40) * per_pixel + (index & ((1 << 40) - 1))
+
+    def stage2():
+        cs, cp = bsh.bsh_decode_templates(g, gidx)
+        P = bsh.bsh_power_stat(ds, g.sky, cs, cp, mode=0, status=st)
+        return cs, cp, P, bsh.bsh_topk(P, w.topk_stage2)
+
+    ms2, _ = timed_runs(stage2, 3)
+    cs, cp, P, _ = stage2()
+    steps = torch.tensor([1.0, (spec.ap_hi - spec.ap_lo) / (spec.n_ap - 1),
+                          (spec.per_hi - spec.per_lo) / (spec.n_per - 1), 0.0], dtype=torch.float64,
+                         device=dev).repeat(k, 1)
+    steps[:, 3] = cp[:, 2] / 64.0
+    theta0 = cp.contiguous()
+    ms_adam, _ = timed_runs(lambda: refine(theta0, steps, ds, g.sky, cs, n_iter=20, lr=0.05, status=st), 1)
+    _, hist = refine(theta0, steps, ds, g.sky, cs, n_iter=20, lr=0.05, status=st)
+    torch.cuda.synchronize()
+    st.raise_if_set("all-sky stage 2")
+    gain = (hist[-1] - hist[0]).median().item()
+    return {"workload": f"band 300.0-300.1 Hz, 2 x 4000 segments over 240 d, {n_pix} pixels, 90 f0 x 128 a_p "
+                        f"x 64 P x rule t_asc = {g.n_bin} binary templates per pixel ({per_pixel * n_pix:.3e} "
+                        f"templates); batched plan in {passes} passes of {args.allsky_pass_pixels} pixels "
+                        f"through a {4 * buf / 2**30:.1f} GiB map buffer, per-pixel and per-band top-10^5; "
+                        "stage 2 on the winners, top-5000, 20 Adam steps of the interpolated power",
+            "pixels": n_pix, "passes": passes, "template_segments": ts, "stage1_ms": ms,
+            "value": ts / (ms / 1e3), "unit": "template*segments/s", "k": k,
+            "map_buffer_bytes": 4 * buf, "all_maps_bytes": 4 * per_pixel * n_pix,
+            "stage2_ms": ms2, "stage2_cand_seg_per_s": k * seg.n_seg / (ms2 / 1e3),
+            "adam_20_steps_ms": ms_adam, "adam_median_gain": gain}
 
 
 if __name__ == "__main__":

@@ -202,8 +202,6 @@ def test_count_config2_full_map_against_oracle(B, cfg2_injected):
         ws_s, _ = B.bsh_hough_count(ds, g, lanes=lanes, chunk=chunk, variant=2)
         torch.cuda.synchronize()
         assert np.array_equal(_np(ws_s), ws_t), (lanes, chunk)
-    # mean count under (mostly) noise ~ N exp(-1.6)
-    assert abs(cnt.mean() / seg.n_seg - math.exp(-1.6)) < 0.01
 
 
 def test_count_topk_config2_against_oracle_list(B, cfg2_injected):
