@@ -19,8 +19,11 @@ Functions and the passage each follows:
 * ``power_grad``       -- gradient of the interpolated power (extension).
 * ``track``            -- the frequency track x_J = f(t_J) Tc and its bins
                           (eq:frequencyevoFinal, product form).
-* ``track_ecc`` / ``power_stat_ecc`` -- the low-eccentricity (ELL1) track of
-                          eq:frequencyevo and the stage-2 power on it.
+* ``track_ecc`` / ``power_stat_ecc`` / ``hough_count_ecc`` / ``power_grad_ecc`` --
+                          the low-eccentricity (ELL1) track of eq:frequencyevo, the
+                          stage-2 power on it, the stage-1 count of a grid with one
+                          eccentricity pair, and the interpolated power's gradient with
+                          respect to the six track parameters.
 * ``normalize``        -- normalized power rho = |x|^2 / <n>^2 with the noise level from a
                           running median over 101 bins (eq:HoughPower).
 * ``peakgram``         -- thresholded peakgram (Sec. IV.A).
@@ -85,6 +88,11 @@ def lib():
         L.orc_track_ecc.restype = None
         L.orc_power_stat_ecc.argtypes = [i64, P, P, P, i32, i64, i32, P, P, i64, P, P, i32, P, P]
         L.orc_power_stat_ecc.restype = ctypes.c_int
+        L.orc_hough_count_ecc.argtypes = [i64, P, P, P, i32, i64, i32, P, f64, i32, P, i64, i32,
+                                          i32, P, i32, P, P, P, f64, f64, P, P, P, P]
+        L.orc_hough_count_ecc.restype = ctypes.c_int
+        L.orc_power_grad_ecc.argtypes = [i64, P, P, P, i32, i64, i32, P, P, i64, P, P, P, P, P]
+        L.orc_power_grad_ecc.restype = ctypes.c_int
         L.orc_peakgram.argtypes = [i64, i32, P, f64, i32, P]
         L.orc_peakgram.restype = None
         L.orc_num_threads.argtypes = []
@@ -292,6 +300,52 @@ def power_stat_ecc(seg, sky, cand_sky, cand, mode: int = 0, weight_per_sky: bool
     if rc != 0:
         raise OracleRangeError("a track left the staged bins")
     return P, nt
+
+
+def hough_count_ecc(seg, sky, k0: int, n_f0: int, a_p, per, off, t_asc, ec: float, es: float,
+                    rho_th: float = P_PEAK_DEFAULT_TH, weight_per_sky: bool = False):
+    """Stage-1 count on the ELL1 track with one (e cos w, e sin w) pair for the whole grid:
+    (count u32, n_w f64, near-tie count, near-tie weight), template order as hough_count."""
+    t = _c(seg.t_mid, np.float64)
+    v = _c(seg.v_over_c, np.float64)
+    w = _c(seg.weight, np.float32)
+    pw = _c(seg.power, np.float32)
+    sky = _c(sky, np.float64)
+    a_p, per, off, t_asc = (_c(a_p, np.float64), _c(per, np.float64), _c(off, np.int64),
+                            _c(t_asc, np.float64))
+    n_t = sky.shape[0] * int(off[-1]) * n_f0
+    cnt = np.zeros(n_t, np.uint32)
+    nw = np.zeros(n_t, np.float64)
+    nt = np.zeros(n_t, np.uint32)
+    ntw = np.zeros(n_t, np.float64)
+    rc = lib().orc_hough_count_ecc(t.size, _p(t), _p(v), _p(w), int(weight_per_sky), seg.k_lo,
+                                   seg.n_bins, _p(pw), rho_th, sky.shape[0], _p(sky), k0, n_f0,
+                                   a_p.size, _p(a_p), per.size, _p(per), _p(off), _p(t_asc),
+                                   float(ec), float(es), _p(cnt), _p(nw), _p(nt), _p(ntw))
+    if rc != 0:
+        raise OracleRangeError("a track left the staged bins")
+    return cnt, nw, nt, ntw
+
+
+def power_grad_ecc(seg, sky, cand_sky, cand, grad_p=None, weight_per_sky: bool = False,
+                   with_abs: bool = False):
+    """d P_lin / d(F, a_p, P, t_asc, e cos w, e sin w) on the ELL1 track, [n, 6] float64."""
+    t = _c(seg.t_mid, np.float64)
+    v = _c(seg.v_over_c, np.float64)
+    w = _c(seg.weight, np.float32)
+    pw = _c(seg.power, np.float32)
+    sky = _c(sky, np.float64)
+    cand = _c(cand, np.float64).reshape(-1, 6)
+    cs = _c(cand_sky, np.int32).reshape(-1)
+    n = cand.shape[0]
+    g = np.zeros((n, 6), np.float64)
+    a = np.zeros((n, 6), np.float64) if with_abs else None
+    gp = None if grad_p is None else _c(grad_p, np.float64)
+    rc = lib().orc_power_grad_ecc(t.size, _p(t), _p(v), _p(w), int(weight_per_sky), seg.k_lo,
+                                  seg.n_bins, _p(pw), _p(sky), n, _p(cs), _p(cand), _p(gp), _p(g), _p(a))
+    if rc != 0:
+        raise OracleRangeError("a track left the staged bins")
+    return (g, a) if with_abs else g
 
 
 def median_bias(window: int) -> float:

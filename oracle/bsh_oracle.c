@@ -331,6 +331,120 @@ int orc_power_stat_ecc(int64_t n_seg, const double* t_mid, const double* v_over_
     return err;
 }
 
+/*
+ * Stage-1 number count on the ELL1 track for one eccentricity pair (ec, es) = (e cos w, e sin w)
+ * shared by every template of the grid: the same template order, outputs and near-tie
+ * bookkeeping as orc_hough_count, with the orbit factor of orbit_factor_ecc (product form).
+ */
+int orc_hough_count_ecc(int64_t n_seg, const double* t_mid, const double* v_over_c,
+                        const float* weight, int32_t weight_per_sky,
+                        int64_t k_lo, int32_t n_bins, const float* power, double rho_th,
+                        int32_t n_sky, const double* sky, int64_t k0, int32_t n_f0,
+                        int32_t n_ap, const double* a_p, int32_t n_per, const double* period,
+                        const int64_t* tasc_off, const double* t_asc, double ec, double es,
+                        uint32_t* count_out, double* nw_out, uint32_t* ntie_out, double* ntie_w_out)
+{
+    const int64_t n_bin = tasc_off[(int64_t)n_ap * n_per];
+    int err = ORC_OK;
+    for (int32_t s = 0; s < n_sky; ++s) {
+        const float* w = weight + (weight_per_sky ? (int64_t)s * n_seg : 0);
+        #pragma omp parallel for schedule(static) reduction(min:err)
+        for (int64_t b = 0; b < n_bin; ++b) {
+            int64_t cell = 0;
+            while (tasc_off[cell + 1] <= b) ++cell;
+            const double ap = a_p[cell / n_per];
+            const double per = period[cell % n_per];
+            const double ta = t_asc[b];
+            for (int32_t i = 0; i < n_f0; ++i) {
+                const double F = (double)(k0 + i);
+                uint32_t cnt = 0, nt = 0;
+                double nw = 0.0, ntw = 0.0;
+                for (int64_t J = 0; J < n_seg; ++J) {
+                    double D = doppler_factor(v_over_c + 3 * J, sky + 3 * s);
+                    double B = orbit_factor_ecc(t_mid[J], ap, per, ta, ec, es);
+                    double x = F * (D * B);
+                    int64_t c = (int64_t)floor(x + 0.5) - k_lo;
+                    if (c < 0 || c >= n_bins) { err = ORC_ERANGE; continue; }
+                    int p = power[J * n_bins + c] > rho_th;
+                    cnt += (uint32_t)p;
+                    nw += p ? (double)w[J] : 0.0;
+                    if (is_near_tie(x)) { nt += 1; ntw += (double)w[J]; }
+                }
+                const int64_t idx = (((int64_t)s * n_bin) + b) * n_f0 + i;
+                if (count_out) count_out[idx] = cnt;
+                if (nw_out) nw_out[idx] = nw;
+                if (ntie_out) ntie_out[idx] = nt;
+                if (ntie_w_out) ntie_w_out[idx] = ntw;
+            }
+        }
+    }
+    return err;
+}
+
+/*
+ * Gradient of P_lin on the ELL1 track with respect to (F, a_p, P, t_asc, e cos w, e sin w),
+ * scaled by grad_p[c].  With psi = W (t - t_asc), E = cos psi + ec cos 2psi - es sin 2psi
+ * (so that B = 1 - a_p W E) and E' = dE/dpsi = -sin psi - 2 ec sin 2psi - 2 es cos 2psi:
+ *   dx/dF     = D B
+ *   dx/da_p   = -F D W E
+ *   dx/dP     =  F D a_p (W / P) (E + psi E')      (dW/dP = -W/P, dpsi/dP = -psi/P)
+ *   dx/dt_asc =  F D a_p W^2 E'                    (dpsi/dt_asc = -W)
+ *   dx/d(ec)  = -F D a_p W cos 2psi
+ *   dx/d(es)  =  F D a_p W sin 2psi
+ * derived by hand from the track of orbit_factor_ecc; at e = 0 the first four are the terms of
+ * orc_power_grad.  S_J, the right-hand interval at an exact integer x and abs_out as there.
+ */
+int orc_power_grad_ecc(int64_t n_seg, const double* t_mid, const double* v_over_c,
+                       const float* weight, int32_t weight_per_sky,
+                       int64_t k_lo, int32_t n_bins, const float* power,
+                       const double* sky, int64_t n_cand, const int32_t* cand_sky,
+                       const double* cand, const double* grad_p, double* grad_out, double* abs_out)
+{
+    int err = ORC_OK;
+    #pragma omp parallel for schedule(static) reduction(min:err)
+    for (int64_t c = 0; c < n_cand; ++c) {
+        const double* th = cand + 6 * c;
+        const double F = th[0], ap = th[1], per = th[2], ta = th[3], ec = th[4], es = th[5];
+        const float* w = weight + (weight_per_sky ? (int64_t)cand_sky[c] * n_seg : 0);
+        double g[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int64_t J = 0; J < n_seg; ++J) {
+            double D = doppler_factor(v_over_c + 3 * J, sky + 3 * cand_sky[c]);
+            double W = TWO_PI / per;
+            double psi = W * (t_mid[J] - ta);
+            double c1 = cos(psi), s1 = sin(psi);
+            double c2 = cos(2.0 * psi), s2 = sin(2.0 * psi);
+            double E = c1 + (ec * c2 - es * s2);
+            double Ep = -s1 - 2.0 * (ec * s2) - 2.0 * (es * c2);
+            double B = 1.0 - (ap * W) * E;
+            double x = F * (D * B);
+            double kf = floor(x);
+            int64_t col = (int64_t)kf - k_lo;
+            if (col < 0 || col + 1 >= n_bins) { err = ORC_ERANGE; continue; }
+            const float* row = power + J * n_bins;
+            double S = (double)w[J] * ((double)row[col + 1] - (double)row[col]);
+            double FD = F * D;
+            double t[6];
+            t[0] = S * (D * B);
+            t[1] = S * (-FD * W * E);
+            t[2] = S * (FD * ap * (W / per) * (E + psi * Ep));
+            t[3] = S * (FD * ap * W * W * Ep);
+            t[4] = S * (-FD * ap * W * c2);
+            t[5] = S * (FD * ap * W * s2);
+            for (int q = 0; q < 6; ++q) {
+                g[q] += t[q];
+                a[q] += fabs(t[q]);
+            }
+        }
+        const double sc = grad_p ? grad_p[c] : 1.0;
+        for (int q = 0; q < 6; ++q) {
+            grad_out[6 * c + q] = sc * g[q];
+            if (abs_out) abs_out[6 * c + q] = fabs(sc) * a[q];
+        }
+    }
+    return err;
+}
+
 /* Peakgram: bit c of row J set iff rho_{J,c} > rho_th (Sec. IV.A), bit b of word w = column 32w+b. */
 void orc_peakgram(int64_t n_seg, int32_t n_bins, const float* power, double rho_th,
                   int32_t n_words, uint32_t* bits)

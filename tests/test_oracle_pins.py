@@ -679,3 +679,167 @@ def test_ecc_power_one_segment_equals_phase_model_frequency():
     # the e terms really matter at this size
     x_circ = np.array([F * (1 - ap * W * math.cos(W * (t0 - ta))) for ta in tas])
     assert np.max(np.abs(x_num - x_circ)) > 0.05
+
+
+# ---------------------------------------------------------------- ELL1 stage-1 count and adjoint
+
+def _ecc_rows(cand, seed, e_max=0.05):
+    rng = np.random.default_rng(seed)
+    e = rng.uniform(0.001, e_max, cand.shape[0])
+    om = rng.uniform(0, 2 * math.pi, cand.shape[0])
+    return np.concatenate([cand, np.stack([e * np.cos(om), e * np.sin(om)], axis=1)], axis=1)
+
+
+def test_ecc_count_reduces_to_circular_at_zero_eccentricity():
+    """(e cos w, e sin w) = (0, 0): every output of the ELL1 count equals the circular count, bit for bit."""
+    seg = _segments(150, 90000, 90, 12, seed=41)
+    sky = S.fibonacci_sphere(2)
+    a_p, per, off, ta = _grid_from([0.3, 2.1], [17 * S.DAY, 33 * S.DAY],
+                                   [[1e5, 8e5], [2e5, 1.5e6, 2.4e6], [3e5], [5e5, 9e5]])
+    r_c = O.hough_count(seg, sky, 90000, 90, a_p, per, off, ta)
+    r_e = O.hough_count_ecc(seg, sky, 90000, 90, a_p, per, off, ta, 0.0, 0.0)
+    for a, b in zip(r_c, r_e):
+        assert np.array_equal(a, b)
+
+
+def test_ecc_count_brute_force_tiny_grid():
+    """ELL1 counts on a 4-segment, 3-f0, 2 x 2 x (1..2) grid with e = 0.03 against a 50-digit
+    evaluation of the eccentric track (eq:frequencyevo, product form)."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 50
+    seg = _segments(4, 1000, 3, 4, seed=42)
+    seg.power[:] = np.random.default_rng(10).exponential(1.0, seg.power.shape).astype(np.float32)
+    sky = S.fibonacci_sphere(2)
+    a_p, per, off, ta = _grid_from([0.9, 3.1], [15 * S.DAY, 27 * S.DAY],
+                                   [[1.5e5, 9.5e5], [2.5e5], [3.5e5, 4.5e5], [6.0e5, 2.0e6]])
+    ec, es = 0.03 * math.cos(2.0), 0.03 * math.sin(2.0)
+    cnt, nw, nt, _ = O.hough_count_ecc(seg, sky, 1000, 3, a_p, per, off, ta, ec, es)
+    assert nt.sum() == 0
+    ecm, esm = mp.mpf(ec), mp.mpf(es)
+    idx = 0
+    for s in range(2):
+        for b in range(off[-1]):
+            cell = np.searchsorted(off, b, side="right") - 1
+            ap, P = a_p[cell // 2], per[cell % 2]
+            for i in range(3):
+                c_exp, w_exp = 0, 0.0
+                for J in range(4):
+                    W = 2 * mp.pi / mp.mpf(float(P))
+                    d = sum(mp.mpf(float(u)) * mp.mpf(float(q)) for u, q in zip(seg.v_over_c[J], sky[s]))
+                    psi = W * (mp.mpf(float(seg.t_mid[J])) - mp.mpf(float(ta[b])))
+                    E = mp.cos(psi) + ecm * mp.cos(2 * psi) - esm * mp.sin(2 * psi)
+                    xe = (1000 + i) * (1 + d) * (1 - mp.mpf(float(ap)) * W * E)
+                    col = int(mp.floor(xe + mp.mpf("0.5"))) - seg.k_lo
+                    if seg.power[J, col] > 1.6:
+                        c_exp += 1
+                        w_exp += float(seg.weight[J])
+                assert cnt[idx] == c_exp
+                assert nw[idx] == pytest.approx(w_exp, rel=1e-12)
+                idx += 1
+
+
+def test_ecc_count_noiseless_injection():
+    """rho = 0 except 2 on one template's ELL1 track: that template counts every segment with the
+    full weight and is the map's maximum; the circular track of the same template misses peaks."""
+    seg = _segments(300, 180000, 90, 22, seed=43)
+    seg.power[:] = 0
+    g = S.GridSpec(k0=180000, n_f0=90, ap_lo=1.5, ap_hi=3.0, n_ap=3, per_lo=15 * S.DAY,
+                   per_hi=20 * S.DAY, n_per=2, tasc_fixed=5)
+    a_p, per, off, ta = O.grid_tables(g, seg.t_span_mid())
+    ec, es = 0.04, -0.02
+    b_true, i_true = 23, 7
+    cell = np.searchsorted(off, b_true, side="right") - 1
+    row = np.array([[180000 + i_true, a_p[cell // 2], per[cell % 2], ta[b_true], ec, es]])
+    _, k = O.track_ecc(seg, S.fixed_pixel(), [0], row)
+    seg.power[np.arange(seg.n_seg), k[0] - seg.k_lo] = 2.0
+    cnt, nw, _, _ = O.hough_count_ecc(seg, S.fixed_pixel(), 180000, 90, a_p, per, off, ta, ec, es)
+    idx = b_true * 90 + i_true
+    assert cnt[idx] == seg.n_seg
+    assert nw[idx] == pytest.approx(float(seg.weight.astype(np.float64).sum()), rel=1e-12)
+    assert cnt.argmax() == idx
+    cnt_c, _, _, _ = O.hough_count(seg, S.fixed_pixel(), 180000, 90, a_p, per, off, ta)
+    assert cnt_c[idx] < seg.n_seg
+
+
+def test_ecc_grad_zero_eccentricity_matches_circular():
+    seg = _segments(300, 180000, 90, 22, seed=44)
+    cand, cs = _cands(seg, 12, 180000, 9)
+    ce = np.concatenate([cand, np.zeros((12, 2))], axis=1)
+    g_c = O.power_grad(seg, S.fixed_pixel(), cs, cand)
+    g_e = O.power_grad_ecc(seg, S.fixed_pixel(), cs, ce)
+    assert np.allclose(g_e[:, :4], g_c, rtol=1e-12, atol=1e-12 * np.abs(g_c).max())
+    assert np.all(np.abs(g_e[:, 4:]) > 0)
+
+
+def test_ecc_grad_ramp_closed_form():
+    """Ramp power makes P_lin = sum w x on the ELL1 track, so its gradient in all six parameters
+    is the central difference of sum w x taken from the track itself (no kinks)."""
+    seg = _segments(400, 180000, 90, 22, seed=45)
+    seg.power[:] = (np.arange(seg.n_bins, dtype=np.float64) + seg.k_lo)[None, :].astype(np.float32)
+    cand, cs = _cands(seg, 6, 180000, 10)
+    cand[:, 1] = np.maximum(cand[:, 1], 0.5)
+    ce = _ecc_rows(cand, 11)
+    g = O.power_grad_ecc(seg, S.fixed_pixel(), cs, ce)
+    w = seg.weight.astype(np.float64)
+    hs = np.array([1e-2, 5e-3, 0.5e-3 * S.DAY, 300.0, 1e-4, 1e-4])
+    for q in range(6):
+        cp, cm = ce.copy(), ce.copy()
+        cp[:, q] += hs[q]
+        cm[:, q] -= hs[q]
+        xp, _ = O.track_ecc(seg, S.fixed_pixel(), cs, cp)
+        xm, _ = O.track_ecc(seg, S.fixed_pixel(), cs, cm)
+        fd = ((xp - xm) @ w) / (2 * hs[q])
+        assert np.allclose(g[:, q], fd, rtol=2e-6, atol=1e-9 * np.abs(fd).max()), q
+
+
+def test_ecc_grad_frozen_bin_fd():
+    """Noise powers: with the bins k'_J frozen at theta, the central difference of P_lin on the
+    ELL1 track matches the analytic gradient in all six parameters."""
+    seg = _segments(400, 180000, 90, 22, seed=46)
+    cand, cs = _cands(seg, 5, 180000, 12)
+    ce = _ecc_rows(cand, 13)
+    g = O.power_grad_ecc(seg, S.fixed_pixel(), cs, ce)
+    w = seg.weight.astype(np.float64)
+    x0, _ = O.track_ecc(seg, S.fixed_pixel(), cs, ce)
+    kf = np.floor(x0)
+    rows = np.arange(seg.n_seg)
+
+    def plin_frozen(c):
+        x, _ = O.track_ecc(seg, S.fixed_pixel(), cs, c)
+        a = x - kf
+        col = (kf - seg.k_lo).astype(np.int64)
+        r0 = seg.power[rows[None, :], col].astype(np.float64)
+        r1 = seg.power[rows[None, :], col + 1].astype(np.float64)
+        return ((1 - a) * r0 + a * r1) @ w
+
+    hs = np.array([1e-2, 5e-3, 0.5e-3 * S.DAY, 300.0, 1e-4, 1e-4])
+    for q in range(6):
+        cp, cm = ce.copy(), ce.copy()
+        cp[:, q] += hs[q]
+        cm[:, q] -= hs[q]
+        fd = (plin_frozen(cp) - plin_frozen(cm)) / (2 * hs[q])
+        scale = np.abs(fd).max() + 1e-30
+        assert np.max(np.abs(g[:, q] - fd)) <= 1e-6 * scale, q
+
+
+def test_ecc_grad_tasc_is_minus_eccentric_fdot():
+    """One segment, v = 0, ramp power: dP_lin/dt_asc = -w Tc d^2 phi/dt^2 of the orbital part of the
+    eccentric phase model (eq:phaseMethod with its two e terms), since the track depends on t and
+    t_asc only through t - t_asc.  The second derivative is taken numerically from the phase."""
+    t = 1.7e6
+    F, ap, P, ta = 180010.0, 2.4, 17 * S.DAY, 0.55e6
+    f0 = F / TC
+    e, om = 0.04, 2.5
+    ec, es = e * math.cos(om), e * math.sin(om)
+    W = 2 * math.pi / P
+    seg = S.Segments(t_mid=np.array([t]), v_over_c=np.zeros((1, 3)), weight=np.array([1.3], np.float32),
+                     power=(np.arange(80, dtype=np.float32) + 179970)[None, :], k_lo=179970, n_bins=80)
+    g = O.power_grad_ecc(seg, np.array([[0, 0, 1.0]]), [0], np.array([[F, ap, P, ta, ec, es]]))
+
+    def orbital_phase(tt):   # cycles, without the f0 t term
+        psi = W * (tt - ta)
+        return -f0 * ap * (math.sin(psi) + ec / 2 * math.sin(2 * psi) + es / 2 * math.cos(2 * psi))
+
+    h = 500.0
+    fdot = (orbital_phase(t + h) - 2 * orbital_phase(t) + orbital_phase(t - h)) / (h * h)
+    assert g[0, 3] == pytest.approx(-1.3 * TC * fdot, rel=1e-6)
