@@ -233,6 +233,21 @@ int bsh_topk_segmented(const float* score, const int64_t* index, const int64_t* 
                        bsh_stream stream);
 
 /*
+ * bsh_topk without allocation, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments and
+ * results as bsh_topk, bit for bit, but no workspace argument: the workspace is a static device
+ * array of bsh_topk_noalloc_max_bytes() bytes (8 MiB; enough for k up to about 2.3e5), one per
+ * GPU, held until the process ends.  k beyond what it holds: BSH_ENOMEM, nothing launched.
+ * The call allocates nothing and calls no allocating routine.  Every call on one GPU shares that
+ * GPU's array (each call clears the state it needs on the stream first), so calls that overlap
+ * in time on one GPU (on different streams, or from different threads) race and must not be
+ * issued; calls on different GPUs are independent.
+ */
+size_t bsh_topk_noalloc_max_bytes(void);
+int bsh_topk_noalloc(const float* score, const int64_t* index, int64_t n, int32_t k,
+                     float* out_score, int64_t* out_index, bsh_stream stream);
+
+/*
  * Stage-1 template index -> candidate row (sky pixel, F = k0+i, a_p, P, t_asc).
  * index [n] int64 (entries < 0 give sky -1 and zero parameters); cand_sky [n]; cand_params [n][4].
  */

@@ -20,7 +20,7 @@ from ._native import BshError, check
 __all__ = [
     "BshError", "DeviceSegments", "DeviceGrid", "Status", "TopK", "Plan", "bsh_version",
     "bsh_grid_build", "bsh_normalize", "bsh_peakgram", "bsh_hough_count", "bsh_hough_count_topk",
-    "bsh_topk",
+    "bsh_topk", "bsh_topk_noalloc",
     "bsh_decode_templates", "bsh_power_stat", "bsh_power_stat_ecc", "bsh_power_stat_grad",
     "bsh_power_stat_value_and_grad",
     "bsh_track_bins", "post_params", "bsh_post_rows", "bsh_significance", "bsh_coincidences",
@@ -304,6 +304,28 @@ def bsh_topk(score: torch.Tensor, k: int, index: Optional[torch.Tensor] = None):
     if index is not None:
         assert index.dtype == torch.int64 and index.numel() == score.numel()
     return TopK(score.numel(), k, score.device)(score, index)
+
+
+def bsh_topk_noalloc(score: torch.Tensor, k: int, index: Optional[torch.Tensor] = None,
+                     out_score: Optional[torch.Tensor] = None, out_index: Optional[torch.Tensor] = None):
+    """bsh_topk through the library's static per-GPU workspace (the library allocates nothing;
+    pass out_score / out_index to allocate nothing here either)."""
+    assert score.dtype == torch.float32 and score.is_contiguous()
+    if index is not None:
+        assert index.dtype == torch.int64 and index.is_contiguous() and index.numel() == score.numel()
+    dev = score.device
+    if out_score is None:
+        out_score = torch.empty(k, dtype=torch.float32, device=dev)
+    if out_index is None:
+        out_index = torch.empty(k, dtype=torch.int64, device=dev)
+    assert out_score.numel() >= k and out_index.numel() >= k
+    check(N.load().bsh_topk_noalloc(_ptr(score), _ptr(index), int(score.numel()), int(k), _ptr(out_score),
+                                    _ptr(out_index), _stream()), "bsh_topk_noalloc")
+    return out_score, out_index
+
+
+def bsh_topk_noalloc_max_bytes() -> int:
+    return int(N.load().bsh_topk_noalloc_max_bytes())
 
 
 def bsh_decode_templates(grid: DeviceGrid, index: torch.Tensor):

@@ -18,6 +18,7 @@
 // Short segments run all of this in one block (small_topk_kernel).  Everything stays on the
 // stream: no host synchronisation, counts live in the workspace.
 #include <cstring>
+#include <mutex>
 
 #include "bsh_internal.h"
 
@@ -919,4 +920,66 @@ extern "C" int bsh_topk_segmented(const float* score, const int64_t* index, cons
     }
     return bsh::topk_segmented(score, index, offsets, n_segs, max_len, index_shift, k, out_score,
                                out_index, ws, ws_bytes, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------- top-k without allocation
+//
+// For callers that cannot allocate (code under graph capture, serving loops): the workspace is
+// a file-scope device array of fixed size, one copy per GPU.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the symbol); it passes the
+// device address that hipGetSymbolAddress gives, taken once per device with that device current.
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)8 << 20;
+constexpr int kScratchDevices = 64;
+
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+// The scratch array's device address on the current device (NULL and an error on failure).
+void* scratch_on_current_device()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchDevices) {
+        set_error("no usable current device for the scratch workspace");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            set_error("hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" size_t bsh_topk_noalloc_max_bytes(void) { return kScratchBytes; }
+
+extern "C" int bsh_topk_noalloc(const float* score, const int64_t* index, int64_t n, int32_t k,
+                                float* out_score, int64_t* out_index, bsh_stream stream)
+{
+    clear_error();
+    if (n < 0 || k < 0) return fail_inval("n or k negative");
+    if (n >= (int64_t)0xffffffff) return fail_inval("n must be below 2^32 - 1");
+    if (k == 0) return BSH_OK;
+    if (!out_score || !out_index) return fail_inval("NULL output");
+    if (n > 0 && !score) return fail_inval("score is NULL");
+    const size_t need = workspace_bytes(1, k);
+    if (need > kScratchBytes) {
+        set_error("k = %d needs a %zu-byte workspace, above the %zu-byte static scratch of bsh_topk_noalloc",
+                  (int)k, need, kScratchBytes);
+        return BSH_ENOMEM;
+    }
+    void* ws = scratch_on_current_device();
+    if (!ws) return BSH_EHIP;
+    return bsh::topk_segmented(score, index, nullptr, 1, n, 0, k, out_score, out_index, ws, kScratchBytes,
+                               (hipStream_t)stream);
 }

@@ -138,6 +138,12 @@ def test_other_entry_points_reject_bad_arguments():
     assert L.bsh_topk(fake, None, 100, 10, fake, fake, fake, 16, None) == N.BSH_ENOMEM
     assert L.bsh_topk(fake, None, -1, 10, fake, fake, fake, 1 << 20, None) == N.BSH_EINVAL
     assert L.bsh_decode_templates(None, fake, 3, fake, fake, None) == N.BSH_EINVAL
+    # the allocation-free top-k refuses a k its static workspace cannot hold, before any launch
+    assert L.bsh_topk_noalloc_max_bytes() == 8 << 20
+    assert L.bsh_topk_noalloc(fake, None, 1000, 1 << 30, fake, fake, None) == N.BSH_ENOMEM
+    assert L.bsh_topk_noalloc(fake, None, -1, 10, fake, fake, None) == N.BSH_EINVAL
+    assert L.bsh_topk_noalloc(fake, None, 100, 10, None, fake, None) == N.BSH_EINVAL
+    assert L.bsh_topk_noalloc(None, None, 0, 0, None, None, None) == N.BSH_OK
     # empty work is a successful no-op without touching any pointer
     assert L.bsh_topk(None, None, 0, 0, None, None, None, 0, None) == N.BSH_OK
     assert L.bsh_power_stat(ctypes.byref(seg), fake, 1, fake, fake, 0, 0, fake, None, None, None, None) == N.BSH_OK
