@@ -102,6 +102,11 @@ typedef struct bsh_grid {
     const double* a_p_host;       /* host copies of the three small tables above */
     const double* period_host;
     const int64_t* tasc_off_host;
+    double ecc_c, ecc_s;          /* (e cos w, e sin w) of every template of the grid: the
+                                     low-eccentricity (ELL1) track of eq:frequencyevo (Sec. II),
+                                     see bsh_power_stat_ecc; (0, 0) is the circular track, bit for
+                                     bit.  A search over eccentricity runs one grid per pair.
+                                     Finite, with e cos w ^2 + e sin w ^2 < 0.25. */
 } bsh_grid;
 
 /* Numeric ranges from which bsh_grid_build enumerates one band's grid. */
@@ -161,6 +166,7 @@ int bsh_peakgram(const float* power, int64_t n_seg, int32_t n_bins, double rho_t
  *   wsum_out [n_sky*n_bin*n_f0]: sum_J w_J p_J  (FP32, at least 64 partial sums per template)
  *   count_out (may be NULL): sum_J p_J (uint32)
  * Either output may be NULL but not both.  Requires n_per <= BSH_MAX_PER, n_f0 <= BSH_MAX_F0.
+ * A grid with a nonzero (ecc_c, ecc_s) is counted on the ELL1 track of bsh_power_stat_ecc.
  */
 int bsh_hough_count(const bsh_segments* seg, const bsh_grid* grid, uint32_t* count_out,
                     float* wsum_out, int32_t* status, bsh_stream stream);
@@ -301,12 +307,35 @@ int bsh_power_stat_value_and_grad(const bsh_segments* seg, const double* sky, in
  * orbits the circular model only approximates (Sec. IV.E bounds when that matters):
  *   x = F (1 + v.n) (1 - a_p W [cos psi + (e cos w) cos 2psi - (e sin w) sin 2psi]),
  *   psi = W (t - t_asc).
- * cand_params [n][6] = (F, a_p, P, t_asc, e cos w, e sin w); modes as bsh_power_stat (P only).
- * With zero eccentricity the result equals bsh_power_stat bit for bit.
+ * With C2, S2 = cos, sin of 2 W t (from those of W t by the double-angle formulas), the
+ * bracket's eccentric part is C2 A_c2 + S2 A_s2 with A_c2 = a_p W (ec c2 + es s2),
+ * A_s2 = a_p W (ec s2 - es c2), c2, s2 = cos, sin of 2 W t_asc; the track is evaluated as
+ * G = [circular G] - fma(D C2, A_c2, (D S2) A_s2), the order the stage-1 count uses for a grid
+ * with an eccentricity pair, so that grid templates select the same bins in both stages.
+ * cand_params [n][6] = (F, a_p, P, t_asc, e cos w, e sin w); modes and outputs as
+ * bsh_power_stat (counts of the same track in mode 0 when seg->peak_bits is set; P_out may then
+ * be NULL).  With zero eccentricity every output equals bsh_power_stat's bit for bit.
  */
 int bsh_power_stat_ecc(const bsh_segments* seg, const double* sky, int32_t n_sky,
                        const int32_t* cand_sky, const double* cand_params, int64_t n, int32_t mode,
-                       float* P_out, int32_t* status, bsh_stream stream);
+                       float* P_out, uint32_t* count_out, float* wsum_out, int32_t* status,
+                       bsh_stream stream);
+
+/*
+ * Vector-Jacobian product of the mode-1 statistic on the ELL1 track (the interpolated extension
+ * of eq:hough3 on the track of bsh_power_stat_ecc), with respect to all six parameters:
+ *   grad_params[c][q] = grad_P[c] * dP_lin/dtheta_q, theta = (F, a_p, P, t_asc, e cos w, e sin w),
+ * FP64, [n][6].  With E = cos psi + ec cos 2psi - es sin 2psi and E' = dE/dpsi,
+ *   dx/dF = D B, dx/da_p = -F D W E, dx/dP = F D a_p (W/P)(E + psi E'), dx/dt_asc = F D a_p W^2 E',
+ *   dx/d(e cos w) = -F D a_p W cos 2psi, dx/d(e sin w) = F D a_p W sin 2psi.
+ * P_out may be NULL; when given it also gets P_lin from the same pass (as
+ * bsh_power_stat_value_and_grad).  grad_P may be NULL (all ones).  At zero eccentricity the first
+ * four columns are bsh_power_stat_grad's within FP64 rounding.
+ */
+int bsh_power_stat_grad_ecc(const bsh_segments* seg, const double* sky, int32_t n_sky,
+                            const int32_t* cand_sky, const double* cand_params, int64_t n,
+                            const double* grad_P, float* P_out, double* grad_params, int32_t* status,
+                            bsh_stream stream);
 
 /*
  * Absolute bins k_J of each candidate's track: bins_out [n][n_seg] int32.  The same

@@ -59,6 +59,8 @@ class Grid(ctypes.Structure):
         ("a_p_host", _vp),
         ("period_host", _vp),
         ("tasc_off_host", _vp),
+        ("ecc_c", _c_f64),
+        ("ecc_s", _c_f64),
     ]
 
 
@@ -161,7 +163,9 @@ SIGNATURES = {
     "bsh_power_stat": (ctypes.c_int, [ctypes.POINTER(Segments), _vp, _c_i32, _vp, _vp, _c_i64, _c_i32,
                                       _vp, _vp, _vp, _vp, _vp]),
     "bsh_power_stat_ecc": (ctypes.c_int, [ctypes.POINTER(Segments), _vp, _c_i32, _vp, _vp, _c_i64, _c_i32,
-                                          _vp, _vp, _vp]),
+                                          _vp, _vp, _vp, _vp, _vp]),
+    "bsh_power_stat_grad_ecc": (ctypes.c_int, [ctypes.POINTER(Segments), _vp, _c_i32, _vp, _vp, _c_i64, _vp,
+                                               _vp, _vp, _vp, _vp]),
     "bsh_power_stat_grad": (ctypes.c_int, [ctypes.POINTER(Segments), _vp, _c_i32, _vp, _vp, _c_i64,
                                            _vp, _vp, _vp, _vp]),
     "bsh_power_stat_value_and_grad": (ctypes.c_int, [ctypes.POINTER(Segments), _vp, _c_i32, _vp, _vp,

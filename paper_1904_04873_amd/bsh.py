@@ -22,6 +22,7 @@ __all__ = [
     "bsh_grid_build", "bsh_normalize", "bsh_peakgram", "bsh_hough_count", "bsh_hough_count_topk",
     "bsh_topk", "bsh_topk_noalloc",
     "bsh_decode_templates", "bsh_power_stat", "bsh_power_stat_ecc", "bsh_power_stat_grad",
+    "bsh_power_stat_grad_ecc", "with_ecc_columns",
     "bsh_power_stat_value_and_grad",
     "bsh_track_bins", "post_params", "bsh_post_rows", "bsh_significance", "bsh_coincidences",
     "bsh_cluster", "bsh_cluster_centroids",
@@ -126,22 +127,28 @@ class DeviceGrid:
     a_p_dev: torch.Tensor
     period_dev: torch.Tensor
     tasc_off_dev: torch.Tensor
+    ecc_c: float = 0.0      # (e cos w, e sin w) of every template: the ELL1 track; 0, 0 = circular
+    ecc_s: float = 0.0
 
     @classmethod
-    def build(cls, spec, t_mid: float, sky, device="cuda") -> "DeviceGrid":
+    def build(cls, spec, t_mid: float, sky, device="cuda", ecc=(0.0, 0.0)) -> "DeviceGrid":
         """Enumerate the grid with bsh_grid_build (host) and upload its tables."""
         a_p, per, off, t_asc = bsh_grid_build(spec, t_mid)
-        return cls.from_tables(sky, spec.k0, spec.n_f0, a_p, per, off, t_asc, device)
+        return cls.from_tables(sky, spec.k0, spec.n_f0, a_p, per, off, t_asc, device, ecc=ecc)
 
     @classmethod
-    def from_tables(cls, sky, k0, n_f0, a_p, per, off, t_asc, device="cuda") -> "DeviceGrid":
+    def from_tables(cls, sky, k0, n_f0, a_p, per, off, t_asc, device="cuda", ecc=(0.0, 0.0)) -> "DeviceGrid":
         a_p = np.ascontiguousarray(a_p, np.float64)
         per = np.ascontiguousarray(per, np.float64)
         off = np.ascontiguousarray(off, np.int64)
         return cls(sky=_dev(sky, torch.float64, device), k0=int(k0), n_f0=int(n_f0), a_p=a_p, period=per,
                    tasc_off=off, t_asc_dev=_dev(t_asc, torch.float64, device),
                    a_p_dev=_dev(a_p, torch.float64, device), period_dev=_dev(per, torch.float64, device),
-                   tasc_off_dev=_dev(off, torch.int64, device))
+                   tasc_off_dev=_dev(off, torch.int64, device), ecc_c=float(ecc[0]), ecc_s=float(ecc[1]))
+
+    def with_ecc(self, ecc_c: float, ecc_s: float) -> "DeviceGrid":
+        """The same template tables (shared, not copied) with another eccentricity pair."""
+        return dataclasses.replace(self, ecc_c=float(ecc_c), ecc_s=float(ecc_s))
 
     @property
     def n_sky(self) -> int:
@@ -161,7 +168,7 @@ class DeviceGrid:
                       period=_ptr(self.period_dev), tasc_off=_ptr(self.tasc_off_dev),
                       t_asc=_ptr(self.t_asc_dev),
                       a_p_host=self.a_p.ctypes.data, period_host=self.period.ctypes.data,
-                      tasc_off_host=self.tasc_off.ctypes.data)
+                      tasc_off_host=self.tasc_off.ctypes.data, ecc_c=self.ecc_c, ecc_s=self.ecc_s)
 
 
 # ---------------------------------------------------------------- entry points
@@ -356,16 +363,48 @@ def bsh_power_stat(seg: DeviceSegments, sky: torch.Tensor, cand_sky: torch.Tenso
     return (P, cnt, ws) if with_counts else P
 
 
+def with_ecc_columns(cand_params: torch.Tensor, ecc_c: float, ecc_s: float) -> torch.Tensor:
+    """[n, 4] candidate rows (e.g. decoded grid templates) -> [n, 6] rows of one eccentricity pair."""
+    n = int(cand_params.shape[0])
+    e = torch.tensor([float(ecc_c), float(ecc_s)], dtype=torch.float64, device=cand_params.device)
+    return torch.cat([cand_params.to(torch.float64), e.expand(n, 2)], dim=1).contiguous()
+
+
 def bsh_power_stat_ecc(seg: DeviceSegments, sky: torch.Tensor, cand_sky: torch.Tensor,
-                       cand_params: torch.Tensor, mode: int = 0, status: Optional[Status] = None):
-    """Stage-2 statistic on the ELL1 track; cand_params [n, 6] = (F, a_p, P, t_asc, e cos w, e sin w)."""
+                       cand_params: torch.Tensor, mode: int = 0, with_power: bool = True,
+                       with_counts: bool = False, status: Optional[Status] = None):
+    """Stage-2 statistic on the ELL1 track; cand_params [n, 6] = (F, a_p, P, t_asc, e cos w, e sin w).
+    P float32 [n] (or None), and (count int32, wsum float32) if with_counts (mode 0)."""
     n = int(cand_sky.numel())
-    P = torch.empty(n, dtype=torch.float32, device=cand_sky.device)
+    dev = cand_sky.device
+    P = torch.empty(n, dtype=torch.float32, device=dev) if with_power else None
+    cnt = torch.empty(n, dtype=torch.int32, device=dev) if with_counts else None
+    ws = torch.empty(n, dtype=torch.float32, device=dev) if with_counts else None
     s_c = seg.struct()
     check(N.load().bsh_power_stat_ecc(ctypes.byref(s_c), _ptr(sky), int(sky.shape[0]), _ptr(cand_sky),
-                                      _ptr(cand_params.contiguous()), n, int(mode), _ptr(P),
+                                      _ptr(cand_params.contiguous()), n, int(mode), _ptr(P), _ptr(cnt), _ptr(ws),
                                       status.ptr() if status else None, _stream()), "bsh_power_stat_ecc")
+    if with_counts:
+        return P, cnt, ws
     return P
+
+
+def bsh_power_stat_grad_ecc(seg: DeviceSegments, sky: torch.Tensor, cand_sky: torch.Tensor,
+                            cand_params: torch.Tensor, grad_P: Optional[torch.Tensor] = None,
+                            with_value: bool = True, status: Optional[Status] = None):
+    """(P_lin float32 [n] or None, grad_P * d P_lin / d(F, a_p, P, t_asc, e cos w, e sin w) float64
+    [n, 6]) on the ELL1 track, in one pass."""
+    n = int(cand_sky.numel())
+    dev = cand_sky.device
+    P = torch.empty(n, dtype=torch.float32, device=dev) if with_value else None
+    out = torch.empty((n, 6), dtype=torch.float64, device=dev)
+    gp = None if grad_P is None else grad_P.to(torch.float64).contiguous()
+    s_c = seg.struct()
+    check(N.load().bsh_power_stat_grad_ecc(ctypes.byref(s_c), _ptr(sky), int(sky.shape[0]), _ptr(cand_sky),
+                                           _ptr(cand_params.contiguous()), n, _ptr(gp), _ptr(P), _ptr(out),
+                                           status.ptr() if status else None, _stream()),
+          "bsh_power_stat_grad_ecc")
+    return P, out
 
 
 def bsh_power_stat_grad(seg: DeviceSegments, sky: torch.Tensor, cand_sky: torch.Tensor,

@@ -53,6 +53,8 @@ int check_grid(const bsh_grid* g)
     for (int32_t i = 0; i < g->n_per; ++i)
         if (!(g->period_host[i] > 0.0) || !std::isfinite(g->period_host[i]))
             return fail_inval("period must be finite and > 0");
+    if (!std::isfinite(g->ecc_c) || !std::isfinite(g->ecc_s) || g->ecc_c * g->ecc_c + g->ecc_s * g->ecc_s >= 0.25)
+        return fail_inval("eccentricity pair must be finite with e < 0.5");
     return BSH_OK;
 }
 
@@ -63,6 +65,8 @@ int check_window(const bsh_segments* seg, const bsh_grid* g)
     for (int32_t ia = 0; ia < g->n_ap; ++ia)
         for (int32_t ip = 0; ip < g->n_per; ++ip)
             apw = std::fmax(apw, std::fabs(g->a_p_host[ia]) * (kTwoPi / g->period_host[ip]));
+    // the ELL1 bracket is at most 1 + e in size
+    apw *= 1.0 + std::sqrt(g->ecc_c * g->ecc_c + g->ecc_s * g->ecc_s);
     const double v = seg->v_max_host;
     const double f_hi = (double)(g->k0 + g->n_f0);
     const double m = std::ceil(f_hi * (v + apw + v * apw));

@@ -210,7 +210,11 @@ extern "C" int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh
     p->k_band = o.k_band;
     p->lanes = lanes;
     p->chunk = chunk;
-    p->mode = kernel_mode(o.variant, false);
+    // one kernel for the whole plan: the ELL1 form when any grid has an eccentricity pair (its
+    // zero eccentric terms leave circular items' maps as the circular kernel gives them)
+    int ecc = 0;
+    for (int32_t q = 0; q < n_grids; ++q) ecc = std::max(ecc, ecc_mode(&grids[q]));
+    p->mode = kernel_mode(o.variant, false) + ecc;
     p->use_graph = o.use_graph != 0;
     p->maps = maps;
     p->band_score = band_score;

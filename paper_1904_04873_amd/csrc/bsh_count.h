@@ -40,6 +40,7 @@ struct ItemDesc {
     int32_t n_per;
     int32_t sky_lo;     // first pixel of the item in the grid's sky table
     int32_t n_sky;      // pixels of the item
+    double ec, es;      // (e cos w, e sin w) of the grid's ELL1 track; zeros for a circular grid
 };
 
 struct PlainLaunch {
@@ -62,26 +63,32 @@ constexpr int kGroup = 4;
 constexpr int kGroup8 = 2 * kGroup;
 constexpr int kFlushGroups = 64;     // eight-segment groups per register partial sum
 
-// Per staged segment: D cos(W t), D sin(W t) and the Doppler factor D of the tile's pixel.
-// The rows come first, so that a window's reads reach them with the small immediate offsets of
-// the paired LDS reads; the segment tables follow, so that their addresses fit the 16-bit
-// immediate offset of an LDS read at every chunk size (no address moves per segment).
-template <int kChunk>
+// Per staged segment: D cos(W t), D sin(W t) and the Doppler factor D of the tile's pixel, and
+// for the ELL1 track D cos(2 W t), D sin(2 W t) (zero-length arrays on a circular grid, which
+// leave the layout as it is).  The rows come first, so that a window's reads reach them with the
+// small immediate offsets of the paired LDS reads; the segment tables follow, so that their
+// addresses fit the 16-bit immediate offset of an LDS read at every chunk size (no address
+// moves per segment).
+template <int kChunk, bool kEcc>
 struct TileSmemLut {
     uint32_t row[kChunk * (BSH_MAX_WORDS + kRowPad)];
     double DC[kChunk];
     double DS[kChunk];
     double D[kChunk];
+    double DC2[kEcc ? kChunk : 0];
+    double DS2[kEcc ? kChunk : 0];
     float T8[(kChunk / kGroup8) * 256];
     float T[(kChunk / kGroup) * 16];
 };
 
-template <int kChunk>
+template <int kChunk, bool kEcc>
 struct TileSmem {
     uint32_t row[kChunk * (BSH_MAX_WORDS + kRowPad)];
     double DC[kChunk];
     double DS[kChunk];
     double D[kChunk];
+    double DC2[kEcc ? kChunk : 0];
+    double DS2[kEcc ? kChunk : 0];
     float W[kChunk];
 };
 
@@ -89,12 +96,16 @@ int64_t plan_tiles(const bsh_grid* g, int lanes, int32_t* tile_start, int64_t* g
 void fill_desc(ItemDesc& d, const bsh_segments* seg, const bsh_grid* grid, int32_t sky_lo,
                int32_t n_sky, uint32_t* count_out, float* wsum_out, int32_t* status);
 int zero_words(void* p, int64_t n_words, hipStream_t stream);
-// mode: 0 select-and-add (weighted sums), 1 select-and-add with counts, 2 subset-sum tables
+// mode: 0 select-and-add (weighted sums), 1 select-and-add with counts, 2 subset-sum tables;
+// plus kEccMode for the same on the ELL1 track
+constexpr int kEccMode = 3;
 int launch_plain(const PlainLaunch& p, int64_t blocks, int lanes, int chunk, int mode, hipStream_t stream);
 int launch_batch(const ItemDesc* items, const WorkUnit* units, int64_t n_units, uint32_t* counter,
                  int blocks, int lanes, int chunk, int mode, hipStream_t stream);
 int batch_blocks_per_cu(int lanes, int chunk, int mode);
 int kernel_mode(int variant, bool with_count);
+// kEccMode for a grid with an eccentricity pair, else 0 (added to kernel_mode's value)
+int ecc_mode(const bsh_grid* g);
 bool valid_tile_shape(int lanes, int chunk);
 
 }  // namespace bsh

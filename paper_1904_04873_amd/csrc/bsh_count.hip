@@ -8,7 +8,7 @@
 namespace bsh {
 
 template <int kMode, int kChunk>
-__global__ __launch_bounds__(kMaxLanes, kMode == 2 ? 2 : 1) void hough_count_kernel(const PlainLaunch p)
+__global__ __launch_bounds__(kMaxLanes, min_blocks<kMode>()) void hough_count_kernel(const PlainLaunch p)
 {
     __shared__ __align__(16) unsigned char smem[smem_bytes<kMode, kChunk>()];
     const int blk = blockIdx.x;
@@ -68,6 +68,8 @@ void fill_desc(ItemDesc& d, const bsh_segments* seg, const bsh_grid* grid, int32
     d.n_per = grid->n_per;
     d.sky_lo = sky_lo;
     d.n_sky = n_sky;
+    d.ec = grid->ecc_c;
+    d.es = grid->ecc_s;
     d.n_bin = grid->tasc_off_host[(int64_t)grid->n_ap * grid->n_per];
 }
 
@@ -101,6 +103,8 @@ int kernel_mode(int variant, bool with_count)
     if (with_count) return 1;
     return variant == BSH_VARIANT_SELECT ? 0 : 2;
 }
+
+int ecc_mode(const bsh_grid* g) { return (g->ecc_c != 0.0 || g->ecc_s != 0.0) ? kEccMode : 0; }
 
 bool valid_tile_shape(int lanes, int chunk)
 {
@@ -142,7 +146,7 @@ extern "C" int bsh_hough_count_ex(const bsh_segments* seg, const bsh_grid* grid,
         if (rc) return rc;
         return zero_words(count_out, count_out ? n_t : 0, s);
     }
-    return launch_plain(p, blocks, lanes, chunk, kernel_mode(variant, count_out != nullptr), s);
+    return launch_plain(p, blocks, lanes, chunk, kernel_mode(variant, count_out != nullptr) + ecc_mode(grid), s);
 }
 
 extern "C" int bsh_hough_count(const bsh_segments* seg, const bsh_grid* grid, uint32_t* count_out,
@@ -263,7 +267,7 @@ extern "C" int bsh_hough_count_topk(const bsh_segments* seg, const bsh_grid* gri
         if (seg->n_seg == 0 || tiles == 0)
             rc = zero_words(map, n_t, s);
         else
-            rc = launch_plain(p, tiles * nc, lanes, chunk, kernel_mode(BSH_VARIANT_AUTO, false), s);
+            rc = launch_plain(p, tiles * nc, lanes, chunk, kernel_mode(BSH_VARIANT_AUTO, false) + ecc_mode(grid), s);
         if (rc) return rc;
         const int64_t first = c0 * per_sky;
         if (single)

@@ -6,7 +6,7 @@
 namespace bsh {
 
 template <int kMode, int kChunk>
-__global__ __launch_bounds__(kMaxLanes, kMode == 2 ? 2 : 1) void hough_batch_kernel(const ItemDesc* __restrict__ items,
+__global__ __launch_bounds__(kMaxLanes, min_blocks<kMode>()) void hough_batch_kernel(const ItemDesc* __restrict__ items,
                                                                const WorkUnit* __restrict__ units,
                                                                int64_t n_units, uint32_t* counter)
 {
@@ -50,6 +50,15 @@ int batch_blocks_per_cu(int lanes, int chunk, int mode)
     case 2128: BSH_OCC(2, 128); break;
     case 2256: BSH_OCC(2, 256); break;
     case 2512: BSH_OCC(2, 512); break;
+    case 3128: BSH_OCC(3, 128); break;
+    case 3256: BSH_OCC(3, 256); break;
+    case 3512: BSH_OCC(3, 512); break;
+    case 4128: BSH_OCC(4, 128); break;
+    case 4256: BSH_OCC(4, 256); break;
+    case 4512: BSH_OCC(4, 512); break;
+    case 5128: BSH_OCC(5, 128); break;
+    case 5256: BSH_OCC(5, 256); break;
+    case 5512: BSH_OCC(5, 512); break;
     default: break;
     }
 #undef BSH_OCC

@@ -39,14 +39,23 @@ struct BandTrack {
     bool ok;
 };
 
+// G of one (binary template, segment): the circular track_G, or track_G_ecc on a grid with an
+// eccentricity pair (Ac2 = As2 = 0 there gives the circular value bit for bit anyway).
+template <bool kEcc>
+__device__ __forceinline__ double tile_G(double DC, double DS, double D, double DC2, double DS2, double Ac,
+                                         double As, double Ac2, double As2)
+{
+    if constexpr (kEcc) return track_G_ecc(D, DC, DS, Ac, As, DC2, DS2, Ac2, As2);
+    else return track_G(D, DC, DS, Ac, As);
+}
+
 // The canonical evaluations (no branches).  ok is false, and a flag is raised, when the track
 // leaves the staged row [klo, khi) or drifts more than one bin across the band.
-__device__ __forceinline__ BandTrack band_track(double DC, double DS, double D, double Ac, double As,
-                                                double F0, double FL, int klo, int khi, int last,
+__device__ __forceinline__ BandTrack band_track(double G, double F0, double FL, int klo, int khi, int last,
                                                 bool& bad_range, bool& bad_model)
 {
     BandTrack t;
-    t.G = track_G(D, DC, DS, Ac, As);
+    t.G = G;
     // the nearest bin floor(F G + 1/2) of a positive track value is its truncation
     t.y0 = fma(F0, t.G, 0.5);
     t.kf = (int)t.y0;
@@ -146,20 +155,19 @@ __device__ __forceinline__ void band_step(const BandTrack& t, double F0, int las
 // The peak bits of the band's n_f0 templates of one (binary template, segment): bit i of the
 // 96-bit (m0, m1, m2) is the peakgram bit of f0 bin i's track.  Returns false, with zero masks,
 // when the track failed.
-__device__ __forceinline__ bool band_mask(const uint32_t* row, double DC, double DS, double D, double Ac,
-                                          double As, double F0, double FL, int klo, int khi, int last,
-                                          int pad_at, uint32_t& m0, uint32_t& m1, uint32_t& m2, bool& bad_range,
-                                          bool& bad_model)
+__device__ __forceinline__ bool band_mask(const uint32_t* row, double G, double F0, double FL, int klo, int khi,
+                                          int last, int pad_at, uint32_t& m0, uint32_t& m1, uint32_t& m2,
+                                          bool& bad_range, bool& bad_model)
 {
-    const BandTrack t = band_track(DC, DS, D, Ac, As, F0, FL, klo, khi, last, bad_range, bad_model);
+    const BandTrack t = band_track(G, F0, FL, klo, khi, last, bad_range, bad_model);
     band_window(row, t, klo, pad_at, m0, m1, m2);
     if (t.ok && t.span != last) band_step(t, F0, last, m0, m1, m2);
     return t.ok;
 }
 
-template <bool kCount, int kChunk>
+template <bool kCount, int kChunk, bool kEcc>
 __device__ __forceinline__ void count_tile(const ItemDesc& d, int s, int ip, int64_t tile,
-                                           TileSmem<kChunk>& sm)
+                                           TileSmem<kChunk, kEcc>& sm)
 {
     const int tid = threadIdx.x;
     const int lanes = blockDim.x;
@@ -181,6 +189,8 @@ __device__ __forceinline__ void count_tile(const ItemDesc& d, int s, int ip, int
     double sb = 0.0, cb = 1.0;
     if (active) track_sincos(W * d.t_asc[b], sb, cb);
     const double Ac = apW * cb, As = apW * sb;
+    double Ac2 = 0.0, As2 = 0.0;
+    if constexpr (kEcc) ecc_coeffs(apW, cb, sb, d.ec, d.es, Ac2, As2);
 
     const int sg = d.sky_lo + s;
     const double nx = d.sky[3 * sg], ny = d.sky[3 * sg + 1], nz = d.sky[3 * sg + 2];
@@ -211,6 +221,12 @@ __device__ __forceinline__ void count_tile(const ItemDesc& d, int s, int ip, int
             sm.DC[jj] = D * cp;
             sm.DS[jj] = D * sp;
             sm.D[jj] = D;
+            if constexpr (kEcc) {
+                double c2, s2;
+                double_angle(cp, sp, c2, s2);
+                sm.DC2[jj] = D * c2;
+                sm.DS2[jj] = D * s2;
+            }
             sm.W[jj] = wrow[J];
         }
         for (int e = tid; e < nj * nwp; e += lanes) {
@@ -223,8 +239,10 @@ __device__ __forceinline__ void count_tile(const ItemDesc& d, int s, int ip, int
 
         for (int jj = 0; jj < nj; ++jj) {
             uint32_t m0, m1, m2;
-            if (!band_mask(sm.row + jj * nwp, sm.DC[jj], sm.DS[jj], sm.D[jj], Ac, As, F0, FL, klo,
-                           klo + d.n_bins, last, 32 * d.n_words, m0, m1, m2, bad_range, bad_model))
+            const double G = tile_G<kEcc>(sm.DC[jj], sm.DS[jj], sm.D[jj], kEcc ? sm.DC2[jj] : 0.0,
+                                          kEcc ? sm.DS2[jj] : 0.0, Ac, As, Ac2, As2);
+            if (!band_mask(sm.row + jj * nwp, G, F0, FL, klo, klo + d.n_bins, last, 32 * d.n_words, m0, m1, m2,
+                           bad_range, bad_model))
                 continue;
 
             const uint32_t wb = __float_as_uint(sm.W[jj]);
@@ -268,9 +286,9 @@ __device__ __forceinline__ void count_tile(const ItemDesc& d, int s, int ip, int
 // folded into the lane's own slots of the output map, which keeps the register footprint
 // small enough for two waves per SIMD; the error of the two-level sum stays below
 // (kFlushGroups + 4 + n_seg / (8 kFlushGroups)) FP32 ulps of the total.
-template <int kChunk>
+template <int kChunk, bool kEcc>
 __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip, int64_t tile,
-                                               TileSmemLut<kChunk>& sm)
+                                               TileSmemLut<kChunk, kEcc>& sm)
 {
     static_assert(kChunk % kGroup8 == 0, "chunks hold whole groups");
     const int tid = threadIdx.x;
@@ -292,6 +310,8 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
     double sb = 0.0, cb = 1.0;
     if (active) track_sincos(W * d.t_asc[b], sb, cb);
     const double Ac = apW * cb, As = apW * sb;
+    double Ac2 = 0.0, As2 = 0.0;
+    if constexpr (kEcc) ecc_coeffs(apW, cb, sb, d.ec, d.es, Ac2, As2);
 
     const int sg = d.sky_lo + s;
     const double nx = d.sky[3 * sg], ny = d.sky[3 * sg + 1], nz = d.sky[3 * sg + 2];
@@ -335,6 +355,12 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
             sm.DC[jj] = D * cp;
             sm.DS[jj] = D * sp;
             sm.D[jj] = D;
+            if constexpr (kEcc) {
+                double c2, s2;
+                double_angle(cp, sp, c2, s2);
+                sm.DC2[jj] = D * c2;
+                sm.DS2[jj] = D * s2;
+            }
         }
         for (int e = tid; e < ng * kGroup * nwp; e += lanes) {
             const int jj = e / nwp;
@@ -377,8 +403,9 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
 #pragma unroll
             for (int u = 0; u < kGroup; ++u) {
                 const int jj = g * kGroup + u;
-                tr[u] = band_track(sm.DC[jj], sm.DS[jj], sm.D[jj], Ac, As, F0, FL, klo, klo + d.n_bins, last,
-                                   bad_range, bad_model);
+                const double G = tile_G<kEcc>(sm.DC[jj], sm.DS[jj], sm.D[jj], kEcc ? sm.DC2[jj] : 0.0,
+                                              kEcc ? sm.DS2[jj] : 0.0, Ac, As, Ac2, As2);
+                tr[u] = band_track(G, F0, FL, klo, klo + d.n_bins, last, bad_range, bad_model);
             }
 #pragma unroll
             for (int u = 0; u < kGroup; ++u)
@@ -445,21 +472,30 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
     if (active && (since_flush > 0 || !flushed)) flush();
 }
 
-// kMode: 0 = select-and-add, weighted sums only; 1 = select-and-add with counts; 2 = table.
+// kMode % kEccMode: 0 = select-and-add, weighted sums only; 1 = select-and-add with counts;
+// 2 = table.  kMode >= kEccMode: the same on the ELL1 track of the item's eccentricity pair.
 template <int kMode, int kChunk>
 __device__ __forceinline__ void run_tile(const ItemDesc& d, int s, int ip, int64_t tile, void* smem)
 {
-    if constexpr (kMode == 2)
-        count_tile_lut<kChunk>(d, s, ip, tile, *reinterpret_cast<TileSmemLut<kChunk>*>(smem));
+    constexpr int kM = kMode % kEccMode;
+    constexpr bool kEcc = kMode >= kEccMode;
+    if constexpr (kM == 2)
+        count_tile_lut<kChunk, kEcc>(d, s, ip, tile, *reinterpret_cast<TileSmemLut<kChunk, kEcc>*>(smem));
     else
-        count_tile<kMode == 1, kChunk>(d, s, ip, tile, *reinterpret_cast<TileSmem<kChunk>*>(smem));
+        count_tile<kM == 1, kChunk, kEcc>(d, s, ip, tile, *reinterpret_cast<TileSmem<kChunk, kEcc>*>(smem));
 }
 
 template <int kMode, int kChunk>
 constexpr size_t smem_bytes()
 {
-    return kMode == 2 ? sizeof(TileSmemLut<kChunk>) : sizeof(TileSmem<kChunk>);
+    constexpr bool kEcc = kMode >= kEccMode;
+    return kMode % kEccMode == 2 ? sizeof(TileSmemLut<kChunk, kEcc>) : sizeof(TileSmem<kChunk, kEcc>);
 }
+
+// Waves per SIMD the kernel is built for: two for the table variant (its 90 partial sums live in
+// registers), one for the select variants.
+template <int kMode>
+constexpr int min_blocks() { return kMode % kEccMode == 2 ? 2 : 1; }
 
 // Instantiate a kernel template for every (mode, chunk) and call f with the chosen one.
 #define BSH_DISPATCH(MODE, CHUNK, F)                                                          \
@@ -473,6 +509,15 @@ constexpr size_t smem_bytes()
     case 2128: F(2, 128); break;                                                              \
     case 2256: F(2, 256); break;                                                              \
     case 2512: F(2, 512); break;                                                              \
+    case 3128: F(3, 128); break;                                                              \
+    case 3256: F(3, 256); break;                                                              \
+    case 3512: F(3, 512); break;                                                              \
+    case 4128: F(4, 128); break;                                                              \
+    case 4256: F(4, 256); break;                                                              \
+    case 4512: F(4, 512); break;                                                              \
+    case 5128: F(5, 128); break;                                                              \
+    case 5256: F(5, 256); break;                                                              \
+    case 5512: F(5, 512); break;                                                              \
     default: return fail_inval("kernel mode / chunk");                                        \
     }
 

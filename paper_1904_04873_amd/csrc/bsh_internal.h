@@ -149,6 +149,36 @@ __device__ __forceinline__ double track_G(double D, double DC, double DS, double
     return D - fma(DC, Ac, DS * As);
 }
 
+// Low-eccentricity (ELL1) track of eq:frequencyevo: the orbit bracket gains
+// (e cos w) cos 2psi - (e sin w) sin 2psi, psi = W (t - t_asc).  Expanding cos 2psi and sin 2psi
+// by the angle-difference formulas in 2 W t and 2 W t_asc, its a_p W multiple is
+// C2 A_c2 + S2 A_s2 with C2, S2 = cos, sin(2 W t) (per segment) and the template's
+// A_c2 = a_p W (ec c2 + es s2), A_s2 = a_p W (ec s2 - es c2), c2, s2 = cos, sin(2 W t_asc).
+// Both double angles come from cos / sin of the single angle, in this one order.
+__device__ __forceinline__ void double_angle(double c, double s, double& c2, double& s2)
+{
+    c2 = (c - s) * (c + s);
+    s2 = 2.0 * (s * c);
+}
+
+__device__ __forceinline__ void ecc_coeffs(double apW, double cb, double sb, double ec, double es, double& Ac2,
+                                           double& As2)
+{
+    double c2, s2;
+    double_angle(cb, sb, c2, s2);
+    Ac2 = apW * (ec * c2 + es * s2);
+    As2 = apW * (ec * s2 - es * c2);
+}
+
+// G on the ELL1 track: the circular G minus D (C2 A_c2 + S2 A_s2), evaluated as
+// track_G(...) - fma(D C2, A_c2, (D S2) A_s2) by every kernel.  With zero eccentricity A_c2 and
+// A_s2 are zeros and G is the circular track_G bit for bit.
+__device__ __forceinline__ double track_G_ecc(double D, double DC, double DS, double Ac, double As, double DC2,
+                                              double DS2, double Ac2, double As2)
+{
+    return track_G(D, DC, DS, Ac, As) - fma(DC2, Ac2, DS2 * As2);
+}
+
 // Nearest bin of the track: floor(F G + 1/2), with F G + 1/2 rounded once.
 __device__ __forceinline__ double track_bin(double F, double G) { return floor(fma(F, G, 0.5)); }
 

@@ -102,6 +102,12 @@ def test_hough_count_rejects_bad_arguments_on_host():
     assert L.bsh_hough_count(ctypes.byref(seg3), ctypes.byref(grid3), fake, fake, None, None) == N.BSH_EINVAL
     seg4, grid4, keep4 = _structs(n_per=300)
     assert L.bsh_hough_count(ctypes.byref(seg4), ctypes.byref(grid4), fake, fake, None, None) == N.BSH_EINVAL
+    # an eccentricity pair must be finite with e < 0.5
+    for ec, es in ((0.4, 0.31), (float("nan"), 0.0), (0.0, float("inf"))):
+        seg5, grid5, keep5 = _structs()
+        grid5.ecc_c, grid5.ecc_s = ec, es
+        assert L.bsh_hough_count(ctypes.byref(seg5), ctypes.byref(grid5), fake, fake, None, None) == N.BSH_EINVAL
+        assert b"eccentricity" in L.bsh_last_error()
     seg.t_coh = float("nan")
     assert L.bsh_hough_count(ctypes.byref(seg), ctypes.byref(grid), fake, fake, None, None) == N.BSH_EINVAL
     assert b"t_coh" in L.bsh_last_error()
@@ -115,6 +121,20 @@ def test_hough_count_host_window_check():
     seg, grid, keep = _structs(n_bins=100, k_lo=90000 - 5, v_max=1.015e-4)
     assert L.bsh_hough_count(ctypes.byref(seg), ctypes.byref(grid), fake, fake, None, None) == N.BSH_ERANGE
     assert b"does not cover" in L.bsh_last_error()
+    # the bound widens by (1 + e) for the ELL1 track's orbit term: a row that covers the circular
+    # tracks with one bin to spare no longer covers eccentric ones
+    g = S.config1().grids[0]
+    apw = max(g.ap_hi * 2 * np.pi / g.per_lo, g.ap_lo * 2 * np.pi / g.per_lo)
+    f_hi = 90000 + 90
+    m = int(np.ceil(f_hi * (1.015e-4 + apw + 1.015e-4 * apw)))
+    seg, grid, keep = _structs(n_bins=90 + 2 * m + 3, k_lo=90000 - m - 1, v_max=1.015e-4)
+    spec = N.TopkSpec(k=10, sky_per_pass=0)
+    # bsh_hough_count_topk checks the window before the workspace size: ENOMEM means it passed
+    assert L.bsh_hough_count_topk(ctypes.byref(seg), ctypes.byref(grid), ctypes.byref(spec), fake, fake, fake, 0,
+                                  None, None) == N.BSH_ENOMEM
+    grid.ecc_c = 0.45
+    assert L.bsh_hough_count_topk(ctypes.byref(seg), ctypes.byref(grid), ctypes.byref(spec), fake, fake, fake, 0,
+                                  None, None) == N.BSH_ERANGE
 
 
 def test_other_entry_points_reject_bad_arguments():
@@ -138,6 +158,12 @@ def test_other_entry_points_reject_bad_arguments():
     assert L.bsh_topk(fake, None, 100, 10, fake, fake, fake, 16, None) == N.BSH_ENOMEM
     assert L.bsh_topk(fake, None, -1, 10, fake, fake, fake, 1 << 20, None) == N.BSH_EINVAL
     assert L.bsh_decode_templates(None, fake, 3, fake, fake, None) == N.BSH_EINVAL
+    assert L.bsh_power_stat_ecc(ctypes.byref(seg), fake, 1, fake, fake, 10, 1, fake, fake, None, None, None) == N.BSH_EINVAL
+    assert L.bsh_power_stat_ecc(ctypes.byref(seg), fake, 1, fake, fake, 10, 0, None, None, None, None, None) == N.BSH_EINVAL
+    assert L.bsh_power_stat_grad_ecc(ctypes.byref(seg), fake, 1, fake, fake, -1, None, None, fake, None,
+                                     None) == N.BSH_EINVAL
+    assert L.bsh_power_stat_grad_ecc(ctypes.byref(seg), fake, 1, fake, fake, 5, None, fake, None, None,
+                                     None) == N.BSH_EINVAL
     # the allocation-free top-k refuses a k its static workspace cannot hold, before any launch
     assert L.bsh_topk_noalloc_max_bytes() == 8 << 20
     assert L.bsh_topk_noalloc(fake, None, 1000, 1 << 30, fake, fake, None) == N.BSH_ENOMEM
