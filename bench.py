@@ -127,6 +127,10 @@ def parse():
                     help="pixels whose maps the all-sky plan's buffer holds")
     ap.add_argument("--skip-extras", action="store_true",
                     help="only the headline (no band step, all-sky slice, refinement, post-processing)")
+    ap.add_argument("--tile", default="",
+                    help="LANESxCHUNK of the batched plan instead of autotuning it (for profiling runs)")
+    ap.add_argument("--plain-tile", default="",
+                    help="LANESxCHUNK of the plain baseline instead of autotuning it (for profiling runs)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="before timing, run one plain device copy of this many MiB (a known-size "
                          "kernel for scaling HBM byte counters)")
@@ -201,9 +205,19 @@ def main():
     torch.cuda.synchronize()
     print(f"[bench] batching workload resident: {ts_total:.3e} template*segments; autotuning",
           file=sys.stderr, flush=True)
-    (lanes, chunk), tune_ms = autotune.tune(items, grids, 4, sample=16, use_cache=False)
+    def fixed(text):
+        lanes_s, chunk_s = text.lower().split("x")
+        return (int(lanes_s), int(chunk_s)), {}
+
+    if args.tile:
+        (lanes, chunk), tune_ms = fixed(args.tile)
+    else:
+        (lanes, chunk), tune_ms = autotune.tune(items, grids, 4, sample=16, use_cache=False)
     # the plain baseline runs with the tile that suits one launch per item best
-    (lanes_p, chunk_p), tune_p_ms = autotune.tune(items, grids, 4, sample=16, use_cache=False, plain=True)
+    if args.plain_tile:
+        (lanes_p, chunk_p), tune_p_ms = fixed(args.plain_tile)
+    else:
+        (lanes_p, chunk_p), tune_p_ms = autotune.tune(items, grids, 4, sample=16, use_cache=False, plain=True)
     k_item, k_band = 1000, 1000
     st = bsh.Status(dev)
     plan = bsh.Plan(items, grids, 4, k_item=k_item, k_band=k_band, lanes=lanes, chunk=chunk,
