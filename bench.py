@@ -5,7 +5,7 @@ per-item launches, at exact top-k.
 One step = one batched run of the batching workload with its inputs resident in HBM: 256 sky
 patches x 4 bands of 0.1 Hz in 100-300 Hz (1024 items of 3000-6000 gapped segments, a_p 64 x
 P 32 x t_asc 4-256 per cell by the eq:binaryres rule, 90 f0 bins; 9.01e9 templates, 4.0e13
-template x segments), as one graph-captured persistent launch followed by per-item and per-band
+template x segments), as one graph-captured launch of one block per queued unit followed by per-item and per-band
 top-1000 lists.  The same work as one plain launch (and top-k) per item is timed beside it.
 Work unit: template x segment of stage 1.
 
@@ -38,9 +38,9 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 FLOOR_OPS_PER_TS = 2 / 8 + 12 / 90
 # VALU lane-operations per template x segment the table count issues on its fast path: the VALU
 # instructions of the segment-group loop in its gfx950 assembly along the path with no f0-shift
-# step and no flush (paper_1904_04873_amd/fastpath_ops.py counts them: 664 per group of 8
-# segments), divided by the group's 8 x 90 template x segments.
-TABLE_OPS_PER_TS = 664 / 720
+# step and no flush (paper_1904_04873_amd/fastpath_ops.py counts them per chunk size), divided by
+# the 8 segments x 45 f0 bins one lane of a template's lane pair covers per group.
+TABLE_OPS_PER_TS = {128: 379 / 360, 256: 379 / 360, 512: 374 / 360}
 # plain select-and-add: extract the peak bit, select the weight, add
 SELECT_OPS_PER_TS = 3
 # HBM bytes per count launch, measured with rocprofv3 counters for one kernel source and tile
@@ -242,7 +242,7 @@ def main():
     ref_lists = (plan.band_score.clone(), plan.band_index.clone())
     units, blocks = plan.units, plan.blocks
 
-    # the dominant kernel alone: the persistent count launch, back to back on the stream it runs
+    # the dominant kernel alone: the batched count launch, back to back on the stream it runs
     # on (the plan enqueues on the current stream), bracketed by HIP events
     n_count = max(3, min(args.steps, 5))
     c0 = torch.cuda.Event(enable_timing=True)
@@ -255,6 +255,26 @@ def main():
     st.raise_if_set("count kernel")
     count_ms = c0.elapsed_time(c1) / n_count
     print(f"[bench] batched {ms_step:.1f} ms/run, count kernel {count_ms:.1f} ms", file=sys.stderr, flush=True)
+
+    # the persistent launch form of the same plan (blocks pulling units from a queue counter),
+    # timed the same way, for comparison
+    plan.close()
+    pp = bsh.Plan(items, grids, 4, k_item=k_item, k_band=k_band, lanes=lanes, chunk=chunk,
+                  use_graph=False, lpt=True, status=st, persistent=True)
+    pp.run_count()
+    torch.cuda.synchronize()
+    c0.record()
+    for _ in range(n_count):
+        pp.run_count()
+    c1.record()
+    torch.cuda.synchronize()
+    st.raise_if_set("persistent count")
+    persistent_form = {"kernel": f"hough_batch_kernel<2, {chunk}>", "blocks": pp.blocks,
+                       "count_ms": c0.elapsed_time(c1) / n_count}
+    pp.close()
+    del pp
+    plan = bsh.Plan(items, grids, 4, k_item=k_item, k_band=k_band, lanes=lanes, chunk=chunk,
+                    use_graph=True, lpt=True, status=st)
 
     if (lanes_p, chunk_p) != (lanes, chunk):
         plan.close()
@@ -270,7 +290,7 @@ def main():
     torch.cuda.empty_cache()
 
     achieved = FLOOR_OPS_PER_TS * ts_total / (count_ms / 1e3)
-    issued = TABLE_OPS_PER_TS * ts_total / (count_ms / 1e3)
+    issued = TABLE_OPS_PER_TS[chunk] * ts_total / (count_ms / 1e3)
     achieved_select = SELECT_OPS_PER_TS * ts_total / (count_ms / 1e3)
 
     cpu = None
@@ -298,7 +318,7 @@ def main():
         "config": {
             "workload": "batched stage 1: 256 sky patches x 4 bands of 0.1 Hz (f_lo 100.0/166.6/233.2/299.8 Hz), "
                         "1024 items of 3000-6000 gapped segments, a_p 64 x P 32 x t_asc 4-256 per cell, 90 f0 "
-                        f"= {n_templates} templates; one graph-captured persistent launch plus per-item and "
+                        f"= {n_templates} templates; one graph-captured launch (one block per queued unit) plus per-item and "
                         "per-band top-1000, against one plain launch and top-k per item",
             "items": 1024,
             "templates": n_templates,
@@ -319,7 +339,8 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": f"hough_batch_kernel<2, {chunk}> (persistent; subset-sum tables of 8 segments)",
+            "kernel": f"hough_unit_kernel<2, {chunk}> (one block per queued unit; subset-sum tables of 8 segments, "
+                      "two lanes per binary template)",
             "achieved": achieved / 1e12,
             "peak": VALU_PEAK_OPS / 1e12,
             "unit": "TOP/s",
@@ -329,14 +350,15 @@ def main():
             "ops_per_template_segment": FLOOR_OPS_PER_TS,
             "floor": "algorithmic: per template and 8 segments one table read and one add; per (binary "
                      "template, segment) a 12-operation track shared by 90 f0 bins",
-            "issued_fast_path": {"ops_per_template_segment": TABLE_OPS_PER_TS, "achieved": issued / 1e12,
+            "issued_fast_path": {"ops_per_template_segment": TABLE_OPS_PER_TS[chunk], "achieved": issued / 1e12,
                                  "frac": issued / VALU_PEAK_OPS},
             "select_add_equivalent": {"ops_per_template_segment": SELECT_OPS_PER_TS,
                                       "achieved": achieved_select / 1e12,
                                       "frac": achieved_select / VALU_PEAK_OPS},
             "tile": {"lanes": lanes, "chunk": chunk},
             "units": units,
-            "persistent_blocks": blocks,
+            "blocks": blocks,
+            "persistent_form": persistent_form,
             "autotune_ms": {f"{l}x{c}": t for (l, c), t in tune_ms.items()},
         },
         "cpu_baseline": cpu,
@@ -457,7 +479,7 @@ def run_band200(args):
         "count_kernel": {"kernel": f"hough_count_kernel<2, {chunk}>", "ms": count_ms,
                          "value": ts_per_step / (count_ms / 1e3),
                          "frac_floor": FLOOR_OPS_PER_TS * ts_per_step / (count_ms / 1e3) / VALU_PEAK_OPS,
-                         "frac_issued_fast_path": TABLE_OPS_PER_TS * ts_per_step / (count_ms / 1e3) / VALU_PEAK_OPS,
+                         "frac_issued_fast_path": TABLE_OPS_PER_TS[chunk] * ts_per_step / (count_ms / 1e3) / VALU_PEAK_OPS,
                          "traffic": measured_traffic(lanes, chunk), "tile": {"lanes": lanes, "chunk": chunk},
                          "autotune_ms": {f"{l}x{c}": t for (l, c), t in tune_ms.items()}},
     }

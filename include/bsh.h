@@ -372,6 +372,9 @@ typedef struct bsh_plan_opts {
     int32_t lpt;          /* 1: queue units longest-first */
     int32_t blocks;       /* persistent blocks (0: CUs x resident blocks per CU) */
     int32_t variant;      /* accumulation variant as in bsh_hough_count_ex */
+    int32_t persistent;   /* 0: one block per unit of the queue, dispatched in queue order (the
+                             default; the tile's registers then fit three waves per SIMD);
+                             1: persistent blocks that pull units from an atomic queue counter */
 } bsh_plan_opts;
 
 typedef struct bsh_plan bsh_plan;
@@ -409,7 +412,8 @@ int bsh_plan_run_plain(bsh_plan* plan, bsh_stream stream);
  * the maps of the last pass, for timing the count kernel on its own. */
 int bsh_plan_run_count(bsh_plan* plan, bsh_stream stream);
 
-/* Number of queued units, persistent blocks and passes of a plan (-1 for NULL). */
+/* Number of queued units, blocks per launch (the persistent blocks, or the largest pass's unit
+ * count with one block per unit) and passes of a plan (-1 for NULL). */
 int64_t bsh_plan_units(const bsh_plan* plan);
 int32_t bsh_plan_blocks(const bsh_plan* plan);
 int32_t bsh_plan_passes(const bsh_plan* plan);

@@ -102,6 +102,7 @@ class PlanOpts(ctypes.Structure):
         ("lpt", _c_i32),
         ("blocks", _c_i32),
         ("variant", _c_i32),
+        ("persistent", _c_i32),
     ]
 
 

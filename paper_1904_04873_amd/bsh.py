@@ -539,7 +539,7 @@ class Plan:
     def __init__(self, items, grids: Sequence[DeviceGrid], n_bands: int, k_item: int = 0,
                  k_band: int = 0, lanes: int = 0, chunk: int = 0, use_graph: bool = True,
                  lpt: bool = True, blocks: int = 0, variant: int = 0, status: Optional[Status] = None,
-                 device="cuda", map_floats: Optional[int] = None):
+                 device="cuda", map_floats: Optional[int] = None, persistent: bool = False):
         L = N.load()
         self._keep = [items, grids]
         self.n_items = len(items)
@@ -565,7 +565,7 @@ class Plan:
         self.status = status if status is not None else Status(device)
         opts = N.PlanOpts(lanes=int(lanes), chunk=int(chunk), k_item=self.k_item, k_band=self.k_band,
                           use_graph=int(bool(use_graph)), lpt=int(bool(lpt)), blocks=int(blocks),
-                          variant=int(variant))
+                          variant=int(variant), persistent=int(bool(persistent)))
         h = ctypes.c_void_p()
         check(L.bsh_plan_create(arr_i, self.n_items, arr_g, len(grids), self.n_bands, ctypes.byref(opts),
                                 _ptr(self.maps), self.maps.numel(), _ptr(self.item_score),

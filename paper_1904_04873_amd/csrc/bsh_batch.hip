@@ -23,7 +23,9 @@ struct bsh_plan {
     int32_t n_items = 0, n_bands = 0, k_item = 0, k_band = 0;
     int32_t lanes = bsh::kDefaultLanes, chunk = bsh::kDefaultChunk, blocks = 0;
     bool use_graph = false;
+    bool persistent = false;
     int32_t mode = 2;
+    int32_t n_words = 1;                          // widest staged row of any item (sizes the rows' LDS)
     int64_t n_units = 0, max_band_len = 0;
     std::vector<bsh::ItemDesc> items;            // host copies (plain mode)
     std::vector<bsh::PlainLaunch> plain;          // per-item plain launch parameters
@@ -133,7 +135,7 @@ int enqueue_batched(bsh_plan* p, hipStream_t s, bool count_only)
         const int64_t u0 = p->pass_unit[q], nu = p->pass_unit[q + 1] - u0;
         if (nu > 0) {
             rc = launch_batch(p->d_items, p->d_units + u0, nu, p->d_counter + q, p->blocks, p->lanes, p->chunk,
-                              p->mode, s);
+                              p->mode, p->n_words, p->persistent, s);
             if (rc) return rc;
         }
         if (p->k_item > 0 && !count_only) {
@@ -216,6 +218,7 @@ extern "C" int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh
     for (int32_t q = 0; q < n_grids; ++q) ecc = std::max(ecc, ecc_mode(&grids[q]));
     p->mode = kernel_mode(o.variant, false) + ecc;
     p->use_graph = o.use_graph != 0;
+    p->persistent = o.persistent != 0;
     p->maps = maps;
     p->band_score = band_score;
     p->band_index = band_index;
@@ -274,7 +277,9 @@ extern "C" int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh
             const bsh_grid& g = grids[it.grid];
             fill_desc(p->items[i], &it.seg, &g, it.sky_lo, it.n_sky, nullptr, maps + p->item_start[i], status);
             std::vector<int64_t> groups(g.n_per);
-            const int64_t tiles = plan_tiles(&g, lanes, tile_start.data(), groups.data());
+            const int tt = tile_templates(p->mode, lanes);
+            const int64_t tiles = plan_tiles(&g, tt, tile_start.data(), groups.data());
+            p->n_words = std::max(p->n_words, p->items[i].n_words);
             PlainLaunch& pl = p->plain[i];
             std::memset(&pl, 0, sizeof(pl));
             pl.d = p->items[i];
@@ -284,7 +289,7 @@ extern "C" int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh
             if (it.seg.n_seg == 0) continue;   // the map is zero-filled at run time
             for (int32_t sk = 0; sk < it.n_sky; ++sk)
                 for (int32_t ip = 0; ip < g.n_per; ++ip) {
-                    const int64_t nt = (groups[ip] + lanes - 1) / lanes;
+                    const int64_t nt = (groups[ip] + tt - 1) / tt;
                     for (int64_t t = 0; t < nt; ++t) {
                         pu.push_back(WorkUnit{i, sk, ip, (int32_t)t});
                         cost.push_back(it.seg.n_seg);
@@ -315,8 +320,19 @@ extern "C" int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh
         delete p;
         return BSH_EHIP;
     }
-    p->blocks = std::max(1, n_cu) * batch_blocks_per_cu(lanes, chunk, p->mode);
+    // persistent form: CUs x resident blocks; else the largest pass's unit count
+    p->blocks = std::max(1, n_cu) * batch_blocks_per_cu(lanes, chunk, p->mode, p->n_words);
     if (o.blocks > 0) p->blocks = o.blocks;
+    if (!p->persistent) {
+        int64_t widest = 0;
+        for (int32_t q = 0; q < n_passes; ++q) widest = std::max(widest, p->pass_unit[q + 1] - p->pass_unit[q]);
+        if (widest > 0x7fffffff) {
+            set_error("more than 2^31 - 1 units in one pass");
+            delete p;
+            return BSH_EINVAL;
+        }
+        p->blocks = (int32_t)widest;
+    }
 
     rc = dev_alloc(&p->d_items, n_items);
     if (!rc) rc = dev_alloc(&p->d_units, units.size());
@@ -407,7 +423,7 @@ extern "C" int bsh_plan_run_plain(bsh_plan* p, bsh_stream stream)
         if (p->items[i].n_seg == 0)
             rc = zero_words(p->maps + p->item_start[i], len, s);
         else
-            rc = launch_plain(p->plain[i], p->plain_blocks[i], p->lanes, p->chunk, p->mode, s);
+            rc = launch_plain(p->plain[i], p->plain_blocks[i], p->lanes, p->chunk, p->mode, p->items[i].n_words, s);
         if (rc) return rc;
         if (p->k_item > 0) {
             // one list per item, from that item's own launch, indices tagged with the item

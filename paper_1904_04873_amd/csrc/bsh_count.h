@@ -12,6 +12,7 @@ constexpr int kDefaultChunk = 256;   // segments staged per LDS pass
 constexpr int kFlush = 64;           // segments per FP32 partial sum
 constexpr int kRowPad = 4;           // zero words staged after each row (a failed track reads them)
 constexpr int kNF = BSH_MAX_F0;
+constexpr int kEccMode = 3;          // kernel modes kEccMode.. are the ELL1 forms of modes 0..
 
 // Everything a tile needs about its work item (one segment set, one band grid, a run of
 // sky pixels of that grid, and the item's output map).
@@ -65,25 +66,22 @@ constexpr int kFlushGroups = 64;     // eight-segment groups per register partia
 
 // Per staged segment: D cos(W t), D sin(W t) and the Doppler factor D of the tile's pixel, and
 // for the ELL1 track D cos(2 W t), D sin(2 W t) (zero-length arrays on a circular grid, which
-// leave the layout as it is).  The rows come first, so that a window's reads reach them with the
-// small immediate offsets of the paired LDS reads; the segment tables follow, so that their
-// addresses fit the 16-bit immediate offset of an LDS read at every chunk size (no address
-// moves per segment).
+// leave the layout as it is); for the table variant the subset-sum tables.  The bit-packed rows
+// follow the structure in LDS, sized at launch for the item's row width (row_bytes), so that a
+// block of the table variant at 256-segment chunks fits three times into a CU's 160 KB.
 template <int kChunk, bool kEcc>
 struct TileSmemLut {
-    uint32_t row[kChunk * (BSH_MAX_WORDS + kRowPad)];
+    float T8[(kChunk / kGroup8) * 256];
     double DC[kChunk];
     double DS[kChunk];
     double D[kChunk];
     double DC2[kEcc ? kChunk : 0];
     double DS2[kEcc ? kChunk : 0];
-    float T8[(kChunk / kGroup8) * 256];
     float T[(kChunk / kGroup) * 16];
 };
 
 template <int kChunk, bool kEcc>
 struct TileSmem {
-    uint32_t row[kChunk * (BSH_MAX_WORDS + kRowPad)];
     double DC[kChunk];
     double DS[kChunk];
     double D[kChunk];
@@ -92,17 +90,26 @@ struct TileSmem {
     float W[kChunk];
 };
 
+// LDS bytes of the staged rows of one chunk: kRowPad zero words after each row's n_words.
+inline size_t row_bytes(int chunk, int n_words) { return (size_t)chunk * (size_t)(n_words + kRowPad) * 4u; }
+
+// Binary templates per tile: the table variant gives each template a pair of lanes.
+inline int tile_templates(int mode, int lanes) { return mode % kEccMode == 2 ? lanes / 2 : lanes; }
+
 int64_t plan_tiles(const bsh_grid* g, int lanes, int32_t* tile_start, int64_t* group_sizes);
 void fill_desc(ItemDesc& d, const bsh_segments* seg, const bsh_grid* grid, int32_t sky_lo,
                int32_t n_sky, uint32_t* count_out, float* wsum_out, int32_t* status);
 int zero_words(void* p, int64_t n_words, hipStream_t stream);
 // mode: 0 select-and-add (weighted sums), 1 select-and-add with counts, 2 subset-sum tables;
 // plus kEccMode for the same on the ELL1 track
-constexpr int kEccMode = 3;
-int launch_plain(const PlainLaunch& p, int64_t blocks, int lanes, int chunk, int mode, hipStream_t stream);
+// n_words: the widest staged row of the launch (sizes the rows' LDS region).
+int launch_plain(const PlainLaunch& p, int64_t blocks, int lanes, int chunk, int mode, int n_words,
+                 hipStream_t stream);
+// persistent: blocks pull units from *counter (zeroed beforehand); else one block per unit.
 int launch_batch(const ItemDesc* items, const WorkUnit* units, int64_t n_units, uint32_t* counter,
-                 int blocks, int lanes, int chunk, int mode, hipStream_t stream);
-int batch_blocks_per_cu(int lanes, int chunk, int mode);
+                 int blocks, int lanes, int chunk, int mode, int n_words, bool persistent, hipStream_t stream);
+int batch_blocks_per_cu(int lanes, int chunk, int mode, int n_words);
+int allow_lds(const void* kernel, size_t bytes);
 int kernel_mode(int variant, bool with_count);
 // kEccMode for a grid with an eccentricity pair, else 0 (added to kernel_mode's value)
 int ecc_mode(const bsh_grid* g);

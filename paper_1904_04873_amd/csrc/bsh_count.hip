@@ -2,6 +2,8 @@
 // one work item.  The tile body is in bsh_count_tile.h.
 #include <algorithm>
 #include <cstring>
+#include <mutex>
+#include <unordered_map>
 
 #include "bsh_count_tile.h"
 
@@ -10,7 +12,7 @@ namespace bsh {
 template <int kMode, int kChunk>
 __global__ __launch_bounds__(kMaxLanes, min_blocks<kMode>()) void hough_count_kernel(const PlainLaunch p)
 {
-    __shared__ __align__(16) unsigned char smem[smem_bytes<kMode, kChunk>()];
+    extern __shared__ __align__(16) unsigned char smem[];
     const int blk = blockIdx.x;
     const int s = blk / p.tiles_per_sky;
     const int t = blk - s * p.tiles_per_sky;
@@ -89,13 +91,38 @@ int zero_words(void* p, int64_t n_words, hipStream_t stream)
     return check_launch("zero fill");
 }
 
-int launch_plain(const PlainLaunch& p, int64_t blocks, int lanes, int chunk, int mode, hipStream_t stream)
+int launch_plain(const PlainLaunch& p, int64_t blocks, int lanes, int chunk, int mode, int n_words,
+                 hipStream_t stream)
 {
+    const size_t lds = smem_bytes_of(mode, chunk, n_words);
+    int rc = BSH_OK;
 #define BSH_LAUNCH_PLAIN(M, C)                                                                \
-    hipLaunchKernelGGL((hough_count_kernel<M, C>), dim3((unsigned)blocks), dim3(lanes), 0, stream, p)
+    rc = allow_lds((const void*)hough_count_kernel<M, C>, lds);                                \
+    if (rc) return rc;                                                                        \
+    hipLaunchKernelGGL((hough_count_kernel<M, C>), dim3((unsigned)blocks), dim3(lanes), lds, stream, p)
     BSH_DISPATCH(mode, chunk, BSH_LAUNCH_PLAIN)
 #undef BSH_LAUNCH_PLAIN
     return check_launch("bsh_hough_count");
+}
+
+// Dynamic LDS above the default per-block limit has to be allowed per kernel; each kernel is
+// raised once to the largest size asked for so far (so a launch under stream capture, after the
+// plan has sized its blocks, makes no runtime call).
+int allow_lds(const void* kernel, size_t bytes)
+{
+    if (bytes <= 64 * 1024) return BSH_OK;
+    static std::mutex mu;
+    static std::unordered_map<const void*, size_t> allowed;
+    std::lock_guard<std::mutex> lock(mu);
+    size_t& have = allowed[kernel];
+    if (bytes <= have) return BSH_OK;
+    const hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) {
+        set_error("allowing %zu bytes of LDS: %s", bytes, hipGetErrorString(e));
+        return BSH_EHIP;
+    }
+    have = bytes;
+    return BSH_OK;
 }
 
 int kernel_mode(int variant, bool with_count)
@@ -133,7 +160,8 @@ extern "C" int bsh_hough_count_ex(const bsh_segments* seg, const bsh_grid* grid,
     PlainLaunch p;
     std::memset(&p, 0, sizeof(p));
     fill_desc(p.d, seg, grid, 0, grid->n_sky, count_out, wsum_out, status);
-    const int64_t tiles = plan_tiles(grid, lanes, p.tile_start, nullptr);
+    const int mode = kernel_mode(variant, count_out != nullptr) + ecc_mode(grid);
+    const int64_t tiles = plan_tiles(grid, tile_templates(mode, lanes), p.tile_start, nullptr);
     p.tiles_per_sky = (int32_t)tiles;
     const int64_t blocks = tiles * grid->n_sky;
     if (tiles == 0 || p.d.n_bin == 0) return BSH_OK;
@@ -146,7 +174,7 @@ extern "C" int bsh_hough_count_ex(const bsh_segments* seg, const bsh_grid* grid,
         if (rc) return rc;
         return zero_words(count_out, count_out ? n_t : 0, s);
     }
-    return launch_plain(p, blocks, lanes, chunk, kernel_mode(variant, count_out != nullptr) + ecc_mode(grid), s);
+    return launch_plain(p, blocks, lanes, chunk, mode, p.d.n_words, s);
 }
 
 extern "C" int bsh_hough_count(const bsh_segments* seg, const bsh_grid* grid, uint32_t* count_out,
@@ -254,7 +282,8 @@ extern "C" int bsh_hough_count_topk(const bsh_segments* seg, const bsh_grid* gri
     hipStream_t s = (hipStream_t)stream;
     const bool single = np >= grid->n_sky;
 
-    int32_t lanes = kDefaultLanes, chunk = kDefaultChunk;
+    const int32_t lanes = kDefaultLanes, chunk = kDefaultChunk;
+    const int mode = kernel_mode(BSH_VARIANT_AUTO, false) + ecc_mode(grid);
     PlainLaunch p;
     for (int64_t c0 = 0; c0 < grid->n_sky; c0 += np) {
         const int32_t nc = (int32_t)std::min<int64_t>(np, grid->n_sky - c0);
@@ -262,12 +291,12 @@ extern "C" int bsh_hough_count_topk(const bsh_segments* seg, const bsh_grid* gri
         std::memset(&p, 0, sizeof(p));
         fill_desc(p.d, seg, grid, (int32_t)c0, nc, nullptr, map, status);
         if (seg->weight_per_sky) p.d.w = seg->weight + c0 * seg->n_seg;
-        const int64_t tiles = plan_tiles(grid, lanes, p.tile_start, nullptr);
+        const int64_t tiles = plan_tiles(grid, tile_templates(mode, lanes), p.tile_start, nullptr);
         p.tiles_per_sky = (int32_t)tiles;
         if (seg->n_seg == 0 || tiles == 0)
             rc = zero_words(map, n_t, s);
         else
-            rc = launch_plain(p, tiles * nc, lanes, chunk, kernel_mode(BSH_VARIANT_AUTO, false) + ecc_mode(grid), s);
+            rc = launch_plain(p, tiles * nc, lanes, chunk, mode, p.d.n_words, s);
         if (rc) return rc;
         const int64_t first = c0 * per_sky;
         if (single)

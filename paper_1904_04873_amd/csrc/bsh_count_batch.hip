@@ -1,6 +1,11 @@
-// Stage-1 weighted number count, persistent launch form of the batched plan: blocks pull
-// (item, pixel, period, tile) units from a queue until it is empty.  The tile body is in
-// bsh_count_tile.h.
+// Stage-1 weighted number count, the batched plan's launch forms over a queue of (item, pixel,
+// period, tile) units: one block per unit, dispatched in queue order (the default), or
+// persistent blocks that pull units from an atomic queue counter until it is empty.  Both run
+// the same tile body (bsh_count_tile.h) and give the same maps.  Measured on the table variant:
+// the persistent loop keeps the tile's loop-invariant values live across units and takes 212
+// registers (two waves per SIMD), one unit per block takes about 160 (three waves), and the
+// hardware dispatcher hands blocks to CUs in queue order as earlier ones finish, which is the
+// balance the queue counter gives.
 #include "bsh_count_tile.h"
 
 namespace bsh {
@@ -10,12 +15,14 @@ __global__ __launch_bounds__(kMaxLanes, min_blocks<kMode>()) void hough_batch_ke
                                                                const WorkUnit* __restrict__ units,
                                                                int64_t n_units, uint32_t* counter)
 {
-    __shared__ __align__(16) unsigned char smem[smem_bytes<kMode, kChunk>()];
+    extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int64_t next;
     for (;;) {
         if (threadIdx.x == 0) next = (int64_t)atomicAdd(counter, 1u);
         __syncthreads();
-        const int64_t u = next;
+        // the unit index is the block's: read as a wave-uniform value, so that the unit and its
+        // item descriptor load into scalar registers
+        const int64_t u = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)next);
         __syncthreads();
         if (u >= n_units) break;
         const WorkUnit w = units[u];
@@ -24,22 +31,47 @@ __global__ __launch_bounds__(kMaxLanes, min_blocks<kMode>()) void hough_batch_ke
     }
 }
 
-int launch_batch(const ItemDesc* items, const WorkUnit* units, int64_t n_units, uint32_t* counter,
-                 int blocks, int lanes, int chunk, int mode, hipStream_t stream)
+template <int kMode, int kChunk>
+__global__ __launch_bounds__(kMaxLanes, min_blocks<kMode>()) void hough_unit_kernel(const ItemDesc* __restrict__ items,
+                                                              const WorkUnit* __restrict__ units)
 {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const WorkUnit w = units[blockIdx.x];
+    const ItemDesc d = items[w.item];
+    run_tile<kMode, kChunk>(d, w.sky, w.ip, w.tile, smem);
+}
+
+int launch_batch(const ItemDesc* items, const WorkUnit* units, int64_t n_units, uint32_t* counter,
+                 int blocks, int lanes, int chunk, int mode, int n_words, bool persistent, hipStream_t stream)
+{
+    const size_t lds = smem_bytes_of(mode, chunk, n_words);
+    int rc = BSH_OK;
+    if (!persistent && n_units > 0x7fffffff) return fail_inval("more than 2^31 - 1 units in one pass");
 #define BSH_LAUNCH_BATCH(M, C)                                                                \
-    hipLaunchKernelGGL((hough_batch_kernel<M, C>), dim3(blocks), dim3(lanes), 0, stream, items, units, \
-                       n_units, counter)
+    if (persistent) {                                                                         \
+        rc = allow_lds((const void*)hough_batch_kernel<M, C>, lds);                            \
+        if (rc) return rc;                                                                    \
+        hipLaunchKernelGGL((hough_batch_kernel<M, C>), dim3(blocks), dim3(lanes), lds, stream, items, units, \
+                           n_units, counter);                                                 \
+    } else {                                                                                  \
+        rc = allow_lds((const void*)hough_unit_kernel<M, C>, lds);                             \
+        if (rc) return rc;                                                                    \
+        hipLaunchKernelGGL((hough_unit_kernel<M, C>), dim3((unsigned)n_units), dim3(lanes), lds, stream, items, \
+                           units);                                                            \
+    }
     BSH_DISPATCH(mode, chunk, BSH_LAUNCH_BATCH)
 #undef BSH_LAUNCH_BATCH
     return check_launch("batched count");
 }
 
-int batch_blocks_per_cu(int lanes, int chunk, int mode)
+int batch_blocks_per_cu(int lanes, int chunk, int mode, int n_words)
 {
     int n = 0;
     hipError_t e = hipSuccess;
-#define BSH_OCC(M, C) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, hough_batch_kernel<M, C>, lanes, 0)
+    const size_t lds = smem_bytes_of(mode, chunk, n_words);
+#define BSH_OCC(M, C)                                                                         \
+    if (allow_lds((const void*)hough_batch_kernel<M, C>, lds) == BSH_OK)                       \
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, hough_batch_kernel<M, C>, lanes, lds)
     switch (mode * 1000 + chunk) {
     case 128: BSH_OCC(0, 128); break;
     case 256: BSH_OCC(0, 256); break;

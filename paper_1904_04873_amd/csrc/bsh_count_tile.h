@@ -23,7 +23,7 @@
 // every template still reads the bin of its own exact track.
 //
 // Accumulation: either select-and-add (each bit selects its weight; optional uint32 counts)
-// or subset-sum tables over groups of segments (see count_tile_lut).
+// or subset-sum tables over groups of segments (see count_tile_pair).
 #pragma once
 
 #include "bsh_count.h"
@@ -167,7 +167,7 @@ __device__ __forceinline__ bool band_mask(const uint32_t* row, double G, double 
 
 template <bool kCount, int kChunk, bool kEcc>
 __device__ __forceinline__ void count_tile(const ItemDesc& d, int s, int ip, int64_t tile,
-                                           TileSmem<kChunk, kEcc>& sm)
+                                           TileSmem<kChunk, kEcc>& sm, uint32_t* row)
 {
     const int tid = threadIdx.x;
     const int lanes = blockDim.x;
@@ -232,7 +232,7 @@ __device__ __forceinline__ void count_tile(const ItemDesc& d, int s, int ip, int
         for (int e = tid; e < nj * nwp; e += lanes) {
             const int jj = e / nwp;
             const int wd = e - jj * nwp;
-            sm.row[e] = wd < d.n_words ? d.bits[(j0 + jj) * d.n_words + wd] : 0u;
+            row[e] = wd < d.n_words ? d.bits[(j0 + jj) * d.n_words + wd] : 0u;
         }
         __syncthreads();
         if (!active) continue;
@@ -241,7 +241,7 @@ __device__ __forceinline__ void count_tile(const ItemDesc& d, int s, int ip, int
             uint32_t m0, m1, m2;
             const double G = tile_G<kEcc>(sm.DC[jj], sm.DS[jj], sm.D[jj], kEcc ? sm.DC2[jj] : 0.0,
                                           kEcc ? sm.DS2[jj] : 0.0, Ac, As, Ac2, As2);
-            if (!band_mask(sm.row + jj * nwp, G, F0, FL, klo, klo + d.n_bins, last, 32 * d.n_words, m0, m1, m2,
+            if (!band_mask(row + jj * nwp, G, F0, FL, klo, klo + d.n_bins, last, 32 * d.n_words, m0, m1, m2,
                            bad_range, bad_model))
                 continue;
 
@@ -276,24 +276,44 @@ __device__ __forceinline__ void count_tile(const ItemDesc& d, int s, int ip, int
 
 
 // Table variant of the weighted count.  Segments are taken in groups of eight; a 256-entry
-// table per group holds every subset sum of the group's eight weights, so that for each f0
-// bin the eight peak bits of the group form a byte index and one table read and one add
-// replace eight select-and-add steps.  The table is built from the 16-entry subset-sum tables
-// of the group's two halves, T8[b] = T_first[b & 15] + T_second[b >> 4].  The byte indices of
-// all 90 bins come from the eight 96-bit masks by a bit interleave of each half, word A[w][r]
-// holding in nibble n the half's four bits of bin 32w + 4n + r, and a merge of the two halves'
-// nibbles into bytes.  The 90 register partial sums (at most kFlushGroups groups each) are
-// folded into the lane's own slots of the output map, which keeps the register footprint
-// small enough for two waves per SIMD; the error of the two-level sum stays below
-// (kFlushGroups + 4 + n_seg / (8 kFlushGroups)) FP32 ulps of the total.
+// table per group holds every subset sum of the group's eight weights, so that for each f0 bin
+// the eight peak bits of the group form a byte index and one table read and one add replace
+// eight select-and-add steps.  The table is built from the 16-entry subset-sum tables of the
+// group's two halves, T8[b] = T_first[b & 15] + T_second[b >> 4].
+//
+// Two adjacent lanes share one binary template.  With bin i = 32 w + 4 n + r (w = 0..2,
+// n = 0..7, r = 0..3), lane h = lane & 1 owns the bins with r = 2h, 2h + 1 (46 and 44 of the
+// band's 90), so it keeps 46 register partial sums instead of 90, which leaves room for three
+// waves per SIMD.  Per group lane h evaluates the tracks of the group's segments 4h .. 4h + 3,
+// transposes their four 96-bit masks (a 4 x 4 bit transpose per nibble column: word A[w][r] holds
+// in nibble n the four segments' bits of bin 32 w + 4 n + r), and the pair swaps the two words
+// A[w][r] of the partner's r values (a cross-lane move inside each pair of lanes).  Each lane then
+// merges the first four segments' nibbles (from lane 0) and the last four's (from lane 1) into
+// bytes, and every one of its bins costs one byte extraction, one table address and one FP32 add
+// per eight segments.  The register partial sums (at most kFlushGroups groups each) are folded
+// into the lane's own slots of the output map, bounding the FP32 error by
+// (kFlushGroups + 4 + n_seg / (8 kFlushGroups)) ulps of the total.  Per bin the table entries and
+// the order of the additions do not depend on the tile shape or on how lanes share templates.
+constexpr int kPairSlots = 46;   // (w, k, n) with k = r - 2h, minus w = 2, n = 7
+
+// (w, k, n) -> 0 .. 45: sixteen slots per word for w = 0, 1, fourteen (n < 7) for w = 2
+__device__ __forceinline__ constexpr int pair_slot(int w, int k, int n) { return w < 2 ? (w * 2 + k) * 8 + n : 32 + k * 7 + n; }
+
+__device__ __forceinline__ uint32_t pair_swap(uint32_t x)
+{
+    // quad_perm [1, 0, 3, 2]: every lane takes its pair partner's value
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);
+}
+
 template <int kChunk, bool kEcc>
-__device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip, int64_t tile,
-                                               TileSmemLut<kChunk, kEcc>& sm)
+__device__ __forceinline__ void count_tile_pair(const ItemDesc& d, int s, int ip, int64_t tile,
+                                                TileSmemLut<kChunk, kEcc>& sm, uint32_t* row)
 {
     static_assert(kChunk % kGroup8 == 0, "chunks hold whole groups");
     const int tid = threadIdx.x;
     const int lanes = blockDim.x;
-    const int64_t q = tile * lanes + tid;
+    const int h = tid & 1;
+    const int64_t q = tile * (lanes >> 1) + (tid >> 1);
 
     int ia = -1;
     int64_t j = 0, cum = 0;
@@ -322,20 +342,26 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
     const int klo = (int)d.k_lo;
     const int nwp = d.n_words + kRowPad;
 
-    float acc[kNF];
+    float acc[kPairSlots];
 #pragma unroll
-    for (int i = 0; i < kNF; ++i) acc[i] = 0.f;
+    for (int i = 0; i < kPairSlots; ++i) acc[i] = 0.f;
     int since_flush = 0;
     bool flushed = false;
     float* out = d.wsum_out + ((int64_t)s * d.n_bin + b) * d.n_f0;
     const int nf = d.n_f0;
-    // fold the register partial sums into the lane's output slots
     auto flush = [&]() {
 #pragma unroll
-        for (int i = 0; i < kNF; ++i) {
-            if (i < nf) out[i] = flushed ? out[i] + acc[i] : acc[i];
-            acc[i] = 0.f;
-        }
+        for (int w = 0; w < 3; ++w)
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int n = 0; n < 8; ++n) {
+                    if (w == 2 && n == 7) continue;
+                    const int sl = pair_slot(w, k, n);
+                    const int i = 32 * w + 4 * n + 2 * h + k;
+                    if (i < nf) out[i] = flushed ? out[i] + acc[sl] : acc[sl];
+                    acc[sl] = 0.f;
+                }
         flushed = true;
     };
     bool bad_range = false, bad_model = false;
@@ -345,8 +371,6 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
         const int ng8 = (nj + kGroup8 - 1) / kGroup8;
         const int ng = 2 * ng8;
         __syncthreads();
-        // slots past the chunk's last segment (up to a whole group) repeat its tables with an
-        // empty row and zero weight, so that every group holds four in-range segments
         for (int jj = tid; jj < ng * kGroup; jj += lanes) {
             const int64_t J = j0 + min(jj, nj - 1);
             double sp, cp;
@@ -365,10 +389,9 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
         for (int e = tid; e < ng * kGroup * nwp; e += lanes) {
             const int jj = e / nwp;
             const int wd = e - jj * nwp;
-            sm.row[e] = (jj < nj && wd < d.n_words) ? d.bits[(j0 + jj) * d.n_words + wd] : 0u;
+            row[e] = (jj < nj && wd < d.n_words) ? d.bits[(j0 + jj) * d.n_words + wd] : 0u;
         }
         for (int g = tid; g < ng; g += lanes) {
-            // subset sums in segment order; missing segments of a last partial group weigh 0
             float w4[kGroup];
 #pragma unroll
             for (int u = 0; u < kGroup; ++u) {
@@ -393,29 +416,26 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
         __syncthreads();
         if (!active) continue;
 
-        // A[w][r] of the four segments of group g: bit (4n + u) holds bit (4n + r) of segment
-        // u's 96-bit band mask word w
-        auto group_bits = [&](int g, uint32_t (&A)[3][4]) {
-            // the four tracks and windows without branches (independent chains the scheduler
-            // can interleave), then the rare f0-shift steps
+        for (int g8 = 0; g8 < ng8; ++g8) {
+            // this lane's half of the group: segments 4h .. 4h + 3
+            const int hg = 2 * g8 + h;
             uint32_t mk[kGroup][3];
             BandTrack tr[kGroup];
 #pragma unroll
             for (int u = 0; u < kGroup; ++u) {
-                const int jj = g * kGroup + u;
+                const int jj = hg * kGroup + u;
                 const double G = tile_G<kEcc>(sm.DC[jj], sm.DS[jj], sm.D[jj], kEcc ? sm.DC2[jj] : 0.0,
                                               kEcc ? sm.DS2[jj] : 0.0, Ac, As, Ac2, As2);
                 tr[u] = band_track(G, F0, FL, klo, klo + d.n_bins, last, bad_range, bad_model);
             }
 #pragma unroll
             for (int u = 0; u < kGroup; ++u)
-                band_window(sm.row + (g * kGroup + u) * nwp, tr[u], klo, 32 * d.n_words, mk[u][0], mk[u][1],
+                band_window(row + (hg * kGroup + u) * nwp, tr[u], klo, 32 * d.n_words, mk[u][0], mk[u][1],
                             mk[u][2]);
 #pragma unroll
             for (int u = 0; u < kGroup; ++u)
                 if (tr[u].ok && tr[u].span != last) band_step(tr[u], F0, last, mk[u][0], mk[u][1], mk[u][2]);
-            // every nibble column of the 4 x 32 bit matrix (mk[0..3][w]) transposed: swap the
-            // off-diagonal 2 x 2 blocks, then the off-diagonal bits of each 2 x 2 block
+            const float* T8 = sm.T8 + g8 * 256;
 #pragma unroll
             for (int w = 0; w < 3; ++w) {
                 uint32_t x0 = mk[0][w], x1 = mk[1][w], x2 = mk[2][w], x3 = mk[3][w];
@@ -424,40 +444,23 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
                 t = ((x1 >> 2) ^ x3) & 0x33333333u; x3 ^= t; x1 ^= t << 2;
                 t = ((x0 >> 1) ^ x1) & 0x55555555u; x1 ^= t; x0 ^= t << 1;
                 t = ((x2 >> 1) ^ x3) & 0x55555555u; x3 ^= t; x2 ^= t << 1;
-                A[w][0] = x0;
-                A[w][1] = x1;
-                A[w][2] = x2;
-                A[w][3] = x3;
-            }
-        };
-
-        for (int g8 = 0; g8 < ng8; ++g8) {
-            uint32_t L[3][4], H[3][4];
-            group_bits(2 * g8, L);
-            group_bits(2 * g8 + 1, H);
-            // byte j of b0 (b1) indexes the eight segments' bits of bin 32w + 8j + r
-            // (32w + 8j + 4 + r): low nibble from the first four segments, high from the rest
-            const float* T8 = sm.T8 + g8 * 256;
-            float v[2][8];
+                // A[w][r] = x_r: this lane's four segments, every bin
+                const uint32_t A[4] = {x0, x1, x2, x3};
 #pragma unroll
-            for (int k = 0; k <= 12; ++k) {
-                if (k < 12) {
-                    const int w = k >> 2, r = k & 3;
-                    const uint32_t b0 = (L[w][r] & 0x0f0f0f0fu) | ((H[w][r] << 4) & 0xf0f0f0f0u);
-                    const uint32_t b1 = ((L[w][r] >> 4) & 0x0f0f0f0fu) | (H[w][r] & 0xf0f0f0f0u);
+                for (int k = 0; k < 2; ++k) {
+                    // the first four segments' nibbles (L) come from lane 0, the last four's (H)
+                    // from lane 1: lane 0 takes its own word of r = k and lane 1's, lane 1 takes
+                    // lane 0's word of r = 2 + k and its own
+                    const uint32_t from_partner_hi = pair_swap(A[2 + k]);   // every lane swaps,
+                    const uint32_t from_partner_lo = pair_swap(A[k]);       // then each selects
+                    const uint32_t L = h == 0 ? A[k] : from_partner_hi;
+                    const uint32_t H = h == 1 ? A[2 + k] : from_partner_lo;
+                    const uint32_t b0 = (L & 0x0f0f0f0fu) | ((H << 4) & 0xf0f0f0f0u);
+                    const uint32_t b1 = ((L >> 4) & 0x0f0f0f0fu) | (H & 0xf0f0f0f0u);
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        if (32 * w + 8 * j + r < kNF) v[k & 1][2 * j] = T8[(b0 >> (8 * j)) & 255u];
-                        if (32 * w + 8 * j + 4 + r < kNF) v[k & 1][2 * j + 1] = T8[(b1 >> (8 * j)) & 255u];
-                    }
-                }
-                if (k > 0) {
-                    const int w = (k - 1) >> 2, r = (k - 1) & 3;
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int i = 32 * w + 8 * j + r;
-                        if (i < kNF) acc[i] += v[(k - 1) & 1][2 * j];
-                        if (i + 4 < kNF) acc[i + 4] += v[(k - 1) & 1][2 * j + 1];
+                    for (int jb = 0; jb < 4; ++jb) {
+                        acc[pair_slot(w, k, 2 * jb)] += T8[(b0 >> (8 * jb)) & 255u];
+                        if (!(w == 2 && jb == 3)) acc[pair_slot(w, k, 2 * jb + 1)] += T8[(b1 >> (8 * jb)) & 255u];
                     }
                 }
             }
@@ -475,25 +478,29 @@ __device__ __forceinline__ void count_tile_lut(const ItemDesc& d, int s, int ip,
 // kMode % kEccMode: 0 = select-and-add, weighted sums only; 1 = select-and-add with counts;
 // 2 = table.  kMode >= kEccMode: the same on the ELL1 track of the item's eccentricity pair.
 template <int kMode, int kChunk>
-__device__ __forceinline__ void run_tile(const ItemDesc& d, int s, int ip, int64_t tile, void* smem)
+constexpr size_t fixed_smem_bytes()
+{
+    constexpr bool kEcc = kMode >= kEccMode;
+    constexpr size_t b = kMode % kEccMode == 2 ? sizeof(TileSmemLut<kChunk, kEcc>) : sizeof(TileSmem<kChunk, kEcc>);
+    return (b + 15) & ~(size_t)15;
+}
+
+// The tile's LDS: the fixed structure, then the rows.
+template <int kMode, int kChunk>
+__device__ __forceinline__ void run_tile(const ItemDesc& d, int s, int ip, int64_t tile, unsigned char* smem)
 {
     constexpr int kM = kMode % kEccMode;
     constexpr bool kEcc = kMode >= kEccMode;
+    uint32_t* row = reinterpret_cast<uint32_t*>(smem + fixed_smem_bytes<kMode, kChunk>());
     if constexpr (kM == 2)
-        count_tile_lut<kChunk, kEcc>(d, s, ip, tile, *reinterpret_cast<TileSmemLut<kChunk, kEcc>*>(smem));
+        count_tile_pair<kChunk, kEcc>(d, s, ip, tile, *reinterpret_cast<TileSmemLut<kChunk, kEcc>*>(smem), row);
     else
-        count_tile<kM == 1, kChunk, kEcc>(d, s, ip, tile, *reinterpret_cast<TileSmem<kChunk, kEcc>*>(smem));
+        count_tile<kM == 1, kChunk, kEcc>(d, s, ip, tile, *reinterpret_cast<TileSmem<kChunk, kEcc>*>(smem), row);
 }
 
-template <int kMode, int kChunk>
-constexpr size_t smem_bytes()
-{
-    constexpr bool kEcc = kMode >= kEccMode;
-    return kMode % kEccMode == 2 ? sizeof(TileSmemLut<kChunk, kEcc>) : sizeof(TileSmem<kChunk, kEcc>);
-}
-
-// Waves per SIMD the kernel is built for: two for the table variant (its 90 partial sums live in
-// registers), one for the select variants.
+// Launch-bounds hint of the blocks per CU: two for the table variant, one for the select
+// variants (whose 90 partial sums, and 90 counts, fill the registers).  The table variant's
+// register allocation comes out at about 155 registers, so three waves per SIMD fit.
 template <int kMode>
 constexpr int min_blocks() { return kMode % kEccMode == 2 ? 2 : 1; }
 
@@ -520,5 +527,36 @@ constexpr int min_blocks() { return kMode % kEccMode == 2 ? 2 : 1; }
     case 5512: F(5, 512); break;                                                              \
     default: return fail_inval("kernel mode / chunk");                                        \
     }
+
+// LDS bytes of one block: the fixed structure and the rows of n_words words (0 for an unknown
+// mode or chunk).
+#define BSH_FIXED_SMEM(M, C) fixed = fixed_smem_bytes<M, C>()
+inline size_t smem_bytes_of(int mode, int chunk, int n_words)
+{
+    size_t fixed = 0;
+    switch (mode * 1000 + chunk) {
+    case 128: BSH_FIXED_SMEM(0, 128); break;
+    case 256: BSH_FIXED_SMEM(0, 256); break;
+    case 512: BSH_FIXED_SMEM(0, 512); break;
+    case 1128: BSH_FIXED_SMEM(1, 128); break;
+    case 1256: BSH_FIXED_SMEM(1, 256); break;
+    case 1512: BSH_FIXED_SMEM(1, 512); break;
+    case 2128: BSH_FIXED_SMEM(2, 128); break;
+    case 2256: BSH_FIXED_SMEM(2, 256); break;
+    case 2512: BSH_FIXED_SMEM(2, 512); break;
+    case 3128: BSH_FIXED_SMEM(3, 128); break;
+    case 3256: BSH_FIXED_SMEM(3, 256); break;
+    case 3512: BSH_FIXED_SMEM(3, 512); break;
+    case 4128: BSH_FIXED_SMEM(4, 128); break;
+    case 4256: BSH_FIXED_SMEM(4, 256); break;
+    case 4512: BSH_FIXED_SMEM(4, 512); break;
+    case 5128: BSH_FIXED_SMEM(5, 128); break;
+    case 5256: BSH_FIXED_SMEM(5, 256); break;
+    case 5512: BSH_FIXED_SMEM(5, 512); break;
+    default: return 0;
+    }
+    return fixed + row_bytes(chunk, n_words);
+}
+#undef BSH_FIXED_SMEM
 
 }  // namespace bsh

@@ -6,9 +6,9 @@ given chunk size the loop over segment groups is walked along the path that ever
 when no lane of the wave meets an f0-shift step and no partial-sum flush is due.  Exec-mask
 regions (s_cbranch_execz) are entered, except the innermost ones that hold the step's position
 guess (v_rcp_f32) and the ones that store to global memory (the flush).  Each VALU instruction
-on that path is one 64-lane wave instruction, so its count divided by (segments per group x 90
-f0 bins) is the lane-operation cost of one template x segment.  This is the floor bench.py
-prices the count kernel's roofline with.
+on that path is one 64-lane wave instruction; a pair of lanes shares one binary template, so a
+lane covers a group's 8 segments x 45 f0 bins (the pair, 90), and the count divided by 8 x 45
+is the lane-operation cost of one template x segment that bench.py reports as the issued work.
 
     python paper_1904_04873_amd/fastpath_ops.py [chunk ...]
 """
@@ -25,6 +25,7 @@ sys.path.insert(0, HERE)
 import build  # noqa: E402
 
 N_F0 = 90
+BINS_PER_LANE = N_F0 // 2      # two lanes share a binary template's 90 f0 bins
 SEGMENTS_PER_GROUP = 8
 
 
@@ -124,5 +125,5 @@ if __name__ == "__main__":
     asm = assembly()
     for c in chunks:
         valu, seg = fast_path(c, asm)
-        print(f"chunk {c}: {valu} VALU per group of {seg} segments x {N_F0} bins = "
-              f"{valu / (seg * N_F0):.3f} per template x segment")
+        print(f"chunk {c}: {valu} VALU per group of {seg} segments x {BINS_PER_LANE} bins = "
+              f"{valu / (seg * BINS_PER_LANE):.3f} per template x segment")

@@ -1,5 +1,5 @@
 """The per-unit work bench.py prices the count kernel's roofline with (VALU instructions per group
-of eight segments on the table variant's fast path) is the count that fastpath_ops.py reads from
+of eight segments x 45 f0 bins per lane on the table variant's fast path) is the count that fastpath_ops.py reads from
 the kernel's gfx950 assembly, for every chunk size the autotuner may pick.  Compiles the count
 kernel to assembly on the host (no GPU needed)."""
 import os
@@ -22,4 +22,4 @@ def test_bench_floor_matches_the_assembly():
     for chunk in (128, 256, 512):
         valu, seg = fastpath_ops.fast_path(chunk, asm)
         assert seg == 8
-        assert valu / (seg * fastpath_ops.N_F0) == pytest.approx(bench.TABLE_OPS_PER_TS, rel=1e-12), chunk
+        assert valu / (seg * fastpath_ops.BINS_PER_LANE) == pytest.approx(bench.TABLE_OPS_PER_TS[chunk], rel=1e-12), chunk

@@ -74,6 +74,17 @@ def test_batched_equals_plain_and_single_item(setup):
         torch.cuda.synchronize()
         assert torch.equal(ws, plan.item_map(q)), f"item {q}"
     plan.close()
+    # the persistent launch form (blocks pulling units from a queue counter) gives the same maps
+    # and lists, also with fewer blocks than CUs
+    for blocks in (0, 7):
+        pp = bsh.Plan(items, grids, n_bands, k_item=500, k_band=300, use_graph=False, persistent=True, blocks=blocks)
+        pp.run()
+        torch.cuda.synchronize()
+        pp.status.raise_if_set("persistent")
+        assert torch.equal(pp.maps, m_b)
+        assert torch.equal(pp.item_index, li_b[1]) and torch.equal(pp.band_index, lb_b[1])
+        assert torch.equal(pp.band_score, lb_b[0])
+        pp.close()
 
 
 def test_lists_are_exact_topk_of_maps(setup):
