@@ -45,7 +45,7 @@ TABLE_OPS_PER_TS = {128: 379 / 360, 256: 379 / 360, 512: 374 / 360}
 SELECT_OPS_PER_TS = 3
 # HBM bytes per count launch, measured with rocprofv3 counters for one kernel source and tile
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hough_count_table_band200Hz_traffic.txt")
-BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hough_batch_table_1024items_traffic.txt")
+BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hough_unit_table_1024items_traffic.txt")
 # the count kernels' sources and the build script (which holds their compiler flags)
 COUNT_SOURCES = ("paper_1904_04873_amd/csrc/bsh_count.hip", "paper_1904_04873_amd/csrc/bsh_count_tile.h",
                  "paper_1904_04873_amd/csrc/bsh_count.h", "paper_1904_04873_amd/csrc/bsh_internal.h",
