@@ -147,7 +147,8 @@ int bsh_grid_build(const bsh_grid_spec* spec, double t_mid, double* a_p, double*
  * beta = sum_{i=m+1}^{2m+1} 1/i, the expected median of 2m+1 unit exponentials, so that noise
  * normalizes to unit mean.  raw [n_seg][n_raw] un-normalized SFT powers (n_raw <= 4096);
  * rho_out [n_seg][n_raw - 2m], column c centred on raw column c + m;
- * rho = (float)((P * beta) / median) evaluated in double precision.
+ * rho = (float)((P * beta) / median) evaluated in double precision.  A window that holds a NaN
+ * has a NaN median, so its output is NaN.
  */
 int bsh_normalize(const float* raw, int64_t n_seg, int32_t n_raw, int32_t window, float* rho_out,
                   bsh_stream stream);

@@ -157,8 +157,9 @@ extern "C" int bsh_grid_build(const bsh_grid_spec* spec, double t_mid, double* a
 // raw position c counts it once for the first window that holds c and then slides the window
 // across the 2m + 1 windows that hold c, updating both counts by the entry that leaves and the
 // one that enters.  A window's median is the first position in window order that meets the
-// condition (an LDS atomic minimum over the positions that do; with finite data they all hold
-// the same value); a window where none does (NaN entries) keeps its centre value.
+// condition (an LDS atomic minimum over the positions that do; they all hold the same value).
+// A window that holds a NaN has no median: its output is NaN (as the median of such a window is
+// taken to be), found by a scan of the window in the rows that hold a NaN at all.
 constexpr int kMaxRaw = 4096;
 
 __global__ __launch_bounds__(256) void normalize_kernel(const float* __restrict__ raw, int32_t n_raw,
@@ -166,10 +167,17 @@ __global__ __launch_bounds__(256) void normalize_kernel(const float* __restrict_
 {
     __shared__ float row[kMaxRaw];
     __shared__ int first[kMaxRaw];
+    __shared__ int any_nan;
     const int64_t J = blockIdx.x;
     const float* src = raw + J * n_raw;
     const int n_out = n_raw - 2 * m;
-    for (int i = threadIdx.x; i < n_raw; i += blockDim.x) row[i] = src[i];
+    if (threadIdx.x == 0) any_nan = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_raw; i += blockDim.x) {
+        const float v = src[i];
+        row[i] = v;
+        if (v != v) any_nan = 1;
+    }
     for (int i = threadIdx.x; i < n_out; i += blockDim.x) first[i] = n_raw;
     __syncthreads();
     for (int c = threadIdx.x; c < n_raw; c += blockDim.x) {
@@ -191,8 +199,11 @@ __global__ __launch_bounds__(256) void normalize_kernel(const float* __restrict_
     __syncthreads();
     for (int w = threadIdx.x; w < n_out; w += blockDim.x) {
         const float centre = row[w + m];
-        const float med = first[w] < n_raw ? row[first[w]] : centre;
-        rho[J * n_out + w] = (float)(((double)centre * beta) / (double)med);
+        bool nan_in_window = false;
+        if (any_nan)
+            for (int i = w; i <= w + 2 * m; ++i) nan_in_window |= row[i] != row[i];
+        const double med = nan_in_window || first[w] >= n_raw ? (double)NAN : (double)row[first[w]];
+        rho[J * n_out + w] = (float)(((double)centre * beta) / med);
     }
 }
 

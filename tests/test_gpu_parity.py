@@ -756,9 +756,13 @@ def test_normalize_bit_exact(B, window, n_raw):
     _say(f"normalize window={window} n_raw={n_raw}")
     raw = S.raw_sft_powers(np.random.default_rng(window + n_raw), 257, n_raw, 180000)
     raw[5, :20] = raw[5, 0]                    # ties inside windows
+    raw[7, n_raw // 2] = np.nan                 # windows holding a NaN have a NaN median
+    raw[9, 0] = np.nan
     rho = B.bsh_normalize(torch.from_numpy(raw).cuda(), window)
     bits = B.bsh_peakgram(rho, 1.6)
     torch.cuda.synchronize()
-    ref = O.normalize(raw, window)
-    assert np.array_equal(_np(rho), ref)
+    with np.errstate(invalid="ignore"):
+        ref = O.normalize(raw, window)
+    assert np.isnan(ref[7]).any() and not np.isnan(ref[6]).any()
+    assert np.array_equal(_np(rho), ref, equal_nan=True)
     assert np.array_equal(_np(bits).view(np.uint32), O.peakgram(ref, 1.6))

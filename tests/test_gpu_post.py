@@ -103,6 +103,50 @@ def test_clusters_match_oracle(env, n):
     assert np.array_equal(got.astype(np.int64), want)
 
 
+def test_clusters_on_grid_frequencies_with_ties(env):
+    """Stage-1 lists carry on-grid frequencies (bin centres), so many rows share f exactly across
+    row and column tiles: 3000 rows on 12 frequency bins (ties in the frequency-window search's key
+    and in its tie-break by position), plus rows whose only difference from a partner is |Delta f|
+    just inside or just outside the window's frequency half-width window / Tc (2e-7 relative)."""
+    torch, bsh = env
+    _say("clusters on-grid f")
+    pp = PP.PostParams()
+    rng = np.random.default_rng(31)
+    n = 3000
+    base = np.array([200.0, 0.2, 0.1, 1.5, 2 * np.pi / (20 * DAY), 3e6])
+    r = PP.resolutions(pp, base)[0]
+    c = np.repeat(base[None, :], n, axis=0)
+    c[:, 0] = 200.0 + rng.integers(0, 12, n) / TC
+    c[:, 1] += rng.normal(0, 4, n) * r[0]
+    c[:, 2] += rng.normal(0, 4, n) * r[0]
+    c[:, 3] += rng.normal(0, 4, n) * r[1]
+    c[:, 4] += rng.normal(0, 4, n) * r[2]
+    c[:, 5] += rng.normal(0, 4, n) * r[3]
+    w = np.sqrt(14.0)
+    far = base.copy()
+    far[3] += 1000 * r[1]                       # away from the cloud in a_p
+    pairs = []
+    for q, rel in enumerate((1 - 2e-7, 1 + 2e-7, 1 - 2e-7, 1 + 2e-7)):
+        a = far.copy()
+        a[5] += 1000 * q * r[3]                 # each pair on its own, apart in t_asc
+        b = a.copy()
+        b[0] += w / TC * rel
+        pairs += [a, b]
+    c = np.concatenate([c, np.array(pairs)])
+    perm = rng.permutation(c.shape[0])
+    c = c[perm]
+    assert _margin_ok(pp, c, w)
+    got = bsh.bsh_cluster(_pp_ctypes(bsh, pp), torch.tensor(c, device="cuda"), w).cpu().numpy()
+    want = PP.clusters(pp, c, w)
+    assert np.array_equal(got.astype(np.int64), want)
+    # the inside pairs joined, the outside pairs did not
+    pos = np.argsort(perm)
+    for q, joined in enumerate((True, False, True, False)):
+        ia, ib = pos[n + 2 * q], pos[n + 2 * q + 1]
+        assert (want[ia] == want[ib]) == joined
+    assert len(np.unique(np.round((c[:n, 0] - 200.0) * TC))) == 12
+
+
 def test_cluster_chain_spans_tiles(env):
     """A chain of 2000 templates 3.5 bins apart, shuffled, is one cluster across 8 row tiles;
     cutting one link splits it in two."""
