@@ -127,8 +127,12 @@ def parse():
                     help="pixels whose maps the all-sky plan's buffer holds")
     ap.add_argument("--skip-extras", action="store_true",
                     help="only the headline (no band step, all-sky slice, refinement, post-processing)")
+    ap.add_argument("--band-only", action="store_true",
+                    help="only the 200 Hz band's two-stage step and the work beside it (for profiling runs; "
+                         "prints that object alone, not the metric line)")
     ap.add_argument("--tile", default="",
-                    help="LANESxCHUNK of the batched plan instead of autotuning it (for profiling runs)")
+                    help="LANESxCHUNK of the batched plan (and of the band step's count) instead of autotuning "
+                         "it (for profiling runs)")
     ap.add_argument("--plain-tile", default="",
                     help="LANESxCHUNK of the plain baseline instead of autotuning it (for profiling runs)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -181,6 +185,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    if args.band_only:
+        print(json.dumps({"band200": run_band200(args)}), flush=True)
+        return
 
     # ---------------------------------------------------------------- the batching workload
     print("[bench] batching workload: generating 1024 items", file=sys.stderr, flush=True)
@@ -423,7 +431,11 @@ def run_band200(args):
     s2_score = torch.empty(k2, dtype=torch.float32, device=dev)
     s2_pos = torch.empty(k2, dtype=torch.int64, device=dev)
     P = torch.empty(k1, dtype=torch.float32, device=dev)
-    (lanes, chunk), tune_ms = autotune.tune_plain(ds, g, use_cache=False)
+    if args.tile:
+        lanes, chunk = (int(x) for x in args.tile.lower().split("x"))
+        tune_ms = {}
+    else:
+        (lanes, chunk), tune_ms = autotune.tune_plain(ds, g, use_cache=False)
 
     def step():
         bsh.bsh_peakgram(ds.power, 1.6, out=ds.peak_bits)
