@@ -38,7 +38,7 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 FLOOR_OPS_PER_TS = 2 / 8 + 12 / 90
 # VALU lane-operations per template x segment the table count issues on its fast path: the VALU
 # instructions of the segment-group loop in its gfx950 assembly along the path with no f0-shift
-# step and no flush (paper_1904_04873_amd/fastpath_ops.py counts them per chunk size), divided by
+# step and no flush (tests/fastpath_ops.py counts them per chunk size), divided by
 # the 8 segments x 45 f0 bins one lane of a template's lane pair covers per group.
 TABLE_OPS_PER_TS = {128: 379 / 360, 256: 379 / 360, 512: 374 / 360}
 # plain select-and-add: extract the peak bit, select the weight, add

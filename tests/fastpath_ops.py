@@ -10,7 +10,7 @@ on that path is one 64-lane wave instruction; a pair of lanes shares one binary 
 lane covers a group's 8 segments x 45 f0 bins (the pair, 90), and the count divided by 8 x 45
 is the lane-operation cost of one template x segment that bench.py reports as the issued work.
 
-    python paper_1904_04873_amd/fastpath_ops.py [chunk ...]
+    python tests/fastpath_ops.py [chunk ...]
 """
 from __future__ import annotations
 
@@ -21,7 +21,7 @@ import sys
 import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-sys.path.insert(0, HERE)
+sys.path.insert(0, os.path.join(os.path.dirname(HERE), "paper_1904_04873_amd"))
 import build  # noqa: E402
 
 N_F0 = 90
