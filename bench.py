@@ -40,17 +40,19 @@ FLOOR_OPS_PER_TS = 2 / 8 + 12 / 90
 # instructions of the segment-group loop in its gfx950 assembly along the path with no f0-shift
 # step and no flush (tests/fastpath_ops.py counts them per chunk size), divided by
 # the 8 segments x 45 f0 bins one lane of a template's lane pair covers per group.
-TABLE_OPS_PER_TS = {128: 379 / 360, 256: 379 / 360, 512: 374 / 360}
+TABLE_OPS_PER_TS = {128: 300 / 360, 256: 300 / 360, 512: 302 / 360}
 # plain select-and-add: extract the peak bit, select the weight, add
 SELECT_OPS_PER_TS = 3
 # HBM bytes per count launch, measured with rocprofv3 counters for one kernel source and tile
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hough_count_table_band200Hz_traffic.txt")
 BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hough_unit_table_1024items_traffic.txt")
 # the count kernels' sources and the build script (which holds their compiler flags)
-COUNT_SOURCES = ("paper_1904_04873_amd/csrc/bsh_count.hip", "paper_1904_04873_amd/csrc/bsh_count_tile.h",
+COUNT_SOURCES = ("paper_1904_04873_amd/csrc/bsh_count.hip", "paper_1904_04873_amd/csrc/bsh_count_table.hip",
+                 "paper_1904_04873_amd/csrc/bsh_count_kernels.h", "paper_1904_04873_amd/csrc/bsh_count_tile.h",
                  "paper_1904_04873_amd/csrc/bsh_count.h", "paper_1904_04873_amd/csrc/bsh_internal.h",
                  "paper_1904_04873_amd/build.py")
-BATCH_SOURCES = ("paper_1904_04873_amd/csrc/bsh_count_batch.hip", "paper_1904_04873_amd/csrc/bsh_count_tile.h",
+BATCH_SOURCES = ("paper_1904_04873_amd/csrc/bsh_count_batch.hip", "paper_1904_04873_amd/csrc/bsh_count_table.hip",
+                 "paper_1904_04873_amd/csrc/bsh_count_kernels.h", "paper_1904_04873_amd/csrc/bsh_count_tile.h",
                  "paper_1904_04873_amd/csrc/bsh_count.h", "paper_1904_04873_amd/csrc/bsh_internal.h",
                  "paper_1904_04873_amd/build.py")
 

@@ -1,5 +1,6 @@
-// Shared declarations of the stage-1 count kernels (bsh_count_tile.h, bsh_count.hip,
-// bsh_count_batch.hip) and the batched plan (bsh_batch.hip).  Internal to libbsh.
+// Shared declarations of the stage-1 count kernels (bsh_count_tile.h, bsh_count_kernels.h,
+// bsh_count.hip, bsh_count_batch.hip, bsh_count_table.hip) and the batched plan (bsh_batch.hip).
+// Internal to libbsh.
 #pragma once
 
 #include "bsh_internal.h"
@@ -70,8 +71,8 @@ constexpr int kFlushGroups = 128;
 // Per staged segment: D cos(W t), D sin(W t) and the Doppler factor D of the tile's pixel, and
 // for the ELL1 track D cos(2 W t), D sin(2 W t) (zero-length arrays on a circular grid, which
 // leave the layout as it is); for the table variant the subset-sum tables.  The bit-packed rows
-// follow the structure in LDS, sized at launch for the item's row width (row_bytes), so that a
-// block of the table variant at 256-segment chunks fits three times into a CU's 160 KB.
+// precede the structure in LDS, sized at launch for the widest row of the launch (row_bytes), so
+// that a block of the table variant at 256-segment chunks fits three times into a CU's 160 KB.
 template <int kChunk, bool kEcc>
 struct TileSmemLut {
     float T8[(kChunk / kGroup8) * 256];
@@ -112,6 +113,12 @@ int launch_plain(const PlainLaunch& p, int64_t blocks, int lanes, int chunk, int
 int launch_batch(const ItemDesc* items, const WorkUnit* units, int64_t n_units, uint32_t* counter,
                  int blocks, int lanes, int chunk, int mode, int n_words, bool persistent, hipStream_t stream);
 int batch_blocks_per_cu(int lanes, int chunk, int mode, int n_words);
+// The table variant's launchers (bsh_count_table.hip); lds: the block's LDS bytes.
+int launch_plain_table(const PlainLaunch& p, int64_t blocks, int lanes, int chunk, int mode, size_t lds,
+                       hipStream_t stream);
+int launch_batch_table(const ItemDesc* items, const WorkUnit* units, int64_t n_units, uint32_t* counter, int blocks,
+                       int lanes, int chunk, int mode, size_t lds, bool persistent, hipStream_t stream);
+int occupancy_table(int lanes, int chunk, int mode, size_t lds);
 int allow_lds(const void* kernel, size_t bytes);
 int kernel_mode(int variant, bool with_count);
 // kEccMode for a grid with an eccentricity pair, else 0 (added to kernel_mode's value)

@@ -1,28 +1,14 @@
 // Stage-1 weighted number count, plain launch form (bsh_hough_count): one block per tile of
-// one work item.  The tile body is in bsh_count_tile.h.
+// one work item.  The tile body is in bsh_count_tile.h, the kernels in bsh_count_kernels.h; the
+// select variants are instantiated here, the table variant in bsh_count_table.hip.
 #include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <unordered_map>
 
-#include "bsh_count_tile.h"
+#include "bsh_count_kernels.h"
 
 namespace bsh {
-
-template <int kMode, int kChunk>
-__global__ __launch_bounds__(kMaxLanes, min_blocks<kMode>()) void hough_count_kernel(const PlainLaunch p)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int blk = blockIdx.x;
-    const int s = blk / p.tiles_per_sky;
-    const int t = blk - s * p.tiles_per_sky;
-    int lo = 0, hi = p.d.n_per;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (p.tile_start[mid] <= t) lo = mid; else hi = mid;
-    }
-    run_tile<kMode, kChunk>(p.d, s, lo, t - p.tile_start[lo], smem);
-}
 
 // Tiles of each period group of one item, in tile_start form.
 int64_t plan_tiles(const bsh_grid* g, int lanes, int32_t* tile_start, int64_t* group_sizes)
@@ -96,12 +82,14 @@ int launch_plain(const PlainLaunch& p, int64_t blocks, int lanes, int chunk, int
 {
     const size_t lds = smem_bytes_of(mode, chunk, n_words);
     int rc = BSH_OK;
-#define BSH_LAUNCH_PLAIN(M, C)                                                                \
-    rc = allow_lds((const void*)hough_count_kernel<M, C>, lds);                                \
-    if (rc) return rc;                                                                        \
-    hipLaunchKernelGGL((hough_count_kernel<M, C>), dim3((unsigned)blocks), dim3(lanes), lds, stream, p)
-    BSH_DISPATCH(mode, chunk, BSH_LAUNCH_PLAIN)
+    if (is_table_mode(mode)) {
+        rc = launch_plain_table(p, blocks, lanes, chunk, mode, lds, stream);
+    } else {
+#define BSH_LAUNCH_PLAIN(M, C) rc = launch_plain_mc<M, C>(p, blocks, lanes, lds, stream)
+        BSH_DISPATCH_SELECT(mode, chunk, BSH_LAUNCH_PLAIN)
 #undef BSH_LAUNCH_PLAIN
+    }
+    if (rc) return rc;
     return check_launch("bsh_hough_count");
 }
 

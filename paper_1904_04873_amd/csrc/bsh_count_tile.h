@@ -26,6 +26,8 @@
 // or subset-sum tables over groups of segments (see count_tile_pair).
 #pragma once
 
+#include <cstddef>
+
 #include "bsh_count.h"
 
 namespace bsh {
@@ -112,8 +114,9 @@ __device__ __forceinline__ int step_exact(double G, int kf, double F0, int last,
 
 // Where the band has an f0-shift step (t.ok and t.span != last), take the bins above it one bit
 // further (span = last + 1) or nearer (span = last - 1).
+// off: the mask bit of f0 bin 0 (bit i + off holds bin i).
 __device__ __forceinline__ void band_step(const BandTrack& t, double F0, int last, uint32_t& m0, uint32_t& m1,
-                                          uint32_t& m2)
+                                          uint32_t& m2, int off = 0)
 {
     // The residual r_i = k_i - (k0 + i) steps once, at the first index past the crossing
     // i* = (u - frac(y0)) / (G - 1) of y0 + i (G - 1) with the next integer above (a step up,
@@ -142,11 +145,12 @@ __device__ __forceinline__ void band_step(const BandTrack& t, double F0, int las
     const uint32_t n0 = __builtin_amdgcn_alignbit(b1, b0, by);
     const uint32_t n1 = __builtin_amdgcn_alignbit(b2, b1, by);
     const uint32_t n2 = __builtin_amdgcn_alignbit(b3, b2, by);
-    // bits hi.. of the 96-bit mask (1 <= hi < 96): one shift, placed by word
-    const uint32_t sh = 0xffffffffu << (hi & 31);
-    const uint32_t s0 = hi < 32 ? sh : 0u;
-    const uint32_t s1 = hi < 32 ? 0xffffffffu : (hi < 64 ? sh : 0u);
-    const uint32_t s2 = hi < 64 ? 0xffffffffu : sh;
+    // bits hb = hi + off .. of the 96-bit mask (1 <= hb < 96): one shift, placed by word
+    const int hb = hi + off;
+    const uint32_t sh = 0xffffffffu << (hb & 31);
+    const uint32_t s0 = hb < 32 ? sh : 0u;
+    const uint32_t s1 = hb < 32 ? 0xffffffffu : (hb < 64 ? sh : 0u);
+    const uint32_t s2 = hb < 64 ? 0xffffffffu : sh;
     m0 = (n0 & s0) | (m0 & ~s0);
     m1 = (n1 & s1) | (m1 & ~s1);
     m2 = (n2 & s2) | (m2 & ~s2);
@@ -281,23 +285,31 @@ __device__ __forceinline__ void count_tile(const ItemDesc& d, int s, int ip, int
 // eight select-and-add steps.  The table is built from the 16-entry subset-sum tables of the
 // group's two halves, T8[b] = T_first[b & 15] + T_second[b >> 4].
 //
-// Two adjacent lanes share one binary template.  With bin i = 32 w + 4 n + r (w = 0..2,
-// n = 0..7, r = 0..3), lane h = lane & 1 owns the bins with r = 2h, 2h + 1 (46 and 44 of the
-// band's 90), so it keeps 46 register partial sums instead of 90, which leaves room for three
-// waves per SIMD.  Per group lane h evaluates the tracks of the group's segments 4h .. 4h + 3,
-// transposes their four 96-bit masks (a 4 x 4 bit transpose per nibble column: word A[w][r] holds
-// in nibble n the four segments' bits of bin 32 w + 4 n + r), and the pair swaps the two words
-// A[w][r] of the partner's r values (a cross-lane move inside each pair of lanes).  Each lane then
-// merges the first four segments' nibbles (from lane 0) and the last four's (from lane 1) into
-// bytes, and every one of its bins costs one byte extraction, one table address and one FP32 add
-// per eight segments.  The register partial sums (at most kFlushGroups groups each) are folded
-// into the lane's own slots of the output map, bounding the FP32 error by
+// Two adjacent lanes share one binary template; lane h = lane & 1 evaluates the tracks of the
+// group's segments 4h .. 4h + 3 and owns the bins i = 32 w + 8 j + 4 h + t (w = 0..2, j = 0..3,
+// t = 0..3; 46 and 44 of the band's 90), so it keeps 46 register partial sums instead of 90,
+// which leaves room for three waves per SIMD.  Lane 1 reads its 96-bit windows four bins lower
+// than lane 0 (its mask bit i + 4 holds bin i).  Per group each lane transposes its four masks (a
+// 4 x 4 bit transpose per nibble column: word A[w][t] holds in nibble n the four segments' bits
+// of the lane's bin 32 w + 4 n + t, minus 4 on lane 1), and both lanes of the pair swap the same
+// word A[w][t].  Merging the low nibbles of lane 0's word with the high nibbles of lane 1's gives,
+// on both lanes, the byte indices (first four segments low, last four high) of bins
+// 32 w + 8 j + t; the word moved down by one nibble (with the next word's first nibble on top)
+// holds those of bins 32 w + 8 j + 4 + t.  Lane 0 takes the first, lane 1 the second, so the
+// exchange needs no select.  The indices are split into 16-bit halves, each turned into its table
+// address by one multiply-add, and every bin of the lane costs that address (and half a split)
+// and one FP32 add per eight segments.  The register partial sums (at most kFlushGroups groups
+// each) are folded into the lane's own slots of the output map, bounding the FP32 error by
 // (kFlushGroups + 4 + n_seg / (8 kFlushGroups)) ulps of the total.  Per bin the table entries and
 // the order of the additions do not depend on the tile shape or on how lanes share templates.
-constexpr int kPairSlots = 46;   // (w, k, n) with k = r - 2h, minus w = 2, n = 7
+constexpr int kPairSlots = 46;   // (w, t, j), minus w = 2, j = 3 for t = 2, 3
 
-// (w, k, n) -> 0 .. 45: sixteen slots per word for w = 0, 1, fourteen (n < 7) for w = 2
-__device__ __forceinline__ constexpr int pair_slot(int w, int k, int n) { return w < 2 ? (w * 2 + k) * 8 + n : 32 + k * 7 + n; }
+// (w, t, j) -> 0 .. 45: sixteen slots per word for w = 0, 1; for w = 2 twelve with j < 3 and two
+// (t = 0, 1) with j = 3
+__device__ __forceinline__ constexpr int pair_slot(int w, int t, int j)
+{
+    return w < 2 ? (w * 4 + t) * 4 + j : (j < 3 ? 32 + t * 3 + j : 44 + t);
+}
 
 __device__ __forceinline__ uint32_t pair_swap(uint32_t x)
 {
@@ -305,9 +317,32 @@ __device__ __forceinline__ uint32_t pair_swap(uint32_t x)
     return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);
 }
 
+// LDS byte address base + 4 x (low or high 16-bit half of y); each half of y holds a table
+// index below 256 in its low byte and zeros above.  lds_at reads the float at such an address.
+__device__ __forceinline__ uint32_t lut_addr_lo(uint32_t y, uint32_t base)
+{
+    uint32_t a;
+    asm("v_mad_u32_u16 %0, %1, 4, %2" : "=v"(a) : "v"(y), "s"(base));
+    return a;
+}
+
+__device__ __forceinline__ uint32_t lut_addr_hi(uint32_t y, uint32_t base)
+{
+    uint32_t a;
+    asm("v_mad_u32_u16 %0, %1, 4, %2 op_sel:[1,0,0,0]" : "=v"(a) : "v"(y), "s"(base));
+    return a;
+}
+
+__device__ __forceinline__ float lds_at(uint32_t a)
+{
+    return *(const __attribute__((address_space(3))) float*)(size_t)a;
+}
+
+// smem: the block's LDS (rows first, then the structure at byte offset sm_off).
 template <int kChunk, bool kEcc>
 __device__ __forceinline__ void count_tile_pair(const ItemDesc& d, int s, int ip, int64_t tile,
-                                                TileSmemLut<kChunk, kEcc>& sm, uint32_t* row)
+                                                TileSmemLut<kChunk, kEcc>& sm, uint32_t* row,
+                                                const unsigned char* smem, uint32_t sm_off)
 {
     static_assert(kChunk % kGroup8 == 0, "chunks hold whole groups");
     const int tid = threadIdx.x;
@@ -341,6 +376,17 @@ __device__ __forceinline__ void count_tile_pair(const ItemDesc& d, int s, int ip
     const double FL = (double)(d.k0 + last);
     const int klo = (int)d.k_lo;
     const int nwp = d.n_words + kRowPad;
+    // The window of f0 bin 0 starts at row bit kf - klo on lane 0 and four bits lower on lane 1,
+    // i.e. up to four bits before the row, in the previous row's zero padding (the rows of lane
+    // 1's segments 4 .. 7 of a group are never the chunk's first); a failed track reads the row's
+    // padding, from four bits before it on lane 1.  The bits below f0 bin 0 are never used.
+    const int off = 4 * h;
+    const int klo_h = klo + off;
+    const int pad_h = 32 * d.n_words - off;
+    const uint32_t nib = (uint32_t)off;
+    // LDS address of the structure (its tables first)
+    const uint32_t lds_base =
+        (uint32_t)(size_t)(const __attribute__((address_space(3))) unsigned char*)smem + sm_off;
 
     float acc[kPairSlots];
 #pragma unroll
@@ -350,16 +396,21 @@ __device__ __forceinline__ void count_tile_pair(const ItemDesc& d, int s, int ip
     float* out = d.wsum_out + ((int64_t)s * d.n_bin + b) * d.n_f0;
     const int nf = d.n_f0;
     auto flush = [&]() {
+        // the lane's offset taken opaque here, so that the 46 per-lane store addresses and bounds
+        // are formed in the (rare) fold and not held in registers across the group loop
+        int o = off;
+        asm volatile("" : "+v"(o));
+        float* po = out + o;
 #pragma unroll
         for (int w = 0; w < 3; ++w)
 #pragma unroll
-            for (int k = 0; k < 2; ++k)
+            for (int t = 0; t < 4; ++t)
 #pragma unroll
-                for (int n = 0; n < 8; ++n) {
-                    if (w == 2 && n == 7) continue;
-                    const int sl = pair_slot(w, k, n);
-                    const int i = 32 * w + 4 * n + 2 * h + k;
-                    if (i < nf) out[i] = flushed ? out[i] + acc[sl] : acc[sl];
+                for (int jb = 0; jb < 4; ++jb) {
+                    if (w == 2 && jb == 3 && t >= 2) continue;
+                    const int sl = pair_slot(w, t, jb);
+                    const int i = 32 * w + 8 * jb + t;
+                    if (i + o < nf) po[i] = flushed ? po[i] + acc[sl] : acc[sl];
                     acc[sl] = 0.f;
                 }
         flushed = true;
@@ -416,8 +467,9 @@ __device__ __forceinline__ void count_tile_pair(const ItemDesc& d, int s, int ip
         __syncthreads();
         if (!active) continue;
 
-        for (int g8 = 0; g8 < ng8; ++g8) {
-            // this lane's half of the group: segments 4h .. 4h + 3
+        // this lane's rows: segments 4h .. 4h + 3 of group 0, then eight rows further per group
+        const uint32_t* lrow = row + 4 * h * nwp;
+        for (int g8 = 0; g8 < ng8; ++g8, lrow += kGroup8 * nwp) {
             const int hg = 2 * g8 + h;
             uint32_t mk[kGroup][3];
             BandTrack tr[kGroup];
@@ -429,39 +481,49 @@ __device__ __forceinline__ void count_tile_pair(const ItemDesc& d, int s, int ip
                 tr[u] = band_track(G, F0, FL, klo, klo + d.n_bins, last, bad_range, bad_model);
             }
 #pragma unroll
-            for (int u = 0; u < kGroup; ++u)
-                band_window(row + (hg * kGroup + u) * nwp, tr[u], klo, 32 * d.n_words, mk[u][0], mk[u][1],
-                            mk[u][2]);
+            for (int u = 0; u < kGroup; ++u) {
+                const int at = tr[u].ok ? tr[u].kf - klo_h : pad_h;
+                const uint32_t* rw = lrow + u * nwp + (at >> 5);
+                const uint32_t w0 = rw[0], w1 = rw[1], w2 = rw[2], w3 = rw[3];
+                mk[u][0] = __builtin_amdgcn_alignbit(w1, w0, at);
+                mk[u][1] = __builtin_amdgcn_alignbit(w2, w1, at);
+                mk[u][2] = __builtin_amdgcn_alignbit(w3, w2, at);
+            }
 #pragma unroll
             for (int u = 0; u < kGroup; ++u)
-                if (tr[u].ok && tr[u].span != last) band_step(tr[u], F0, last, mk[u][0], mk[u][1], mk[u][2]);
-            const float* T8 = sm.T8 + g8 * 256;
+                if (tr[u].ok && tr[u].span != last) band_step(tr[u], F0, last, mk[u][0], mk[u][1], mk[u][2], off);
+
+            // Words from the top (w = 2) down, so that only the word above stays live.  A[t]: the
+            // transposed masks; Z[t]: this lane's low nibbles with the partner's high ones.
+            const uint32_t T8 = lds_base + (uint32_t)g8 * 1024u;   // LDS address of the group's table
+            uint32_t Zup[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-            for (int w = 0; w < 3; ++w) {
+            for (int w = 2; w >= 0; --w) {
                 uint32_t x0 = mk[0][w], x1 = mk[1][w], x2 = mk[2][w], x3 = mk[3][w];
-                uint32_t t;
-                t = ((x0 >> 2) ^ x2) & 0x33333333u; x2 ^= t; x0 ^= t << 2;
-                t = ((x1 >> 2) ^ x3) & 0x33333333u; x3 ^= t; x1 ^= t << 2;
-                t = ((x0 >> 1) ^ x1) & 0x55555555u; x1 ^= t; x0 ^= t << 1;
-                t = ((x2 >> 1) ^ x3) & 0x55555555u; x3 ^= t; x2 ^= t << 1;
-                // A[w][r] = x_r: this lane's four segments, every bin
+                uint32_t y0, y1, y2, y3;
+                // bit pairs at distance 2 (segments 0, 2 and 1, 3), then single bits at distance 1
+                y0 = (x0 & 0x33333333u) | ((x2 << 2) & 0xccccccccu);
+                y2 = ((x0 >> 2) & 0x33333333u) | (x2 & 0xccccccccu);
+                y1 = (x1 & 0x33333333u) | ((x3 << 2) & 0xccccccccu);
+                y3 = ((x1 >> 2) & 0x33333333u) | (x3 & 0xccccccccu);
+                x0 = (y0 & 0x55555555u) | ((y1 << 1) & 0xaaaaaaaau);
+                x1 = ((y0 >> 1) & 0x55555555u) | (y1 & 0xaaaaaaaau);
+                x2 = (y2 & 0x55555555u) | ((y3 << 1) & 0xaaaaaaaau);
+                x3 = ((y2 >> 1) & 0x55555555u) | (y3 & 0xaaaaaaaau);
                 const uint32_t A[4] = {x0, x1, x2, x3};
 #pragma unroll
-                for (int k = 0; k < 2; ++k) {
-                    // the first four segments' nibbles (L) come from lane 0, the last four's (H)
-                    // from lane 1: lane 0 takes its own word of r = k and lane 1's, lane 1 takes
-                    // lane 0's word of r = 2 + k and its own
-                    const uint32_t from_partner_hi = pair_swap(A[2 + k]);   // every lane swaps,
-                    const uint32_t from_partner_lo = pair_swap(A[k]);       // then each selects
-                    const uint32_t L = h == 0 ? A[k] : from_partner_hi;
-                    const uint32_t H = h == 1 ? A[2 + k] : from_partner_lo;
-                    const uint32_t b0 = (L & 0x0f0f0f0fu) | ((H << 4) & 0xf0f0f0f0u);
-                    const uint32_t b1 = ((L >> 4) & 0x0f0f0f0fu) | (H & 0xf0f0f0f0u);
-#pragma unroll
-                    for (int jb = 0; jb < 4; ++jb) {
-                        acc[pair_slot(w, k, 2 * jb)] += T8[(b0 >> (8 * jb)) & 255u];
-                        if (!(w == 2 && jb == 3)) acc[pair_slot(w, k, 2 * jb + 1)] += T8[(b1 >> (8 * jb)) & 255u];
-                    }
+                for (int t = 0; t < 4; ++t) {
+                    const uint32_t p = pair_swap(A[t]);
+                    const uint32_t Z = (A[t] & 0x0f0f0f0fu) | (p & 0xf0f0f0f0u);
+                    // bytes j of x: bin 32 w + 8 j + 4 h + t (lane 1 takes the word one nibble down)
+                    const uint32_t x = __builtin_amdgcn_alignbit(Zup[t], Z, nib);
+                    Zup[t] = Z;
+                    const uint32_t ye = x & 0x00ff00ffu;                            // bytes 0 and 2
+                    const uint32_t yo = __builtin_amdgcn_perm(x, x, 0x0c030c01u);   // bytes 1 and 3
+                    acc[pair_slot(w, t, 0)] += lds_at(lut_addr_lo(ye, T8));
+                    acc[pair_slot(w, t, 1)] += lds_at(lut_addr_lo(yo, T8));
+                    acc[pair_slot(w, t, 2)] += lds_at(lut_addr_hi(ye, T8));
+                    if (!(w == 2 && t >= 2)) acc[pair_slot(w, t, 3)] += lds_at(lut_addr_hi(yo, T8));
                 }
             }
             if (++since_flush == kFlushGroups) {
@@ -485,17 +547,24 @@ constexpr size_t fixed_smem_bytes()
     return (b + 15) & ~(size_t)15;
 }
 
-// The tile's LDS: the fixed structure, then the rows.
+// The tile's LDS: the rows, then the fixed structure.
 template <int kMode, int kChunk>
 __device__ __forceinline__ void run_tile(const ItemDesc& d, int s, int ip, int64_t tile, unsigned char* smem)
 {
     constexpr int kM = kMode % kEccMode;
     constexpr bool kEcc = kMode >= kEccMode;
-    uint32_t* row = reinterpret_cast<uint32_t*>(smem + fixed_smem_bytes<kMode, kChunk>());
-    if constexpr (kM == 2)
-        count_tile_pair<kChunk, kEcc>(d, s, ip, tile, *reinterpret_cast<TileSmemLut<kChunk, kEcc>*>(smem), row);
-    else
-        count_tile<kM == 1, kChunk, kEcc>(d, s, ip, tile, *reinterpret_cast<TileSmem<kChunk, kEcc>*>(smem), row);
+    // rows at offset 0 (a row's words are then addressed by the read instructions' own offsets);
+    // the structure follows the item's rows (a multiple of 512 bytes)
+    uint32_t* row = reinterpret_cast<uint32_t*>(smem);
+    const uint32_t sm_off = (uint32_t)kChunk * (uint32_t)(d.n_words + kRowPad) * 4u;
+    unsigned char* st = smem + sm_off;
+    if constexpr (kM == 2) {
+        using Lut = TileSmemLut<kChunk, kEcc>;
+        static_assert(offsetof(Lut, T8) == 0, "tables first");
+        count_tile_pair<kChunk, kEcc>(d, s, ip, tile, *reinterpret_cast<Lut*>(st), row, smem, sm_off);
+    } else {
+        count_tile<kM == 1, kChunk, kEcc>(d, s, ip, tile, *reinterpret_cast<TileSmem<kChunk, kEcc>*>(st), row);
+    }
 }
 
 // Launch-bounds hint of the blocks per CU: two for the table variant, one for the select
@@ -504,8 +573,10 @@ __device__ __forceinline__ void run_tile(const ItemDesc& d, int s, int ip, int64
 template <int kMode>
 constexpr int min_blocks() { return kMode % kEccMode == 2 ? 2 : 1; }
 
-// Instantiate a kernel template for every (mode, chunk) and call f with the chosen one.
-#define BSH_DISPATCH(MODE, CHUNK, F)                                                          \
+// Instantiate a kernel template for every (mode, chunk) of the select variants (modes 0, 1 and
+// their ELL1 forms 3, 4) or of the table variant (modes 2, 5) and call f with the chosen one.  The
+// two families are compiled in different sources (bsh_count_table.hip holds the table variant).
+#define BSH_DISPATCH_SELECT(MODE, CHUNK, F)                                                   \
     switch ((MODE) * 1000 + (CHUNK)) {                                                        \
     case 128: F(0, 128); break;                                                               \
     case 256: F(0, 256); break;                                                               \
@@ -513,20 +584,27 @@ constexpr int min_blocks() { return kMode % kEccMode == 2 ? 2 : 1; }
     case 1128: F(1, 128); break;                                                              \
     case 1256: F(1, 256); break;                                                              \
     case 1512: F(1, 512); break;                                                              \
-    case 2128: F(2, 128); break;                                                              \
-    case 2256: F(2, 256); break;                                                              \
-    case 2512: F(2, 512); break;                                                              \
     case 3128: F(3, 128); break;                                                              \
     case 3256: F(3, 256); break;                                                              \
     case 3512: F(3, 512); break;                                                              \
     case 4128: F(4, 128); break;                                                              \
     case 4256: F(4, 256); break;                                                              \
     case 4512: F(4, 512); break;                                                              \
+    default: return fail_inval("kernel mode / chunk");                                        \
+    }
+
+#define BSH_DISPATCH_TABLE(MODE, CHUNK, F)                                                    \
+    switch ((MODE) * 1000 + (CHUNK)) {                                                        \
+    case 2128: F(2, 128); break;                                                              \
+    case 2256: F(2, 256); break;                                                              \
+    case 2512: F(2, 512); break;                                                              \
     case 5128: F(5, 128); break;                                                              \
     case 5256: F(5, 256); break;                                                              \
     case 5512: F(5, 512); break;                                                              \
     default: return fail_inval("kernel mode / chunk");                                        \
     }
+
+inline bool is_table_mode(int mode) { return mode % kEccMode == 2; }
 
 // LDS bytes of one block: the fixed structure and the rows of n_words words (0 for an unknown
 // mode or chunk).

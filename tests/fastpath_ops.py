@@ -30,7 +30,7 @@ SEGMENTS_PER_GROUP = 8
 
 
 def assembly() -> str:
-    src = "bsh_count.hip"
+    src = "bsh_count_table.hip"
     with tempfile.TemporaryDirectory() as tmp:
         out = os.path.join(tmp, "count.s")
         cmd = ([build.hipcc()] + build.FLAGS + build.SOURCE_FLAGS.get(src, []) +
