@@ -59,8 +59,8 @@ struct WorkUnit {
     int32_t tile;       // tile inside the period group
 };
 
-// Table variant: the 16-entry subset-sum tables of groups of four segments are joined in pairs
-// into 256-entry tables of eight segments (1 KB each), which the count reads.
+// Table variant: 256-entry subset-sum tables of groups of eight segments (1 KB each), each entry
+// the sum of the 16-entry subset sums of the group's two halves.
 constexpr int kGroup = 4;
 constexpr int kGroup8 = 2 * kGroup;
 // Eight-segment groups per register partial sum of the table variant: each fold into the map is a
@@ -81,7 +81,6 @@ struct TileSmemLut {
     double D[kChunk];
     double DC2[kEcc ? kChunk : 0];
     double DS2[kEcc ? kChunk : 0];
-    float T[(kChunk / kGroup) * 16];
 };
 
 template <int kChunk, bool kEcc>

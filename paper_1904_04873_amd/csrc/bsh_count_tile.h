@@ -416,6 +416,8 @@ __device__ __forceinline__ void count_tile_pair(const ItemDesc& d, int s, int ip
         flushed = true;
     };
     bool bad_range = false, bad_model = false;
+    // the rows' zero padding, which the chunks' copies leave as it is
+    for (int e = tid; e < kChunk * kRowPad; e += lanes) row[(e / kRowPad) * nwp + d.n_words + (e % kRowPad)] = 0u;
 
     for (int64_t j0 = 0; j0 < d.n_seg; j0 += kChunk) {
         const int nj = (int)min((int64_t)kChunk, d.n_seg - j0);
@@ -437,32 +439,50 @@ __device__ __forceinline__ void count_tile_pair(const ItemDesc& d, int s, int ip
                 sm.DS2[jj] = D * s2;
             }
         }
-        for (int e = tid; e < ng * kGroup * nwp; e += lanes) {
-            const int jj = e / nwp;
-            const int wd = e - jj * nwp;
-            row[e] = (jj < nj && wd < d.n_words) ? d.bits[(j0 + jj) * d.n_words + wd] : 0u;
-        }
-        for (int g = tid; g < ng; g += lanes) {
-            float w4[kGroup];
-#pragma unroll
-            for (int u = 0; u < kGroup; ++u) {
-                const int jj = g * kGroup + u;
-                w4[u] = jj < nj ? wrow[j0 + jj] : 0.f;
-            }
-            float* T = sm.T + g * 16;
-#pragma unroll
-            for (int m = 0; m < 16; ++m) {
-                float t = 0.f;
-#pragma unroll
-                for (int u = 0; u < kGroup; ++u)
-                    if (m & (1 << u)) t += w4[u];
-                T[m] = t;
+        // the rows' data words (their kRowPad zero words are written once, before the first chunk):
+        // word e of the chunk's rows is word wd of row jj, stepped without a division
+        {
+            const int nw = d.n_words;
+            const int n_e = ng * kGroup * nw;
+            int jj = tid / nw, wd = tid - jj * nw;
+            const int dq = lanes / nw, dr = lanes - dq * nw;
+            for (int e = tid; e < n_e; e += lanes) {
+                row[jj * nwp + wd] = jj < nj ? d.bits[(j0 + jj) * nw + wd] : 0u;
+                jj += dq;
+                wd += dr;
+                if (wd >= nw) { wd -= nw; ++jj; }
             }
         }
-        __syncthreads();
-        for (int e = tid; e < ng8 * 256; e += lanes) {
-            const int g = e >> 8, m = e & 255;
-            sm.T8[e] = sm.T[(2 * g) * 16 + (m & 15)] + sm.T[(2 * g + 1) * 16 + (m >> 4)];
+        // The 256-entry tables, 32 entries (two high nibbles) per work item: T8[16 h + l] =
+        // Tlo[l] + Thi[h], each half's subset sum taken in segment order from +0 (as a sum over the
+        // set bits, one weight at a time, would give it).
+        for (int it = tid; it < ng8 * 8; it += lanes) {
+            const int g = it >> 3, k8 = it & 7;
+            float w8[kGroup8];
+#pragma unroll
+            for (int u = 0; u < kGroup8; ++u) {
+                const int jj = g * kGroup8 + u;
+                w8[u] = jj < nj ? wrow[j0 + jj] : 0.f;
+            }
+            float lo[16];
+            lo[0] = 0.f;
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u)
+#pragma unroll
+                for (int l = 0; l < (1 << u); ++l) lo[(1 << u) + l] = lo[l] + w8[u];
+            // high nibbles 2 k8 (bit 0 clear) and 2 k8 + 1: bits 1..3 from k8
+            const float s5 = (k8 & 1) ? w8[5] : 0.f;
+            const float s6 = (k8 & 2) ? w8[6] : 0.f;
+            const float s7 = (k8 & 4) ? w8[7] : 0.f;
+            const float hi0 = ((0.f + s5) + s6) + s7;
+            const float hi1 = (((0.f + w8[4]) + s5) + s6) + s7;
+            float4* dst = reinterpret_cast<float4*>(sm.T8 + g * 256 + k8 * 32);
+#pragma unroll
+            for (int q4 = 0; q4 < 8; ++q4) {
+                const float hv = q4 < 4 ? hi0 : hi1;
+                const int l = (q4 & 3) * 4;
+                dst[q4] = make_float4(lo[l] + hv, lo[l + 1] + hv, lo[l + 2] + hv, lo[l + 3] + hv);
+            }
         }
         __syncthreads();
         if (!active) continue;
