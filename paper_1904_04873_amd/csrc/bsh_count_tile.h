@@ -1,12 +1,13 @@
 // Tile body of the stage-1 weighted number count (Sec. IV.C eq:hough2; the GPU loop K1 of
-// Sec. IV.B), shared by the plain kernel (bsh_count.hip) and the persistent kernel of the
-// batched plan (bsh_count_batch.hip).  Internal to libbsh.
+// Sec. IV.B), shared by the kernels of every launch form (bsh_count_kernels.h).  Internal to
+// libbsh.
 //
-// Work decomposition.  A tile is one sky pixel, one orbital period P and `lanes` binary
-// templates (a_p, t_asc) of that period; each lane owns one binary template and all n_f0
-// (<= 90) frequency bins of the band.  Segments stream through LDS in chunks: per segment the
-// block stages D cos(W t_J), D sin(W t_J) and D (W is the tile's, D_J the pixel's Doppler
-// factor), the weight (or the group subset sums) and the bit-packed peakgram row.
+// Work decomposition.  A tile is one sky pixel, one orbital period P and binary templates
+// (a_p, t_asc) of that period: in the select variant each of the `lanes` lanes owns one binary
+// template and all n_f0 (<= 90) frequency bins of the band; in the table variant two lanes share
+// one (count_tile_pair).  Segments stream through LDS in chunks: per segment the block stages
+// D cos(W t_J), D sin(W t_J) and D (W is the tile's, D_J the pixel's Doppler factor), the weight
+// (or the groups' subset-sum tables) and the bit-packed peakgram row.
 //
 // Per (lane, segment) G = D (1 - a_p W cos(W (t_J - t_asc))) is evaluated as track_G does in
 // every kernel, from the staged D C, D S and the lane's a_p W cos / sin(W t_asc).  The band's
