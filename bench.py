@@ -45,7 +45,11 @@ TABLE_OPS_PER_TS = {128: 300 / 360, 256: 300 / 360, 512: 302 / 360}
 SELECT_OPS_PER_TS = 3
 # HBM bytes per count launch, measured with rocprofv3 counters for one kernel source and tile
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hough_count_table_band200Hz_traffic.txt")
-BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hough_unit_table_1024items_traffic.txt")
+# per launch form of the batched count: the persistent kernel, or one block per queued unit
+BATCH_TRAFFIC_FILES = {True: os.path.join(ROOT, "profiles", "hough_batch_table_1024items_traffic.txt"),
+                       False: os.path.join(ROOT, "profiles", "hough_unit_table_1024items_traffic.txt")}
+BATCH_KERNELS = {True: "hough_batch_kernel<2, {chunk}> (persistent blocks pulling queued units from a counter; ",
+                 False: "hough_unit_kernel<2, {chunk}> (one block per queued unit; "}
 # the count kernels' sources and the build script (which holds their compiler flags)
 COUNT_SOURCES = ("paper_1904_04873_amd/csrc/bsh_count.hip", "paper_1904_04873_amd/csrc/bsh_count_table.hip",
                  "paper_1904_04873_amd/csrc/bsh_count_kernels.h", "paper_1904_04873_amd/csrc/bsh_count_tile.h",
@@ -232,8 +236,10 @@ def main():
     st = bsh.Status(dev)
     plan = bsh.Plan(items, grids, 4, k_item=k_item, k_band=k_band, lanes=lanes, chunk=chunk,
                     use_graph=True, lpt=True, status=st)
-    print(f"[bench] batched: tile {lanes} x {chunk}, {plan.units} units on {plan.blocks} blocks; "
-          f"{args.warmup} warmup + {args.steps} timed runs", file=sys.stderr, flush=True)
+    form = plan.persistent      # the library's choice of launch form
+    print(f"[bench] batched: tile {lanes} x {chunk}, {plan.units} units on {plan.blocks} blocks "
+          f"({'persistent' if form else 'one per unit'}); {args.warmup} warmup + {args.steps} timed runs",
+          file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         plan.run()
     torch.cuda.synchronize()
@@ -266,11 +272,11 @@ def main():
     count_ms = c0.elapsed_time(c1) / n_count
     print(f"[bench] batched {ms_step:.1f} ms/run, count kernel {count_ms:.1f} ms", file=sys.stderr, flush=True)
 
-    # the persistent launch form of the same plan (blocks pulling units from a queue counter),
-    # timed the same way, for comparison
+    # the other launch form of the same plan (persistent blocks pulling units from a queue
+    # counter, or one block per unit), timed the same way, for comparison
     plan.close()
     pp = bsh.Plan(items, grids, 4, k_item=k_item, k_band=k_band, lanes=lanes, chunk=chunk,
-                  use_graph=False, lpt=True, status=st, persistent=True)
+                  use_graph=False, lpt=True, status=st, persistent=not form)
     pp.run_count()
     torch.cuda.synchronize()
     c0.record()
@@ -278,9 +284,9 @@ def main():
         pp.run_count()
     c1.record()
     torch.cuda.synchronize()
-    st.raise_if_set("persistent count")
-    persistent_form = {"kernel": f"hough_batch_kernel<2, {chunk}>", "blocks": pp.blocks,
-                       "count_ms": c0.elapsed_time(c1) / n_count}
+    st.raise_if_set("other form count")
+    other_form = {"kernel": ("hough_unit_kernel" if form else "hough_batch_kernel") + f"<2, {chunk}>",
+                  "blocks": pp.blocks, "count_ms": c0.elapsed_time(c1) / n_count}
     pp.close()
     del pp
     plan = bsh.Plan(items, grids, 4, k_item=k_item, k_band=k_band, lanes=lanes, chunk=chunk,
@@ -349,13 +355,13 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": f"hough_unit_kernel<2, {chunk}> (one block per queued unit; subset-sum tables of 8 segments, "
-                      "two lanes per binary template)",
+            "kernel": BATCH_KERNELS[form].format(chunk=chunk) + "subset-sum tables of 8 segments, two lanes "
+                      "per binary template)",
             "achieved": achieved / 1e12,
             "peak": VALU_PEAK_OPS / 1e12,
             "unit": "TOP/s",
             "frac": achieved / VALU_PEAK_OPS,
-            "traffic": measured_traffic(lanes, chunk, BATCH_TRAFFIC_FILE, BATCH_SOURCES),
+            "traffic": measured_traffic(lanes, chunk, BATCH_TRAFFIC_FILES[form], BATCH_SOURCES),
             "count_kernel_ms": count_ms,
             "ops_per_template_segment": FLOOR_OPS_PER_TS,
             "floor": "algorithmic: per template and 8 segments one table read and one add; per (binary "
@@ -368,7 +374,7 @@ def main():
             "tile": {"lanes": lanes, "chunk": chunk},
             "units": units,
             "blocks": blocks,
-            "persistent_form": persistent_form,
+            "other_form": other_form,
             "autotune_ms": {f"{l}x{c}": t for (l, c), t in tune_ms.items()},
         },
         "cpu_baseline": cpu,

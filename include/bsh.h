@@ -373,9 +373,11 @@ typedef struct bsh_plan_opts {
     int32_t lpt;          /* 1: queue units longest-first */
     int32_t blocks;       /* persistent blocks (0: CUs x resident blocks per CU) */
     int32_t variant;      /* accumulation variant as in bsh_hough_count_ex */
-    int32_t persistent;   /* 0: one block per unit of the queue, dispatched in queue order (the
-                             default; the tile's registers then fit three waves per SIMD);
-                             1: persistent blocks that pull units from an atomic queue counter */
+    int32_t persistent;   /* 0: one block per unit of the queue, dispatched in queue order;
+                             1: persistent blocks that pull units from an atomic queue counter;
+                             < 0: the persistent blocks when as many of them are resident per CU
+                             as blocks of the one-block-per-unit form, else one block per unit
+                             (bsh_plan_persistent tells which) */
 } bsh_plan_opts;
 
 typedef struct bsh_plan bsh_plan;
@@ -393,7 +395,7 @@ int64_t bsh_items_map_floats(const bsh_item* items, int32_t n_items, const bsh_g
  *
  * Bounded memory: maps_floats may be smaller than bsh_items_map_floats (but not smaller than
  * the largest item's map); the items are then split, in order, into passes whose maps fit in
- * `maps` together, each pass one persistent launch followed by its items' lists, and `maps`
+ * `maps` together, each pass one count launch followed by its items' lists, and `maps`
  * is reused (it then holds the last pass's maps after a run).  This needs k_item > 0; the item
  * and band lists are the same as with room for every map, because the best k of a band are
  * among the best k of each of its items.  At most 65535 items.
@@ -403,20 +405,22 @@ int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh_grid* grid
                     float* item_score, int64_t* item_index, float* band_score, int64_t* band_index,
                     int32_t* status, bsh_plan** plan);
 
-/* One batched run: persistent count kernel, per-item lists, per-band lists (one graph launch). */
+/* One batched run: the count launch(es), per-item lists, per-band lists (one graph launch). */
 int bsh_plan_run(bsh_plan* plan, bsh_stream stream);
 
 /* The same results from one plain launch (plus its own top-k) per item, in item order. */
 int bsh_plan_run_plain(bsh_plan* plan, bsh_stream stream);
 
-/* The persistent count launches of a run alone (every pass, no lists; not graph-captured):
+/* The count launches of a run alone (every pass, no lists; not graph-captured):
  * the maps of the last pass, for timing the count kernel on its own. */
 int bsh_plan_run_count(bsh_plan* plan, bsh_stream stream);
 
 /* Number of queued units, blocks per launch (the persistent blocks, or the largest pass's unit
- * count with one block per unit) and passes of a plan (-1 for NULL). */
+ * count with one block per unit), launch form (1: persistent blocks, 0: one block per unit) and
+ * passes of a plan (-1 for NULL). */
 int64_t bsh_plan_units(const bsh_plan* plan);
 int32_t bsh_plan_blocks(const bsh_plan* plan);
+int32_t bsh_plan_persistent(const bsh_plan* plan);
 int32_t bsh_plan_passes(const bsh_plan* plan);
 
 int bsh_plan_destroy(bsh_plan* plan);

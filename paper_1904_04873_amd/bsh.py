@@ -534,12 +534,14 @@ class Plan:
     """A batched stage-1 run over many items (bsh_plan_create / _run / _run_plain).
 
     items: sequence of (DeviceSegments, grid index, sky_lo, n_sky, band), ordered by band.
+    persistent: True / False for the persistent or one-block-per-unit launch form, None for the
+    library's choice (the `persistent` property tells which).
     The plan keeps references to every tensor it points at."""
 
     def __init__(self, items, grids: Sequence[DeviceGrid], n_bands: int, k_item: int = 0,
                  k_band: int = 0, lanes: int = 0, chunk: int = 0, use_graph: bool = True,
                  lpt: bool = True, blocks: int = 0, variant: int = 0, status: Optional[Status] = None,
-                 device="cuda", map_floats: Optional[int] = None, persistent: bool = False):
+                 device="cuda", map_floats: Optional[int] = None, persistent: Optional[bool] = None):
         L = N.load()
         self._keep = [items, grids]
         self.n_items = len(items)
@@ -565,7 +567,7 @@ class Plan:
         self.status = status if status is not None else Status(device)
         opts = N.PlanOpts(lanes=int(lanes), chunk=int(chunk), k_item=self.k_item, k_band=self.k_band,
                           use_graph=int(bool(use_graph)), lpt=int(bool(lpt)), blocks=int(blocks),
-                          variant=int(variant), persistent=int(bool(persistent)))
+                          variant=int(variant), persistent=-1 if persistent is None else int(bool(persistent)))
         h = ctypes.c_void_p()
         check(L.bsh_plan_create(arr_i, self.n_items, arr_g, len(grids), self.n_bands, ctypes.byref(opts),
                                 _ptr(self.maps), self.maps.numel(), _ptr(self.item_score),
@@ -602,6 +604,10 @@ class Plan:
     @property
     def blocks(self) -> int:
         return int(N.load().bsh_plan_blocks(self.h))
+
+    @property
+    def persistent(self) -> bool:
+        return int(N.load().bsh_plan_persistent(self.h)) == 1
 
     def close(self) -> None:
         if getattr(self, "h", None):

@@ -1,6 +1,7 @@
-// Batched stage 1 over many work items (sky patches x bands) with uneven sizes: one
-// persistent launch whose blocks pull (item, pixel, period, tile) units from a queue ordered
-// longest-first, then per-item and per-band top-lists, all captured in one HIP graph.
+// Batched stage 1 over many work items (sky patches x bands) with uneven sizes: one launch over
+// a queue of (item, pixel, period, tile) units ordered longest-first (persistent blocks pulling
+// units from a counter, or one block per unit), then per-item and per-band top-lists, all
+// captured in one HIP graph.
 //
 // The paper splits a search into independent band x sky-patch x binary-block jobs (eq:cost)
 // and notes that the GPU idles while the host prepares the next job; here the whole set of
@@ -9,7 +10,7 @@
 // Bounded memory.  A search keeps only the top candidates of each band (Sec. IV.C), and the
 // stage-1 maps of a whole band of sky patches do not fit in HBM (eq:RAM1 counts them per patch).
 // When the caller's map buffer is smaller than all maps together, the items are split, in
-// order, into passes whose maps fit in it; each pass is one persistent launch followed by the
+// order, into passes whose maps fit in it; each pass is one count launch followed by the
 // top-k of each of its items, after which the buffer is reused.  The per-band lists are then
 // merged from the item lists, which is exact: the best k of a union are among the best k of
 // each part.
@@ -122,7 +123,7 @@ int zero_empty_items(bsh_plan* p, int32_t lo, int32_t hi, hipStream_t s)
     return BSH_OK;
 }
 
-// The persistent count launches of every pass, each followed (when lists are asked for) by
+// The count launches of every pass, each followed (when lists are asked for) by
 // the top-k of each of its items; then the band lists.
 int enqueue_batched(bsh_plan* p, hipStream_t s, bool count_only)
 {
@@ -218,7 +219,6 @@ extern "C" int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh
     for (int32_t q = 0; q < n_grids; ++q) ecc = std::max(ecc, ecc_mode(&grids[q]));
     p->mode = kernel_mode(o.variant, false) + ecc;
     p->use_graph = o.use_graph != 0;
-    p->persistent = o.persistent != 0;
     p->maps = maps;
     p->band_score = band_score;
     p->band_index = band_index;
@@ -320,8 +320,14 @@ extern "C" int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh
         delete p;
         return BSH_EHIP;
     }
-    // persistent form: CUs x resident blocks; else the largest pass's unit count
-    p->blocks = std::max(1, n_cu) * batch_blocks_per_cu(lanes, chunk, p->mode, p->n_words);
+    // Launch form: asked for, or (persistent < 0) the persistent blocks when as many of them fit
+    // per CU as blocks of the one-block-per-unit form (both are bound by the tile's registers and
+    // LDS; the persistent loop keeps more registers live, and with fewer resident blocks it is the
+    // slower form).  Persistent form: CUs x resident blocks; else the largest pass's unit count.
+    const int per_cu = batch_blocks_per_cu(lanes, chunk, p->mode, p->n_words, true);
+    p->persistent = o.persistent > 0 ||
+                    (o.persistent < 0 && per_cu >= batch_blocks_per_cu(lanes, chunk, p->mode, p->n_words, false));
+    p->blocks = std::max(1, n_cu) * per_cu;
     if (o.blocks > 0) p->blocks = o.blocks;
     if (!p->persistent) {
         int64_t widest = 0;
@@ -443,6 +449,8 @@ extern "C" int bsh_plan_run_plain(bsh_plan* p, bsh_stream stream)
 extern "C" int64_t bsh_plan_units(const bsh_plan* p) { return p ? p->n_units : -1; }
 
 extern "C" int32_t bsh_plan_blocks(const bsh_plan* p) { return p ? p->blocks : -1; }
+
+extern "C" int32_t bsh_plan_persistent(const bsh_plan* p) { return p ? (p->persistent ? 1 : 0) : -1; }
 
 extern "C" int32_t bsh_plan_passes(const bsh_plan* p) { return p ? p->n_passes() : -1; }
 

@@ -111,13 +111,14 @@ int launch_plain(const PlainLaunch& p, int64_t blocks, int lanes, int chunk, int
 // persistent: blocks pull units from *counter (zeroed beforehand); else one block per unit.
 int launch_batch(const ItemDesc* items, const WorkUnit* units, int64_t n_units, uint32_t* counter,
                  int blocks, int lanes, int chunk, int mode, int n_words, bool persistent, hipStream_t stream);
-int batch_blocks_per_cu(int lanes, int chunk, int mode, int n_words);
+// Resident blocks per CU of the persistent form (or, persistent false, of one block per unit).
+int batch_blocks_per_cu(int lanes, int chunk, int mode, int n_words, bool persistent = true);
 // The table variant's launchers (bsh_count_table.hip); lds: the block's LDS bytes.
 int launch_plain_table(const PlainLaunch& p, int64_t blocks, int lanes, int chunk, int mode, size_t lds,
                        hipStream_t stream);
 int launch_batch_table(const ItemDesc* items, const WorkUnit* units, int64_t n_units, uint32_t* counter, int blocks,
                        int lanes, int chunk, int mode, size_t lds, bool persistent, hipStream_t stream);
-int occupancy_table(int lanes, int chunk, int mode, size_t lds);
+int occupancy_table(int lanes, int chunk, int mode, size_t lds, bool persistent);
 int allow_lds(const void* kernel, size_t bytes);
 int kernel_mode(int variant, bool with_count);
 // kEccMode for a grid with an eccentricity pair, else 0 (added to kernel_mode's value)

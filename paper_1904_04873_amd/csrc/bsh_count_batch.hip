@@ -22,19 +22,20 @@ int launch_batch(const ItemDesc* items, const WorkUnit* units, int64_t n_units, 
     return check_launch("batched count");
 }
 
-static int occupancy_select(int lanes, int chunk, int mode, size_t lds)
+static int occupancy_select(int lanes, int chunk, int mode, size_t lds, bool persistent)
 {
     int n = 0;
-#define BSH_OCC(M, C) n = occupancy_mc<M, C>(lanes, lds)
+#define BSH_OCC(M, C) n = occupancy_mc<M, C>(lanes, lds, persistent)
     BSH_DISPATCH_SELECT(mode, chunk, BSH_OCC)
 #undef BSH_OCC
     return n;
 }
 
-int batch_blocks_per_cu(int lanes, int chunk, int mode, int n_words)
+int batch_blocks_per_cu(int lanes, int chunk, int mode, int n_words, bool persistent)
 {
     const size_t lds = smem_bytes_of(mode, chunk, n_words);
-    const int n = is_table_mode(mode) ? occupancy_table(lanes, chunk, mode, lds) : occupancy_select(lanes, chunk, mode, lds);
+    const int n = is_table_mode(mode) ? occupancy_table(lanes, chunk, mode, lds, persistent)
+                                      : occupancy_select(lanes, chunk, mode, lds, persistent);
     return n < 1 ? 1 : n;
 }
 

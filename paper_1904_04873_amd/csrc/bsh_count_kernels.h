@@ -89,15 +89,18 @@ int launch_batch_mc(const ItemDesc* items, const WorkUnit* units, int64_t n_unit
     return BSH_OK;
 }
 
-// Resident blocks per CU of the persistent form (0 when the occupancy query fails).
+// Resident blocks per CU of the persistent form, or of the one-block-per-unit form (0 when the
+// occupancy query fails).
 template <int kMode, int kChunk>
-int occupancy_mc(int lanes, size_t lds)
+int occupancy_mc(int lanes, size_t lds, bool persistent)
 {
     int n = 0;
-    if (allow_lds((const void*)hough_batch_kernel<kMode, kChunk>, lds) != BSH_OK) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, hough_batch_kernel<kMode, kChunk>, lanes, lds) != hipSuccess)
-        return 0;
-    return n;
+    const void* k = persistent ? (const void*)hough_batch_kernel<kMode, kChunk> : (const void*)hough_unit_kernel<kMode, kChunk>;
+    if (allow_lds(k, lds) != BSH_OK) return 0;
+    const hipError_t e = persistent
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, hough_batch_kernel<kMode, kChunk>, lanes, lds)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, hough_unit_kernel<kMode, kChunk>, lanes, lds);
+    return e == hipSuccess ? n : 0;
 }
 
 }  // namespace bsh

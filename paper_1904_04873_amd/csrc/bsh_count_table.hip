@@ -28,10 +28,10 @@ int launch_batch_table(const ItemDesc* items, const WorkUnit* units, int64_t n_u
     return rc;
 }
 
-int occupancy_table(int lanes, int chunk, int mode, size_t lds)
+int occupancy_table(int lanes, int chunk, int mode, size_t lds, bool persistent)
 {
     int n = 0;
-#define BSH_OCC(M, C) n = occupancy_mc<M, C>(lanes, lds)
+#define BSH_OCC(M, C) n = occupancy_mc<M, C>(lanes, lds, persistent)
     BSH_DISPATCH_TABLE(mode, chunk, BSH_OCC)
 #undef BSH_OCC
     return n;

@@ -51,7 +51,8 @@ def test_batched_equals_plain_and_single_item(setup):
     import torch
     w, bsh, items, grids, hosts, n_bands = setup
     _say("batched vs plain vs single")
-    plan = bsh.Plan(items, grids, n_bands, k_item=500, k_band=300, use_graph=False)
+    plan = bsh.Plan(items, grids, n_bands, k_item=500, k_band=300, use_graph=False, persistent=False)
+    assert not plan.persistent
     plan.run()
     torch.cuda.synchronize()
     plan.status.raise_if_set("batched")
@@ -75,9 +76,10 @@ def test_batched_equals_plain_and_single_item(setup):
         assert torch.equal(ws, plan.item_map(q)), f"item {q}"
     plan.close()
     # the persistent launch form (blocks pulling units from a queue counter) gives the same maps
-    # and lists, also with fewer blocks than CUs
-    for blocks in (0, 7):
-        pp = bsh.Plan(items, grids, n_bands, k_item=500, k_band=300, use_graph=False, persistent=True, blocks=blocks)
+    # and lists, also with fewer blocks than CUs, and so does the library's choice of form
+    for blocks, form in ((0, True), (7, True), (0, None)):
+        pp = bsh.Plan(items, grids, n_bands, k_item=500, k_band=300, use_graph=False, persistent=form, blocks=blocks)
+        assert form is None or pp.persistent == form
         pp.run()
         torch.cuda.synchronize()
         pp.status.raise_if_set("persistent")
