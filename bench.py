@@ -489,7 +489,20 @@ def run_band200(args):
     c1.record()
     torch.cuda.synchronize()
     count_ms = c0.elapsed_time(c1) / n_count
-    print(f"[bench] band 200 Hz: {ms_step:.3f} ms/step, count kernel {count_ms:.3f} ms", file=sys.stderr, flush=True)
+    # the same count on the ELL1 track: the band's grid with an eccentricity pair
+    g_e = bsh.DeviceGrid.build(spec, seg.t_span_mid(), w.sky, ecc=(1e-3, 5e-4))
+    for _ in range(2):
+        bsh.bsh_hough_count(ds, g_e, status=st, wsum_out=ws_map, lanes=lanes, chunk=chunk)
+    c0.record()
+    for _ in range(n_count):
+        bsh.bsh_hough_count(ds, g_e, status=st, wsum_out=ws_map, lanes=lanes, chunk=chunk)
+    c1.record()
+    torch.cuda.synchronize()
+    st.raise_if_set("band ELL1 count")
+    count_ecc_ms = c0.elapsed_time(c1) / n_count
+    del g_e
+    print(f"[bench] band 200 Hz: {ms_step:.3f} ms/step, count kernel {count_ms:.3f} ms (ELL1 track {count_ecc_ms:.3f} ms)",
+          file=sys.stderr, flush=True)
     out = {
         "workload": "band 200.0-200.1 Hz: 4000 segments (2 detectors x 2000, gapped), 1 sky pixel, 90 f0 x "
                     "64 a_p x 32 P x 64 t_asc = 11796480 templates; stage-1 weighted count -> top-10^4 -> "
@@ -502,6 +515,8 @@ def run_band200(args):
                          "frac_issued_fast_path": TABLE_OPS_PER_TS[chunk] * ts_per_step / (count_ms / 1e3) / VALU_PEAK_OPS,
                          "traffic": measured_traffic(lanes, chunk), "tile": {"lanes": lanes, "chunk": chunk},
                          "autotune_ms": {f"{l}x{c}": t for (l, c), t in tune_ms.items()}},
+        "count_kernel_ell1": {"kernel": f"hough_count_kernel<5, {chunk}>", "ecc": [1e-3, 5e-4], "ms": count_ecc_ms,
+                              "value": ts_per_step / (count_ecc_ms / 1e3)},
     }
     out["post"] = run_post(bsh, ds, g, s1_score, s1_index, seg.t_coh, seg.t_span_mid(), st)
     out["refine"] = run_refine(bsh, spec, st)

@@ -588,11 +588,14 @@ __device__ __forceinline__ void run_tile(const ItemDesc& d, int s, int ip, int64
     }
 }
 
-// Launch-bounds hint of the blocks per CU: two for the table variant, one for the select
-// variants (whose 90 partial sums, and 90 counts, fill the registers).  The table variant's
-// register allocation comes out at about 155 registers, so three waves per SIMD fit.
+// Launch bound: the least waves per SIMD the register allocation must allow.  The circular
+// table variant comes out at 155-168 registers, three waves, with the bound at two: bounding it
+// to three makes the ILP scheduler keep two table reads in flight instead of eight (22 % slower).
+// The ELL1 table variant needs 171-183 registers unbounded (two waves); bounded to three it
+// spills a few and is faster (200 Hz band 2.05 -> 1.88 ms, batched launch 651 -> 462 ms on 256
+// items).  The select variants hold 90 partial sums (and counts): one.
 template <int kMode>
-constexpr int min_blocks() { return kMode % kEccMode == 2 ? 2 : 1; }
+constexpr int min_blocks() { return kMode == kEccMode + 2 ? 3 : (kMode % kEccMode == 2 ? 2 : 1); }
 
 // Instantiate a kernel template for every (mode, chunk) of the select variants (modes 0, 1 and
 // their ELL1 forms 3, 4) or of the table variant (modes 2, 5) and call f with the chosen one.  The
