@@ -176,11 +176,14 @@ int bsh_hough_count(const bsh_segments* seg, const bsh_grid* grid, uint32_t* cou
  * Same as bsh_hough_count with an explicit tile shape and accumulation variant: `lanes` binary
  * templates per block (64, 128, 256 or 512), `chunk` segments staged in LDS per pass (128, 256
  * or 512), and `variant`:
- *   BSH_VARIANT_SELECT  every peak bit selects its weight, which is added;
+ *   BSH_VARIANT_SELECT  every peak bit selects its weight, which is added (and counted);
  *   BSH_VARIANT_TABLE   segments in groups of eight, whose 256 subset sums of weights are looked
- *                       up with the eight peak bits as index (weighted sums only);
- *   BSH_VARIANT_AUTO    the table unless counts are requested (the default of bsh_hough_count).
- * Results do not depend on the tile shape; the two variants agree to FP32 rounding.
+ *                       up with the eight peak bits as index;
+ *   BSH_VARIANT_AUTO    the table (the default of bsh_hough_count).
+ * Counts with the table (AUTO or TABLE, fewer than 2^24 segments) are the table's sums with every
+ * weight one, exact in FP32 and so the same counts bit for bit, computed in a launch of their own
+ * (after the weighted sums' launch when both are asked for).  Results do not depend on the tile
+ * shape; the two variants' weighted sums agree to FP32 rounding, their counts exactly.
  */
 #define BSH_VARIANT_AUTO 0
 #define BSH_VARIANT_SELECT 1

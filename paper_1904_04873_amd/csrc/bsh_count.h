@@ -103,6 +103,7 @@ int64_t plan_tiles(const bsh_grid* g, int lanes, int32_t* tile_start, int64_t* g
 void fill_desc(ItemDesc& d, const bsh_segments* seg, const bsh_grid* grid, int32_t sky_lo,
                int32_t n_sky, uint32_t* count_out, float* wsum_out, int32_t* status);
 int zero_words(void* p, int64_t n_words, hipStream_t stream);
+int floats_to_counts(uint32_t* p, int64_t n, hipStream_t stream);
 // mode: 0 select-and-add (weighted sums), 1 select-and-add with counts, 2 subset-sum tables;
 // plus kEccMode for the same on the ELL1 track
 // n_words: the widest staged row of the launch (sizes the rows' LDS region).

@@ -68,6 +68,22 @@ __global__ void fill_zero_kernel(uint32_t* p, int64_t n)
         p[e] = 0u;
 }
 
+// In place: the exact integer-valued floats of a unit-weight count become uint32 counts.
+__global__ void floats_to_counts_kernel(uint32_t* p, int64_t n)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = (uint32_t)__uint_as_float(p[e]);
+}
+
+int floats_to_counts(uint32_t* p, int64_t n, hipStream_t stream)
+{
+    if (n <= 0) return BSH_OK;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(floats_to_counts_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, p, n);
+    return check_launch("count conversion");
+}
+
 int zero_words(void* p, int64_t n_words, hipStream_t stream)
 {
     if (n_words <= 0 || !p) return BSH_OK;
@@ -147,8 +163,14 @@ extern "C" int bsh_hough_count_ex(const bsh_segments* seg, const bsh_grid* grid,
 
     PlainLaunch p;
     std::memset(&p, 0, sizeof(p));
-    fill_desc(p.d, seg, grid, 0, grid->n_sky, count_out, wsum_out, status);
-    const int mode = kernel_mode(variant, count_out != nullptr) + ecc_mode(grid);
+    // Counts from the table variant: the weighted count with every weight one, whose sums of small
+    // integers are exact in FP32 (below 2^24), written as floats into count_out and converted there
+    // (a second launch when the weighted sums are asked for too); the select variant, whose
+    // partial sums and counts take more registers than a wave has, counts on request.
+    const bool table_counts = count_out && variant != BSH_VARIANT_SELECT && seg->n_seg < ((int64_t)1 << 24);
+    fill_desc(p.d, seg, grid, 0, grid->n_sky, table_counts ? nullptr : count_out, wsum_out, status);
+    const int mode = (table_counts ? kernel_mode(BSH_VARIANT_TABLE, false) : kernel_mode(variant, count_out != nullptr)) +
+                     ecc_mode(grid);
     const int64_t tiles = plan_tiles(grid, tile_templates(mode, lanes), p.tile_start, nullptr);
     p.tiles_per_sky = (int32_t)tiles;
     const int64_t blocks = tiles * grid->n_sky;
@@ -162,7 +184,18 @@ extern "C" int bsh_hough_count_ex(const bsh_segments* seg, const bsh_grid* grid,
         if (rc) return rc;
         return zero_words(count_out, count_out ? n_t : 0, s);
     }
-    return launch_plain(p, blocks, lanes, chunk, mode, p.d.n_words, s);
+    if (!table_counts) return launch_plain(p, blocks, lanes, chunk, mode, p.d.n_words, s);
+    if (wsum_out) {
+        rc = launch_plain(p, blocks, lanes, chunk, mode, p.d.n_words, s);
+        if (rc) return rc;
+    }
+    PlainLaunch pc = p;
+    pc.d.w = nullptr;
+    pc.d.w_per_sky = 0;
+    pc.d.wsum_out = reinterpret_cast<float*>(count_out);
+    rc = launch_plain(pc, blocks, lanes, chunk, mode, pc.d.n_words, s);
+    if (rc) return rc;
+    return floats_to_counts(count_out, (int64_t)grid->n_sky * p.d.n_bin * grid->n_f0, s);
 }
 
 extern "C" int bsh_hough_count(const bsh_segments* seg, const bsh_grid* grid, uint32_t* count_out,

@@ -371,7 +371,8 @@ __device__ __forceinline__ void count_tile_pair(const ItemDesc& d, int s, int ip
 
     const int sg = d.sky_lo + s;
     const double nx = d.sky[3 * sg], ny = d.sky[3 * sg + 1], nz = d.sky[3 * sg + 2];
-    const float* wrow = d.w + (d.w_per_sky ? (int64_t)s * d.n_seg : 0);
+    // NULL weights: every weight is one (the sums are then the unweighted counts)
+    const float* wrow = d.w ? d.w + (d.w_per_sky ? (int64_t)s * d.n_seg : 0) : nullptr;
     const double F0 = (double)d.k0;
     const int last = d.n_f0 - 1;
     const double FL = (double)(d.k0 + last);
@@ -463,7 +464,7 @@ __device__ __forceinline__ void count_tile_pair(const ItemDesc& d, int s, int ip
 #pragma unroll
             for (int u = 0; u < kGroup8; ++u) {
                 const int jj = g * kGroup8 + u;
-                w8[u] = jj < nj ? wrow[j0 + jj] : 0.f;
+                w8[u] = jj < nj ? (wrow ? wrow[j0 + jj] : 1.f) : 0.f;
             }
             float lo[16];
             lo[0] = 0.f;

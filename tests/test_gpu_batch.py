@@ -165,15 +165,17 @@ def test_every_tile_shape_gives_identical_maps(setup):
     g = grids[gi]
     g1 = bsh.DeviceGrid.from_tables(_np(g.sky)[lo:lo + 1], g.k0, g.n_f0, g.a_p, g.period, g.tasc_off,
                                     _np(g.t_asc_dev))
-    ref, rc = bsh.bsh_hough_count(ds, g1, with_count=True)
-    ref_t, _ = bsh.bsh_hough_count(ds, g1, variant=2)
+    ref, rc = bsh.bsh_hough_count(ds, g1, with_count=True, variant=1)      # select, with counts
+    ref_t, rc_t = bsh.bsh_hough_count(ds, g1, with_count=True)            # table, counts with unit weights
+    torch.cuda.synchronize()
+    assert torch.equal(rc, rc_t)
     for lanes in (64, 128, 256, 512):
         for chunk in (128, 256, 512):
-            ws, c = bsh.bsh_hough_count(ds, g1, with_count=True, lanes=lanes, chunk=chunk)
-            wt, _ = bsh.bsh_hough_count(ds, g1, lanes=lanes, chunk=chunk, variant=2)
+            ws, c = bsh.bsh_hough_count(ds, g1, with_count=True, lanes=lanes, chunk=chunk, variant=1)
+            wt, ct = bsh.bsh_hough_count(ds, g1, with_count=True, lanes=lanes, chunk=chunk)
             torch.cuda.synchronize()
             assert torch.equal(ws, ref) and torch.equal(c, rc), (lanes, chunk)
-            assert torch.equal(wt, ref_t), (lanes, chunk)
+            assert torch.equal(wt, ref_t) and torch.equal(ct, rc), (lanes, chunk)
     for variant, want in ((1, ref), (2, ref_t)):
         one = [(ds, 0, lo, ns, 0)]          # the item's grid is the only grid of this plan
         plan = bsh.Plan(one, [g], 1, lanes=64, chunk=512, use_graph=False, lpt=False, variant=variant)
@@ -251,11 +253,14 @@ def test_two_whole_items_against_the_oracle_map(setup):
         for m in (_np(plan.item_map(q)), _np(tab.item_map(q))):
             err = np.abs(m.astype(np.float64) - nw_o)
             assert np.all(err <= 1e-5 * nw_o + ntw_o + 1e-30), f"item {ITEMS[q]}: max rel {np.max(err / np.maximum(nw_o, 1e-30))}"
-        # unweighted counts: the select variant with counts, standalone on the item's pixel
+        # unweighted counts, standalone on the item's pixel: the table variant's (unit weights) and
+        # the select variant's, the same bit for bit
         g1 = bsh.DeviceGrid.from_tables(_np(g.sky)[lo:lo + 1], g.k0, g.n_f0, g.a_p, g.period, g.tasc_off,
                                         _np(g.t_asc_dev))
         _, c = bsh.bsh_hough_count(ds, g1, with_count=True)
+        _, c_s = bsh.bsh_hough_count(ds, g1, with_count=True, variant=1)
         torch.cuda.synchronize()
+        assert torch.equal(c, c_s)
         c = _np(c).view(np.uint32).astype(np.int64)
         assert np.all(np.abs(c - cnt_o.astype(np.int64)) <= nt_o), f"item {ITEMS[q]} counts"
         _say(f"item {ITEMS[q]}: near-tie templates {int((nt_o > 0).sum())}")

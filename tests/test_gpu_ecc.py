@@ -74,6 +74,9 @@ def test_ecc_count_matches_oracle_map(B, e):
     _check_counts(cnt, ws, cnt_o, nw_o, nt_o, ntw_o)
     ws_t, _ = _count(B, ds, g, 2, False)
     _check_counts(None, ws_t, cnt_o, nw_o, nt_o, ntw_o)
+    # counts from the table variant (unit weights): the select variant's, bit for bit
+    ws_tc, cnt_t = _count(B, ds, g, 2, True)
+    assert np.array_equal(cnt_t, cnt) and np.array_equal(ws_tc, ws_t)
     # the eccentric terms move bins: the circular map differs
     ws_c, _ = _count(B, ds, g.with_ecc(0.0, 0.0), 2, False)
     assert not np.array_equal(ws_c, ws_t)

@@ -110,15 +110,17 @@ def test_count_weighted_several_tiles(B):
     ds, g, o, ws, cnt = _run_count(B, seg, spec, w.sky)
     cnt_o, nw_o, nt_o, ntw_o = O.hough_count(seg, w.sky, spec.k0, spec.n_f0, *o)
     _check_counts(cnt, ws, cnt_o, nw_o, nt_o, ntw_o)
-    # both accumulation variants without counts: same oracle bar, and the select variant
-    # without counts sums in the same order as with counts
+    # both accumulation variants without counts: same oracle bar; each sums in the same order with
+    # and without counts (the default counts with the table variant), and the select variant's
+    # counts are the table's, bit for bit
     import torch
+    ws1c, c1 = B.bsh_hough_count(ds, g, with_count=True, variant=1)
     for variant in (1, 2):
         ws2, _ = B.bsh_hough_count(ds, g, with_count=False, variant=variant)
         torch.cuda.synchronize()
         _check_counts(cnt_o, _np(ws2), cnt_o, nw_o, nt_o, ntw_o)
-        if variant == 1:
-            assert np.array_equal(_np(ws2), ws)
+        assert np.array_equal(_np(ws2), _np(ws1c) if variant == 1 else ws)
+    assert np.array_equal(_np(c1).view(np.uint32), cnt)
 
 
 def test_count_ragged_rule_grid_multisky_per_sky_weights(B):
@@ -186,14 +188,15 @@ def test_count_config2_full_map_against_oracle(B, cfg2_injected):
     ds = B.DeviceSegments.from_host(seg)
     g, o2 = _grid_pair(B, spec, seg, w.sky)
     st = _status(B)
-    ws, cnt = B.bsh_hough_count(ds, g, with_count=True, status=st)
-    ws_t, _ = B.bsh_hough_count(ds, g, status=st)          # default: table variant, as the benchmark runs it
+    ws, cnt = B.bsh_hough_count(ds, g, with_count=True, status=st, variant=1)    # select, with counts
+    ws_t, cnt_t = B.bsh_hough_count(ds, g, with_count=True, status=st)  # default: table, as the benchmark runs it
     torch.cuda.synchronize()
     st.raise_if_set("count")
-    ws, cnt, ws_t = _np(ws), _np(cnt).view(np.uint32), _np(ws_t)
+    ws, cnt, ws_t, cnt_t = _np(ws), _np(cnt).view(np.uint32), _np(ws_t), _np(cnt_t).view(np.uint32)
     assert ws.size == 11796480
     _check_counts(cnt, ws, cnt_o, nw_o, nt_o, ntw_o)
-    _check_counts(cnt_o, ws_t, cnt_o, nw_o, nt_o, ntw_o)
+    _check_counts(cnt_t, ws_t, cnt_o, nw_o, nt_o, ntw_o)
+    assert np.array_equal(cnt, cnt_t)
     n_tie = int((nt_o > 0).sum())
     _say(f"templates with a near-tie segment: {n_tie}")
     if n_tie == 0:
