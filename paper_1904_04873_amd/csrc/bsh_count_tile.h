@@ -293,11 +293,10 @@ __device__ __forceinline__ void count_tile(const ItemDesc& d, int s, int ip, int
 // than lane 0 (its mask bit i + 4 holds bin i).  Per group each lane transposes its four masks (a
 // 4 x 4 bit transpose per nibble column: word A[w][t] holds in nibble n the four segments' bits
 // of the lane's bin 32 w + 4 n + t, minus 4 on lane 1), and both lanes of the pair swap the same
-// word A[w][t].  Merging the low nibbles of lane 0's word with the high nibbles of lane 1's gives,
-// on both lanes, the byte indices (first four segments low, last four high) of bins
-// 32 w + 8 j + t; the word moved down by one nibble (with the next word's first nibble on top)
-// holds those of bins 32 w + 8 j + 4 + t.  Lane 0 takes the first, lane 1 the second, so the
-// exchange needs no select.  The indices are split into 16-bit halves, each turned into its table
+// word A[w][t].  Each lane merges its own low nibbles with its partner's high nibbles: on lane 0
+// the merged word's bytes are the indices (first four segments low, last four high) of bins
+// 32 w + 8 j + t, and on lane 1 the merged word moved down by one nibble (with the next word's
+// first nibble on top) holds those of bins 32 w + 8 j + 4 + t, so the exchange needs no select.  The indices are split into 16-bit halves, each turned into its table
 // address by one multiply-add, and every bin of the lane costs that address (and half a split)
 // and one FP32 add per eight segments.  The register partial sums (at most kFlushGroups groups
 // each) are folded into the lane's own slots of the output map, bounding the FP32 error by
