@@ -313,6 +313,28 @@ def bsh_topk(score: torch.Tensor, k: int, index: Optional[torch.Tensor] = None):
     return TopK(score.numel(), k, score.device)(score, index)
 
 
+def bsh_topk_segmented(score: torch.Tensor, offsets: np.ndarray, k: int, index: Optional[torch.Tensor] = None,
+                       index_shift: int = 0):
+    """Independent top-k lists of the segments score[offsets[g] .. offsets[g+1]):
+    (scores float32 [n_segs, k], indices int64 [n_segs, k])."""
+    assert score.dtype == torch.float32 and score.is_contiguous()
+    if index is not None:
+        assert index.dtype == torch.int64 and index.is_contiguous() and index.numel() == score.numel()
+    dev = score.device
+    off_h = np.ascontiguousarray(offsets, dtype=np.int64)
+    n_segs = off_h.size - 1
+    off_d = torch.from_numpy(off_h).to(dev)
+    L = N.load()
+    wsb = int(L.bsh_topk_segmented_workspace(n_segs, int(k)))
+    ws = torch.empty(max(1, wsb), dtype=torch.uint8, device=dev)
+    out_s = torch.empty((n_segs, k), dtype=torch.float32, device=dev)
+    out_i = torch.empty((n_segs, k), dtype=torch.int64, device=dev)
+    check(L.bsh_topk_segmented(_ptr(score), _ptr(index), _ptr(off_d), off_h.ctypes.data_as(ctypes.c_void_p),
+                               n_segs, int(k), int(index_shift), _ptr(out_s), _ptr(out_i), _ptr(ws), wsb,
+                               _stream()), "bsh_topk_segmented")
+    return out_s, out_i
+
+
 def bsh_topk_noalloc(score: torch.Tensor, k: int, index: Optional[torch.Tensor] = None,
                      out_score: Optional[torch.Tensor] = None, out_index: Optional[torch.Tensor] = None):
     """bsh_topk through the library's static per-GPU workspace (the library allocates nothing;

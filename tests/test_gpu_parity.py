@@ -475,6 +475,34 @@ def test_topk_with_index_array_merges_lists(B, per, k):
     assert np.array_equal(_np(ix2), ri)
 
 
+@pytest.mark.parametrize("explicit", [False, True])
+def test_topk_segmented_many_lists_with_ties(B, explicit):
+    """700 lists of 0 .. 40000 integer scores (ties at every cut), k = 300, implicit indices
+    (g << 40) | position or explicit ones: every list against the oracle's sort."""
+    import torch
+    _say(f"segmented top-k, 700 lists, explicit={explicit}")
+    rng = np.random.default_rng(5 + explicit)
+    lens = rng.integers(0, 40000, 700)
+    lens[:3] = (0, 1, 299)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    sc = rng.integers(0, 40, int(off[-1])).astype(np.float32)
+    k, shift = 300, 40
+    if explicit:
+        idx = rng.permutation(2 * sc.size)[:sc.size].astype(np.int64) + (7 << 45)
+        vs, ix = B.bsh_topk_segmented(torch.from_numpy(sc).cuda(), off, k, index=torch.from_numpy(idx).cuda())
+    else:
+        vs, ix = B.bsh_topk_segmented(torch.from_numpy(sc).cuda(), off, k, index_shift=shift)
+    torch.cuda.synchronize()
+    vs, ix = _np(vs), _np(ix)
+    for g in range(len(lens)):
+        a, b = int(off[g]), int(off[g + 1])
+        own = idx[a:b] if explicit else (np.int64(g) << shift) | np.arange(b - a, dtype=np.int64)
+        rv, ri = _topk_ref(sc[a:b], k, own)
+        kk = min(k, b - a)
+        assert np.array_equal(ix[g, :kk], ri[:kk]) and np.array_equal(vs[g, :kk], rv[:kk]), g
+        assert np.all(ix[g, kk:] == -1) and np.all(np.isneginf(vs[g, kk:])), g
+
+
 # ---------------------------------------------------------------- stage 2
 
 def _cands(seg, n, k0, seed, n_sky=1, spread=89.0):
