@@ -814,15 +814,12 @@ int topk_launch(Seg s, int64_t max_len, float* out_score, int64_t* out_index, hi
     for (int pass = 0; pass < kKeyPasses; ++pass)
         hipLaunchKernelGGL(key_hist_kernel, grid2, dim3(kThreads), 0, st, s, pass);
     hipLaunchKernelGGL(split_kernel, grid2, dim3(kThreads), 0, st, s);
-    // The tie passes usually find nothing to resolve and return at once; their grids are cut to
-    // about 4096 blocks in all (still filling the device when ties must be resolved), so that
-    // the early returns cost little (with 1024 long segments, four launches of 10^6 blocks took
-    // 1.5 ms).
-    const int tie_bps = std::max(1, std::min(bps, (4096 + s.n_segs - 1) / s.n_segs));
-    const dim3 grid_tie(tie_bps, s.n_segs);
+    // The tie passes keep the full grid: the stage-1 maps hold exact ties (templates whose tracks
+    // pick the same bins), so some lists resolve ties, and a list's tie pass on few blocks is the
+    // launch's tail (cut to about 4096 blocks in all, the batched step's lists took 10 ms more).
     for (int pass = 0; pass < n_pass; ++pass)
-        hipLaunchKernelGGL(tie_hist_kernel, grid_tie, dim3(kThreads), 0, st, s, pass, n_pass);
-    hipLaunchKernelGGL(tie_take_kernel, grid_tie, dim3(kThreads), 0, st, s, n_pass);
+        hipLaunchKernelGGL(tie_hist_kernel, grid2, dim3(kThreads), 0, st, s, pass, n_pass);
+    hipLaunchKernelGGL(tie_take_kernel, grid2, dim3(kThreads), 0, st, s, n_pass);
     if (s.bcnt) {
         // grouped by key bucket, then ranks within the buckets
         hipLaunchKernelGGL(winners_max_kernel, dim3(kb, s.n_segs), dim3(kThreads), 0, st, s);
