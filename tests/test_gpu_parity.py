@@ -354,6 +354,35 @@ def test_count_widest_row_tracks_at_its_top(B, n_f0):
     assert np.all(err <= REL * np.abs(nw_o) + ntw_o + 1e-30)
 
 
+@pytest.mark.parametrize("n_f0", [1, 3, 8])
+def test_count_one_word_rows(B, n_f0):
+    """Rows of one word (n_f0 + 24 <= 32 bins), so the tracks start within four bins of the row's
+    first bin and the second lane of a template's pair reads its window from before its row (the
+    previous row's zero padding): the table variant's map and counts, at every tile shape,
+    against the oracle."""
+    import torch
+    _say(f"count one-word rows n_f0={n_f0}")
+    k0, margin = 90000, 12                # the tracks drift by at most about 11 bins here
+    seg = S.tiny_segments(n_seg=300, k0=k0, n_f0=n_f0, margin=margin, seed=70 + n_f0, span_days=60)
+    assert seg.n_bins <= 32
+    spec = S.GridSpec(k0=k0, n_f0=n_f0, ap_lo=0.05, ap_hi=3.0, n_ap=4, per_lo=15 * S.DAY,
+                      per_hi=45 * S.DAY, n_per=3, tasc_fixed=40)
+    ds = B.DeviceSegments.from_host(seg)
+    g, o = _grid_pair(B, spec, seg, S.fixed_pixel())
+    c_o, nw_o, nt_o, ntw_o = O.hough_count(seg, S.fixed_pixel(), k0, n_f0, *o)
+    ref = None
+    for lanes, chunk in ((64, 128), (256, 256), (512, 512)):
+        st = _status(B)
+        ws, cnt = B.bsh_hough_count(ds, g, with_count=True, lanes=lanes, chunk=chunk, status=st)
+        torch.cuda.synchronize()
+        st.raise_if_set("one-word rows")
+        ws, cnt = _np(ws), _np(cnt).view(np.uint32)
+        if ref is None:
+            ref = (ws, cnt)
+            _check_counts(cnt, ws, c_o, nw_o, nt_o, ntw_o)
+        assert np.array_equal(ws, ref[0]) and np.array_equal(cnt, ref[1]), (lanes, chunk)
+
+
 def test_count_noiseless_injection_full_weight(B):
     import torch
     _say("count noiseless injection")
