@@ -39,8 +39,10 @@ FLOOR_OPS_PER_TS = 2 / 8 + 12 / 90
 # VALU lane-operations per template x segment the table count issues on its fast path: the VALU
 # instructions of the segment-group loop in its gfx950 assembly along the path with no f0-shift
 # step and no flush (tests/fastpath_ops.py counts them per chunk size), divided by
-# the 8 segments x 45 f0 bins one lane of a template's lane pair covers per group.
-TABLE_OPS_PER_TS = {128: 300 / 360, 256: 300 / 360, 512: 302 / 360}
+# the 8 segments x 45 f0 bins one lane of a template's lane pair covers per group.  The kernel's
+# form for host-proven windows (the benchmark's launches) leaves out the per-track range tests.
+TABLE_OPS_PER_TS = {128: 269 / 360, 256: 269 / 360, 512: 275 / 360}
+TABLE_OPS_PER_TS_CHECKED = {128: 300 / 360, 256: 300 / 360, 512: 302 / 360}
 # plain select-and-add: extract the peak bit, select the weight, add
 SELECT_OPS_PER_TS = 3
 # HBM bytes per count launch, measured with rocprofv3 counters for one kernel source and tile
@@ -48,8 +50,17 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hough_count_table_band200Hz_traff
 # per launch form of the batched count: the persistent kernel, or one block per queued unit
 BATCH_TRAFFIC_FILES = {True: os.path.join(ROOT, "profiles", "hough_batch_table_1024items_traffic.txt"),
                        False: os.path.join(ROOT, "profiles", "hough_unit_table_1024items_traffic.txt")}
-BATCH_KERNELS = {True: "hough_batch_kernel<2, {chunk}> (persistent blocks pulling queued units from a counter; ",
-                 False: "hough_unit_kernel<2, {chunk}> (one block per queued unit; "}
+BATCH_KERNELS = {True: "hough_batch_kernel<{mode}, {chunk}> (persistent blocks pulling queued units from a counter; ",
+                 False: "hough_unit_kernel<{mode}, {chunk}> (one block per queued unit; "}
+
+
+def table_mode(proven: bool) -> int:
+    """Kernel mode of the circular table count: 10 for host-proven windows, else 2."""
+    return 10 if proven else 2
+
+
+def table_ops(chunk: int, proven: bool) -> float:
+    return (TABLE_OPS_PER_TS if proven else TABLE_OPS_PER_TS_CHECKED)[chunk]
 # the count kernels' sources and the build script (which holds their compiler flags)
 COUNT_SOURCES = ("paper_1904_04873_amd/csrc/bsh_count.hip", "paper_1904_04873_amd/csrc/bsh_count_table.hip",
                  "paper_1904_04873_amd/csrc/bsh_count_kernels.h", "paper_1904_04873_amd/csrc/bsh_count_tile.h",
@@ -237,6 +248,8 @@ def main():
     plan = bsh.Plan(items, grids, 4, k_item=k_item, k_band=k_band, lanes=lanes, chunk=chunk,
                     use_graph=True, lpt=True, status=st)
     form = plan.persistent      # the library's choice of launch form
+    proven = plan.proven        # the table kernel's form for host-proven windows
+    mode = table_mode(proven)
     print(f"[bench] batched: tile {lanes} x {chunk}, {plan.units} units on {plan.blocks} blocks "
           f"({'persistent' if form else 'one per unit'}); {args.warmup} warmup + {args.steps} timed runs",
           file=sys.stderr, flush=True)
@@ -285,7 +298,7 @@ def main():
     c1.record()
     torch.cuda.synchronize()
     st.raise_if_set("other form count")
-    other_form = {"kernel": ("hough_unit_kernel" if form else "hough_batch_kernel") + f"<2, {chunk}>",
+    other_form = {"kernel": ("hough_unit_kernel" if form else "hough_batch_kernel") + f"<{mode}, {chunk}>",
                   "blocks": pp.blocks, "count_ms": c0.elapsed_time(c1) / n_count}
     pp.close()
     del pp
@@ -306,7 +319,7 @@ def main():
     torch.cuda.empty_cache()
 
     achieved = FLOOR_OPS_PER_TS * ts_total / (count_ms / 1e3)
-    issued = TABLE_OPS_PER_TS[chunk] * ts_total / (count_ms / 1e3)
+    issued = table_ops(chunk, proven) * ts_total / (count_ms / 1e3)
     achieved_select = SELECT_OPS_PER_TS * ts_total / (count_ms / 1e3)
 
     cpu = None
@@ -355,7 +368,7 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": BATCH_KERNELS[form].format(chunk=chunk) + "subset-sum tables of 8 segments, two lanes "
+            "kernel": BATCH_KERNELS[form].format(mode=mode, chunk=chunk) + "subset-sum tables of 8 segments, two lanes "
                       "per binary template)",
             "achieved": achieved / 1e12,
             "peak": VALU_PEAK_OPS / 1e12,
@@ -366,7 +379,7 @@ def main():
             "ops_per_template_segment": FLOOR_OPS_PER_TS,
             "floor": "algorithmic: per template and 8 segments one table read and one add; per (binary "
                      "template, segment) a 12-operation track shared by 90 f0 bins",
-            "issued_fast_path": {"ops_per_template_segment": TABLE_OPS_PER_TS[chunk], "achieved": issued / 1e12,
+            "issued_fast_path": {"ops_per_template_segment": table_ops(chunk, proven), "achieved": issued / 1e12,
                                  "frac": issued / VALU_PEAK_OPS},
             "select_add_equivalent": {"ops_per_template_segment": SELECT_OPS_PER_TS,
                                       "achieved": achieved_select / 1e12,
@@ -500,7 +513,9 @@ def run_band200(args):
     torch.cuda.synchronize()
     st.raise_if_set("band ELL1 count")
     count_ecc_ms = c0.elapsed_time(c1) / n_count
+    proven_e = bsh.count_window_proven(ds, g_e)
     del g_e
+    proven = bsh.count_window_proven(ds, g)
     print(f"[bench] band 200 Hz: {ms_step:.3f} ms/step, count kernel {count_ms:.3f} ms (ELL1 track {count_ecc_ms:.3f} ms)",
           file=sys.stderr, flush=True)
     out = {
@@ -509,13 +524,14 @@ def run_band200(args):
                     "stage-2 power -> top-100, one HIP graph replay per step",
         "steps": args.band_steps, "ms_per_step": ms_step, "value": ts_per_step / (ms_step / 1e3),
         "unit": "template*segments/s",
-        "count_kernel": {"kernel": f"hough_count_kernel<2, {chunk}>", "ms": count_ms,
+        "count_kernel": {"kernel": f"hough_count_kernel<{table_mode(proven)}, {chunk}>", "ms": count_ms,
                          "value": ts_per_step / (count_ms / 1e3),
                          "frac_floor": FLOOR_OPS_PER_TS * ts_per_step / (count_ms / 1e3) / VALU_PEAK_OPS,
-                         "frac_issued_fast_path": TABLE_OPS_PER_TS[chunk] * ts_per_step / (count_ms / 1e3) / VALU_PEAK_OPS,
+                         "frac_issued_fast_path": table_ops(chunk, proven) * ts_per_step / (count_ms / 1e3) / VALU_PEAK_OPS,
                          "traffic": measured_traffic(lanes, chunk), "tile": {"lanes": lanes, "chunk": chunk},
                          "autotune_ms": {f"{l}x{c}": t for (l, c), t in tune_ms.items()}},
-        "count_kernel_ell1": {"kernel": f"hough_count_kernel<5, {chunk}>", "ecc": [1e-3, 5e-4], "ms": count_ecc_ms,
+        "count_kernel_ell1": {"kernel": f"hough_count_kernel<{13 if proven_e else 5}, {chunk}>", "ecc": [1e-3, 5e-4],
+                              "ms": count_ecc_ms,
                               "value": ts_per_step / (count_ecc_ms / 1e3)},
     }
     out["post"] = run_post(bsh, ds, g, s1_score, s1_index, seg.t_coh, seg.t_span_mid(), st)

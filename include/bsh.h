@@ -24,8 +24,10 @@
  *     (thread-local, valid until the next call on the same thread).
  *   - `status` (where present) is a device int32 that the caller zeroes and later reads:
  *     kernels OR in BSH_STATUS_RANGE when a track leaves the staged row [k_lo, k_lo+n_bins)
- *     (the segment is then skipped, never clamped, and the outputs of that call are not
- *     meaningful) and BSH_STATUS_MODEL when a track's drift across the f0 band exceeds one
+ *     or, in a stage-1 launch whose window the host has proven (see bsh_hough_count_ex), when a
+ *     segment's |v.n| or a template's a_p W (1 + e) exceeds that proof's bound (no track is
+ *     clamped into the row; the outputs of that call are then not meaningful) and
+ *     BSH_STATUS_MODEL when a track's drift across the f0 band exceeds one
  *     bin (parameters outside the model's validity), and BSH_STATUS_INPUT when a candidate
  *     names a sky pixel outside [0, n_sky) (that candidate's outputs are then 0) or a
  *     post-processing input is invalid (a significance that is not finite and positive, or a
@@ -184,10 +186,20 @@ int bsh_hough_count(const bsh_segments* seg, const bsh_grid* grid, uint32_t* cou
  * weight one, exact in FP32 and so the same counts bit for bit, computed in a launch of their own
  * (after the weighted sums' launch when both are asked for).  Results do not depend on the tile
  * shape; the two variants' weighted sums agree to FP32 rounding, their counts exactly.
+ * When seg->v_max_host > 0 the host bounds every track: |G - 1| <= v + A + v A with v =
+ * v_max_host and A = max a_p W (1 + e) over the grid.  If the staged row covers that bound (else
+ * BSH_ERANGE, as always) and the band's drift (n_f0 - 1)(v + A + v A) is below half a bin, the
+ * table variant runs without its per-track range and drift tests: instead every staged segment's
+ * |v.n| and every template's a_p W (1 + e) are tested against v and A (device copies against the
+ * host's bound), and a violation raises BSH_STATUS_RANGE.  Results are the same bit for bit.
  */
 #define BSH_VARIANT_AUTO 0
 #define BSH_VARIANT_SELECT 1
 #define BSH_VARIANT_TABLE 2
+
+/* 1 when the table variant's launches for (seg, grid) take the form for proven windows (see
+ * above), 0 when they test every track, negative on invalid arguments.  Host-only. */
+int32_t bsh_count_window_proven(const bsh_segments* seg, const bsh_grid* grid);
 int bsh_hough_count_ex(const bsh_segments* seg, const bsh_grid* grid, int32_t lanes, int32_t chunk,
                        int32_t variant, uint32_t* count_out, float* wsum_out, int32_t* status,
                        bsh_stream stream);
@@ -420,10 +432,15 @@ int bsh_plan_run_count(bsh_plan* plan, bsh_stream stream);
 
 /* Number of queued units, blocks per launch (the persistent blocks, or the largest pass's unit
  * count with one block per unit), launch form (1: persistent blocks, 0: one block per unit) and
- * passes of a plan (-1 for NULL). */
+ * passes of a plan (-1 for NULL).  bsh_plan_proven: 1 when the count launches take the form of
+ * the table kernel for proven windows, i.e. every item with segments gave v_max_host > 0 and a
+ * staged row that covers its tracks' bound with the band's drift below half a bin, so that the
+ * per-track range checks are left out (the bound itself is checked per staged segment and
+ * template, and a violation raises BSH_STATUS_RANGE); 0 otherwise (-1 for NULL). */
 int64_t bsh_plan_units(const bsh_plan* plan);
 int32_t bsh_plan_blocks(const bsh_plan* plan);
 int32_t bsh_plan_persistent(const bsh_plan* plan);
+int32_t bsh_plan_proven(const bsh_plan* plan);
 int32_t bsh_plan_passes(const bsh_plan* plan);
 
 int bsh_plan_destroy(bsh_plan* plan);

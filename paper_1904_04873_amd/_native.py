@@ -152,6 +152,8 @@ SIGNATURES = {
     "bsh_plan_units": (_c_i64, [_vp]),
     "bsh_plan_blocks": (_c_i32, [_vp]),
     "bsh_plan_persistent": (_c_i32, [_vp]),
+    "bsh_plan_proven": (_c_i32, [_vp]),
+    "bsh_count_window_proven": (_c_i32, [_vp, _vp]),
     "bsh_plan_passes": (_c_i32, [_vp]),
     "bsh_plan_destroy": (ctypes.c_int, [_vp]),
     "bsh_topk_workspace": (ctypes.c_size_t, [_c_i64, _c_i32]),

@@ -249,6 +249,15 @@ def bsh_hough_count(seg: DeviceSegments, grid: DeviceGrid, with_count: bool = Fa
     return wsum_out, (count_out if with_count else None)
 
 
+def count_window_proven(seg: DeviceSegments, grid: DeviceGrid) -> bool:
+    """Whether the table count of (seg, grid) takes the kernel form for host-proven windows."""
+    s_c, g_c = seg.struct(), grid.struct()
+    rc = int(N.load().bsh_count_window_proven(ctypes.byref(s_c), ctypes.byref(g_c)))
+    if rc < 0:
+        check(rc, "bsh_count_window_proven")
+    return rc == 1
+
+
 class CountTopK:
     """Reusable workspace for bsh_hough_count_topk (stage 1 with its top-k and bounded memory)."""
 
@@ -630,6 +639,11 @@ class Plan:
     @property
     def persistent(self) -> bool:
         return int(N.load().bsh_plan_persistent(self.h)) == 1
+
+    @property
+    def proven(self) -> bool:
+        """The count launches take the table kernel's form for proven windows."""
+        return int(N.load().bsh_plan_proven(self.h)) == 1
 
     def close(self) -> None:
         if getattr(self, "h", None):

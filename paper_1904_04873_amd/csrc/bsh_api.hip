@@ -58,26 +58,53 @@ int check_grid(const bsh_grid* g)
     return BSH_OK;
 }
 
-int check_window(const bsh_segments* seg, const bsh_grid* g)
+// The bound on |G - 1| that the window checks use: |v/c| <= v, a_p W (1 + e) <= apw, so
+// |D B - 1| <= v + apw + v apw; m is that bound in bins at the band's top, rounded up.
+static void track_bound(const bsh_segments* seg, const bsh_grid* g, double& v, double& apw, double& m)
 {
-    if (seg->v_max_host <= 0.0) return BSH_OK;   // unknown: the device status flag decides
-    double apw = 0.0;
+    apw = 0.0;
     for (int32_t ia = 0; ia < g->n_ap; ++ia)
         for (int32_t ip = 0; ip < g->n_per; ++ip)
             apw = std::fmax(apw, std::fabs(g->a_p_host[ia]) * (kTwoPi / g->period_host[ip]));
     // the ELL1 bracket is at most 1 + e in size
     apw *= 1.0 + std::sqrt(g->ecc_c * g->ecc_c + g->ecc_s * g->ecc_s);
-    const double v = seg->v_max_host;
+    v = seg->v_max_host;
     const double f_hi = (double)(g->k0 + g->n_f0);
-    const double m = std::ceil(f_hi * (v + apw + v * apw));
-    const double lo = (double)g->k0 - m - 1.0;
-    const double hi = (double)(g->k0 + g->n_f0 - 1) + m + 1.0;
-    if (lo < (double)seg->k_lo || hi > (double)(seg->k_lo + seg->n_bins - 1)) {
+    m = std::ceil(f_hi * (v + apw + v * apw));
+}
+
+static bool window_covers(const bsh_segments* seg, const bsh_grid* g, double m, double& lo, double& hi)
+{
+    lo = (double)g->k0 - m - 1.0;
+    hi = (double)(g->k0 + g->n_f0 - 1) + m + 1.0;
+    return lo >= (double)seg->k_lo && hi <= (double)(seg->k_lo + seg->n_bins - 1);
+}
+
+int check_window(const bsh_segments* seg, const bsh_grid* g)
+{
+    if (seg->v_max_host <= 0.0) return BSH_OK;   // unknown: the device status flag decides
+    double v, apw, m, lo, hi;
+    track_bound(seg, g, v, apw, m);
+    if (!window_covers(seg, g, m, lo, hi)) {
         set_error("staged row [%lld, %lld) does not cover the tracks' bound [%.0f, %.0f]",
                   (long long)seg->k_lo, (long long)(seg->k_lo + seg->n_bins), lo, hi);
         return BSH_ERANGE;
     }
     return BSH_OK;
+}
+
+bool proven_window(const bsh_segments* seg, const bsh_grid* g, double* v_out, double* apw_out)
+{
+    if (!(seg->v_max_host > 0.0)) return false;
+    double v, apw, m, lo, hi;
+    track_bound(seg, g, v, apw, m);
+    // the band's offsets k_i - (k0 + i) drift by at most (n_f0 - 1) |G - 1| bins: below one half
+    // they step at most once, so every track's span is last - 1, last or last + 1
+    const double drift = (double)(g->n_f0 - 1) * (v + apw + v * apw);
+    if (!window_covers(seg, g, m, lo, hi) || !(drift < 0.5)) return false;
+    *v_out = v;
+    *apw_out = apw;
+    return true;
 }
 
 }  // namespace bsh

@@ -269,6 +269,8 @@ extern "C" int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh
     p->band_off.assign(n_bands + 1, 0);
     std::vector<int32_t> tile_start(BSH_MAX_PER + 1);
     p->pass_unit.push_back(0);
+    // the proven form of the table kernel when every item with segments is proven (proven_window)
+    bool all_proven = mode_table(p->mode);
     for (int32_t q = 0; q < n_passes; ++q) {
         std::vector<WorkUnit> pu;
         std::vector<int64_t> cost;
@@ -276,6 +278,7 @@ extern "C" int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh
             const bsh_item& it = items[i];
             const bsh_grid& g = grids[it.grid];
             fill_desc(p->items[i], &it.seg, &g, it.sky_lo, it.n_sky, nullptr, maps + p->item_start[i], status);
+            if (it.seg.n_seg > 0 && !prove_item(p->mode, p->items[i], &it.seg, &g)) all_proven = false;
             std::vector<int64_t> groups(g.n_per);
             const int tt = tile_templates(p->mode, lanes);
             const int64_t tiles = plan_tiles(&g, tt, tile_start.data(), groups.data());
@@ -312,6 +315,7 @@ extern "C" int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh
         p->max_band_len = std::max(p->max_band_len, p->band_off[b + 1] - p->band_off[b]);
     }
     p->n_units = (int64_t)units.size();
+    if (all_proven) p->mode += kProvenMode;   // (the descriptors hold the proofs' bounds)
 
     int dev = 0, n_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -451,6 +455,8 @@ extern "C" int64_t bsh_plan_units(const bsh_plan* p) { return p ? p->n_units : -
 extern "C" int32_t bsh_plan_blocks(const bsh_plan* p) { return p ? p->blocks : -1; }
 
 extern "C" int32_t bsh_plan_persistent(const bsh_plan* p) { return p ? (p->persistent ? 1 : 0) : -1; }
+
+extern "C" int32_t bsh_plan_proven(const bsh_plan* p) { return p ? (mode_proven(p->mode) ? 1 : 0) : -1; }
 
 extern "C" int32_t bsh_plan_passes(const bsh_plan* p) { return p ? p->n_passes() : -1; }
 

@@ -14,6 +14,14 @@ constexpr int kFlush = 64;           // segments per FP32 partial sum
 constexpr int kRowPad = 4;           // zero words staged after each row (a failed track reads them)
 constexpr int kNF = BSH_MAX_F0;
 constexpr int kEccMode = 3;          // kernel modes kEccMode.. are the ELL1 forms of modes 0..
+// Kernel mode + kProvenMode: the same table variant for a launch whose every track the host has
+// proven to stay inside the staged rows and to drift less than half a bin across the band
+// (proven_window): the per-track range and model checks are left out.
+constexpr int kProvenMode = 8;
+constexpr int mode_base(int mode) { return mode % kProvenMode; }
+constexpr bool mode_ecc(int mode) { return mode_base(mode) >= kEccMode; }
+constexpr bool mode_table(int mode) { return mode_base(mode) % kEccMode == 2; }
+constexpr bool mode_proven(int mode) { return mode >= kProvenMode; }
 
 // Everything a tile needs about its work item (one segment set, one band grid, a run of
 // sky pixels of that grid, and the item's output map).
@@ -43,6 +51,9 @@ struct ItemDesc {
     int32_t sky_lo;     // first pixel of the item in the grid's sky table
     int32_t n_sky;      // pixels of the item
     double ec, es;      // (e cos w, e sin w) of the grid's ELL1 track; zeros for a circular grid
+    // The bounds a proven launch relies on (0 when the window is not proven): |v/c| of every
+    // segment and a_p W (1 + e) of every template, checked on the device as they are staged.
+    double v_claim, apw_claim;
 };
 
 struct PlainLaunch {
@@ -97,7 +108,7 @@ struct TileSmem {
 inline size_t row_bytes(int chunk, int n_words) { return (size_t)chunk * (size_t)(n_words + kRowPad) * 4u; }
 
 // Binary templates per tile: the table variant gives each template a pair of lanes.
-inline int tile_templates(int mode, int lanes) { return mode % kEccMode == 2 ? lanes / 2 : lanes; }
+inline int tile_templates(int mode, int lanes) { return mode_table(mode) ? lanes / 2 : lanes; }
 
 int64_t plan_tiles(const bsh_grid* g, int lanes, int32_t* tile_start, int64_t* group_sizes);
 void fill_desc(ItemDesc& d, const bsh_segments* seg, const bsh_grid* grid, int32_t sky_lo,
@@ -124,6 +135,9 @@ int allow_lds(const void* kernel, size_t bytes);
 int kernel_mode(int variant, bool with_count);
 // kEccMode for a grid with an eccentricity pair, else 0 (added to kernel_mode's value)
 int ecc_mode(const bsh_grid* g);
+// For a table mode: when proven_window holds for the item, stores the proof's bounds in its
+// descriptor and returns true (the launch may then take mode + kProvenMode).
+bool prove_item(int mode, ItemDesc& d, const bsh_segments* seg, const bsh_grid* grid);
 bool valid_tile_shape(int lanes, int chunk);
 
 }  // namespace bsh

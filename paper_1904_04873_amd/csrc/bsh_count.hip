@@ -137,6 +137,15 @@ int kernel_mode(int variant, bool with_count)
 
 int ecc_mode(const bsh_grid* g) { return (g->ecc_c != 0.0 || g->ecc_s != 0.0) ? kEccMode : 0; }
 
+bool prove_item(int mode, ItemDesc& d, const bsh_segments* seg, const bsh_grid* grid)
+{
+    double v, apw;
+    if (!mode_table(mode) || !proven_window(seg, grid, &v, &apw)) return false;
+    d.v_claim = v;
+    d.apw_claim = apw;
+    return true;
+}
+
 bool valid_tile_shape(int lanes, int chunk)
 {
     return (lanes == 64 || lanes == 128 || lanes == 256 || lanes == 512) && (chunk == 128 || chunk == 256 || chunk == 512);
@@ -169,8 +178,9 @@ extern "C" int bsh_hough_count_ex(const bsh_segments* seg, const bsh_grid* grid,
     // partial sums and counts take more registers than a wave has, counts on request.
     const bool table_counts = count_out && variant != BSH_VARIANT_SELECT && seg->n_seg < ((int64_t)1 << 24);
     fill_desc(p.d, seg, grid, 0, grid->n_sky, table_counts ? nullptr : count_out, wsum_out, status);
-    const int mode = (table_counts ? kernel_mode(BSH_VARIANT_TABLE, false) : kernel_mode(variant, count_out != nullptr)) +
-                     ecc_mode(grid);
+    int mode = (table_counts ? kernel_mode(BSH_VARIANT_TABLE, false) : kernel_mode(variant, count_out != nullptr)) +
+               ecc_mode(grid);
+    if (prove_item(mode, p.d, seg, grid)) mode += kProvenMode;
     const int64_t tiles = plan_tiles(grid, tile_templates(mode, lanes), p.tile_start, nullptr);
     p.tiles_per_sky = (int32_t)tiles;
     const int64_t blocks = tiles * grid->n_sky;
@@ -196,6 +206,17 @@ extern "C" int bsh_hough_count_ex(const bsh_segments* seg, const bsh_grid* grid,
     rc = launch_plain(pc, blocks, lanes, chunk, mode, pc.d.n_words, s);
     if (rc) return rc;
     return floats_to_counts(count_out, (int64_t)grid->n_sky * p.d.n_bin * grid->n_f0, s);
+}
+
+extern "C" int32_t bsh_count_window_proven(const bsh_segments* seg, const bsh_grid* grid)
+{
+    clear_error();
+    int rc = check_segments(seg, false, false);
+    if (rc) return rc;
+    rc = check_grid(grid);
+    if (rc) return rc;
+    double v, apw;
+    return proven_window(seg, grid, &v, &apw) ? 1 : 0;
 }
 
 extern "C" int bsh_hough_count(const bsh_segments* seg, const bsh_grid* grid, uint32_t* count_out,
@@ -312,12 +333,13 @@ extern "C" int bsh_hough_count_topk(const bsh_segments* seg, const bsh_grid* gri
         std::memset(&p, 0, sizeof(p));
         fill_desc(p.d, seg, grid, (int32_t)c0, nc, nullptr, map, status);
         if (seg->weight_per_sky) p.d.w = seg->weight + c0 * seg->n_seg;
+        const int pmode = prove_item(mode, p.d, seg, grid) ? mode + kProvenMode : mode;
         const int64_t tiles = plan_tiles(grid, tile_templates(mode, lanes), p.tile_start, nullptr);
         p.tiles_per_sky = (int32_t)tiles;
         if (seg->n_seg == 0 || tiles == 0)
             rc = zero_words(map, n_t, s);
         else
-            rc = launch_plain(p, tiles * nc, lanes, chunk, mode, p.d.n_words, s);
+            rc = launch_plain(p, tiles * nc, lanes, chunk, pmode, p.d.n_words, s);
         if (rc) return rc;
         const int64_t first = c0 * per_sky;
         if (single)

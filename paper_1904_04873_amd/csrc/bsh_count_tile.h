@@ -53,7 +53,9 @@ __device__ __forceinline__ double tile_G(double DC, double DS, double D, double 
 }
 
 // The canonical evaluations (no branches).  ok is false, and a flag is raised, when the track
-// leaves the staged row [klo, khi) or drifts more than one bin across the band.
+// leaves the staged row [klo, khi) or drifts more than one bin across the band.  kProven: the
+// launch's bounds exclude both (proven_window), so neither is tested.
+template <bool kProven = false>
 __device__ __forceinline__ BandTrack band_track(double G, double F0, double FL, int klo, int khi, int last,
                                                 bool& bad_range, bool& bad_model)
 {
@@ -64,10 +66,14 @@ __device__ __forceinline__ BandTrack band_track(double G, double F0, double FL, 
     t.kf = (int)t.y0;
     const int kl = (int)fma(FL, t.G, 0.5);
     t.span = kl - t.kf;
-    const bool in_range = (t.kf >= klo) & (kl < khi);
-    t.ok = in_range & (t.span >= last - 1) & (t.span <= last + 1);
-    bad_range |= !in_range;
-    bad_model |= in_range & !t.ok;
+    if constexpr (kProven) {
+        t.ok = true;
+    } else {
+        const bool in_range = (t.kf >= klo) & (kl < khi);
+        t.ok = in_range & (t.span >= last - 1) & (t.span <= last + 1);
+        bad_range |= !in_range;
+        bad_model |= in_range & !t.ok;
+    }
     return t;
 }
 
@@ -339,7 +345,14 @@ __device__ __forceinline__ float lds_at(uint32_t a)
 }
 
 // smem: the block's LDS (rows first, then the structure at byte offset sm_off).
-template <int kChunk, bool kEcc>
+// kProven: the launch's tracks are proven to stay inside the rows with at most one f0-shift step
+// (proven_window).  Instead of testing every track, the inputs of the proof are tested as they
+// are staged: each segment's |D - 1| against the proof's |v/c| and its phase for finiteness, each
+// lane's a_p W (1 + e) against the proof's bound and its t_asc phase for finiteness.  A failed
+// test raises the range flag (the outputs are then undefined, as for any track outside the rows);
+// the segment is staged as one with G = 1, and the lane skips its groups, so that every window
+// the kernel reads is one of a track inside the rows.
+template <int kChunk, bool kEcc, bool kProven = false>
 __device__ __forceinline__ void count_tile_pair(const ItemDesc& d, int s, int ip, int64_t tile,
                                                 TileSmemLut<kChunk, kEcc>& sm, uint32_t* row,
                                                 const unsigned char* smem, uint32_t sm_off)
@@ -367,6 +380,11 @@ __device__ __forceinline__ void count_tile_pair(const ItemDesc& d, int s, int ip
     const double Ac = apW * cb, As = apW * sb;
     double Ac2 = 0.0, As2 = 0.0;
     if constexpr (kEcc) ecc_coeffs(apW, cb, sb, d.ec, d.es, Ac2, As2);
+    // the lane's a_p W (1 + e) within the proof's bound (a relative 1e-12 for rounding), and its
+    // phase finite (fails on NaN)
+    const bool claim_bad = kProven && active &&
+                           !((fabs(apW) * (1.0 + sqrt(d.ec * d.ec + d.es * d.es)) <= d.apw_claim * (1.0 + 1e-12)) &
+                             (fabs(sb) <= 1.0) & (fabs(cb) <= 1.0));
 
     const int sg = d.sky_lo + s;
     const double nx = d.sky[3 * sg], ny = d.sky[3 * sg + 1], nz = d.sky[3 * sg + 2];
@@ -416,7 +434,7 @@ __device__ __forceinline__ void count_tile_pair(const ItemDesc& d, int s, int ip
                 }
         flushed = true;
     };
-    bool bad_range = false, bad_model = false;
+    bool bad_range = claim_bad, bad_model = false;
     // the rows' zero padding, which the chunks' copies leave as it is
     for (int e = tid; e < kChunk * kRowPad; e += lanes) row[(e / kRowPad) * nwp + d.n_words + (e % kRowPad)] = 0u;
 
@@ -429,7 +447,16 @@ __device__ __forceinline__ void count_tile_pair(const ItemDesc& d, int s, int ip
             const int64_t J = j0 + min(jj, nj - 1);
             double sp, cp;
             track_sincos(W * d.t_mid[J], sp, cp);
-            const double D = doppler_factor(d.v + 3 * J, nx, ny, nz);
+            double D = doppler_factor(d.v + 3 * J, nx, ny, nz);
+            if constexpr (kProven) {
+                // |v . n| <= |v/c| of the proof (unit n; slack for the rounding of D), finite phase
+                if (!((fabs(D - 1.0) <= d.v_claim * (1.0 + 1e-9) + 1e-15) & (fabs(cp) <= 1.0) & (fabs(sp) <= 1.0))) {
+                    bad_range = true;
+                    D = 1.0;
+                    cp = 0.0;
+                    sp = 0.0;
+                }
+            }
             sm.DC[jj] = D * cp;
             sm.DS[jj] = D * sp;
             sm.D[jj] = D;
@@ -486,7 +513,7 @@ __device__ __forceinline__ void count_tile_pair(const ItemDesc& d, int s, int ip
             }
         }
         __syncthreads();
-        if (!active) continue;
+        if (!active || claim_bad) continue;
 
         // this lane's rows: segments 4h .. 4h + 3 of group 0, then eight rows further per group
         const uint32_t* lrow = row + 4 * h * nwp;
@@ -499,11 +526,11 @@ __device__ __forceinline__ void count_tile_pair(const ItemDesc& d, int s, int ip
                 const int jj = hg * kGroup + u;
                 const double G = tile_G<kEcc>(sm.DC[jj], sm.DS[jj], sm.D[jj], kEcc ? sm.DC2[jj] : 0.0,
                                               kEcc ? sm.DS2[jj] : 0.0, Ac, As, Ac2, As2);
-                tr[u] = band_track(G, F0, FL, klo, klo + d.n_bins, last, bad_range, bad_model);
+                tr[u] = band_track<kProven>(G, F0, FL, klo, klo + d.n_bins, last, bad_range, bad_model);
             }
 #pragma unroll
             for (int u = 0; u < kGroup; ++u) {
-                const int at = tr[u].ok ? tr[u].kf - klo_h : pad_h;
+                const int at = tr[u].ok ? tr[u].kf - klo_h : pad_h;   // (always ok when proven)
                 const uint32_t* rw = lrow + u * nwp + (at >> 5);
                 const uint32_t w0 = rw[0], w1 = rw[1], w2 = rw[2], w3 = rw[3];
                 mk[u][0] = __builtin_amdgcn_alignbit(w1, w0, at);
@@ -563,8 +590,8 @@ __device__ __forceinline__ void count_tile_pair(const ItemDesc& d, int s, int ip
 template <int kMode, int kChunk>
 constexpr size_t fixed_smem_bytes()
 {
-    constexpr bool kEcc = kMode >= kEccMode;
-    constexpr size_t b = kMode % kEccMode == 2 ? sizeof(TileSmemLut<kChunk, kEcc>) : sizeof(TileSmem<kChunk, kEcc>);
+    constexpr bool kEcc = mode_ecc(kMode);
+    constexpr size_t b = mode_table(kMode) ? sizeof(TileSmemLut<kChunk, kEcc>) : sizeof(TileSmem<kChunk, kEcc>);
     return (b + 15) & ~(size_t)15;
 }
 
@@ -572,8 +599,8 @@ constexpr size_t fixed_smem_bytes()
 template <int kMode, int kChunk>
 __device__ __forceinline__ void run_tile(const ItemDesc& d, int s, int ip, int64_t tile, unsigned char* smem)
 {
-    constexpr int kM = kMode % kEccMode;
-    constexpr bool kEcc = kMode >= kEccMode;
+    constexpr int kM = mode_base(kMode) % kEccMode;
+    constexpr bool kEcc = mode_ecc(kMode);
     // rows at offset 0 (a row's words are then addressed by the read instructions' own offsets);
     // the structure follows the item's rows (a multiple of 512 bytes)
     uint32_t* row = reinterpret_cast<uint32_t*>(smem);
@@ -582,7 +609,8 @@ __device__ __forceinline__ void run_tile(const ItemDesc& d, int s, int ip, int64
     if constexpr (kM == 2) {
         using Lut = TileSmemLut<kChunk, kEcc>;
         static_assert(offsetof(Lut, T8) == 0, "tables first");
-        count_tile_pair<kChunk, kEcc>(d, s, ip, tile, *reinterpret_cast<Lut*>(st), row, smem, sm_off);
+        count_tile_pair<kChunk, kEcc, mode_proven(kMode)>(d, s, ip, tile, *reinterpret_cast<Lut*>(st), row, smem,
+                                                          sm_off);
     } else {
         count_tile<kM == 1, kChunk, kEcc>(d, s, ip, tile, *reinterpret_cast<TileSmem<kChunk, kEcc>*>(st), row);
     }
@@ -595,7 +623,7 @@ __device__ __forceinline__ void run_tile(const ItemDesc& d, int s, int ip, int64
 // spills a few and is faster (200 Hz band 2.05 -> 1.88 ms, batched launch 651 -> 462 ms on 256
 // items).  The select variants hold 90 partial sums (and counts): one.
 template <int kMode>
-constexpr int min_blocks() { return kMode == kEccMode + 2 ? 3 : (kMode % kEccMode == 2 ? 2 : 1); }
+constexpr int min_blocks() { return mode_base(kMode) == kEccMode + 2 ? 3 : (mode_table(kMode) ? 2 : 1); }
 
 // Instantiate a kernel template for every (mode, chunk) of the select variants (modes 0, 1 and
 // their ELL1 forms 3, 4) or of the table variant (modes 2, 5) and call f with the chosen one.  The
@@ -625,10 +653,16 @@ constexpr int min_blocks() { return kMode == kEccMode + 2 ? 3 : (kMode % kEccMod
     case 5128: F(5, 128); break;                                                              \
     case 5256: F(5, 256); break;                                                              \
     case 5512: F(5, 512); break;                                                              \
+    case 10128: F(10, 128); break;                                                            \
+    case 10256: F(10, 256); break;                                                            \
+    case 10512: F(10, 512); break;                                                            \
+    case 13128: F(13, 128); break;                                                            \
+    case 13256: F(13, 256); break;                                                            \
+    case 13512: F(13, 512); break;                                                            \
     default: return fail_inval("kernel mode / chunk");                                        \
     }
 
-inline bool is_table_mode(int mode) { return mode % kEccMode == 2; }
+inline bool is_table_mode(int mode) { return mode_table(mode); }
 
 // LDS bytes of one block: the fixed structure and the rows of n_words words (0 for an unknown
 // mode or chunk).
@@ -655,6 +689,12 @@ inline size_t smem_bytes_of(int mode, int chunk, int n_words)
     case 5128: BSH_FIXED_SMEM(5, 128); break;
     case 5256: BSH_FIXED_SMEM(5, 256); break;
     case 5512: BSH_FIXED_SMEM(5, 512); break;
+    case 10128: BSH_FIXED_SMEM(10, 128); break;
+    case 10256: BSH_FIXED_SMEM(10, 256); break;
+    case 10512: BSH_FIXED_SMEM(10, 512); break;
+    case 13128: BSH_FIXED_SMEM(13, 128); break;
+    case 13256: BSH_FIXED_SMEM(13, 256); break;
+    case 13512: BSH_FIXED_SMEM(13, 512); break;
     default: return 0;
     }
     return fixed + row_bytes(chunk, n_words);

@@ -45,6 +45,10 @@ int check_segments(const bsh_segments* seg, bool need_bits, bool need_power);
 int check_grid(const bsh_grid* g);
 // Conservative host check that every stage-1 track stays inside the staged row.
 int check_window(const bsh_segments* seg, const bsh_grid* g);
+// True when v_max_host is given, the staged row covers every track's bound with the margin of
+// check_window, and the band's offsets drift by less than half a bin (at most one f0-shift
+// step); *v and *apw receive the bounds on |v/c| and a_p W (1 + e) that the proof used.
+bool proven_window(const bsh_segments* seg, const bsh_grid* g, double* v, double* apw);
 
 // Segmented exact top-k (bsh_topk.hip): offsets on the device, longest segment from the host.
 // With implicit indices (index NULL) the written indices are index_base + ((g << shift) | position);

@@ -2,7 +2,10 @@
 in its gfx950 assembly.
 
 The count kernel is compiled to assembly with the library's own flags; in the kernel of the
-given chunk size the loop over segment groups is walked along the path that every group takes
+given mode and chunk size (by default mode 10, the table variant for a launch whose tracks the
+host has proven to stay inside the staged rows, which the benchmark's launches are; mode 2 is
+the same kernel with the per-track range checks) the loop over segment groups is walked along
+the path that every group takes
 when no lane of the wave meets an f0-shift step and no partial-sum flush is due.  Exec-mask
 regions (s_cbranch_execz) are entered, except the innermost ones that hold the step's position
 guess (v_rcp_f32) and the ones that store to global memory (the flush).  Each VALU instruction
@@ -10,7 +13,7 @@ on that path is one 64-lane wave instruction; a pair of lanes shares one binary 
 lane covers a group's 8 segments x 45 f0 bins (the pair, 90), and the count divided by 8 x 45
 is the lane-operation cost of one template x segment that bench.py reports as the issued work.
 
-    python tests/fastpath_ops.py [chunk ...]
+    python tests/fastpath_ops.py [chunk ...]      (BSH_FASTPATH_MODE=2 for the checked kernel)
 """
 from __future__ import annotations
 
@@ -40,8 +43,11 @@ def assembly() -> str:
             return f.read()
 
 
-def kernel_lines(asm: str, chunk: int) -> list[str]:
-    sym = f"_ZN3bsh18hough_count_kernelILi2ELi{chunk}EEEvNS_11PlainLaunchE:"
+PROVEN_MODE = 10
+
+
+def kernel_lines(asm: str, chunk: int, mode: int = PROVEN_MODE) -> list[str]:
+    sym = f"_ZN3bsh18hough_count_kernelILi{mode}ELi{chunk}EEEvNS_11PlainLaunchE:"
     lines = asm.splitlines()
     start = next(i for i, l in enumerate(lines) if l.startswith(sym))
     end = next(i for i in range(start, len(lines)) if lines[i].startswith(".Lfunc_end"))
@@ -104,9 +110,9 @@ def walk(lines: list[str], head: int) -> dict[str, int]:
     return counts
 
 
-def fast_path(chunk: int, asm: str | None = None) -> tuple[int, int]:
+def fast_path(chunk: int, asm: str | None = None, mode: int = PROVEN_MODE) -> tuple[int, int]:
     """(VALU instructions per group on the fast path, segments per group)."""
-    lines = kernel_lines(asm or assembly(), chunk)
+    lines = kernel_lines(asm or assembly(), chunk, mode)
     best = None
     for i, l in enumerate(lines):
         if re.match(r"^\.LBB\d+_\d+:", l) and i + 1 < len(lines) and "This Loop Header: Depth=2" in lines[i + 1]:
@@ -122,8 +128,9 @@ def fast_path(chunk: int, asm: str | None = None) -> tuple[int, int]:
 
 if __name__ == "__main__":
     chunks = [int(c) for c in sys.argv[1:]] or [128, 256, 512]
+    mode = int(os.environ.get("BSH_FASTPATH_MODE", PROVEN_MODE))
     asm = assembly()
     for c in chunks:
-        valu, seg = fast_path(c, asm)
+        valu, seg = fast_path(c, asm, mode)
         print(f"chunk {c}: {valu} VALU per group of {seg} segments x {BINS_PER_LANE} bins = "
               f"{valu / (seg * BINS_PER_LANE):.3f} per template x segment")

@@ -242,6 +242,7 @@ def test_plan_rejects_bad_items_on_host():
     assert L.bsh_plan_destroy(None) == N.BSH_OK
     assert L.bsh_plan_units(None) == -1
     assert L.bsh_plan_persistent(None) == -1
+    assert L.bsh_plan_proven(None) == -1
 
 
 def test_post_processing_entry_points_reject_bad_arguments():

@@ -1,6 +1,7 @@
 """The per-unit work bench.py prices the count kernel's roofline with (VALU instructions per group
 of eight segments x 45 f0 bins per lane on the table variant's fast path) is the count that fastpath_ops.py reads from
-the kernel's gfx950 assembly, for every chunk size the autotuner may pick.  Compiles the count
+the kernel's gfx950 assembly, for every chunk size the autotuner may pick, in the kernel's form for host-proven windows
+(the benchmark's) and in its checked form.  Compiles the count
 kernel to assembly on the host (no GPU needed)."""
 import os
 import shutil
@@ -20,6 +21,7 @@ def test_bench_floor_matches_the_assembly():
 
     asm = fastpath_ops.assembly()
     for chunk in (128, 256, 512):
-        valu, seg = fastpath_ops.fast_path(chunk, asm)
-        assert seg == 8
-        assert valu / (seg * fastpath_ops.BINS_PER_LANE) == pytest.approx(bench.TABLE_OPS_PER_TS[chunk], rel=1e-12), chunk
+        for mode, table in ((10, bench.TABLE_OPS_PER_TS), (2, bench.TABLE_OPS_PER_TS_CHECKED)):
+            valu, seg = fastpath_ops.fast_path(chunk, asm, mode)
+            assert seg == 8
+            assert valu / (seg * fastpath_ops.BINS_PER_LANE) == pytest.approx(table[chunk], rel=1e-12), (chunk, mode)

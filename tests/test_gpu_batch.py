@@ -89,6 +89,36 @@ def test_batched_equals_plain_and_single_item(setup):
         pp.close()
 
 
+def test_proven_plan_equals_checked_plan(setup):
+    """Every item's window proven on the host: the plan takes the table kernel's proven form
+    (no per-track range tests); with one item's bound unknown it takes the checked form, and
+    maps and lists agree bit for bit."""
+    import torch
+    w, bsh, items, grids, hosts, n_bands = setup
+    _say("proven vs checked plan")
+    pp = bsh.Plan(items, grids, n_bands, k_item=500, k_band=300, use_graph=False)
+    assert pp.proven
+    pp.run()
+    torch.cuda.synchronize()
+    pp.status.raise_if_set("proven")
+    ds0 = items[0][0]
+    v_max = ds0.v_max
+    ds0.v_max = 0.0
+    try:
+        pc = bsh.Plan(items, grids, n_bands, k_item=500, k_band=300, use_graph=False)
+    finally:
+        ds0.v_max = v_max
+    assert not pc.proven
+    pc.run()
+    torch.cuda.synchronize()
+    pc.status.raise_if_set("checked")
+    assert torch.equal(pp.maps, pc.maps)
+    assert torch.equal(pp.item_index, pc.item_index) and torch.equal(pp.band_index, pc.band_index)
+    assert torch.equal(pp.band_score, pc.band_score)
+    pp.close()
+    pc.close()
+
+
 def test_lists_are_exact_topk_of_maps(setup):
     import torch
     w, bsh, items, grids, hosts, n_bands = setup

@@ -426,6 +426,68 @@ def test_count_window_violation_sets_status(B):
         B.bsh_hough_count(ds, g)
 
 
+@pytest.mark.parametrize("ecc", [None, (0.012, -0.007)], ids=["circular", "ell1"])
+def test_count_proven_window_equals_checked(B, ecc):
+    """The table kernel's form for host-proven windows (no per-track range or drift tests) gives
+    the checked kernel's maps and counts bit for bit; both match the oracle at samples."""
+    import torch
+    _say(f"count proven vs checked ({'ell1' if ecc else 'circular'})")
+    w = S.config2(n_per_det=300)
+    seg = w.segments[0]
+    spec = S.GridSpec(k0=180000, n_f0=90, ap_lo=0.01, ap_hi=3.0, n_ap=16, per_lo=15 * S.DAY,
+                      per_hi=45 * S.DAY, n_per=4, tasc_fixed=32)
+    ds = B.DeviceSegments.from_host(seg)
+    assert ds.v_max > 0
+    g = B.DeviceGrid.build(spec, seg.t_span_mid(), w.sky, ecc=ecc) if ecc else \
+        B.DeviceGrid.build(spec, seg.t_span_mid(), w.sky)
+    st = _status(B)
+    ws_p, cnt_p = B.bsh_hough_count(ds, g, with_count=True, status=st)     # proven (v_max given)
+    v_max = ds.v_max
+    ds.v_max = 0.0                                                          # bound unknown: checked
+    ws_c, cnt_c = B.bsh_hough_count(ds, g, with_count=True, status=st)
+    ds.v_max = v_max
+    torch.cuda.synchronize()
+    assert st.value() == 0
+    assert np.array_equal(_np(ws_p).view(np.uint32), _np(ws_c).view(np.uint32))
+    assert np.array_equal(_np(cnt_p), _np(cnt_c))
+    # oracle at sampled templates
+    o = O.grid_tables(spec, seg.t_span_mid())
+    rng = np.random.default_rng(11)
+    n_bin = int(o[2][-1])
+    pick = rng.choice(n_bin, 24, replace=False)
+    for b in pick:
+        cell = int(np.searchsorted(o[2], b, side="right") - 1)
+        ia, ip = divmod(cell, spec.n_per)
+        sub = (o[0][ia:ia + 1], o[1][ip:ip + 1], np.array([0, 1], np.int64), o[3][b:b + 1])
+        if ecc:
+            c_o, nw_o, nt_o, ntw_o = O.hough_count_ecc(seg, w.sky, spec.k0, spec.n_f0, *sub, *ecc)
+        else:
+            c_o, nw_o, nt_o, ntw_o = O.hough_count(seg, w.sky, spec.k0, spec.n_f0, *sub)
+        sl = slice(int(b) * spec.n_f0, (int(b) + 1) * spec.n_f0)
+        _check_counts(_np(cnt_p)[sl], _np(ws_p)[sl], c_o, nw_o, nt_o, ntw_o)
+
+
+def test_count_understated_bound_sets_status(B):
+    """A v_max_host below the segments' true |v/c|: the host proof passes on the claim, the
+    proven kernel finds the staged segments outside it, raises RANGE and reads nothing out of
+    the rows (the call completes)."""
+    import torch
+    _say("count understated bound status")
+    seg = S.tiny_segments(n_seg=40, k0=90000, n_f0=90, margin=2, seed=5)
+    spec = S.GridSpec(k0=90000, n_f0=90, ap_lo=0.001, ap_hi=0.002, n_ap=2, per_lo=15 * S.DAY,
+                      per_hi=20 * S.DAY, n_per=2, tasc_fixed=4)
+    ds = B.DeviceSegments.from_host(seg)
+    assert ds.v_max > 5e-5
+    ds.v_max = 1e-7                  # understated: |v/c| is about 1e-4
+    g, _ = _grid_pair(B, spec, seg, S.fixed_pixel())
+    st = _status(B)
+    ws, _ = B.bsh_hough_count(ds, g, status=st)
+    torch.cuda.synchronize()
+    assert st.value() & 1
+    with pytest.raises(B.BshError):
+        st.raise_if_set()
+
+
 def test_count_deterministic(B):
     import torch
     _say("count determinism")
