@@ -81,9 +81,9 @@ def count_sources_digest(sources=COUNT_SOURCES) -> str:
     return h.hexdigest()
 
 
-def measured_traffic(lanes: int, chunk: int, path=TRAFFIC_FILE, sources=COUNT_SOURCES):
+def measured_traffic(lanes: int, chunk: int, path=TRAFFIC_FILE, sources=COUNT_SOURCES, mode=None):
     """HBM bytes per launch from the committed counter summary, or None when the count kernel's
-    sources or the tile differ from those the counters were taken on."""
+    sources, the tile or the kernel mode differ from those the counters were taken on."""
     try:
         kv = {}
         with open(path) as f:
@@ -94,6 +94,8 @@ def measured_traffic(lanes: int, chunk: int, path=TRAFFIC_FILE, sources=COUNT_SO
         if kv.get("sources_sha256") != count_sources_digest(sources):
             return None
         if (int(kv["lanes"]), int(kv["chunk"])) != (lanes, chunk):
+            return None
+        if mode is not None and int(kv.get("mode", -1)) != mode:
             return None
         return float(kv["traffic_bytes"])
     except (OSError, KeyError, ValueError):
@@ -374,7 +376,7 @@ def main():
             "peak": VALU_PEAK_OPS / 1e12,
             "unit": "TOP/s",
             "frac": achieved / VALU_PEAK_OPS,
-            "traffic": measured_traffic(lanes, chunk, BATCH_TRAFFIC_FILES[form], BATCH_SOURCES),
+            "traffic": measured_traffic(lanes, chunk, BATCH_TRAFFIC_FILES[form], BATCH_SOURCES, mode),
             "count_kernel_ms": count_ms,
             "ops_per_template_segment": FLOOR_OPS_PER_TS,
             "floor": "algorithmic: per template and 8 segments one table read and one add; per (binary "
@@ -528,7 +530,8 @@ def run_band200(args):
                          "value": ts_per_step / (count_ms / 1e3),
                          "frac_floor": FLOOR_OPS_PER_TS * ts_per_step / (count_ms / 1e3) / VALU_PEAK_OPS,
                          "frac_issued_fast_path": table_ops(chunk, proven) * ts_per_step / (count_ms / 1e3) / VALU_PEAK_OPS,
-                         "traffic": measured_traffic(lanes, chunk), "tile": {"lanes": lanes, "chunk": chunk},
+                         "traffic": measured_traffic(lanes, chunk, mode=table_mode(proven)),
+                         "tile": {"lanes": lanes, "chunk": chunk},
                          "autotune_ms": {f"{l}x{c}": t for (l, c), t in tune_ms.items()}},
         "count_kernel_ell1": {"kernel": f"hough_count_kernel<{13 if proven_e else 5}, {chunk}>", "ecc": [1e-3, 5e-4],
                               "ms": count_ecc_ms,
