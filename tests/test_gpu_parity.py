@@ -488,6 +488,45 @@ def test_count_understated_bound_sets_status(B):
         st.raise_if_set()
 
 
+@pytest.mark.parametrize("proven", [True, False], ids=["proven", "checked"])
+def test_count_non_finite_inputs_set_status(B, proven):
+    """A NaN segment time and a NaN t_asc in the device tables: both kernel forms complete and
+    raise RANGE (the proven form stages the segment as one with G = 1 and skips the lane pair, the
+    checked form's tracks fail their range test), and a clean run afterwards gives the clean map."""
+    import torch
+    _say(f"count non-finite inputs ({'proven' if proven else 'checked'})")
+    w = S.config2(n_per_det=100)
+    seg = w.segments[0]
+    spec = S.GridSpec(k0=180000, n_f0=90, ap_lo=0.01, ap_hi=3.0, n_ap=4, per_lo=15 * S.DAY,
+                      per_hi=45 * S.DAY, n_per=2, tasc_fixed=16)
+    ds = B.DeviceSegments.from_host(seg)
+    if not proven:
+        ds.v_max = 0.0
+    g = B.DeviceGrid.build(spec, seg.t_span_mid(), w.sky)
+    assert B.count_window_proven(ds, g) == proven
+    st = _status(B)
+    ws0, _ = B.bsh_hough_count(ds, g, status=st)
+    torch.cuda.synchronize()
+    assert st.value() == 0
+    ref = _np(ws0).copy()
+    t_mid = ds.t_mid.clone()
+    t_asc = g.t_asc_dev.clone()
+    ds.t_mid[7] = float("nan")
+    g.t_asc_dev[3] = float("nan")
+    try:
+        ws1, _ = B.bsh_hough_count(ds, g, status=st)
+        torch.cuda.synchronize()
+    finally:
+        ds.t_mid.copy_(t_mid)
+        g.t_asc_dev.copy_(t_asc)
+    assert st.value() & 1
+    st2 = _status(B)
+    ws2, _ = B.bsh_hough_count(ds, g, status=st2)
+    torch.cuda.synchronize()
+    assert st2.value() == 0
+    assert np.array_equal(_np(ws2).view(np.uint32), ref.view(np.uint32))
+
+
 def test_count_deterministic(B):
     import torch
     _say("count determinism")
