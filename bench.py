@@ -41,8 +41,8 @@ FLOOR_OPS_PER_TS = 2 / 8 + 12 / 90
 # step and no flush (tests/fastpath_ops.py counts them per chunk size), divided by
 # the 8 segments x 45 f0 bins one lane of a template's lane pair covers per group.  The kernel's
 # form for host-proven windows (the benchmark's launches) leaves out the per-track range tests.
-TABLE_OPS_PER_TS = {128: 269 / 360, 256: 269 / 360, 512: 275 / 360}
-TABLE_OPS_PER_TS_CHECKED = {128: 300 / 360, 256: 300 / 360, 512: 302 / 360}
+TABLE_OPS_PER_TS = {128: 267 / 360, 256: 267 / 360, 512: 273 / 360}
+TABLE_OPS_PER_TS_CHECKED = {128: 309 / 360, 256: 309 / 360, 512: 313 / 360}
 # plain select-and-add: extract the peak bit, select the weight, add
 SELECT_OPS_PER_TS = 3
 # HBM bytes per count launch, measured with rocprofv3 counters for one kernel source and tile

@@ -410,7 +410,10 @@ __device__ __forceinline__ void count_tile_pair(const ItemDesc& d, int s, int ip
     float acc[kPairSlots];
 #pragma unroll
     for (int i = 0; i < kPairSlots; ++i) acc[i] = 0.f;
-    int since_flush = 0;
+    // groups of eight segments staged so far (uniform over the block): the partial sums are folded
+    // after every kFlushGroups of them, which always ends a chunk (a chunk holds kChunk / 8 groups)
+    static_assert(kFlushGroups % (kChunk / kGroup8) == 0, "folds fall at chunk ends");
+    int64_t groups_done = 0;
     bool flushed = false;
     float* out = d.wsum_out + ((int64_t)s * d.n_bin + b) * d.n_f0;
     const int nf = d.n_f0;
@@ -442,6 +445,7 @@ __device__ __forceinline__ void count_tile_pair(const ItemDesc& d, int s, int ip
         const int nj = (int)min((int64_t)kChunk, d.n_seg - j0);
         const int ng8 = (nj + kGroup8 - 1) / kGroup8;
         const int ng = 2 * ng8;
+        groups_done += ng8;
         __syncthreads();
         for (int jj = tid; jj < ng * kGroup; jj += lanes) {
             const int64_t J = j0 + min(jj, nj - 1);
@@ -574,15 +578,12 @@ __device__ __forceinline__ void count_tile_pair(const ItemDesc& d, int s, int ip
                     if (!(w == 2 && t >= 2)) acc[pair_slot(w, t, 3)] += lds_at(lut_addr_hi(yo, T8));
                 }
             }
-            if (++since_flush == kFlushGroups) {
-                since_flush = 0;
-                flush();
-            }
         }
+        if (groups_done % kFlushGroups == 0) flush();
     }
     if (bad_range) raise_status(d.status, BSH_STATUS_RANGE);
     if (bad_model) raise_status(d.status, BSH_STATUS_MODEL);
-    if (active && (since_flush > 0 || !flushed)) flush();
+    if (active && (groups_done % kFlushGroups != 0 || !flushed)) flush();
 }
 
 // kMode % kEccMode: 0 = select-and-add, weighted sums only; 1 = select-and-add with counts;

@@ -63,21 +63,39 @@ def _labels(lines: list[str]) -> dict[str, int]:
     return out
 
 
+def _region(lines: list[str], labels: dict[str, int], a: int, b: int) -> set[int]:
+    """Lines executed from the fall-through of the exec-mask branch at line a until control
+    reaches its target (line b): fall-through and unconditional jumps are followed (the compiler
+    may place a region's tail, and its target, before the branch)."""
+    seen: set[int] = set()
+    i = a + 1
+    for _ in range(20000):
+        if i >= len(lines) or i == b or i in seen:
+            break
+        seen.add(i)
+        t = lines[i].split()
+        if t and t[0] == "s_branch":
+            i = labels[t[1]]
+            continue
+        i += 1
+    return seen
+
+
 def _rare_regions(lines: list[str], labels: dict[str, int]) -> set[int]:
     """Lines of the exec-mask branches whose regions the fast path skips."""
-    spans = []
+    regions = {}
     for i, l in enumerate(lines):
         t = l.split()
         if t and t[0] == "s_cbranch_execz":
-            spans.append((i, labels[t[1]]))
-    has = lambda a, b, what: any(what in lines[k] for k in range(a + 1, b))
-    with_rcp = [(a, b) for a, b in spans if has(a, b, "v_rcp_f32")]
+            regions[i] = _region(lines, labels, i, labels[t[1]])
+    has = lambda r, what: any(what in lines[k] for k in r)
+    with_rcp = {a: r for a, r in regions.items() if has(r, "v_rcp_f32")}
     rare = set()
-    for a, b in with_rcp:
-        if not any(a < a2 and b2 <= b and (a2, b2) != (a, b) for a2, b2 in with_rcp):
+    for a, r in with_rcp.items():
+        if not any(a2 != a and a2 in r for a2 in with_rcp):
             rare.add(a)                       # innermost region holding the step's guess
-    for a, b in spans:
-        if has(a, b, "global_store"):
+    for a, r in regions.items():
+        if has(r, "global_store"):
             rare.add(a)                       # the flush of the partial sums
     return rare
 
@@ -88,7 +106,9 @@ def walk(lines: list[str], head: int) -> dict[str, int]:
     counts: dict[str, int] = {}
     i = head + 1
     for _ in range(100000):
-        if i >= len(lines):
+        # back at the header: by a branch (below) or, when the loop's latch is placed before its
+        # header, by falling through into it
+        if i >= len(lines) or i == head:
             break
         l = lines[i].strip()
         if not l or l.startswith(";") or l.startswith("."):
