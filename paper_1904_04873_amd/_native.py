@@ -161,6 +161,7 @@ SIGNATURES = {
     "bsh_topk_noalloc_max_bytes": (ctypes.c_size_t, []),
     "bsh_topk_noalloc": (ctypes.c_int, [_vp, _vp, _c_i64, _c_i32, _vp, _vp, _vp]),
     "bsh_topk_segmented_workspace": (ctypes.c_size_t, [_c_i32, _c_i32]),
+    "bsh_topk_segmented_candidate_workspace": (ctypes.c_size_t, [_c_i32, _c_i32]),
     "bsh_topk_segmented": (ctypes.c_int, [_vp, _vp, _vp, _vp, _c_i32, _c_i32, _c_i32, _vp, _vp, _vp,
                                           ctypes.c_size_t, _vp]),
     "bsh_decode_templates": (ctypes.c_int, [ctypes.POINTER(Grid), _vp, _c_i64, _vp, _vp, _vp]),

@@ -323,9 +323,10 @@ def bsh_topk(score: torch.Tensor, k: int, index: Optional[torch.Tensor] = None):
 
 
 def bsh_topk_segmented(score: torch.Tensor, offsets: np.ndarray, k: int, index: Optional[torch.Tensor] = None,
-                       index_shift: int = 0):
+                       index_shift: int = 0, candidates: bool = True):
     """Independent top-k lists of the segments score[offsets[g] .. offsets[g+1]):
-    (scores float32 [n_segs, k], indices int64 [n_segs, k])."""
+    (scores float32 [n_segs, k], indices int64 [n_segs, k]).  candidates: give the workspace
+    that lets long segments take the candidate pass (the same lists)."""
     assert score.dtype == torch.float32 and score.is_contiguous()
     if index is not None:
         assert index.dtype == torch.int64 and index.is_contiguous() and index.numel() == score.numel()
@@ -334,7 +335,8 @@ def bsh_topk_segmented(score: torch.Tensor, offsets: np.ndarray, k: int, index: 
     n_segs = off_h.size - 1
     off_d = torch.from_numpy(off_h).to(dev)
     L = N.load()
-    wsb = int(L.bsh_topk_segmented_workspace(n_segs, int(k)))
+    wsb = int((L.bsh_topk_segmented_candidate_workspace if candidates else L.bsh_topk_segmented_workspace)(
+        n_segs, int(k)))
     ws = torch.empty(max(1, wsb), dtype=torch.uint8, device=dev)
     out_s = torch.empty((n_segs, k), dtype=torch.float32, device=dev)
     out_i = torch.empty((n_segs, k), dtype=torch.int64, device=dev)

@@ -355,10 +355,10 @@ extern "C" int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh
         // one single-segment call per item: room for either
         int32_t widest = 1;
         for (int32_t q = 0; q < n_passes; ++q) widest = std::max(widest, p->pass_item[q + 1] - p->pass_item[q]);
-        p->ws_item = std::max(topk_workspace_bytes(widest, p->k_item), topk_workspace_bytes(1, p->k_item));
+        p->ws_item = std::max(topk_candidate_workspace_bytes(widest, p->k_item), topk_workspace_bytes(1, p->k_item));
         if (!rc) rc = dev_alloc((char**)&p->d_ws_item, p->ws_item);
         if (!rc && p->k_band > 0) {
-            p->ws_band = topk_workspace_bytes(n_bands, p->k_band);
+            p->ws_band = topk_candidate_workspace_bytes(n_bands, p->k_band);
             rc = dev_alloc((char**)&p->d_ws_band, p->ws_band);
         }
     }

@@ -54,6 +54,8 @@ bool proven_window(const bsh_segments* seg, const bsh_grid* g, double* v, double
 // With implicit indices (index NULL) the written indices are index_base + ((g << shift) | position);
 // the order among a segment's entries does not depend on the base.
 size_t topk_workspace_bytes(int32_t n_segs, int32_t k);
+// A workspace of this size lets a segmented call with long segments take the candidate pass.
+size_t topk_candidate_workspace_bytes(int32_t n_segs, int32_t k);
 int topk_segmented(const float* score, const int64_t* index, const int64_t* offsets, int32_t n_segs,
                    int64_t max_len, int32_t shift, int32_t k, float* out_score, int64_t* out_index,
                    void* ws, size_t ws_bytes, hipStream_t stream, int64_t index_base = 0);

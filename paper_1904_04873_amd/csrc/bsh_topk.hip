@@ -17,6 +17,16 @@
 //    precede it), which is exact, deterministic and independent of the arrival order.
 // Short segments run all of this in one block (small_topk_kernel).  Everything stays on the
 // stream: no host synchronisation, counts live in the workspace.
+//
+// Candidate pass (many long segments, k <= kSmallK, given the larger workspace): instead of the
+// six or more passes over every entry above, one block per segment takes the key T_g of rank m
+// in a sample of the segment (runs of consecutive entries spread over it, m chosen so that
+// about kCandCap / 4 entries of the segment are expected at or above it), one pass copies the
+// entries with key >= T_g to a buffer of kCandCap per segment, and the one-block selection runs
+// on that buffer.  It is exact whenever at least k_eff and at most kCandCap entries were
+// copied: every entry of the segment's top-k then has a key >= T_g.  The segments where either
+// bound fails (a sample that misrepresents its segment, mass ties at T_g) are marked and taken
+// by the passes above afterwards, whose kernels skip the settled segments.
 #include <algorithm>
 #include <cstring>
 #include <mutex>
@@ -70,6 +80,15 @@ struct Seg {
     uint32_t* tkey;          // [n_segs][k] chosen entries grouped by bucket
     float* tscore;           // [n_segs][k]
     int64_t* tindex;         // [n_segs][k]
+    // candidate pass: a Seg over the candidate buffers takes segment g as entries
+    // [g cand_cap, g cand_cap + min(cand_cnt[g], cand_cap)) and records in done_out[g] whether
+    // they settle it (cand_keff[g]: k_eff of the full segment); the passes over the full
+    // segments then skip every g with done[g] set
+    const uint32_t* cand_cnt;
+    int64_t cand_cap;
+    const uint32_t* cand_keff;
+    uint32_t* done_out;
+    const uint32_t* done;
 };
 
 __host__ __device__ inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -150,7 +169,10 @@ void carve(void* ws, Seg& s)
 
 __device__ __forceinline__ void seg_range(const Seg& s, int g, int64_t& lo, int64_t& hi)
 {
-    if (s.off) {
+    if (s.cand_cnt) {
+        lo = (int64_t)g * s.cand_cap;
+        hi = lo + min((int64_t)s.cand_cnt[g], s.cand_cap);
+    } else if (s.off) {
         lo = s.off[g];
         hi = s.off[g + 1];
     } else {
@@ -185,6 +207,10 @@ __device__ __forceinline__ uint32_t score_key(float f)
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
+
+// Segment g was settled by the candidate pass (block-uniform; the passes over the full segments
+// return at once for it).
+__device__ __forceinline__ bool seg_done(const Seg& s, int g) { return s.done && s.done[g]; }
 
 __device__ __forceinline__ int64_t entry_index(const Seg& s, int g, int64_t e, int64_t lo)
 {
@@ -269,6 +295,7 @@ __device__ void pick_digit(const uint32_t* h, uint32_t rem, bool from_top, uint3
 __global__ void init_kernel(Seg s)
 {
     const int g = blockIdx.y;
+    if (seg_done(s, g)) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         int64_t lo, hi;
         seg_range(s, g, lo, hi);
@@ -325,6 +352,7 @@ __global__ __launch_bounds__(kThreads) void key_hist_kernel(Seg s, int pass)
 {
     __shared__ uint32_t h[kBins], scan[kBins];
     const int g = blockIdx.y;
+    if (seg_done(s, g)) return;
     uint32_t prefix = 0u, remaining = s.st[g].remaining[0];
     if (pass > 0) {
         const KeyStep k = key_step(s, g, pass, scan);
@@ -362,6 +390,7 @@ __global__ __launch_bounds__(kThreads) void split_kernel(Seg s)
     __shared__ int64_t lix[kCap];
     __shared__ uint32_t lcount, gbase, scan[kBins];
     const int g = blockIdx.y;
+    if (seg_done(s, g)) return;
     const uint32_t k_eff = s.st[g].k_eff;
     if (k_eff == 0u) return;
     const KeyStep k = key_step(s, g, kKeyPasses, scan);
@@ -443,6 +472,7 @@ __global__ __launch_bounds__(kThreads) void tie_hist_kernel(Seg s, int pass, int
 {
     __shared__ uint32_t h[kBins], scan[kBins];
     const int g = blockIdx.y;
+    if (seg_done(s, g)) return;
     unsigned long long prefix = 0ull;
     uint32_t remaining = s.st[g].iremaining[0];
     if (pass > 0) {
@@ -473,6 +503,7 @@ __global__ __launch_bounds__(kThreads) void tie_take_kernel(Seg s, int n_pass)
 {
     __shared__ uint32_t scan[kBins];
     const int g = blockIdx.y;
+    if (seg_done(s, g)) return;
     const uint32_t k_eff = s.st[g].k_eff;
     if (k_eff == 0u || s.st[g].remaining[kKeyPasses] == 0u) return;
     // largest index (low bits) that makes the cut
@@ -501,6 +532,7 @@ __global__ __launch_bounds__(kThreads) void rank_kernel(Seg s, uint32_t slice)
     __shared__ uint32_t tk[kThreads];
     __shared__ int64_t ti[kThreads];
     const int g = blockIdx.y;
+    if (seg_done(s, g)) return;
     const uint32_t k_eff = s.st[g].k_eff;
     if (blockIdx.x * kThreads >= k_eff) return;
     const uint32_t f_lo = blockIdx.z * slice;
@@ -530,6 +562,7 @@ __global__ __launch_bounds__(kThreads) void rank_kernel(Seg s, uint32_t slice)
 __global__ void scatter_kernel(Seg s, float* __restrict__ out_score, int64_t* __restrict__ out_index)
 {
     const int g = blockIdx.y;
+    if (seg_done(s, g)) return;
     const uint32_t k_eff = s.st[g].k_eff;
     const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (uint32_t)s.k) return;
@@ -550,6 +583,7 @@ __global__ void scatter_kernel(Seg s, float* __restrict__ out_score, int64_t* __
 __global__ __launch_bounds__(kThreads) void winners_max_kernel(Seg s)
 {
     const int g = blockIdx.y;
+    if (seg_done(s, g)) return;
     const uint32_t k_eff = s.st[g].k_eff;
     const uint32_t e = blockIdx.x * kThreads + threadIdx.x;
     uint32_t key = e < k_eff ? score_key(s.sel_score[(size_t)g * s.k + e]) : 0u;
@@ -574,6 +608,7 @@ __device__ __forceinline__ uint32_t bucket_of(const Seg& s, int g, uint32_t key)
 __global__ __launch_bounds__(kThreads) void bucket_count_kernel(Seg s)
 {
     const int g = blockIdx.y;
+    if (seg_done(s, g)) return;
     const uint32_t e = blockIdx.x * kThreads + threadIdx.x;
     if (e >= s.st[g].k_eff) return;
     const uint32_t b = bucket_of(s, g, score_key(s.sel_score[(size_t)g * s.k + e]));
@@ -585,6 +620,7 @@ __global__ __launch_bounds__(1024) void bucket_scan_kernel(Seg s)
 {
     __shared__ uint32_t part[1024];
     const int g = blockIdx.x;
+    if (seg_done(s, g)) return;
     const int t = threadIdx.x;
     const uint32_t nb = 1u << s.bucket_log2;
     const uint32_t per = (nb + 1023) / 1024;
@@ -610,6 +646,7 @@ __global__ __launch_bounds__(1024) void bucket_scan_kernel(Seg s)
 __global__ __launch_bounds__(kThreads) void bucket_scatter_kernel(Seg s)
 {
     const int g = blockIdx.y;
+    if (seg_done(s, g)) return;
     const uint32_t e = blockIdx.x * kThreads + threadIdx.x;
     if (e >= s.st[g].k_eff) return;
     const float sc = s.sel_score[(size_t)g * s.k + e];
@@ -627,6 +664,7 @@ __global__ __launch_bounds__(kThreads) void bucket_rank_kernel(Seg s, float* __r
                                                                int64_t* __restrict__ out_index)
 {
     const int g = blockIdx.y;
+    if (seg_done(s, g)) return;
     const uint32_t k_eff = s.st[g].k_eff;
     const uint32_t p = blockIdx.x * kThreads + threadIdx.x;
     if (p >= (uint32_t)s.k) return;
@@ -674,6 +712,15 @@ __global__ __launch_bounds__(kSmallThreads) void small_topk_kernel(Seg s, float*
     __shared__ int64_t ci[kSmallK];
     const int g = blockIdx.x;
     const int t = threadIdx.x;
+    if (seg_done(s, g)) return;
+    if (s.done_out) {
+        // over a segment's candidates: they settle it when none was dropped for want of room
+        // and at least k_eff of the full segment's entries were copied
+        const uint32_t c = s.cand_cnt[g];
+        const bool ok = (int64_t)c <= s.cand_cap && c >= s.cand_keff[g];
+        if (t == 0) s.done_out[g] = ok ? 1u : 0u;
+        if (!ok) return;
+    }
     int64_t lo, hi;
     seg_range(s, g, lo, hi);
     const int64_t len = hi - lo;
@@ -783,7 +830,158 @@ __global__ __launch_bounds__(kSmallThreads) void small_topk_kernel(Seg s, float*
     }
 }
 
-int topk_launch(Seg s, int64_t max_len, float* out_score, int64_t* out_index, hipStream_t st)
+// ---------------------------------------------------------------- candidate pass
+
+constexpr int64_t kCandCap = 32768;      // candidates kept per segment
+constexpr int kSampleRun = 64;           // consecutive entries per sampled run
+constexpr int kSampleRuns = 512;         // runs per segment, first and last at its two ends
+constexpr int kSample = kSampleRun * kSampleRuns;
+constexpr int kGuessThreads = 512;
+constexpr int kFallbackBlocks = 64;      // blocks per segment of the passes after the candidates
+
+static_assert(kCandCap <= kSmallLen, "the one-block selection takes a segment's candidates");
+static_assert(kSample % kGuessThreads == 0, "every thread takes the same number of samples");
+
+struct CandBufs {
+    uint32_t* T;        // [n_segs] threshold key
+    uint32_t* cnt;      // [n_segs] entries with key >= T (also those beyond the buffer)
+    uint32_t* keff;     // [n_segs] k_eff of the full segment
+    uint32_t* done;     // [n_segs] settled by the candidates
+    float* score;       // [n_segs][kCandCap]
+    int64_t* index;     // [n_segs][kCandCap]
+};
+
+size_t cand_bytes(int32_t n_segs)
+{
+    const size_t ns = (size_t)(n_segs > 0 ? n_segs : 1);
+    return 4 * align_up(sizeof(uint32_t) * ns) + align_up(sizeof(float) * (size_t)kCandCap * ns) +
+           align_up(sizeof(int64_t) * (size_t)kCandCap * ns);
+}
+
+CandBufs carve_cand(void* base, int32_t n_segs)
+{
+    const size_t ns = (size_t)n_segs;
+    char* p = (char*)base;
+    CandBufs c;
+    c.T = (uint32_t*)p;
+    p += align_up(sizeof(uint32_t) * ns);
+    c.cnt = (uint32_t*)p;
+    p += align_up(sizeof(uint32_t) * ns);
+    c.keff = (uint32_t*)p;
+    p += align_up(sizeof(uint32_t) * ns);
+    c.done = (uint32_t*)p;
+    p += align_up(sizeof(uint32_t) * ns);
+    c.score = (float*)p;
+    p += align_up(sizeof(float) * (size_t)kCandCap * ns);
+    c.index = (int64_t*)p;
+    return c;
+}
+
+// One block per segment: T_g = the key of rank m (from the top) among kSample entries of the
+// segment, in kSampleRuns runs of kSampleRun consecutive entries spread evenly from its first
+// entry to its last; m is chosen so that about kCandCap / 4 of the segment's entries are
+// expected at or above T_g.  A segment of at most kCandCap entries takes T_g = 0 (all of it).
+// Also clears the segment's candidate count and records its k_eff.
+__global__ __launch_bounds__(kGuessThreads) void cand_guess_kernel(Seg s, uint32_t* cand_T, uint32_t* cand_cnt,
+                                                                   uint32_t* cand_keff)
+{
+    __shared__ uint32_t h[kBins], scan[kBins];
+    __shared__ uint32_t prefix, remaining, passed;
+    __shared__ int digit;
+    const int g = blockIdx.x;
+    const int t = threadIdx.x;
+    int64_t lo, hi;
+    seg_range(s, g, lo, hi);
+    const int64_t len = hi - lo;
+    if (t == 0) {
+        cand_cnt[g] = 0u;
+        cand_keff[g] = (uint32_t)(len < (int64_t)s.k ? len : (int64_t)s.k);
+    }
+    if (len <= kCandCap) {
+        if (t == 0) cand_T[g] = 0u;
+        return;
+    }
+    const uint32_t m = (uint32_t)max((int64_t)1, (int64_t)kSample * (kCandCap / 4) / len);
+    // run r starts at lo + r (len - kSampleRun) / (kSampleRuns - 1): inside the segment
+    const int64_t gap = len - kSampleRun;
+    if (t == 0) {
+        prefix = 0u;
+        remaining = m;
+    }
+    for (int pass = 0; pass < kKeyPasses; ++pass) {
+        for (int b = t; b < kBins; b += kGuessThreads) h[b] = 0u;
+        __syncthreads();
+        const int shift = 24 - 8 * pass;
+        const uint32_t pre = prefix;
+        for (int e = t; e < kSample; e += kGuessThreads) {
+            const int r = e / kSampleRun;
+            const int64_t at = lo + (int64_t)r * gap / (kSampleRuns - 1) + (e - r * kSampleRun);
+            const uint32_t key = score_key(s.score[at]);
+            wave_hist_add(h, pass == 0 || (key >> (shift + 8)) == pre, (key >> shift) & 0xffu);
+        }
+        __syncthreads();
+        pick_digit(h, remaining, true, scan, &digit, &passed);
+        if (t == 0) {
+            remaining -= passed;
+            prefix = (prefix << 8) | (uint32_t)digit;
+        }
+        __syncthreads();
+    }
+    if (t == 0) cand_T[g] = prefix;
+}
+
+// Copies the entries with key >= T_g (score and index) to the segment's candidate buffer; the
+// count goes on past kCandCap, so that an overfull buffer is seen.  As in split_kernel, each block
+// gathers its entries in LDS and reserves their slots with one atomic (all blocks of a segment
+// run at once, and an atomic per entry on the segment's one counter serializes at the L2).
+__global__ __launch_bounds__(kThreads) void cand_compact_kernel(Seg s, const uint32_t* __restrict__ cand_T,
+                                                                uint32_t* cand_cnt, float* __restrict__ cs,
+                                                                int64_t* __restrict__ ci)
+{
+    constexpr uint32_t kLCap = 1024;
+    __shared__ float lsc[kLCap];
+    __shared__ int64_t lix[kLCap];
+    __shared__ uint32_t lcount, gbase;
+    const int g = blockIdx.y;
+    int64_t lo, hi;
+    seg_range(s, g, lo, hi);
+    const uint32_t T = cand_T[g];
+    float* os = cs + (size_t)g * kCandCap;
+    int64_t* oi = ci + (size_t)g * kCandCap;
+    if (threadIdx.x == 0) lcount = 0u;
+    __syncthreads();
+    for_each_score(s.score, lo, hi, [&](int64_t e, float sc) {
+        const bool take = score_key(sc) >= T;
+        const uint32_t pos = wave_claim(&lcount, take);
+        if (take) {
+            const int64_t ix = entry_index(s, g, e, lo);
+            if (pos < kLCap) {
+                lsc[pos] = sc;
+                lix[pos] = ix;
+            } else {
+                const uint32_t gp = atomicAdd(&cand_cnt[g], 1u);
+                if (gp < (uint32_t)kCandCap) {
+                    os[gp] = sc;
+                    oi[gp] = ix;
+                }
+            }
+        }
+    });
+    __syncthreads();
+    const uint32_t n_local = min(lcount, kLCap);
+    if (threadIdx.x == 0) gbase = n_local ? atomicAdd(&cand_cnt[g], n_local) : 0u;
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < n_local; q += kThreads) {
+        const uint32_t pos = gbase + q;
+        if (pos < (uint32_t)kCandCap) {
+            os[pos] = lsc[q];
+            oi[pos] = lix[q];
+        }
+    }
+}
+
+int topk_launch(Seg s, int64_t max_len, float* out_score, int64_t* out_index, hipStream_t st,
+                const CandBufs* cb = nullptr)
 {
     int bps = (int)((max_len + kThreads - 1) / kThreads);
     if (bps > kMaxBlocksPerSeg) bps = kMaxBlocksPerSeg;
@@ -799,6 +997,29 @@ int topk_launch(Seg s, int64_t max_len, float* out_score, int64_t* out_index, hi
     const int n_pass = (bits + 7) / 8;
     s.idx_bits = bits;
 
+    dim3 grid_full = grid2;
+    if (cb) {
+        hipLaunchKernelGGL(cand_guess_kernel, dim3(s.n_segs), dim3(kGuessThreads), 0, st, s, cb->T, cb->cnt, cb->keff);
+        hipLaunchKernelGGL(cand_compact_kernel, grid2, dim3(kThreads), 0, st, s, cb->T, cb->cnt, cb->score,
+                           cb->index);
+        // the one-block selection over each segment's candidates (explicit indices: those of the
+        // full segment, whose implicit ones were formed in the copy)
+        Seg f = s;
+        f.score = cb->score;
+        f.index = cb->index;
+        f.off = nullptr;
+        f.cand_cnt = cb->cnt;
+        f.cand_cap = kCandCap;
+        f.cand_keff = cb->keff;
+        f.done_out = cb->done;
+        hipLaunchKernelGGL(small_topk_kernel<false>, dim3(s.n_segs), dim3(kSmallThreads), 0, st, f, out_score,
+                           out_index, n_pass);
+        // the segments the candidates did not settle: the passes below, which return at once for
+        // the others, on fewer blocks per segment
+        s.done = cb->done;
+        grid_full = dim3(bps < kFallbackBlocks ? bps : kFallbackBlocks, s.n_segs);
+    }
+
     if (max_len <= kSmallLen && s.k <= kSmallK) {
         if (max_len <= kStageLen)
             hipLaunchKernelGGL(small_topk_kernel<true>, dim3(s.n_segs), dim3(kSmallThreads), 0, st, s,
@@ -812,14 +1033,14 @@ int topk_launch(Seg s, int64_t max_len, float* out_score, int64_t* out_index, hi
     const uint32_t kb = (uint32_t)((s.k + kThreads - 1) / kThreads);
     hipLaunchKernelGGL(init_kernel, dim3(kb, s.n_segs), dim3(kThreads), 0, st, s);
     for (int pass = 0; pass < kKeyPasses; ++pass)
-        hipLaunchKernelGGL(key_hist_kernel, grid2, dim3(kThreads), 0, st, s, pass);
-    hipLaunchKernelGGL(split_kernel, grid2, dim3(kThreads), 0, st, s);
+        hipLaunchKernelGGL(key_hist_kernel, grid_full, dim3(kThreads), 0, st, s, pass);
+    hipLaunchKernelGGL(split_kernel, grid_full, dim3(kThreads), 0, st, s);
     // The tie passes keep the full grid: the stage-1 maps hold exact ties (templates whose tracks
     // pick the same bins), so some lists resolve ties, and a list's tie pass on few blocks is the
     // launch's tail (cut to about 4096 blocks in all, the batched step's lists took 10 ms more).
     for (int pass = 0; pass < n_pass; ++pass)
-        hipLaunchKernelGGL(tie_hist_kernel, grid2, dim3(kThreads), 0, st, s, pass, n_pass);
-    hipLaunchKernelGGL(tie_take_kernel, grid2, dim3(kThreads), 0, st, s, n_pass);
+        hipLaunchKernelGGL(tie_hist_kernel, grid_full, dim3(kThreads), 0, st, s, pass, n_pass);
+    hipLaunchKernelGGL(tie_take_kernel, grid_full, dim3(kThreads), 0, st, s, n_pass);
     if (s.bcnt) {
         // grouped by key bucket, then ranks within the buckets
         hipLaunchKernelGGL(winners_max_kernel, dim3(kb, s.n_segs), dim3(kThreads), 0, st, s);
@@ -843,6 +1064,11 @@ int topk_launch(Seg s, int64_t max_len, float* out_score, int64_t* out_index, hi
 namespace bsh {
 
 size_t topk_workspace_bytes(int32_t n_segs, int32_t k) { return workspace_bytes(n_segs, k); }
+
+size_t topk_candidate_workspace_bytes(int32_t n_segs, int32_t k)
+{
+    return workspace_bytes(n_segs, k) + (n_segs >= 2 && k <= kSmallK ? cand_bytes(n_segs) : 0);
+}
 
 // Segmented top-k for library-internal callers (the batched plan); offsets on the device,
 // the longest segment given by the host.  NULL offsets: one segment [0, max_len).
@@ -868,6 +1094,13 @@ int topk_segmented(const float* score, const int64_t* index, const int64_t* offs
     s.k = k;
     s.out_base = index ? 0 : index_base;
     carve(ws, s);
+    // the candidate pass when there are several long segments, the lists fit the one-block
+    // selection and the workspace has room for the candidates
+    const size_t base = workspace_bytes(n_segs, k);
+    if (n_segs >= 2 && k <= kSmallK && max_len > kCandCap && ws_bytes >= base + cand_bytes(n_segs)) {
+        const CandBufs cb = carve_cand((char*)ws + base, n_segs);
+        return topk_launch(s, max_len, out_score, out_index, stream, &cb);
+    }
     return topk_launch(s, max_len, out_score, out_index, stream);
 }
 
@@ -903,6 +1136,12 @@ extern "C" size_t bsh_topk_segmented_workspace(int32_t n_segs, int32_t k)
 {
     if (n_segs < 1 || k < 1) return 0;
     return workspace_bytes(n_segs, k);
+}
+
+extern "C" size_t bsh_topk_segmented_candidate_workspace(int32_t n_segs, int32_t k)
+{
+    if (n_segs < 1 || k < 1) return 0;
+    return bsh::topk_candidate_workspace_bytes(n_segs, k);
 }
 
 extern "C" int bsh_topk_segmented(const float* score, const int64_t* index, const int64_t* offsets,

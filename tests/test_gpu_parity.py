@@ -633,6 +633,62 @@ def test_topk_segmented_many_lists_with_ties(B, explicit):
         assert np.all(ix[g, kk:] == -1) and np.all(np.isneginf(vs[g, kk:])), g
 
 
+def _sample_positions(n):
+    """Entries the candidate pass samples in a segment of n > 32768 entries: 512 runs of 64,
+    run r from r (n - 64) // 511 (the layout include/bsh.h states)."""
+    starts = np.arange(512, dtype=np.int64) * (n - 64) // 511
+    return (starts[:, None] + np.arange(64)).ravel()
+
+
+@pytest.mark.parametrize("explicit", [False, True])
+def test_topk_segmented_candidate_pass(B, explicit):
+    """Segmented top-k with the candidate workspace on long segments, against the oracle's sort
+    and against the same call without the candidate pass, bit for bit.  The segments are built
+    to reach every outcome of the pass: settled by its copy (random scores; integer scores with
+    ties at the threshold; segments short enough to be copied whole; an empty one), too few
+    copied (the sampled entries hold the segment's largest scores, so only about m of them
+    reach the threshold, fewer than k) and an overfull copy (one score repeated 100000 times),
+    the last two then taken by the ordinary passes."""
+    import torch
+    _say(f"segmented top-k, candidate pass, explicit={explicit}")
+    rng = np.random.default_rng(11 + explicit)
+    k = 2048
+    n_big = 1 << 20
+    few = rng.uniform(0.0, 1.0, n_big).astype(np.float32)
+    few[_sample_positions(n_big)] = rng.uniform(2.0, 3.0, 512 * 64).astype(np.float32)
+    segs = [rng.normal(0.0, 1.0, 700001).astype(np.float32),
+            rng.integers(0, 60, 300000).astype(np.float32),
+            few,
+            np.full(100000, 1.5, np.float32),
+            rng.normal(5.0, 2.0, 32768).astype(np.float32),
+            np.zeros(0, np.float32),
+            rng.integers(0, 5, 1500).astype(np.float32),
+            -np.abs(rng.normal(0.0, 1.0, 40000)).astype(np.float32)]
+    lens = np.array([x.size for x in segs])
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    sc = np.concatenate(segs)
+    shift = 32
+    kw = {}
+    if explicit:
+        idx = rng.permutation(3 * sc.size)[:sc.size].astype(np.int64) + (3 << 50)
+        kw["index"] = torch.from_numpy(idx).cuda()
+    else:
+        kw["index_shift"] = shift
+    d_sc = torch.from_numpy(sc).cuda()
+    vs, ix = B.bsh_topk_segmented(d_sc, off, k, candidates=True, **kw)
+    vs0, ix0 = B.bsh_topk_segmented(d_sc, off, k, candidates=False, **kw)
+    torch.cuda.synchronize()
+    vs, ix, vs0, ix0 = _np(vs), _np(ix), _np(vs0), _np(ix0)
+    assert np.array_equal(ix, ix0) and np.array_equal(vs.view(np.uint32), vs0.view(np.uint32))
+    for g in range(len(lens)):
+        a, b = int(off[g]), int(off[g + 1])
+        own = idx[a:b] if explicit else (np.int64(g) << shift) | np.arange(b - a, dtype=np.int64)
+        rv, ri = _topk_ref(sc[a:b], k, own)
+        kk = min(k, b - a)
+        assert np.array_equal(ix[g, :kk], ri[:kk]) and np.array_equal(vs[g, :kk], rv[:kk]), g
+        assert np.all(ix[g, kk:] == -1) and np.all(np.isneginf(vs[g, kk:])), g
+
+
 # ---------------------------------------------------------------- stage 2
 
 def _cands(seg, n, k0, seed, n_sky=1, spread=89.0):
