@@ -247,13 +247,14 @@ int bsh_topk(const float* score, const int64_t* index, int64_t n, int32_t k,
  * 2^32 - 1.  index NULL: entry e of segment g gets the implicit index
  * (g << index_shift) | (e - offsets[g]) (just the position when index_shift is 0).
  * Workspace: bsh_topk_segmented_workspace(n_segs, k) bytes.  n_segs <= 65535.
- * Given at least bsh_topk_segmented_candidate_workspace(n_segs, k) bytes (about 393 KiB per
- * segment more when n_segs >= 2 and k <= 2048), a call whose longest segment exceeds 32768
- * entries first selects candidates: per segment, the key of a set rank among 32768 sampled
- * entries (512 runs of 64 consecutive ones, the first and last at the segment's ends) as a
- * threshold, one pass that copies the entries at or above it (up to 32768), and the selection
- * over that copy; a segment whose copy holds fewer than min(k, length) or overflowed takes the
- * ordinary passes instead.  The lists are the same either way, bit for bit.
+ * Given at least bsh_topk_segmented_candidate_workspace(n_segs, k) bytes (for n_segs >= 2,
+ * 12 bytes per segment and candidate slot more: C = 32768 slots for k <= 2048, else 8 k rounded
+ * up to a multiple of 1024 if that is larger), a call whose longest segment exceeds C entries
+ * first selects candidates: per segment, the key of a set rank among 32768 sampled entries
+ * (512 runs of 64 consecutive ones, run r from r (length - 64) / 511, integer division) as a
+ * threshold aiming at C / 4 entries at or above it, one pass that copies those entries (up to
+ * C), and the selection over that copy; a segment whose copy holds fewer than min(k, length) or
+ * overflowed takes the ordinary passes instead.  The lists are the same either way, bit for bit.
  */
 size_t bsh_topk_segmented_workspace(int32_t n_segs, int32_t k);
 size_t bsh_topk_segmented_candidate_workspace(int32_t n_segs, int32_t k);

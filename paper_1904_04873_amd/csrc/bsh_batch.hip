@@ -355,7 +355,11 @@ extern "C" int bsh_plan_create(const bsh_item* items, int32_t n_items, const bsh
         // one single-segment call per item: room for either
         int32_t widest = 1;
         for (int32_t q = 0; q < n_passes; ++q) widest = std::max(widest, p->pass_item[q + 1] - p->pass_item[q]);
-        p->ws_item = std::max(topk_candidate_workspace_bytes(widest, p->k_item), topk_workspace_bytes(1, p->k_item));
+        // with room for the segmented top-k's candidate pass when that costs at most 2 GiB more
+        const size_t plain_ws = topk_workspace_bytes(widest, p->k_item);
+        const size_t cand_ws = topk_candidate_workspace_bytes(widest, p->k_item);
+        p->ws_item = std::max(cand_ws - plain_ws <= ((size_t)2 << 30) ? cand_ws : plain_ws,
+                              topk_workspace_bytes(1, p->k_item));
         if (!rc) rc = dev_alloc((char**)&p->d_ws_item, p->ws_item);
         if (!rc && p->k_band > 0) {
             p->ws_band = topk_candidate_workspace_bytes(n_bands, p->k_band);

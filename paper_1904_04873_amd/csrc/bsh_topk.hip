@@ -18,15 +18,16 @@
 // Short segments run all of this in one block (small_topk_kernel).  Everything stays on the
 // stream: no host synchronisation, counts live in the workspace.
 //
-// Candidate pass (many long segments, k <= kSmallK, given the larger workspace): instead of the
-// six or more passes over every entry above, one block per segment takes the key T_g of rank m
-// in a sample of the segment (runs of consecutive entries spread over it, m chosen so that
-// about kCandCap / 4 entries of the segment are expected at or above it), one pass copies the
-// entries with key >= T_g to a buffer of kCandCap per segment, and the one-block selection runs
-// on that buffer.  It is exact whenever at least k_eff and at most kCandCap entries were
-// copied: every entry of the segment's top-k then has a key >= T_g.  The segments where either
-// bound fails (a sample that misrepresents its segment, mass ties at T_g) are marked and taken
-// by the passes above afterwards, whose kernels skip the settled segments.
+// Candidate pass (several long segments, given the larger workspace): instead of the six or
+// more passes over every entry above, one block per segment takes the key T_g of rank m in a
+// sample of the segment (runs of consecutive entries spread over it, m chosen so that about a
+// quarter of the buffer's room is expected at or above it), one pass copies the entries with
+// key >= T_g to a buffer per segment (cand_cap(k) entries), and the selection runs on that
+// buffer: one block per segment for k <= kSmallK, else the passes above on the buffers.  It is
+// exact whenever at least k_eff entries were copied and none dropped: every entry of the
+// segment's top-k then has a key >= T_g.  The segments where either bound fails (a sample that
+// misrepresents its segment, mass ties at T_g) are marked and taken by the passes above over
+// the whole segments afterwards, whose kernels skip the settled ones.
 #include <algorithm>
 #include <cstring>
 #include <mutex>
@@ -89,6 +90,7 @@ struct Seg {
     const uint32_t* cand_keff;
     uint32_t* done_out;
     const uint32_t* done;
+    uint32_t done_skip;      // segments with done[g] == done_skip are skipped
 };
 
 __host__ __device__ inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -208,9 +210,9 @@ __device__ __forceinline__ uint32_t score_key(float f)
 }
 
 
-// Segment g was settled by the candidate pass (block-uniform; the passes over the full segments
-// return at once for it).
-__device__ __forceinline__ bool seg_done(const Seg& s, int g) { return s.done && s.done[g]; }
+// Segment g is not this launch's to take (block-uniform): settled by the candidate pass, for the
+// passes over the whole segments; not settled, for the passes over the candidate buffers.
+__device__ __forceinline__ bool seg_done(const Seg& s, int g) { return s.done && s.done[g] == s.done_skip; }
 
 __device__ __forceinline__ int64_t entry_index(const Seg& s, int g, int64_t e, int64_t lo)
 {
@@ -832,7 +834,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_topk_kernel(Seg s, float*
 
 // ---------------------------------------------------------------- candidate pass
 
-constexpr int64_t kCandCap = 32768;      // candidates kept per segment
+constexpr int64_t kCandCap = 32768;      // candidates kept per segment for k <= kSmallK (at least)
 constexpr int kSampleRun = 64;           // consecutive entries per sampled run
 constexpr int kSampleRuns = 512;         // runs per segment, first and last at its two ends
 constexpr int kSample = kSampleRun * kSampleRuns;
@@ -842,27 +844,38 @@ constexpr int kFallbackBlocks = 64;      // blocks per segment of the passes aft
 static_assert(kCandCap <= kSmallLen, "the one-block selection takes a segment's candidates");
 static_assert(kSample % kGuessThreads == 0, "every thread takes the same number of samples");
 
+// Room per segment: 32768 for the one-block selection, else 8 k (rounded up to 1024), so that
+// the threshold aims at 2 k candidates.
+int64_t cand_cap(int32_t k)
+{
+    const int64_t c = ((int64_t)8 * k + 1023) / 1024 * 1024;
+    return k <= kSmallK || c < kCandCap ? kCandCap : c;
+}
+
 struct CandBufs {
+    int64_t cap;        // cand_cap(k)
     uint32_t* T;        // [n_segs] threshold key
     uint32_t* cnt;      // [n_segs] entries with key >= T (also those beyond the buffer)
     uint32_t* keff;     // [n_segs] k_eff of the full segment
     uint32_t* done;     // [n_segs] settled by the candidates
-    float* score;       // [n_segs][kCandCap]
-    int64_t* index;     // [n_segs][kCandCap]
+    float* score;       // [n_segs][cap]
+    int64_t* index;     // [n_segs][cap]
 };
 
-size_t cand_bytes(int32_t n_segs)
+size_t cand_bytes(int32_t n_segs, int32_t k)
 {
     const size_t ns = (size_t)(n_segs > 0 ? n_segs : 1);
-    return 4 * align_up(sizeof(uint32_t) * ns) + align_up(sizeof(float) * (size_t)kCandCap * ns) +
-           align_up(sizeof(int64_t) * (size_t)kCandCap * ns);
+    const size_t cap = (size_t)cand_cap(k);
+    return 4 * align_up(sizeof(uint32_t) * ns) + align_up(sizeof(float) * cap * ns) +
+           align_up(sizeof(int64_t) * cap * ns);
 }
 
-CandBufs carve_cand(void* base, int32_t n_segs)
+CandBufs carve_cand(void* base, int32_t n_segs, int32_t k)
 {
     const size_t ns = (size_t)n_segs;
     char* p = (char*)base;
     CandBufs c;
+    c.cap = cand_cap(k);
     c.T = (uint32_t*)p;
     p += align_up(sizeof(uint32_t) * ns);
     c.cnt = (uint32_t*)p;
@@ -872,18 +885,18 @@ CandBufs carve_cand(void* base, int32_t n_segs)
     c.done = (uint32_t*)p;
     p += align_up(sizeof(uint32_t) * ns);
     c.score = (float*)p;
-    p += align_up(sizeof(float) * (size_t)kCandCap * ns);
+    p += align_up(sizeof(float) * (size_t)c.cap * ns);
     c.index = (int64_t*)p;
     return c;
 }
 
 // One block per segment: T_g = the key of rank m (from the top) among kSample entries of the
 // segment, in kSampleRuns runs of kSampleRun consecutive entries spread evenly from its first
-// entry to its last; m is chosen so that about kCandCap / 4 of the segment's entries are
-// expected at or above T_g.  A segment of at most kCandCap entries takes T_g = 0 (all of it).
-// Also clears the segment's candidate count and records its k_eff.
-__global__ __launch_bounds__(kGuessThreads) void cand_guess_kernel(Seg s, uint32_t* cand_T, uint32_t* cand_cnt,
-                                                                   uint32_t* cand_keff)
+// entry to its last; m is chosen so that about cap / 4 of the segment's entries are expected at
+// or above T_g.  A segment of at most cap entries takes T_g = 0 (all of it).  Also clears the
+// segment's candidate count and records its k_eff.
+__global__ __launch_bounds__(kGuessThreads) void cand_guess_kernel(Seg s, int64_t cap, uint32_t* cand_T,
+                                                                   uint32_t* cand_cnt, uint32_t* cand_keff)
 {
     __shared__ uint32_t h[kBins], scan[kBins];
     __shared__ uint32_t prefix, remaining, passed;
@@ -897,11 +910,12 @@ __global__ __launch_bounds__(kGuessThreads) void cand_guess_kernel(Seg s, uint32
         cand_cnt[g] = 0u;
         cand_keff[g] = (uint32_t)(len < (int64_t)s.k ? len : (int64_t)s.k);
     }
-    if (len <= kCandCap) {
+    if (len <= cap) {
         if (t == 0) cand_T[g] = 0u;
         return;
     }
-    const uint32_t m = (uint32_t)max((int64_t)1, (int64_t)kSample * (kCandCap / 4) / len);
+    // (len > cap, so m < kSample / 4)
+    const uint32_t m = (uint32_t)max((int64_t)1, (int64_t)kSample * (cap / 4) / len);
     // run r starts at lo + r (len - kSampleRun) / (kSampleRuns - 1): inside the segment
     const int64_t gap = len - kSampleRun;
     if (t == 0) {
@@ -931,10 +945,10 @@ __global__ __launch_bounds__(kGuessThreads) void cand_guess_kernel(Seg s, uint32
 }
 
 // Copies the entries with key >= T_g (score and index) to the segment's candidate buffer; the
-// count goes on past kCandCap, so that an overfull buffer is seen.  As in split_kernel, each block
+// count goes on past the buffer's room (cap), so that an overfull buffer is seen.  As in split_kernel, each block
 // gathers its entries in LDS and reserves their slots with one atomic (all blocks of a segment
 // run at once, and an atomic per entry on the segment's one counter serializes at the L2).
-__global__ __launch_bounds__(kThreads) void cand_compact_kernel(Seg s, const uint32_t* __restrict__ cand_T,
+__global__ __launch_bounds__(kThreads) void cand_compact_kernel(Seg s, int64_t cap, const uint32_t* __restrict__ cand_T,
                                                                 uint32_t* cand_cnt, float* __restrict__ cs,
                                                                 int64_t* __restrict__ ci)
 {
@@ -946,8 +960,8 @@ __global__ __launch_bounds__(kThreads) void cand_compact_kernel(Seg s, const uin
     int64_t lo, hi;
     seg_range(s, g, lo, hi);
     const uint32_t T = cand_T[g];
-    float* os = cs + (size_t)g * kCandCap;
-    int64_t* oi = ci + (size_t)g * kCandCap;
+    float* os = cs + (size_t)g * cap;
+    int64_t* oi = ci + (size_t)g * cap;
     if (threadIdx.x == 0) lcount = 0u;
     __syncthreads();
     for_each_score(s.score, lo, hi, [&](int64_t e, float sc) {
@@ -960,7 +974,7 @@ __global__ __launch_bounds__(kThreads) void cand_compact_kernel(Seg s, const uin
                 lix[pos] = ix;
             } else {
                 const uint32_t gp = atomicAdd(&cand_cnt[g], 1u);
-                if (gp < (uint32_t)kCandCap) {
+                if ((int64_t)gp < cap) {
                     os[gp] = sc;
                     oi[gp] = ix;
                 }
@@ -973,53 +987,27 @@ __global__ __launch_bounds__(kThreads) void cand_compact_kernel(Seg s, const uin
     __syncthreads();
     for (uint32_t q = threadIdx.x; q < n_local; q += kThreads) {
         const uint32_t pos = gbase + q;
-        if (pos < (uint32_t)kCandCap) {
+        if ((int64_t)pos < cap) {
             os[pos] = lsc[q];
             oi[pos] = lix[q];
         }
     }
 }
 
-int topk_launch(Seg s, int64_t max_len, float* out_score, int64_t* out_index, hipStream_t st,
-                const CandBufs* cb = nullptr)
+// Whether each segment's candidates settle it: none dropped for want of room, and at least
+// k_eff of the full segment's entries copied.
+__global__ void cand_done_kernel(const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ keff, int64_t cap,
+                                 uint32_t* __restrict__ done, int n_segs)
 {
-    int bps = (int)((max_len + kThreads - 1) / kThreads);
-    if (bps > kMaxBlocksPerSeg) bps = kMaxBlocksPerSeg;
-    if (bps < 1) bps = 1;
-    if (s.n_segs > 65535) return fail_inval("more than 65535 segments");
-    const dim3 grid2(bps, s.n_segs);
-    // index digits to resolve: 64 bits for explicit indices, the position bits otherwise
-    int bits = 64;
-    if (!s.index) {
-        bits = 1;
-        while (bits < 63 && ((int64_t)1 << bits) < max_len) ++bits;
-    }
-    const int n_pass = (bits + 7) / 8;
-    s.idx_bits = bits;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < n_segs) done[g] = ((int64_t)cnt[g] <= cap && cnt[g] >= keff[g]) ? 1u : 0u;
+}
 
-    dim3 grid_full = grid2;
-    if (cb) {
-        hipLaunchKernelGGL(cand_guess_kernel, dim3(s.n_segs), dim3(kGuessThreads), 0, st, s, cb->T, cb->cnt, cb->keff);
-        hipLaunchKernelGGL(cand_compact_kernel, grid2, dim3(kThreads), 0, st, s, cb->T, cb->cnt, cb->score,
-                           cb->index);
-        // the one-block selection over each segment's candidates (explicit indices: those of the
-        // full segment, whose implicit ones were formed in the copy)
-        Seg f = s;
-        f.score = cb->score;
-        f.index = cb->index;
-        f.off = nullptr;
-        f.cand_cnt = cb->cnt;
-        f.cand_cap = kCandCap;
-        f.cand_keff = cb->keff;
-        f.done_out = cb->done;
-        hipLaunchKernelGGL(small_topk_kernel<false>, dim3(s.n_segs), dim3(kSmallThreads), 0, st, f, out_score,
-                           out_index, n_pass);
-        // the segments the candidates did not settle: the passes below, which return at once for
-        // the others, on fewer blocks per segment
-        s.done = cb->done;
-        grid_full = dim3(bps < kFallbackBlocks ? bps : kFallbackBlocks, s.n_segs);
-    }
-
+// The selection over s's segments (at most max_len entries each): one block per segment for
+// short ones and small k, else the radix passes on `blocks` blocks per segment.
+void run_passes(const Seg& s, int64_t max_len, int blocks, int n_pass, float* out_score, int64_t* out_index,
+                hipStream_t st)
+{
     if (max_len <= kSmallLen && s.k <= kSmallK) {
         if (max_len <= kStageLen)
             hipLaunchKernelGGL(small_topk_kernel<true>, dim3(s.n_segs), dim3(kSmallThreads), 0, st, s,
@@ -1027,20 +1015,21 @@ int topk_launch(Seg s, int64_t max_len, float* out_score, int64_t* out_index, hi
         else
             hipLaunchKernelGGL(small_topk_kernel<false>, dim3(s.n_segs), dim3(kSmallThreads), 0, st, s,
                                out_score, out_index, n_pass);
-        return check_launch("bsh_topk");
+        return;
     }
+    const dim3 grid(blocks, s.n_segs);
     // 8 + n_pass launches: the digit picks run at the head of the next pass's kernel
     const uint32_t kb = (uint32_t)((s.k + kThreads - 1) / kThreads);
     hipLaunchKernelGGL(init_kernel, dim3(kb, s.n_segs), dim3(kThreads), 0, st, s);
     for (int pass = 0; pass < kKeyPasses; ++pass)
-        hipLaunchKernelGGL(key_hist_kernel, grid_full, dim3(kThreads), 0, st, s, pass);
-    hipLaunchKernelGGL(split_kernel, grid_full, dim3(kThreads), 0, st, s);
+        hipLaunchKernelGGL(key_hist_kernel, grid, dim3(kThreads), 0, st, s, pass);
+    hipLaunchKernelGGL(split_kernel, grid, dim3(kThreads), 0, st, s);
     // The tie passes keep the full grid: the stage-1 maps hold exact ties (templates whose tracks
     // pick the same bins), so some lists resolve ties, and a list's tie pass on few blocks is the
     // launch's tail (cut to about 4096 blocks in all, the batched step's lists took 10 ms more).
     for (int pass = 0; pass < n_pass; ++pass)
-        hipLaunchKernelGGL(tie_hist_kernel, grid_full, dim3(kThreads), 0, st, s, pass, n_pass);
-    hipLaunchKernelGGL(tie_take_kernel, grid_full, dim3(kThreads), 0, st, s, n_pass);
+        hipLaunchKernelGGL(tie_hist_kernel, grid, dim3(kThreads), 0, st, s, pass, n_pass);
+    hipLaunchKernelGGL(tie_take_kernel, grid, dim3(kThreads), 0, st, s, n_pass);
     if (s.bcnt) {
         // grouped by key bucket, then ranks within the buckets
         hipLaunchKernelGGL(winners_max_kernel, dim3(kb, s.n_segs), dim3(kThreads), 0, st, s);
@@ -1049,13 +1038,68 @@ int topk_launch(Seg s, int64_t max_len, float* out_score, int64_t* out_index, hi
         hipLaunchKernelGGL(bucket_scatter_kernel, dim3(kb, s.n_segs), dim3(kThreads), 0, st, s);
         hipLaunchKernelGGL(bucket_rank_kernel, dim3(kb, s.n_segs), dim3(kThreads), 0, st, s, out_score,
                            out_index);
-        return check_launch("bsh_topk");
+        return;
     }
     // rank counting: k x k comparisons spread over (k/256) x slices blocks
     const uint32_t n_slices = kb < 64 ? kb : 64;
     const uint32_t slice = (uint32_t)((s.k + n_slices - 1) / n_slices);
     hipLaunchKernelGGL(rank_kernel, dim3(kb, s.n_segs, n_slices), dim3(kThreads), 0, st, s, slice);
     hipLaunchKernelGGL(scatter_kernel, dim3(kb, s.n_segs), dim3(kThreads), 0, st, s, out_score, out_index);
+}
+
+int blocks_for(int64_t len)
+{
+    const int64_t b = (len + kThreads - 1) / kThreads;
+    return (int)(b > kMaxBlocksPerSeg ? kMaxBlocksPerSeg : (b < 1 ? 1 : b));
+}
+
+int topk_launch(Seg s, int64_t max_len, float* out_score, int64_t* out_index, hipStream_t st,
+                const CandBufs* cb = nullptr)
+{
+    const int bps = blocks_for(max_len);
+    if (s.n_segs > 65535) return fail_inval("more than 65535 segments");
+    // index digits to resolve: 64 bits for explicit indices, the position bits otherwise
+    int bits = 64;
+    if (!s.index) {
+        bits = 1;
+        while (bits < 63 && ((int64_t)1 << bits) < max_len) ++bits;
+    }
+    const int n_pass = (bits + 7) / 8;
+    s.idx_bits = bits;
+    if (!cb) {
+        run_passes(s, max_len, bps, n_pass, out_score, out_index, st);
+        return check_launch("bsh_topk");
+    }
+    hipLaunchKernelGGL(cand_guess_kernel, dim3(s.n_segs), dim3(kGuessThreads), 0, st, s, cb->cap, cb->T, cb->cnt,
+                       cb->keff);
+    hipLaunchKernelGGL(cand_compact_kernel, dim3(bps, s.n_segs), dim3(kThreads), 0, st, s, cb->cap, cb->T, cb->cnt,
+                       cb->score, cb->index);
+    // the selection over each segment's candidates (explicit indices: those of the full segment,
+    // whose implicit ones were formed in the copy)
+    Seg f = s;
+    f.score = cb->score;
+    f.index = cb->index;
+    f.off = nullptr;
+    f.cand_cnt = cb->cnt;
+    f.cand_cap = cb->cap;
+    f.cand_keff = cb->keff;
+    if (s.k <= kSmallK) {
+        // one block per segment, which also records which segments its candidates settle
+        f.done_out = cb->done;
+        hipLaunchKernelGGL(small_topk_kernel<false>, dim3(s.n_segs), dim3(kSmallThreads), 0, st, f, out_score,
+                           out_index, n_pass);
+    } else {
+        hipLaunchKernelGGL(cand_done_kernel, dim3((s.n_segs + 255) / 256), dim3(256), 0, st, cb->cnt, cb->keff,
+                           cb->cap, cb->done, s.n_segs);
+        f.done = cb->done;
+        f.done_skip = 0u;
+        run_passes(f, cb->cap, blocks_for(cb->cap), n_pass, out_score, out_index, st);
+    }
+    // the segments the candidates did not settle: the passes over the whole segments, which
+    // return at once for the others, on fewer blocks per segment
+    s.done = cb->done;
+    s.done_skip = 1u;
+    run_passes(s, max_len, bps < kFallbackBlocks ? bps : kFallbackBlocks, n_pass, out_score, out_index, st);
     return check_launch("bsh_topk");
 }
 
@@ -1067,7 +1111,7 @@ size_t topk_workspace_bytes(int32_t n_segs, int32_t k) { return workspace_bytes(
 
 size_t topk_candidate_workspace_bytes(int32_t n_segs, int32_t k)
 {
-    return workspace_bytes(n_segs, k) + (n_segs >= 2 && k <= kSmallK ? cand_bytes(n_segs) : 0);
+    return workspace_bytes(n_segs, k) + (n_segs >= 2 ? cand_bytes(n_segs, k) : 0);
 }
 
 // Segmented top-k for library-internal callers (the batched plan); offsets on the device,
@@ -1094,11 +1138,11 @@ int topk_segmented(const float* score, const int64_t* index, const int64_t* offs
     s.k = k;
     s.out_base = index ? 0 : index_base;
     carve(ws, s);
-    // the candidate pass when there are several long segments, the lists fit the one-block
-    // selection and the workspace has room for the candidates
+    // the candidate pass when there are several segments longer than its buffers and the
+    // workspace has room for them
     const size_t base = workspace_bytes(n_segs, k);
-    if (n_segs >= 2 && k <= kSmallK && max_len > kCandCap && ws_bytes >= base + cand_bytes(n_segs)) {
-        const CandBufs cb = carve_cand((char*)ws + base, n_segs);
+    if (n_segs >= 2 && max_len > cand_cap(k) && ws_bytes >= base + cand_bytes(n_segs, k)) {
+        const CandBufs cb = carve_cand((char*)ws + base, n_segs, k);
         return topk_launch(s, max_len, out_score, out_index, stream, &cb);
     }
     return topk_launch(s, max_len, out_score, out_index, stream);

@@ -210,11 +210,11 @@ def test_topk_workspace_is_order_k():
     c = L.bsh_topk_workspace(1000, 5000)
     assert a == b and c > a and c >= 12 * 5000
     assert L.bsh_topk_segmented_workspace(100, 10) > L.bsh_topk_segmented_workspace(1, 10)
-    # the candidate pass's room: 32768 scores and indices per segment, for several lists of
-    # k <= 2048 only
-    assert (L.bsh_topk_segmented_candidate_workspace(100, 2048) - L.bsh_topk_segmented_workspace(100, 2048)
-            >= 100 * 32768 * 12)
-    assert L.bsh_topk_segmented_candidate_workspace(100, 2049) == L.bsh_topk_segmented_workspace(100, 2049)
+    # the candidate pass's room for several lists: 32768 scores and indices per segment up to
+    # k = 4096, 8 k (rounded up to 1024) beyond; none for a single list
+    for k, cap in ((2048, 32768), (2049, 32768), (100000, 800768)):
+        extra = L.bsh_topk_segmented_candidate_workspace(100, k) - L.bsh_topk_segmented_workspace(100, k)
+        assert 100 * cap * 12 <= extra < 100 * cap * 12 + 4096, k
     assert L.bsh_topk_segmented_candidate_workspace(1, 10) == L.bsh_topk_segmented_workspace(1, 10)
     assert L.bsh_topk_segmented_candidate_workspace(0, 10) == 0
 

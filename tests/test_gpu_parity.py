@@ -640,19 +640,20 @@ def _sample_positions(n):
     return (starts[:, None] + np.arange(64)).ravel()
 
 
-@pytest.mark.parametrize("explicit", [False, True])
-def test_topk_segmented_candidate_pass(B, explicit):
+@pytest.mark.parametrize("explicit,k", [(False, 2048), (True, 2048), (False, 5000), (True, 20000)])
+def test_topk_segmented_candidate_pass(B, explicit, k):
     """Segmented top-k with the candidate workspace on long segments, against the oracle's sort
     and against the same call without the candidate pass, bit for bit.  The segments are built
     to reach every outcome of the pass: settled by its copy (random scores; integer scores with
     ties at the threshold; segments short enough to be copied whole; an empty one), too few
     copied (the sampled entries hold the segment's largest scores, so only about m of them
-    reach the threshold, fewer than k) and an overfull copy (one score repeated 100000 times),
-    the last two then taken by the ordinary passes."""
+    reach the threshold, fewer than k) and, for k <= 5000, an overfull copy (one score repeated
+    100000 times), the last two then taken by the ordinary passes.  k = 2048 selects the
+    candidates in one block per list, 5000 with the radix passes on the buffers, 20000 also
+    orders the winners by key buckets."""
     import torch
-    _say(f"segmented top-k, candidate pass, explicit={explicit}")
-    rng = np.random.default_rng(11 + explicit)
-    k = 2048
+    _say(f"segmented top-k, candidate pass, explicit={explicit}, k={k}")
+    rng = np.random.default_rng(11 + explicit + k)
     n_big = 1 << 20
     few = rng.uniform(0.0, 1.0, n_big).astype(np.float32)
     few[_sample_positions(n_big)] = rng.uniform(2.0, 3.0, 512 * 64).astype(np.float32)
