@@ -82,9 +82,10 @@ struct Seg {
     float* tscore;           // [n_segs][k]
     int64_t* tindex;         // [n_segs][k]
     // candidate pass: a Seg over the candidate buffers takes segment g as entries
-    // [g cand_cap, g cand_cap + min(cand_cnt[g], cand_cap)) and records in done_out[g] whether
-    // they settle it (cand_keff[g]: k_eff of the full segment); the passes over the full
-    // segments then skip every g with done[g] set
+    // [g cand_cap, g cand_cap + min(cand_cnt[g], cand_cap)); the one-block selection records in
+    // done_out[g] whether they settle it (cand_keff[g]: k_eff of the full segment).  Launches
+    // skip the segments whose done[g] equals done_skip: over the buffers those not settled,
+    // over the whole segments those settled.
     const uint32_t* cand_cnt;
     int64_t cand_cap;
     const uint32_t* cand_keff;
