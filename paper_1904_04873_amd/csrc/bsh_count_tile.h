@@ -352,6 +352,11 @@ __device__ __forceinline__ float lds_at(uint32_t a)
 // test raises the range flag (the outputs are then undefined, as for any track outside the rows);
 // the segment is staged as one with G = 1, and the lane skips its groups, so that every window
 // the kernel reads is one of a track inside the rows.
+// Row words per lane whose loads a chunk of the form for proven windows issues ahead of their
+// stores (four of the five of a typical row at one lane per segment; one more and the batched
+// kernel's registers no longer allow three waves per SIMD).
+constexpr int kPreWords = 4;
+
 template <int kChunk, bool kEcc, bool kProven = false>
 __device__ __forceinline__ void count_tile_pair(const ItemDesc& d, int s, int ip, int64_t tile,
                                                 TileSmemLut<kChunk, kEcc>& sm, uint32_t* row,
@@ -471,18 +476,47 @@ __device__ __forceinline__ void count_tile_pair(const ItemDesc& d, int s, int ip
                 sm.DS2[jj] = D * s2;
             }
         }
-        // the rows' data words (their kRowPad zero words are written once, before the first chunk):
-        // word e of the chunk's rows is word wd of row jj, stepped without a division
+        // The rows' data words (their kRowPad zero words are written once, before the first chunk):
+        // word e of the chunk's rows is word e of the item's rows from segment j0 on (zero past
+        // segment nj, the last group's padding) and goes to word wd of row jj (e = jj nw + wd),
+        // stepped without a division.  In the form for proven windows on the circular track the
+        // lane's first kPreWords words are all loaded before any is stored, so that their
+        // latencies overlap (one after another they cost the batched launch 2 %); the other forms
+        // keep one load per store, which holds their registers where they were.
         {
             const int nw = d.n_words;
             const int n_e = ng * kGroup * nw;
             int jj = tid / nw, wd = tid - jj * nw;
             const int dq = lanes / nw, dr = lanes - dq * nw;
-            for (int e = tid; e < n_e; e += lanes) {
-                row[jj * nwp + wd] = jj < nj ? d.bits[(j0 + jj) * nw + wd] : 0u;
-                jj += dq;
-                wd += dr;
-                if (wd >= nw) { wd -= nw; ++jj; }
+            if constexpr (kProven && !kEcc) {
+                const int n_src = nj * nw;
+                const uint32_t* src = d.bits + j0 * nw;
+                uint32_t pre[kPreWords];
+#pragma unroll
+                for (int k = 0; k < kPreWords; ++k) {
+                    const int e = tid + k * lanes;
+                    pre[k] = e < n_src ? src[e] : 0u;
+                }
+#pragma unroll
+                for (int k = 0; k < kPreWords; ++k) {
+                    if (tid + k * lanes < n_e) row[jj * nwp + wd] = pre[k];
+                    jj += dq;
+                    wd += dr;
+                    if (wd >= nw) { wd -= nw; ++jj; }
+                }
+                for (int e = tid + kPreWords * lanes; e < n_e; e += lanes) {
+                    row[jj * nwp + wd] = e < n_src ? src[e] : 0u;
+                    jj += dq;
+                    wd += dr;
+                    if (wd >= nw) { wd -= nw; ++jj; }
+                }
+            } else {
+                for (int e = tid; e < n_e; e += lanes) {
+                    row[jj * nwp + wd] = jj < nj ? d.bits[(j0 + jj) * nw + wd] : 0u;
+                    jj += dq;
+                    wd += dr;
+                    if (wd >= nw) { wd -= nw; ++jj; }
+                }
             }
         }
         // The 256-entry tables, 32 entries (two high nibbles) per work item: T8[16 h + l] =
