@@ -451,6 +451,19 @@ __device__ __forceinline__ void count_tile_pair(const ItemDesc& d, int s, int ip
         const int ng8 = (nj + kGroup8 - 1) / kGroup8;
         const int ng = 2 * ng8;
         groups_done += ng8;
+        // (form for proven windows on the circular track: the lane's first kPreWords row words
+        // are loaded before the barrier, so that their latency overlaps the wait for the other
+        // waves' groups; they are stored below)
+        const int n_src = nj * d.n_words;
+        const uint32_t* src = d.bits + j0 * d.n_words;
+        uint32_t pre[(kProven && !kEcc) ? kPreWords : 1];
+        if constexpr (kProven && !kEcc) {
+#pragma unroll
+            for (int k = 0; k < kPreWords; ++k) {
+                const int e = tid + k * lanes;
+                pre[k] = e < n_src ? src[e] : 0u;
+            }
+        }
         __syncthreads();
         for (int jj = tid; jj < ng * kGroup; jj += lanes) {
             const int64_t J = j0 + min(jj, nj - 1);
@@ -489,14 +502,6 @@ __device__ __forceinline__ void count_tile_pair(const ItemDesc& d, int s, int ip
             int jj = tid / nw, wd = tid - jj * nw;
             const int dq = lanes / nw, dr = lanes - dq * nw;
             if constexpr (kProven && !kEcc) {
-                const int n_src = nj * nw;
-                const uint32_t* src = d.bits + j0 * nw;
-                uint32_t pre[kPreWords];
-#pragma unroll
-                for (int k = 0; k < kPreWords; ++k) {
-                    const int e = tid + k * lanes;
-                    pre[k] = e < n_src ? src[e] : 0u;
-                }
 #pragma unroll
                 for (int k = 0; k < kPreWords; ++k) {
                     if (tid + k * lanes < n_e) row[jj * nwp + wd] = pre[k];
