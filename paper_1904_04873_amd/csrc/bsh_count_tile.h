@@ -344,6 +344,11 @@ __device__ __forceinline__ float lds_at(uint32_t a)
     return *(const __attribute__((address_space(3))) float*)(size_t)a;
 }
 
+// Row words per lane whose loads a chunk of the form for proven windows issues ahead of their
+// stores (four of the five of a typical row at one lane per segment; one more and the batched
+// kernel's registers no longer allow three waves per SIMD).
+constexpr int kPreWords = 4;
+
 // smem: the block's LDS (rows first, then the structure at byte offset sm_off).
 // kProven: the launch's tracks are proven to stay inside the rows with at most one f0-shift step
 // (proven_window).  Instead of testing every track, the inputs of the proof are tested as they
@@ -352,11 +357,6 @@ __device__ __forceinline__ float lds_at(uint32_t a)
 // test raises the range flag (the outputs are then undefined, as for any track outside the rows);
 // the segment is staged as one with G = 1, and the lane skips its groups, so that every window
 // the kernel reads is one of a track inside the rows.
-// Row words per lane whose loads a chunk of the form for proven windows issues ahead of their
-// stores (four of the five of a typical row at one lane per segment; one more and the batched
-// kernel's registers no longer allow three waves per SIMD).
-constexpr int kPreWords = 4;
-
 template <int kChunk, bool kEcc, bool kProven = false>
 __device__ __forceinline__ void count_tile_pair(const ItemDesc& d, int s, int ip, int64_t tile,
                                                 TileSmemLut<kChunk, kEcc>& sm, uint32_t* row,
